@@ -1,0 +1,465 @@
+"""Synthetic cells shaped like the paper's Gamma-point supercells.
+
+Units are Hartree atomic units (bohr, Ha).  Cut-offs are in Rydberg, so a
+plane wave G = (2 pi / L) n belongs to the wavefunction sphere when
+|G|^2 <= ecut_ry (bohr^-2).
+
+Real-packed coefficient layout (one real orbital, length n_pw):
+  index 0            -> c_0 (real, the G = 0 coefficient)
+  index 1 + 2k       -> sqrt(2) Re c_{G_k}
+  index 2 + 2k       -> sqrt(2) Im c_{G_k}
+where G_k runs over the half-space Miller indices returned by
+``miller_half`` (lexicographically positive n).  With this packing the
+inner product over the full sphere of two real functions is a plain dot
+product.  An orbital on the grid is u(r_j) = sum_G c_G exp(i G.r_j), which is
+sqrt(Omega) psi(r_j) for a normalised psi.
+
+The ground state (lowest eigenpairs of -1/2 nabla^2 + V in the sphere) stands
+in for the DFT orbitals the paper takes from a plane-wave code (Sec. 4); the
+JADE rotation follows Sec. 2, Eq. (wannier) and Eq. (spread); the PDEP basis
+is synthetic (orthonormal Gaussian-weighted random G-space vectors with the
+eigenvalue law lambda_a = -0.8 / (1 + a/8)), used in the low-rank form of
+Eq. (pdep).
+"""
+from __future__ import annotations
+
+import hashlib
+import os
+from dataclasses import dataclass, field, asdict
+from typing import Optional
+
+import numpy as np
+import scipy.fft as sfft
+from scipy.sparse.linalg import LinearOperator, eigsh
+
+SQRT2 = np.sqrt(2.0)
+_WORKERS = max(1, min(16, os.cpu_count() or 1))
+
+
+# --------------------------------------------------------------------------
+# specifications
+# --------------------------------------------------------------------------
+@dataclass
+class CellSpec:
+    name: str
+    L: float                 # cubic cell edge (bohr)
+    n: int                   # grid points per axis
+    ecut_ry: float           # wavefunction cut-off (Ry): |G|^2 <= ecut_ry
+    n_occ: int               # occupied orbitals
+    n_pdep: int              # PDEP eigenpotentials
+    m: int = 1               # diamond lattice: m^3 conventional cells
+    a: float = 10.0          # conventional lattice constant (bohr)
+    amp: float = 2.0         # well depth A (Ha)
+    sigma: float = 0.8       # well width (bohr)
+    jitter: float = 0.0      # Gaussian jitter of the well positions (bohr)
+    n_sites: Optional[int] = None   # subset of lattice sites (None = all)
+    seed: int = 0            # seed of jitter / site subset / PDEP
+    localize: bool = True    # JADE-localise the occupied orbitals
+
+    def key(self) -> str:
+        s = repr(sorted(asdict(self).items())).encode()
+        return hashlib.sha1(s).hexdigest()[:12]
+
+
+def _spec_table():
+    t = {}
+    # Brute-force cell: 16^3 grid, 4.8 Ry keeps products alias-free.
+    t["tiny"] = CellSpec("tiny", 10.0, 16, 4.8, n_occ=8, n_pdep=32, m=1)
+    t["tiny_lit"] = CellSpec("tiny_lit", 10.0, 16, 4.8, n_occ=4, n_pdep=32, m=1)
+    # Tiny plain-FP64 cell, 8 wells, 24^3, 10 Ry.
+    t["c1"] = CellSpec("c1", 10.0, 24, 10.0, n_occ=8, n_pdep=32, m=1)
+    t["c1_lit"] = CellSpec("c1_lit", 10.0, 24, 10.0, n_occ=16, n_pdep=32, m=1)
+    # 64-site cell, 72^3, 25 Ry.
+    t["c2"] = CellSpec("c2", 20.0, 72, 25.0, n_occ=64, n_pdep=256, m=2)
+    t["c2_lit"] = CellSpec("c2_lit", 20.0, 72, 25.0, n_occ=128, n_pdep=256, m=2,
+                           localize=True)
+    # 216-site cell, 96^3, 25 Ry.
+    t["c3"] = CellSpec("c3", 30.0, 96, 25.0, n_occ=216, n_pdep=512, m=3)
+    t["c3_lit"] = CellSpec("c3_lit", 30.0, 96, 25.0, n_occ=432, n_pdep=512, m=3)
+    # Jittered 64-site snapshots (20 seeds).
+    for s in range(20):
+        t[f"c5_{s:02d}"] = CellSpec(f"c5_{s:02d}", 20.0, 72, 25.0, n_occ=64,
+                                    n_pdep=256, m=2, jitter=0.2, seed=100 + s)
+    # Jittered 8-site snapshots: small stand-ins for quick learning tests.
+    for s in range(20):
+        t[f"c1j_{s:02d}"] = CellSpec(f"c1j_{s:02d}", 10.0, 24, 10.0, n_occ=8,
+                                     n_pdep=32, m=1, jitter=0.2, seed=200 + s)
+    return t
+
+
+SPECS = _spec_table()
+
+
+def spec_by_name(name: str) -> CellSpec:
+    return SPECS[name]
+
+
+def uneven_batch_specs(n_cells: int = 12, seed: int = 7):
+    """Seeded cells of uneven size: grids 48/60/72, L = g*20/72, 25 Ry."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_cells):
+        g = int(rng.choice([48, 60, 72]))
+        L = g * 20.0 / 72.0
+        m_max = max(1, int(np.floor(L / 5.0)))
+        hi = min(160, 8 * m_max ** 3)
+        n_occ = int(rng.integers(32, hi + 1)) if hi > 32 else hi
+        m = 1
+        while 8 * m ** 3 < n_occ:
+            m += 1
+        n_pdep = int(rng.integers(64, 257))
+        out.append(CellSpec(f"c4_{i:02d}", L, g, 25.0, n_occ=n_occ, n_pdep=n_pdep,
+                            m=m, a=L / m, jitter=0.2, n_sites=n_occ,
+                            seed=1000 + i))
+    return out
+
+
+# --------------------------------------------------------------------------
+# geometry and basis
+# --------------------------------------------------------------------------
+_DIAMOND_FRAC = np.array([
+    [0.0, 0.0, 0.0], [0.0, 0.5, 0.5], [0.5, 0.0, 0.5], [0.5, 0.5, 0.0],
+    [0.25, 0.25, 0.25], [0.25, 0.75, 0.75], [0.75, 0.25, 0.75], [0.75, 0.75, 0.25],
+])
+
+
+def diamond_sites(m: int, a: float) -> np.ndarray:
+    """Well centres of m^3 conventional diamond cells of edge a (bohr)."""
+    cells = np.array([[i, j, k] for i in range(m) for j in range(m) for k in range(m)],
+                     dtype=np.float64)
+    pts = (cells[:, None, :] + _DIAMOND_FRAC[None, :, :]).reshape(-1, 3) * a
+    return pts
+
+
+def miller_half(L: float, ecut_ry: float) -> np.ndarray:
+    """Half-space Miller indices n (int32, shape [n_half, 3]) with
+    |2 pi n / L|^2 <= ecut_ry, sorted lexicographically; G = 0 excluded."""
+    b = 2.0 * np.pi / L
+    nmax = int(np.floor(np.sqrt(ecut_ry) / b)) + 1
+    r = np.arange(-nmax, nmax + 1)
+    n = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(-1, 3)
+    g2 = (b * b) * (n * n).sum(1)
+    n = n[g2 <= ecut_ry * (1 + 1e-12)]
+    pos = (n[:, 0] > 0) | ((n[:, 0] == 0) & (n[:, 1] > 0)) | \
+          ((n[:, 0] == 0) & (n[:, 1] == 0) & (n[:, 2] > 0))
+    n = n[pos]
+    order = np.lexsort((n[:, 2], n[:, 1], n[:, 0]))
+    return np.ascontiguousarray(n[order].astype(np.int32))
+
+
+def packed_g2(L: float, miller: np.ndarray) -> np.ndarray:
+    """|G|^2 per packed real degree of freedom (length 1 + 2 n_half)."""
+    b = 2.0 * np.pi / L
+    g2h = (b * b) * (miller.astype(np.float64) ** 2).sum(1)
+    out = np.empty(1 + 2 * len(miller))
+    out[0] = 0.0
+    out[1::2] = g2h
+    out[2::2] = g2h
+    return out
+
+
+def potential_grid(L: float, n: int, sites: np.ndarray, amp: float, sigma: float) -> np.ndarray:
+    """V(r_j) = -amp sum_sites sum_{T in {-1,0,1}^3} exp(-|r_j - R - L T|^2 / (2 sigma^2)),
+    r_j = L j / n.  The Gaussian and the image sum both factor per axis."""
+    x = L * np.arange(n) / n
+    V = np.zeros((n, n, n))
+    shifts = np.array([-L, 0.0, L])
+    for R in sites:
+        f = []
+        for ax in range(3):
+            d = x[:, None] - R[ax] - shifts[None, :]
+            f.append(np.exp(-(d * d) / (2.0 * sigma * sigma)).sum(1))
+        V -= amp * f[0][:, None, None] * f[1][None, :, None] * f[2][None, None, :]
+    return V
+
+
+# --------------------------------------------------------------------------
+# packed <-> grid maps used by the ground-state solver (input preparation)
+# --------------------------------------------------------------------------
+class _RealBasis:
+    def __init__(self, L, n, miller):
+        self.L, self.n, self.miller = L, n, miller
+        self.nr = n ** 3
+        m = miller
+        self.nh = len(m)
+        self.npw = 1 + 2 * self.nh
+        pz = m[:, 2] > 0
+        nz = m[:, 2] < 0
+        zz = m[:, 2] == 0
+        self.i_pz = np.nonzero(pz)[0]
+        self.i_nz = np.nonzero(nz)[0]
+        self.i_zz = np.nonzero(zz)[0]
+        mm = m % n
+        mn = (-m) % n
+        self.pos_pz = (mm[pz, 0], mm[pz, 1], m[pz, 2])
+        self.pos_nz = (mn[nz, 0], mn[nz, 1], -m[nz, 2])
+        self.pos_zz = (mm[zz, 0], mm[zz, 1], np.zeros(zz.sum(), dtype=int))
+        self.pos_zzm = (mn[zz, 0], mn[zz, 1], np.zeros(zz.sum(), dtype=int))
+        self.g2 = packed_g2(L, miller)
+
+    def to_grid(self, p):
+        """p [..., npw] -> u(r) [..., n, n, n] with u = sum_G c_G e^{iG.r}."""
+        lead = p.shape[:-1]
+        c = (p[..., 1::2] + 1j * p[..., 2::2]) / SQRT2
+        arr = np.zeros(lead + (self.n, self.n, self.n // 2 + 1), dtype=np.complex128)
+        arr[(...,) + self.pos_pz] = c[..., self.i_pz]
+        arr[(...,) + self.pos_nz] = np.conj(c[..., self.i_nz])
+        arr[(...,) + self.pos_zz] = c[..., self.i_zz]
+        arr[(...,) + self.pos_zzm] = np.conj(c[..., self.i_zz])
+        arr[..., 0, 0, 0] = p[..., 0]
+        axes = (-3, -2, -1)
+        return sfft.irfftn(arr, s=(self.n,) * 3, axes=axes, workers=_WORKERS) * self.nr
+
+    def to_packed(self, f):
+        """real f(r) [..., n, n, n] -> packed coefficients of its projection on the sphere."""
+        axes = (-3, -2, -1)
+        F = sfft.rfftn(f, axes=axes, workers=_WORKERS) / self.nr
+        lead = f.shape[:-3]
+        c = np.empty(lead + (self.nh,), dtype=np.complex128)
+        c[..., self.i_pz] = F[(...,) + self.pos_pz]
+        c[..., self.i_nz] = np.conj(F[(...,) + self.pos_nz])
+        c[..., self.i_zz] = F[(...,) + self.pos_zz]
+        out = np.empty(lead + (self.npw,))
+        out[..., 0] = F[..., 0, 0, 0].real
+        out[..., 1::2] = SQRT2 * c.real
+        out[..., 2::2] = SQRT2 * c.imag
+        return out
+
+    def ham(self, p, V):
+        return 0.5 * self.g2 * p + self.to_packed(V * self.to_grid(p))
+
+
+def _ground_state(basis: _RealBasis, V: np.ndarray, k: int, seed: int):
+    npw = basis.npw
+    if npw <= 3200:
+        H = np.empty((npw, npw))
+        step = max(1, int(2e8 // (basis.nr * 16)))
+        for i in range(0, npw, step):
+            j = min(npw, i + step)
+            E = np.zeros((j - i, npw))
+            E[np.arange(j - i), np.arange(i, j)] = 1.0
+            H[i:j] = basis.ham(E, V)
+        H = 0.5 * (H + H.T)
+        w, X = np.linalg.eigh(H)
+        return w[:k], np.ascontiguousarray(X[:, :k].T)
+    rng = np.random.default_rng(seed + 12345)
+    v0 = rng.standard_normal(npw)
+    op = LinearOperator((npw, npw), matvec=lambda x: basis.ham(x, V), dtype=np.float64)
+    w, X = eigsh(op, k=k, which="SA", v0=v0, tol=1e-12, ncv=min(npw, max(2 * k + 1, k + 64)))
+    o = np.argsort(w)
+    return w[o], np.ascontiguousarray(X[:, o].T)
+
+
+# --------------------------------------------------------------------------
+# JADE localisation (input preparation, Sec. 2 Eq. (wannier), Eq. (spread))
+# --------------------------------------------------------------------------
+def jade(A: np.ndarray, tol: float = 1e-7, max_sweeps: int = 60):
+    """Joint approximate diagonalisation of the real symmetric matrices A[n].
+
+    Returns (Q, history) with Q orthogonal such that Q^T A[n] Q are as
+    diagonal as the Jacobi sweeps reach; history holds the off-diagonal sum
+    sum_n sum_{v != w} (Q^T A[n] Q)_{vw}^2 after the start and each sweep.
+    Start: eigenvectors of A[0].  Pair rotation angle: the principal
+    eigenvector of G = sum_n h_n h_n^T, h_n = (A_pp - A_qq, 2 A_pq), gives
+    (cos 2t, sin 2t) (Cardoso & Souloumiac).
+    """
+    A = np.array(A, dtype=np.float64, copy=True)
+    nm, N, _ = A.shape
+    _, Q = np.linalg.eigh(A[0])
+    A = np.einsum("ip,nij,jq->npq", Q, A, Q)
+
+    def offsum(A):
+        d = np.einsum("nii->ni", A)
+        return float((A * A).sum() - (d * d).sum())
+
+    hist = [offsum(A)]
+    for _ in range(max_sweeps):
+        smax = 0.0
+        for p in range(N - 1):
+            for q in range(p + 1, N):
+                h0 = A[:, p, p] - A[:, q, q]
+                h1 = 2.0 * A[:, p, q]
+                g00 = h0 @ h0
+                g11 = h1 @ h1
+                g01 = h0 @ h1
+                t = 0.25 * np.arctan2(2.0 * g01, g00 - g11)
+                c, s = np.cos(t), np.sin(t)
+                if abs(s) < tol:
+                    continue
+                smax = max(smax, abs(s))
+                ap = A[:, :, p].copy()
+                aq = A[:, :, q]
+                A[:, :, p] = c * ap + s * aq
+                A[:, :, q] = -s * ap + c * aq
+                ap = A[:, p, :].copy()
+                aq = A[:, q, :]
+                A[:, p, :] = c * ap + s * aq
+                A[:, q, :] = -s * ap + c * aq
+                qp = Q[:, p].copy()
+                Q[:, p] = c * qp + s * Q[:, q]
+                Q[:, q] = -s * qp + c * Q[:, q]
+        hist.append(offsum(A))
+        if smax < tol:
+            break
+    return Q, hist
+
+
+def spread_matrices(u: np.ndarray, L: float, n: int) -> np.ndarray:
+    """A^(n)_{vw} = <psi_v | M^(n) | psi_w> for M = cos/sin(2 pi x_i / L),
+    with u = sqrt(Omega) psi on the grid, [N_occ, n, n, n]."""
+    x = 2.0 * np.pi * np.arange(n) / n
+    N = u.shape[0]
+    uf = u.reshape(N, -1)
+    out = np.empty((6, N, N))
+    k = 0
+    for ax in range(3):
+        for fn in (np.cos, np.sin):
+            m1 = fn(x)
+            shp = [1, 1, 1]
+            shp[ax] = n
+            M = np.broadcast_to(m1.reshape(shp), (n, n, n)).reshape(-1)
+            out[k] = (uf * M) @ uf.T / uf.shape[1]
+            k += 1
+    return out
+
+
+# --------------------------------------------------------------------------
+# the cell
+# --------------------------------------------------------------------------
+@dataclass
+class Cell:
+    spec: CellSpec
+    L: float
+    n: int
+    omega: float
+    miller: np.ndarray          # [n_half, 3] int32
+    g2: np.ndarray              # [n_pw] |G|^2 per packed dof
+    V: np.ndarray               # [n, n, n] float64 (x, y, z; z fastest)
+    sites: np.ndarray
+    eps: np.ndarray             # [n_occ] canonical energies
+    eps_next: float             # lowest empty eigenvalue
+    psi_canon: np.ndarray       # [n_occ, n_pw] canonical orbitals
+    U: np.ndarray               # [n_occ, n_occ] rotation, psi = U psi_canon
+    psi: np.ndarray             # [n_occ, n_pw] localised orbitals
+    eps_mat: np.ndarray         # [n_occ, n_occ] U diag(eps) U^T
+    phi: np.ndarray             # [n_pdep, n_pw - 1] PDEP basis, packed, G != 0
+    lam: np.ndarray             # [n_pdep]
+    jade_history: list = field(default_factory=list)
+
+    @property
+    def npw(self):
+        return self.g2.shape[0]
+
+    @property
+    def n_occ(self):
+        return self.psi.shape[0]
+
+    @property
+    def n_pdep(self):
+        return self.phi.shape[0]
+
+    @property
+    def gap(self):
+        return float(self.eps_next - self.eps[-1])
+
+    @property
+    def nr(self):
+        return self.n ** 3
+
+    def psi_grid(self, localized: bool = True) -> np.ndarray:
+        b = _RealBasis(self.L, self.n, self.miller)
+        return b.to_grid(self.psi if localized else self.psi_canon)
+
+
+def _cache_dir():
+    d = os.environ.get("BSE_CELL_CACHE",
+                       os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                                    "build", "cells"))
+    os.makedirs(d, exist_ok=True)
+    return d
+
+
+_FIELDS = ("miller", "g2", "V", "sites", "eps", "psi_canon", "U", "psi", "eps_mat",
+           "phi", "lam")
+
+
+def make_cell(spec: CellSpec | str, cache: bool = True) -> Cell:
+    if isinstance(spec, str):
+        spec = spec_by_name(spec)
+    path = os.path.join(_cache_dir(), f"{spec.name}_{spec.key()}.npz")
+    if cache and os.path.exists(path):
+        z = np.load(path, allow_pickle=False)
+        kw = {f: z[f] for f in _FIELDS}
+        return Cell(spec=spec, L=spec.L, n=spec.n, omega=spec.L ** 3,
+                    eps_next=float(z["eps_next"]), jade_history=list(z["jade_history"]), **kw)
+    cell = _build_cell(spec)
+    if cache:
+        tmp = path + ".tmp.npz"
+        np.savez(tmp, eps_next=cell.eps_next, jade_history=np.array(cell.jade_history),
+                 **{f: getattr(cell, f) for f in _FIELDS})
+        os.replace(tmp, path)
+    return cell
+
+
+def _build_cell(spec: CellSpec) -> Cell:
+    rng = np.random.default_rng(spec.seed)
+    sites = diamond_sites(spec.m, spec.a)
+    if spec.n_sites is not None and spec.n_sites < len(sites):
+        sel = np.sort(rng.choice(len(sites), size=spec.n_sites, replace=False))
+        sites = sites[sel]
+    if spec.jitter > 0:
+        sites = sites + rng.normal(0.0, spec.jitter, size=sites.shape)
+    L, n = spec.L, spec.n
+    miller = miller_half(L, spec.ecut_ry)
+    assert 2 * np.abs(miller).max() < n // 2, "grid too coarse for orbital products"
+    basis = _RealBasis(L, n, miller)
+    V = potential_grid(L, n, sites, spec.amp, spec.sigma)
+    k = spec.n_occ + 1
+    w, X = _ground_state(basis, V, k + 7, spec.seed)
+    eps = w[:spec.n_occ].copy()
+    psi_c = X[:spec.n_occ].copy()
+    # deterministic sign: largest-|.| packed coefficient positive
+    sgn = np.sign(psi_c[np.arange(len(psi_c)), np.abs(psi_c).argmax(1)])
+    psi_c *= sgn[:, None]
+    eps_next = float(w[spec.n_occ])
+    hist = []
+    if spec.localize and spec.n_occ > 1:
+        u = basis.to_grid(psi_c)
+        A = spread_matrices(u, L, n)
+        Q, hist = jade(A, max_sweeps=60 if spec.n_occ <= 256 else 30)
+        U = np.ascontiguousarray(Q.T)
+        psi = U @ psi_c
+        s2 = np.sign(psi[np.arange(len(psi)), np.abs(psi).argmax(1)])
+        U *= s2[:, None]
+        psi = U @ psi_c
+    else:
+        U = np.eye(spec.n_occ)
+        psi = psi_c.copy()
+    eps_mat = (U * eps[None, :]) @ U.T
+    eps_mat = 0.5 * (eps_mat + eps_mat.T)
+    # synthetic PDEP basis on the sphere without G = 0
+    g2 = basis.g2
+    wgt = np.exp(-0.5 * g2[1:])
+    Z = rng.standard_normal((basis.npw - 1, spec.n_pdep)) * wgt[:, None]
+    Qp, R = np.linalg.qr(Z)
+    Qp *= np.sign(np.diag(R))[None, :]
+    phi = np.ascontiguousarray(Qp.T)
+    lam = -0.8 / (1.0 + np.arange(spec.n_pdep) / 8.0)
+    return Cell(spec=spec, L=L, n=n, omega=L ** 3, miller=miller, g2=g2, V=V, sites=sites,
+                eps=eps, eps_next=eps_next, psi_canon=psi_c, U=U, psi=psi, eps_mat=eps_mat,
+                phi=phi, lam=lam, jade_history=hist)
+
+
+# --------------------------------------------------------------------------
+# seeded random blocks (the random numbers the method draws are inputs)
+# --------------------------------------------------------------------------
+def trial_block(cell: Cell, n_vec: int, seed: int = 1234) -> np.ndarray:
+    """z ~ N(0,1) / (1 + |G|^2/2) per packed dof, shape [n_vec, n_occ, n_pw]."""
+    rng = np.random.default_rng(seed)
+    z = rng.standard_normal((n_vec, cell.n_occ, cell.npw))
+    return z / (1.0 + 0.5 * cell.g2)[None, None, :]
+
+
+def random_block(shape, seed: int) -> np.ndarray:
+    """Plain N(0,1) block of the given shape."""
+    return np.random.default_rng(seed).standard_normal(shape)
