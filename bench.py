@@ -1,0 +1,258 @@
+"""Benchmark: Liouville applies/sec (and Davidson time to solution) on one MI355X.
+
+Default workload: the 64-well diamond cell (L = 20 bohr, 72^3 grid, 25 Ry,
+N_pw = 16879 real dofs) at its literal filling N_occ = 128, N_pdep = 256,
+about 40 % of the orbital pairs kept, a block of 16 trial vectors, FP32
+apply replayed from a hipGraph.  One step = one application of the whole
+operator (sphere->grid FFTs, K1d + V a, K1e Hartree, grid->sphere FFTs,
+eps and P_c GEMMs) to the block.  value = 16 * steps / elapsed seconds.
+
+Also reported: per-stage times of the same apply (HIP events on the
+library's stream), the roofline of the dominant kernel, the FP64 CPU oracle
+on a bounded sample of the same apply (host cores), and the Davidson time to
+the 8 lowest excitation energies of the gapped cell (N_occ = 64) in FP64,
+FP32 and BF16x3 against the stored FP64 oracle result.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--precision fp32]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Liouville applies/sec and time to 8 lowest VEEs at 1 meV vs FP64 oracle"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+MEV = 3.674932e-5
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def sphere_shape(miller, n):
+    full = np.concatenate([miller, -miller, np.zeros((1, 3), dtype=miller.dtype)])
+    cols = {(int(x) % n, int(y) % n) for x, y, _ in full}
+    ncol = len(cols) + 1                      # + the empty column that pads pairs
+    nxp = 2 * int(np.abs(miller[:, 0]).max()) + 1
+    return ncol, nxp
+
+
+def stage_bytes(cell, B, n_pairs, ncol, nxp, esz):
+    """Algorithmic HBM bytes of each apply stage: every operand read once and
+    every result written once (the unit of each figure is one block apply)."""
+    n, nr, no, npw = cell.n, cell.nr, cell.n_occ, cell.npw
+    norb = B * no
+    nq = (norb + 1) // 2
+    c = 2 * esz
+    t1 = nq * ncol * n * c
+    t2 = nq * nxp * n * n * c
+    grid = norb * nr * esz
+    nbh = (B + 1) // 2
+    return {
+        "inv_z": norb * npw * esz + t1,
+        "inv_y": t1 + t2,
+        "inv_x": t2 + grid,
+        "k1d": n_pairs * nr * esz + grid + no * nr * esz + nr * esz + grid + nbh * nr * c,
+        "hartree": 2 * 3 * 2 * nbh * nr * c + 2 * nbh * nr * c,
+        "fwd_x": grid + no * nr * esz + nbh * nr * c + t2,
+        "fwd_y": t2 + t1,
+        "fwd_z": t1 + 2 * norb * npw * esz,
+        "eps_gemm": 2 * norb * npw * esz + no * no * esz,
+        "pc_gemm": 3 * norb * npw * esz + 2 * no * npw * esz,
+    }
+
+
+def cpu_baseline(cell, X, threshold):
+    """FP64 oracle on a bounded sample of one block apply: every stage of one
+    trial vector, with the K1d products of a sample of output orbitals
+    scaled to all orbitals by their pair count."""
+    from oracle.liouville import Basis, LiouvilleOracle
+    from oracle.pairs import MEASURE_ABS_L1, build_pairs, pair_measure
+    from oracle.screening import screened_integrals
+    b = Basis(cell.L, cell.n, cell.miller)
+    u = b.to_grid(cell.psi)
+    pairs = build_pairs(pair_measure(u, MEASURE_ABS_L1), threshold)
+    rows = [0, cell.n_occ // 2]
+    sub = [p for p in pairs if p[0] in rows or p[1] in rows]
+    tau = screened_integrals(b, u, sub, cell.phi, cell.lam)
+    x = X[:1]
+    op0 = LiouvilleOracle(b, cell.psi, cell.eps_mat, cell.V, [], None, k1d=0.0)
+    op1 = LiouvilleOracle(b, cell.psi, cell.eps_mat, cell.V, sub, tau)
+    t = time.time()
+    op0.apply(x)
+    t0 = time.time() - t
+    t = time.time()
+    op1.apply(x, rows=rows)
+    t1 = time.time() - t
+    # K1d work per pair: both directions for v != w
+    inc_all = sum(1 if v == w else 2 for v, w in pairs)
+    inc_sub = sum(1 if v == w else 2 for v, w in sub)
+    k1d_scaled = max(0.0, t1 - t0) * inc_all / max(1, inc_sub)
+    t_vec = t0 + k1d_scaled
+    try:
+        import threadpoolctl
+        threads = max(i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()) \
+            if threadpoolctl.threadpool_info() else 1
+    except Exception:
+        threads = os.cpu_count() or 1
+    return {"value": 1.0 / t_vec, "unit": "applies/s", "cores": int(threads), "kind": "oracle",
+            "sample": (f"one trial vector of the same cell; all stages timed except K1d, which "
+                       f"is timed on output orbitals {rows} ({inc_sub} of {inc_all} pair "
+                       f"products) and scaled by pair count; {t_vec:.1f} s per vector")}
+
+
+def time_to_solution(args, torch, pkg):
+    """Davidson to the 8 lowest VEEs of the gapped 64-well cell, B = 16."""
+    from synth import make_cell, trial_block
+    gpath = os.path.join(ROOT, "tests", "golden", "c2_oracle.json")
+    gold = json.load(open(gpath)) if os.path.exists(gpath) else None
+    cell = make_cell("c2")
+    st = torch.cuda.Stream()
+    out = {"cell": "64-well diamond cell, N_occ = 64 (gapped), 72^3, 25 Ry, N_pdep = 256, "
+                   "~44% pairs, 8 lowest, block 16, tol 1e-5 Ha"}
+    with torch.cuda.stream(st):
+        ctx = pkg.context_for(cell, stream=st)
+        thr = pkg.setup_pairs_and_screen(ctx, cell, fraction=0.4, precision=pkg.FP64)
+        X0 = torch.from_numpy(trial_block(cell, 16, seed=4321)).to("cuda")
+        ctx.set_graph(True)
+        for name, prec in (("fp64", pkg.FP64), ("fp32", pkg.FP32), ("bf16x3", pkg.BF16X3)):
+            torch.cuda.synchronize()
+            t = time.time()
+            om, X, stt = ctx.davidson(X0, 8, block=16, precision=prec, tol=1e-5, max_iter=300)
+            torch.cuda.synchronize()
+            dt = time.time() - t
+            r = {"seconds": dt, "iterations": stt["iterations"], "n_apply": stt["n_apply"],
+                 "omega_ha": [float(x) for x in om]}
+            if gold:
+                err = np.abs(om - np.array(gold["omega_ha"][:8])).max()
+                r["max_err_vs_oracle_ha"] = float(err)
+                r["within_1mev"] = bool(err <= MEV)
+            out[name] = r
+            log("tts", name, r)
+        ctx.close()
+    if gold:
+        out["oracle_cpu_seconds"] = gold.get("seconds_davidson")
+        out["oracle_iterations"] = gold.get("iterations")
+    out["threshold"] = thr
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cell", default="c2_lit")
+    ap.add_argument("--block", type=int, default=16)
+    ap.add_argument("--fraction", type=float, default=0.4)
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tts", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU layout is a design, not a measured path.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2409_15116_amd as pkg
+    from synth import make_cell, trial_block
+    pkg.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    prec = {"fp64": pkg.FP64, "fp32": pkg.FP32, "bf16x3": pkg.BF16X3}[args.precision]
+    dt = torch.float64 if prec == pkg.FP64 else torch.float32
+    esz = 8 if prec == pkg.FP64 else 4
+    B = args.block
+
+    log("generating cell", args.cell)
+    t = time.time()
+    cell = make_cell(args.cell)
+    log(f"cell ready in {time.time() - t:.1f} s: n_occ={cell.n_occ} npw={cell.npw} n={cell.n}")
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        ctx = pkg.context_for(cell, stream=st)
+        t = time.time()
+        thr = pkg.setup_pairs_and_screen(ctx, cell, fraction=args.fraction, precision=prec)
+        torch.cuda.synchronize()
+        t_setup = time.time() - t
+        P = ctx.n_pairs
+        log(f"pairs {P} (threshold {thr:.4g}), setup {t_setup:.2f} s")
+        Xh = trial_block(cell, B, seed=1234)
+        X = torch.from_numpy(Xh).to("cuda", dtype=dt)
+        Y = torch.empty_like(X)
+        stages = ctx.profile_apply(X, Y, prec, n_rep=3)
+        log("stages (ms):", {k: round(v, 3) for k, v in stages.items()})
+        ctx.set_graph(not args.no_graph)
+        for _ in range(args.warmup):
+            ctx.apply(X, Y, prec)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.time()
+        e0.record(st)
+        for _ in range(args.steps):
+            ctx.apply(X, Y, prec)
+        e1.record(st)
+        torch.cuda.synchronize()
+        wall = time.time() - t0
+        ms_gpu = e0.elapsed_time(e1)
+    elapsed = max(wall, ms_gpu / 1e3)
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = B * args.steps / elapsed
+
+    ncol, nxp = sphere_shape(cell.miller, cell.n)
+    nbytes = stage_bytes(cell, B, P, ncol, nxp, esz)
+    dom = max(stages, key=stages.get)
+    if dom in ("eps_gemm", "pc_gemm"):
+        no, npw = cell.n_occ, cell.npw
+        fl = 2 * B * no * no * npw * (1 if dom == "eps_gemm" else 2)
+        ach = fl / (stages[dom] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": ach, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / FP32_PEAK_TFLOPS, "traffic": None, "kernel": dom}
+    else:
+        ach = nbytes[dom] / (stages[dom] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": dom}
+    roof["stage_ms"] = {k: round(v, 4) for k, v in stages.items()}
+    roof["stage_gbs"] = {k: round(nbytes[k] / (stages[k] * 1e-3) / 1e9, 1) for k in stages}
+    whole_bytes = sum(nbytes[k] for k in nbytes)
+    res = {
+        "metric": METRIC, "value": value, "unit": "applies/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "f32+bf16x3"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": (f"{args.cell}: {len(cell.sites)}-well diamond cell, L={cell.L} "
+                                f"bohr, {cell.n}^3 grid, {cell.spec.ecut_ry} Ry, N_pw={cell.npw}, "
+                                f"N_occ={cell.n_occ}, N_pdep={cell.n_pdep}, {P} pairs "
+                                f"(fraction {args.fraction}), block {B}, "
+                                f"{'hipGraph replay' if not args.no_graph else 'eager'}"),
+                   "block": B, "n_occ": cell.n_occ, "grid": cell.n, "n_pairs": P,
+                   "precision": args.precision},
+        "roofline": roof,
+        "whole_apply_gbs": whole_bytes / (ms_per_step * 1e-3) / 1e9,
+        "setup_seconds": t_setup,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample)")
+        res["cpu_baseline"] = cpu_baseline(cell, Xh, thr)
+    if not args.no_tts:
+        log("time to solution")
+        res["time_to_solution"] = time_to_solution(args, torch, pkg)
+    ctx.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

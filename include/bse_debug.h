@@ -1,0 +1,34 @@
+/*
+ * bse_debug.h -- test hooks of libbse.so that expose single stages of the
+ * Liouville apply, so that a parity test can localise a mismatch.  Same
+ * conventions as bse.h; not needed by applications.
+ */
+#ifndef BSE_DEBUG_H
+#define BSE_DEBUG_H
+
+#include <stdint.h>
+
+#include "bse.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Sphere -> grid transform of n_orb real-packed orbitals (step a1 of the
+ * apply): out[o](r_j) = sum_G c_G exp(i G.r_j).
+ *   X    dev [n_orb][n_pw]  double (BSE_FP64) or float (BSE_FP32)
+ *   out  dev [n_orb][n^3]   same type
+ * Synchronises the stream. */
+bse_status bse_debug_to_grid(bse_ctx *ctx, int n_orb, const void *X, void *out, int precision);
+
+/* C[M][N] = alpha * A[M][K] * op(B) + beta * C with op(B) = B^T (B is
+ * [N][K], nt = 1) or B (B is [K][N], nt = 0), row-major, one batch.
+ *   precision BSE_FP64 (double), BSE_FP32 (float, vector FMA),
+ *             BSE_BF16X3 (float, split-BF16x3 MFMA).  Synchronises. */
+bse_status bse_debug_gemm(bse_ctx *ctx, int nt, int M, int N, int K, double alpha, const void *A,
+                          const void *B, double beta, void *C, int precision);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BSE_DEBUG_H */

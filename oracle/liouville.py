@@ -131,8 +131,12 @@ class LiouvilleOracle:
         S = np.einsum("...vg,wg->...vw", Y, self.psi)
         return Y - np.einsum("...vw,wg->...vg", S, self.psi)
 
-    def apply(self, X: np.ndarray) -> np.ndarray:
-        """L applied to a block X [B, N_occ, npw] (or one vector [N_occ, npw])."""
+    def apply(self, X: np.ndarray, rows=None) -> np.ndarray:
+        """L applied to a block X [B, N_occ, npw] (or one vector [N_occ, npw]).
+
+        ``rows``: compute only these orbital slots of the output (the others
+        are left as NaN).  Each slot's output needs only the pairs that touch
+        it, so an operator built with just those pairs is exact there."""
         single = X.ndim == 2
         if single:
             X = X[None]
@@ -150,9 +154,16 @@ class LiouvilleOracle:
                     f[v] -= self.k1d * self.tau[p] * a[w]
                     if w != v:
                         f[w] -= self.k1d * self.tau[p] * a[v]
-            Y = b.to_sphere(f) + 0.5 * b.g2_packed[None] * X[s]      # H a_v
-            Y = Y - self.eps @ X[s] + self.scissor * X[s]             # - eps a (Eq. d)
-            out[s] = self.project_c(Y)
+            if rows is None:
+                Y = b.to_sphere(f) + 0.5 * b.g2_packed[None] * X[s]      # H a_v
+                Y = Y - self.eps @ X[s] + self.scissor * X[s]             # - eps a (Eq. d)
+                out[s] = self.project_c(Y)
+            else:
+                r = np.asarray(rows)
+                Y = b.to_sphere(f[r]) + 0.5 * b.g2_packed[None] * X[s, r]
+                Y = Y - self.eps[r] @ X[s] + self.scissor * X[s, r]
+                out[s] = np.nan
+                out[s, r] = self.project_c(Y)
         return out[0] if single else out
 
     def diag_estimate(self) -> np.ndarray:

@@ -44,15 +44,36 @@ def build_pairs(m: np.ndarray, threshold: float):
     return out
 
 
-def threshold_for_fraction(m: np.ndarray, fraction: float) -> float:
-    """Threshold that keeps about ``fraction`` of the unordered pairs v < w."""
+def threshold_for_fraction(m: np.ndarray, fraction: float, rel_gap: float = 1e-6) -> float:
+    """Threshold that keeps about ``fraction`` of the unordered pairs v < w.
+
+    Symmetry-equivalent pairs have equal measures; a cut through such a group
+    would keep an arbitrary, rounding-dependent subset.  The cut is therefore
+    moved to the nearest place in the descending list of measures where two
+    neighbours differ by more than ``rel_gap`` (relative), the nearer one
+    below the target on a tie, and set half-way across that gap."""
     iu = np.triu_indices(m.shape[0], 1)
     vals = np.sort(m[iu])[::-1]
-    if len(vals) == 0:
+    n = len(vals)
+    if n == 0:
         return 0.0
-    k = int(round(fraction * len(vals)))
-    if k <= 0:
-        return float(vals[0])
-    if k >= len(vals):
+    target = int(np.floor(fraction * n + 0.5))
+
+    def is_gap(k):      # a cut keeping the first k values is clean
+        if k <= 0 or k >= n:
+            return True
+        return vals[k - 1] - vals[k] > rel_gap * abs(vals[k - 1])
+
+    best = None
+    for d in range(n + 1):
+        for k in (target - d, target + d):
+            if 0 <= k <= n and is_gap(k):
+                best = k
+                break
+        if best is not None:
+            break
+    if best <= 0:
+        return float(vals[0]) * (1 + 1e-9) + 1e-300
+    if best >= n:
         return float(vals[-1]) * 0.5
-    return float(0.5 * (vals[k - 1] + vals[k]))
+    return float(0.5 * (vals[best - 1] + vals[best]))

@@ -1,0 +1,295 @@
+// extern "C" entry points: argument checks, exception -> status mapping.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "ctx.hpp"
+
+namespace bse {
+static thread_local char g_err[1024] = "";
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+const char *last_error() { return g_err; }
+}  // namespace bse
+
+using bse::Err;
+using bse::set_error;
+
+#define BSE_GUARD(...)                                      \
+    try {                                                   \
+        __VA_ARGS__;                                        \
+        return BSE_OK;                                      \
+    } catch (const Err &e) {                                \
+        return e.st;                                        \
+    } catch (const std::bad_alloc &) {                      \
+        set_error("host allocation failed");                \
+        return BSE_ERR_OOM;                                 \
+    } catch (...) {                                         \
+        set_error("unexpected C++ exception");              \
+        return BSE_ERR_HIP;                                 \
+    }
+
+#define CHECK_CTX(c)                                        \
+    if (!(c)) {                                             \
+        set_error("null context");                          \
+        return BSE_ERR_ARG;                                 \
+    }
+
+extern "C" {
+
+bse_status bse_create(bse_ctx **out, const bse_cell *cell, const double *psi, const double *eps,
+                      const double *V, void *stream) {
+    if (!out || !cell || !psi || !eps || !V || !cell->miller) {
+        set_error("bse_create: null argument");
+        return BSE_ERR_ARG;
+    }
+    *out = nullptr;
+    const long long npw = 1 + 2LL * cell->n_half;
+    if (!(cell->L > 0) || !std::isfinite(cell->L) || cell->n < 8 || cell->n > 256 ||
+        cell->n_half < 1 || cell->n_occ < 1 || cell->n_occ >= npw) {
+        set_error("bse_create: bad cell (L=%g n=%d n_half=%d n_occ=%d)", cell->L, cell->n,
+                  cell->n_half, cell->n_occ);
+        return BSE_ERR_ARG;
+    }
+    bse_ctx *c = nullptr;
+    try {
+        c = new bse_ctx;
+        c->stream = (hipStream_t)stream;
+        BSE_HIP(hipGetDevice(&c->device));
+        bse::ctx_setup(c, cell, psi, eps, V);
+    } catch (const Err &e) {
+        if (c) bse::ctx_free(c);
+        delete c;
+        return e.st;
+    } catch (const std::bad_alloc &) {
+        if (c) bse::ctx_free(c);
+        delete c;
+        set_error("host allocation failed");
+        return BSE_ERR_OOM;
+    }
+    *out = c;
+    return BSE_OK;
+}
+
+bse_status bse_destroy(bse_ctx *c) {
+    if (!c) return BSE_OK;
+    BSE_GUARD({
+        (void)hipStreamSynchronize(c->stream);
+        bse::ctx_free(c);
+        delete c;
+    })
+}
+
+bse_status bse_set_terms(bse_ctx *c, double k1e, double k1d, double scissor) {
+    CHECK_CTX(c);
+    if (!std::isfinite(k1e) || !std::isfinite(k1d) || !std::isfinite(scissor)) {
+        set_error("bse_set_terms: non-finite value");
+        return BSE_ERR_ARG;
+    }
+    BSE_GUARD(bse::ctx_set_terms(c, k1e, k1d, scissor))
+}
+
+bse_status bse_pair_measure(bse_ctx *c, int measure, double *m) {
+    CHECK_CTX(c);
+    if (!m) {
+        set_error("bse_pair_measure: null output");
+        return BSE_ERR_ARG;
+    }
+    BSE_GUARD(bse::ctx_measure(c, measure, m))
+}
+
+bse_status bse_build_pairs(bse_ctx *c, int measure, double threshold, int64_t *n_pairs) {
+    CHECK_CTX(c);
+    if (!std::isfinite(threshold)) {
+        set_error("bse_build_pairs: non-finite threshold");
+        return BSE_ERR_ARG;
+    }
+    BSE_GUARD({
+        bse::ctx_build_pairs(c, measure, threshold);
+        if (n_pairs) *n_pairs = c->n_pairs;
+    })
+}
+
+double bse_threshold_for_fraction(const double *m, int n_occ, double fraction) {
+    std::vector<double> v;
+    for (int i = 0; i < n_occ; ++i)
+        for (int j = i + 1; j < n_occ; ++j) v.push_back(m[(size_t)i * n_occ + j]);
+    const long long n = (long long)v.size();
+    if (n == 0) return 0.0;
+    std::sort(v.begin(), v.end(), [](double a, double b) { return a > b; });
+    // a cut must not split a group of equal (symmetry-equivalent) measures:
+    // move it to the nearest index where neighbours differ by > 1e-6 relative
+    auto clean = [&](long long k) {
+        return k <= 0 || k >= n || v[k - 1] - v[k] > 1e-6 * std::fabs(v[k - 1]);
+    };
+    const long long target = std::llround(fraction * (double)n);
+    long long best = -1;
+    for (long long d = 0; d <= n && best < 0; ++d) {
+        if (target - d >= 0 && target - d <= n && clean(target - d)) best = target - d;
+        else if (target + d >= 0 && target + d <= n && clean(target + d)) best = target + d;
+    }
+    if (best <= 0) return v[0] * (1 + 1e-9) + 1e-300;
+    if (best >= n) return 0.5 * v[n - 1];
+    return 0.5 * (v[best - 1] + v[best]);
+}
+
+bse_status bse_get_pairs(bse_ctx *c, int32_t *pairs) {
+    CHECK_CTX(c);
+    if (!pairs) {
+        set_error("bse_get_pairs: null output");
+        return BSE_ERR_ARG;
+    }
+    std::memcpy(pairs, c->pairs_h.data(), c->pairs_h.size() * sizeof(int));
+    return BSE_OK;
+}
+
+bse_status bse_screen_pairs(bse_ctx *c, const double *phi, const double *lambda, int n_pdep,
+                            int precision) {
+    CHECK_CTX(c);
+    if (!phi || !lambda) {
+        set_error("bse_screen_pairs: null argument");
+        return BSE_ERR_ARG;
+    }
+    if (precision != BSE_FP64 && precision != BSE_FP32 && precision != BSE_BF16X3) {
+        set_error("bse_screen_pairs: unknown precision %d", precision);
+        return BSE_ERR_ARG;
+    }
+    BSE_GUARD(bse::ctx_screen(c, phi, lambda, n_pdep, precision))
+}
+
+bse_status bse_copy_tau(bse_ctx *c, int64_t p0, int64_t count, double *out) {
+    CHECK_CTX(c);
+    if (!out || p0 < 0 || count < 0 || p0 + count > c->n_pairs) {
+        set_error("bse_copy_tau: bad range");
+        return BSE_ERR_ARG;
+    }
+    if (!c->have_tau64 && !c->have_tau32) {
+        set_error("bse_copy_tau: no tau");
+        return BSE_ERR_STATE;
+    }
+    BSE_GUARD({
+        const size_t len = (size_t)count * c->nr;
+        if (c->have_tau64)
+            BSE_HIP(hipMemcpyAsync(out, c->tau64.p + (size_t)p0 * c->nr, len * 8,
+                                   hipMemcpyDeviceToDevice, c->stream));
+        else
+            bse::convert<float, double>(c->tau32.p + (size_t)p0 * c->nr, out, (long long)len,
+                                        c->stream);
+        BSE_HIP(hipStreamSynchronize(c->stream));
+    })
+}
+
+bse_status bse_apply_liouville(bse_ctx *c, int n_vec, const void *A_in, void *A_out,
+                               int precision) {
+    CHECK_CTX(c);
+    BSE_GUARD(bse::ctx_apply_entry(c, n_vec, A_in, A_out, precision))
+}
+
+bse_status bse_profile_apply(bse_ctx *c, int n_vec, const void *A_in, void *A_out, int precision,
+                             int n_rep, double *ms) {
+    CHECK_CTX(c);
+    if (!ms) {
+        set_error("bse_profile_apply: null output");
+        return BSE_ERR_ARG;
+    }
+    BSE_GUARD({
+        bse::ctx_apply(c, n_vec, A_in, A_out, precision);  // argument and state checks
+        bse::ctx_profile_apply(c, n_vec, A_in, A_out, precision, n_rep, ms);
+    })
+}
+
+bse_status bse_set_graph(bse_ctx *c, int enable) {
+    CHECK_CTX(c);
+    c->use_graph = enable != 0;
+    return BSE_OK;
+}
+
+bse_status bse_davidson(bse_ctx *c, const bse_davidson_opts *opts, const double *X0,
+                        double *omega, double *X, bse_davidson_stats *stats) {
+    CHECK_CTX(c);
+    if (!opts || !X0 || !omega || !X) {
+        set_error("bse_davidson: null argument");
+        return BSE_ERR_ARG;
+    }
+    BSE_GUARD(bse::ctx_davidson(c, opts, X0, omega, X, stats))
+}
+
+const char *bse_status_str(bse_status s) {
+    switch (s) {
+        case BSE_OK: return "ok";
+        case BSE_ERR_ARG: return "invalid argument";
+        case BSE_ERR_HIP: return "HIP error";
+        case BSE_ERR_OOM: return "out of device memory";
+        case BSE_ERR_NOCONV: return "not converged";
+        case BSE_ERR_STATE: return "call out of order";
+    }
+    return "unknown status";
+}
+
+const char *bse_last_error(void) { return bse::last_error(); }
+
+}  // extern "C"
+
+// ------------------------------------------------------------- test hooks
+#include "../../include/bse_debug.h"
+
+extern "C" {
+
+bse_status bse_debug_to_grid(bse_ctx *c, int n_orb, const void *X, void *out, int precision) {
+    CHECK_CTX(c);
+    if (!X || !out || n_orb < 1) {
+        set_error("bse_debug_to_grid: bad argument");
+        return BSE_ERR_ARG;
+    }
+    BSE_GUARD({
+        const size_t nq = (size_t)(n_orb + 1) / 2;
+        if (precision == BSE_FP64) {
+            bse::Dev<double2> T1, T2;
+            T1.alloc(nq * c->maps.ncol * c->n);
+            T2.alloc(nq * c->maps.nxp * c->n * c->n);
+            bse::sph_inverse<double>(c->maps, (const double *)X, n_orb, (double *)out, T1.p, T2.p,
+                                     c->tw64.p, c->stream);
+            BSE_HIP(hipStreamSynchronize(c->stream));
+        } else {
+            bse::Dev<float2> T1, T2;
+            T1.alloc(nq * c->maps.ncol * c->n);
+            T2.alloc(nq * c->maps.nxp * c->n * c->n);
+            bse::sph_inverse<float>(c->maps, (const float *)X, n_orb, (float *)out, T1.p, T2.p,
+                                    c->tw32.p, c->stream);
+            BSE_HIP(hipStreamSynchronize(c->stream));
+        }
+    })
+}
+
+bse_status bse_debug_gemm(bse_ctx *c, int nt, int M, int N, int K, double alpha, const void *A,
+                          const void *B, double beta, void *Cm, int precision) {
+    CHECK_CTX(c);
+    if (!A || !B || !Cm || M < 1 || N < 1 || K < 1) {
+        set_error("bse_debug_gemm: bad argument");
+        return BSE_ERR_ARG;
+    }
+    BSE_GUARD({
+        const long long lda = K, ldb = nt ? K : N, ldc = N;
+        if (precision == BSE_FP64)
+            bse::gemm<double>(nt != 0, M, N, K, alpha, (const double *)A, lda, 0,
+                              (const double *)B, ldb, 0, beta, (double *)Cm, ldc, 0, 1, c->gws,
+                              c->stream);
+        else if (precision == BSE_FP32)
+            bse::gemm<float>(nt != 0, M, N, K, (float)alpha, (const float *)A, lda, 0,
+                             (const float *)B, ldb, 0, (float)beta, (float *)Cm, ldc, 0, 1, c->gws,
+                             c->stream);
+        else
+            bse::gemm_bf16x3(nt != 0, M, N, K, (float)alpha, (const float *)A, lda, 0,
+                             (const float *)B, ldb, 0, (float)beta, (float *)Cm, ldc, 0, 1, c->gws,
+                             c->stream);
+        BSE_HIP(hipStreamSynchronize(c->stream));
+    })
+}
+
+}  // extern "C"

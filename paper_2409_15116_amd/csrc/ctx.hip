@@ -1,0 +1,604 @@
+// Context set-up, pair list, screening and the Liouville apply pipeline.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <vector>
+
+#include "ctx.hpp"
+
+namespace bse {
+
+static inline int wrap(int a, int n) { return ((a % n) + n) % n; }
+
+static void drop_graph(bse_ctx *c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->g_nvec = -1;
+}
+
+// ---------------------------------------------------------------------------
+// set-up: sphere maps, twiddles, orbitals on the grid, Coulomb kernels
+// ---------------------------------------------------------------------------
+static void build_maps(bse_ctx *c) {
+    const int n = c->n, nh = c->nh;
+    struct E {
+        int x, y, z, kind, k;
+    };
+    std::vector<E> all;
+    all.reserve(2 * nh + 1);
+    all.push_back({0, 0, 0, 0, 0});
+    int nxmax = 0;
+    for (int i = 0; i < nh; ++i) {
+        const int *m = &c->miller[3 * i];
+        all.push_back({wrap(m[0], n), wrap(m[1], n), wrap(m[2], n), 1, 1 + 2 * i});
+        all.push_back({wrap(-m[0], n), wrap(-m[1], n), wrap(-m[2], n), 2, 1 + 2 * i});
+        nxmax = std::max(nxmax, std::abs(m[0]));
+    }
+    // columns: (0,0), an empty column, then each column followed by its mirror
+    std::map<std::pair<int, int>, std::vector<E>> cols;
+    for (auto &e : all) cols[{e.x, e.y}].push_back(e);
+    std::vector<std::pair<int, int>> order;
+    order.push_back({0, 0});
+    order.push_back({-1, -1});
+    std::map<std::pair<int, int>, bool> seen;
+    seen[{0, 0}] = true;
+    // representative: signed (sx, sy) lexicographically positive
+    std::vector<std::pair<int, int>> reps;
+    for (auto &kv : cols) {
+        const int x = kv.first.first, y = kv.first.second;
+        const int sx = x > n / 2 ? x - n : x, sy = y > n / 2 ? y - n : y;
+        if (sx > 0 || (sx == 0 && sy > 0)) reps.push_back({sx, sy});
+    }
+    std::sort(reps.begin(), reps.end());
+    for (auto &r : reps) {
+        const std::pair<int, int> a{wrap(r.first, n), wrap(r.second, n)};
+        const std::pair<int, int> b{wrap(-r.first, n), wrap(-r.second, n)};
+        BSE_REQUIRE(cols.count(b), BSE_ERR_ARG, "sphere is not symmetric under G -> -G");
+        order.push_back(a);
+        order.push_back(b);
+    }
+    BSE_REQUIRE(order.size() == cols.size() + 1, BSE_ERR_ARG, "sphere column bookkeeping failed");
+    const int ncol = (int)order.size();
+    std::vector<int> col_ptr(ncol + 1, 0), colmap((size_t)n * n, -1);
+    std::vector<int2> ent;
+    for (int ci = 0; ci < ncol; ++ci) {
+        col_ptr[ci] = (int)ent.size();
+        if (ci == 1) continue;
+        auto &v = cols[order[ci]];
+        std::sort(v.begin(), v.end(), [](const E &a, const E &b) { return a.z < b.z; });
+        for (auto &e : v) ent.push_back(make_int2(e.z | (e.kind << 16), e.k));
+        colmap[(size_t)order[ci].first * n + order[ci].second] = ci;
+    }
+    col_ptr[ncol] = (int)ent.size();
+    std::vector<int> xlist, xinv(n, -1);
+    for (int s = -nxmax; s <= nxmax; ++s) xlist.push_back(wrap(s, n));
+    std::sort(xlist.begin(), xlist.end());
+    for (size_t i = 0; i < xlist.size(); ++i) xinv[xlist[i]] = (int)i;
+    std::vector<double> kin(c->npw, 0.0);
+    const double b = 2.0 * M_PI / c->L;
+    for (int i = 0; i < nh; ++i) {
+        const int *m = &c->miller[3 * i];
+        const double g2 = b * b * ((double)m[0] * m[0] + (double)m[1] * m[1] + (double)m[2] * m[2]);
+        kin[1 + 2 * i] = kin[2 + 2 * i] = 0.5 * g2;
+    }
+    auto up = [&](auto &dev, const auto &host) {
+        dev.alloc(host.size());
+        BSE_HIP(hipMemcpy(dev.p, host.data(), host.size() * sizeof(host[0]), hipMemcpyHostToDevice));
+    };
+    up(c->ent, ent);
+    up(c->col_ptr, col_ptr);
+    up(c->colmap, colmap);
+    up(c->xlist, xlist);
+    up(c->xinv, xinv);
+    up(c->kin, kin);
+    SphereMaps &M = c->maps;
+    M.n = n;
+    M.npw = c->npw;
+    M.ncol = ncol;
+    M.nxp = (int)xlist.size();
+    M.plan = c->plan;
+    M.ent = c->ent.p;
+    M.col_ptr = c->col_ptr.p;
+    M.colmap = c->colmap.p;
+    M.xlist = c->xlist.p;
+    M.xinv = c->xinv.p;
+    M.kin = c->kin.p;
+
+    // twiddles exp(-2 pi i k / n)
+    std::vector<double2> tw(n);
+    std::vector<float2> tw32(n);
+    for (int k = 0; k < n; ++k) {
+        const double a = 2.0 * M_PI * (double)k / (double)n;
+        tw[k] = make_double2(std::cos(a), -std::sin(a));
+        tw32[k] = make_float2((float)tw[k].x, (float)tw[k].y);
+    }
+    up(c->tw64, tw);
+    up(c->tw32, tw32);
+
+    // Coulomb kernel on the whole grid (FFT order), divided by N_r; and the
+    // flat grid indices and sqrt(v) of the half sphere (PDEP gather/scatter)
+    const size_t nr = (size_t)c->nr;
+    std::vector<double> vc(nr);
+    auto freq = [n](int i) { return i < (n + 1) / 2 ? i : i - n; };
+    for (int x = 0; x < n; ++x)
+        for (int y = 0; y < n; ++y)
+            for (int z = 0; z < n; ++z) {
+                const double fx = freq(x), fy = freq(y), fz = freq(z);
+                const double g2 = b * b * (fx * fx + fy * fy + fz * fz);
+                vc[((size_t)x * n + y) * n + z] = g2 > 0 ? 4.0 * M_PI / g2 / (double)nr : 0.0;
+            }
+    std::vector<float> vc32(vc.begin(), vc.end());
+    up(c->vc64, vc);
+    up(c->vc32, vc32);
+    std::vector<int> ip(nh), im(nh);
+    std::vector<double> sqv(nh);
+    for (int i = 0; i < nh; ++i) {
+        const int *m = &c->miller[3 * i];
+        ip[i] = (wrap(m[0], n) * n + wrap(m[1], n)) * n + wrap(m[2], n);
+        im[i] = (wrap(-m[0], n) * n + wrap(-m[1], n)) * n + wrap(-m[2], n);
+        sqv[i] = std::sqrt(2.0 * kin[1 + 2 * i] > 0 ? 4.0 * M_PI / (2.0 * kin[1 + 2 * i]) : 0.0);
+    }
+    std::vector<float> sqv32(sqv.begin(), sqv.end());
+    up(c->idx_p, ip);
+    up(c->idx_m, im);
+    up(c->sqv64, sqv);
+    up(c->sqv32, sqv32);
+}
+
+void ctx_set_terms(bse_ctx *c, double k1e, double k1d, double scissor) {
+    c->k1e = k1e;
+    c->k1d = k1d;
+    c->scissor = scissor;
+    const int no = c->n_occ;
+    std::vector<double> e(c->eps_h);
+    for (int v = 0; v < no; ++v) e[(size_t)v * no + v] -= scissor;
+    std::vector<float> e32(e.begin(), e.end());
+    std::vector<double> d(no);
+    for (int v = 0; v < no; ++v) d[v] = c->eps_h[(size_t)v * no + v] - scissor;
+    c->eps64.alloc(e.size());
+    c->eps32.alloc(e.size());
+    c->epsd.alloc(no);
+    BSE_HIP(hipMemcpy(c->eps64.p, e.data(), e.size() * 8, hipMemcpyHostToDevice));
+    BSE_HIP(hipMemcpy(c->eps32.p, e32.data(), e32.size() * 4, hipMemcpyHostToDevice));
+    BSE_HIP(hipMemcpy(c->epsd.p, d.data(), d.size() * 8, hipMemcpyHostToDevice));
+    drop_graph(c);  // a captured apply bakes the terms in
+}
+
+void ctx_setup(bse_ctx *c, const bse_cell *cell, const double *psi, const double *eps,
+               const double *V) {
+    c->L = cell->L;
+    c->omega = cell->L * cell->L * cell->L;
+    c->n = cell->n;
+    c->nr = (long long)cell->n * cell->n * cell->n;
+    c->nh = cell->n_half;
+    c->npw = 1 + 2 * cell->n_half;
+    c->n_occ = cell->n_occ;
+    c->miller.assign(cell->miller, cell->miller + 3 * (size_t)cell->n_half);
+    int nmax = 0;
+    for (int v : c->miller) nmax = std::max(nmax, std::abs(v));
+    BSE_REQUIRE(2 * nmax < c->n, BSE_ERR_ARG, "sphere (|n| <= %d) does not fit the %d grid", nmax,
+                c->n);
+    c->plan = make_plan(c->n);
+    build_maps(c);
+    const size_t no = c->n_occ, npw = c->npw, nr = c->nr;
+    // copies of the inputs
+    c->psi64.alloc(no * npw);
+    BSE_HIP(hipMemcpy(c->psi64.p, psi, no * npw * 8, hipMemcpyDeviceToDevice));
+    c->V64.alloc(nr);
+    BSE_HIP(hipMemcpy(c->V64.p, V, nr * 8, hipMemcpyDeviceToDevice));
+    std::vector<double> Vh(nr), ph(no * npw);
+    BSE_HIP(hipMemcpy(Vh.data(), V, nr * 8, hipMemcpyDeviceToHost));
+    BSE_HIP(hipMemcpy(ph.data(), psi, no * npw * 8, hipMemcpyDeviceToHost));
+    double s = 0;
+    for (double x : Vh) {
+        BSE_REQUIRE(std::isfinite(x), BSE_ERR_ARG, "V has a non-finite value");
+        s += x;
+    }
+    for (double x : ph) BSE_REQUIRE(std::isfinite(x), BSE_ERR_ARG, "psi has a non-finite value");
+    c->vbar = s / (double)nr;
+    c->eps_h.assign(eps, eps + no * no);
+    for (size_t i = 0; i < no; ++i)
+        for (size_t j = 0; j < no; ++j) {
+            BSE_REQUIRE(std::isfinite(eps[i * no + j]), BSE_ERR_ARG, "eps has a non-finite value");
+            BSE_REQUIRE(std::fabs(eps[i * no + j] - eps[j * no + i]) <= 1e-10 * (1 + std::fabs(eps[i * no + j])),
+                        BSE_ERR_ARG, "eps is not symmetric");
+        }
+    ctx_set_terms(c, c->k1e, c->k1d, c->scissor);
+    c->psi32.alloc(no * npw);
+    convert<double, float>(c->psi64.p, c->psi32.p, no * npw, c->stream);
+    c->V32.alloc(nr);
+    convert<double, float>(c->V64.p, c->V32.p, nr, c->stream);
+    // orbitals on the grid through the library's own inverse transform
+    c->u64.alloc(no * nr);
+    {
+        const int nq = (int)(no + 1) / 2;
+        Dev<double2> T1, T2;
+        T1.alloc((size_t)nq * c->maps.ncol * c->n);
+        T2.alloc((size_t)nq * c->maps.nxp * c->n * c->n);
+        sph_inverse<double>(c->maps, c->psi64.p, (int)no, c->u64.p, T1.p, T2.p, c->tw64.p,
+                            c->stream);
+        BSE_HIP(hipStreamSynchronize(c->stream));
+        T1.free();
+        T2.free();
+    }
+    c->u32.alloc(no * nr);
+    convert<double, float>(c->u64.p, c->u32.p, no * nr, c->stream);
+    BSE_HIP(hipStreamSynchronize(c->stream));
+}
+
+void ctx_free(bse_ctx *c) { drop_graph(c); }
+
+// ---------------------------------------------------------------------------
+// pair measure and list (Eq. overlap)
+// ---------------------------------------------------------------------------
+void ctx_measure(bse_ctx *c, int kind, double *m_host) {
+    BSE_REQUIRE(kind == BSE_MEASURE_ABS_L1 || kind == BSE_MEASURE_OVERLAP, BSE_ERR_ARG,
+                "unknown measure %d", kind);
+    const int no = c->n_occ;
+    const long long nr = c->nr;
+    Dev<double> q, mm;
+    q.alloc((size_t)no * nr);
+    mm.alloc((size_t)no * no);
+    measure_prep(c->u64.p, (long long)no * nr, kind, q.p, c->stream);
+    gemm<double>(true, no, no, (int)nr, 1.0, q.p, nr, 0, q.p, nr, 0, 0.0, mm.p, no, 0, 1, c->gws,
+                 c->stream);
+    std::vector<double> h((size_t)no * no);
+    BSE_HIP(hipMemcpyAsync(h.data(), mm.p, h.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    BSE_HIP(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < no; ++i)
+        for (int j = 0; j < no; ++j) {
+            const double a = h[(size_t)i * no + j];
+            if (kind == BSE_MEASURE_ABS_L1)
+                m_host[(size_t)i * no + j] = a / (double)nr;
+            else
+                m_host[(size_t)i * no + j] =
+                    a / std::sqrt(h[(size_t)i * no + i] * h[(size_t)j * no + j]);
+        }
+}
+
+void ctx_build_pairs(bse_ctx *c, int kind, double thr) {
+    const int no = c->n_occ;
+    std::vector<double> m((size_t)no * no);
+    ctx_measure(c, kind, m.data());
+    std::vector<int> pr;
+    for (int v = 0; v < no; ++v)
+        for (int w = v; w < no; ++w)
+            if (v == w || m[(size_t)v * no + w] > thr) {
+                pr.push_back(v);
+                pr.push_back(w);
+            }
+    c->pairs_h = pr;
+    c->n_pairs = (long long)pr.size() / 2;
+    c->have_tau64 = c->have_tau32 = false;
+    c->tau64.free();
+    c->tau32.free();
+    drop_graph(c);
+    // symmetric CSR: row v holds (w, p) for every pair touching v, sorted by w
+    std::vector<std::vector<std::pair<int, int>>> rows(no);
+    for (long long p = 0; p < c->n_pairs; ++p) {
+        const int v = pr[2 * p], w = pr[2 * p + 1];
+        rows[v].push_back({w, (int)p});
+        if (w != v) rows[w].push_back({v, (int)p});
+    }
+    std::vector<int> col, pidx, rp(no + 1, 0);
+    for (int v = 0; v < no; ++v) {
+        std::sort(rows[v].begin(), rows[v].end());
+        rp[v] = (int)col.size();
+        for (auto &e : rows[v]) {
+            col.push_back(e.first);
+            pidx.push_back(e.second);
+        }
+    }
+    rp[no] = (int)col.size();
+    auto up = [&](auto &dev, const auto &host) {
+        dev.alloc(std::max<size_t>(1, host.size()));
+        if (!host.empty())
+            BSE_HIP(hipMemcpy(dev.p, host.data(), host.size() * sizeof(host[0]), hipMemcpyHostToDevice));
+    };
+    up(c->csr_col, col);
+    up(c->csr_pidx, pidx);
+    c->csr.col = c->csr_col.p;
+    c->csr.pidx = c->csr_pidx.p;
+    c->csr.nnz = (int)col.size();
+    {
+        const int chunk = c->csr.chunk;
+        const int nchunk = (no + chunk - 1) / chunk;
+        const int nIb = (no + K1D_BI - 1) / K1D_BI;
+        std::vector<int> lo((size_t)nchunk * no), hi((size_t)nchunk * no);
+        std::vector<unsigned char> nz((size_t)nIb * nchunk, 0);
+        for (int k = 0; k < nchunk; ++k) {
+            const int c0 = k * chunk, c1 = std::min(no, c0 + chunk);
+            for (int v = 0; v < no; ++v) {
+                int a = rp[v];
+                while (a < rp[v + 1] && col[a] < c0) ++a;
+                int b = a;
+                while (b < rp[v + 1] && col[b] < c1) ++b;
+                lo[(size_t)k * no + v] = a;
+                hi[(size_t)k * no + v] = b;
+                if (b > a) nz[(size_t)(v / K1D_BI) * nchunk + k] = 1;
+            }
+        }
+        up(c->csr_lo, lo);
+        up(c->csr_hi, hi);
+        up(c->csr_nz, nz);
+        c->csr.nchunk = nchunk;
+        c->csr.lo = c->csr_lo.p;
+        c->csr.hi = c->csr_hi.p;
+        c->csr.blk_nz = c->csr_nz.p;
+    }
+    std::vector<int2> pd(c->n_pairs);
+    for (long long p = 0; p < c->n_pairs; ++p) pd[p] = make_int2(pr[2 * p], pr[2 * p + 1]);
+    up(c->pairs_d, pd);
+}
+
+// ---------------------------------------------------------------------------
+// screened integrals (Eqs. tau, tau_from_tau_u, pdep)
+// ---------------------------------------------------------------------------
+template <typename T>
+static void screen_impl(bse_ctx *c, const T *phi, const T *phif, int n_pdep, bool bf16x3,
+                        T *tau_out, float *tau32_copy) {
+    const long long nr = c->nr;
+    const int nh = c->nh, npw1 = c->npw - 1;
+    const long long P = c->n_pairs;
+    // pairs per chunk: bounded by ~1 GB of complex grid workspace
+    long long chunk = std::max<long long>(2, (1LL << 30) / (nr * (long long)sizeof(cplx<T>)) * 2);
+    chunk = std::min<long long>(chunk, 512);
+    chunk -= chunk % 2;
+    Dev<cplx<T>> Hc;
+    Dev<T> Rb, Cm, D;
+    Hc.alloc((size_t)(chunk / 2) * nr);
+    Rb.alloc((size_t)chunk * npw1);
+    D.alloc((size_t)chunk * npw1);
+    Cm.alloc((size_t)chunk * n_pdep);
+    const T *u = std::is_same<T, double>::value ? (const T *)c->u64.p : (const T *)c->u32.p;
+    const T *vc = std::is_same<T, double>::value ? (const T *)c->vc64.p : (const T *)c->vc32.p;
+    const T *sqv = std::is_same<T, double>::value ? (const T *)c->sqv64.p : (const T *)c->sqv32.p;
+    const cplx<T> *tw =
+        std::is_same<T, double>::value ? (const cplx<T> *)c->tw64.p : (const cplx<T> *)c->tw32.p;
+    for (long long p0 = 0; p0 < P; p0 += chunk) {
+        const int cnt = (int)std::min<long long>(chunk, P - p0);
+        const int nq = (cnt + 1) / 2;
+        pair_density<T>(u, c->pairs_d.p, (int)p0, cnt, nr, (T)(1.0 / c->omega), Hc.p, c->stream);
+        grid_fft<T>(c->plan, Hc.p, nq, (T)-1, tw, c->stream);
+        pdep_gather<T>(Hc.p, cnt, nr, c->idx_p.p, c->idx_m.p, sqv, nh, Rb.p, c->stream);
+        if (bf16x3) {
+            gemm_bf16x3(true, cnt, n_pdep, npw1, 1.0f, (const float *)Rb.p, npw1, 0,
+                        (const float *)phi, npw1, 0, 0.0f, (float *)Cm.p, n_pdep, 0, 1, c->gws,
+                        c->stream);
+            gemm_bf16x3(false, cnt, npw1, n_pdep, 1.0f, (const float *)Cm.p, n_pdep, 0,
+                        (const float *)phif, npw1, 0, 0.0f, (float *)D.p, npw1, 0, 1, c->gws,
+                        c->stream);
+        } else {
+            gemm<T>(true, cnt, n_pdep, npw1, (T)1, Rb.p, npw1, 0, phi, npw1, 0, (T)0, Cm.p, n_pdep,
+                    0, 1, c->gws, c->stream);
+            gemm<T>(false, cnt, npw1, n_pdep, (T)1, Cm.p, n_pdep, 0, phif, npw1, 0, (T)0, D.p, npw1,
+                    0, 1, c->gws, c->stream);
+        }
+        scale_grid<T>(Hc.p, vc, nr, nq, c->stream);
+        pdep_scatter<T>(Hc.p, cnt, nr, c->idx_p.p, c->idx_m.p, sqv, nh, D.p, c->stream);
+        grid_fft<T>(c->plan, Hc.p, nq, (T)1, tw, c->stream);
+        store_tau<T, T>(Hc.p, cnt, nr, tau_out + (size_t)p0 * nr, c->stream);
+    }
+    if (tau32_copy)
+        convert<double, float>((const double *)tau_out, tau32_copy, P * nr, c->stream);
+    BSE_HIP(hipStreamSynchronize(c->stream));
+}
+
+void ctx_screen(bse_ctx *c, const double *phi, const double *lam, int n_pdep, int prec) {
+    BSE_REQUIRE(c->n_pairs > 0, BSE_ERR_STATE, "bse_screen_pairs needs bse_build_pairs first");
+    BSE_REQUIRE(n_pdep >= 1, BSE_ERR_ARG, "n_pdep must be >= 1");
+    for (int a = 0; a < n_pdep; ++a)
+        BSE_REQUIRE(std::isfinite(lam[a]) && lam[a] < 1.0, BSE_ERR_ARG,
+                    "lambda[%d] must be finite and < 1", a);
+    const size_t npw1 = c->npw - 1;
+    const size_t P = c->n_pairs, nr = c->nr;
+    // phi_f = (lambda / (1 - lambda)) phi, built on the device row by row
+    std::vector<double> f(n_pdep);
+    for (int a = 0; a < n_pdep; ++a) f[a] = lam[a] / (1.0 - lam[a]);
+    Dev<double> phif;
+    phif.alloc((size_t)n_pdep * npw1);
+    Dev<double> fd;
+    fd.alloc(n_pdep);
+    BSE_HIP(hipMemcpy(fd.p, f.data(), n_pdep * 8, hipMemcpyHostToDevice));
+    {
+        // scale rows: phif = diag(f) phi via a batched GEMM with 1x1 "matrices"
+        gemm<double>(false, 1, (int)npw1, 1, 1.0, fd.p, 1, 1, phi, npw1, npw1, 0.0, phif.p, npw1,
+                     npw1, n_pdep, c->gws, c->stream);
+    }
+    drop_graph(c);
+    if (prec == BSE_FP64) {
+        c->tau64.alloc(P * nr);
+        c->tau32.alloc(P * nr);
+        screen_impl<double>(c, phi, phif.p, n_pdep, false, c->tau64.p, c->tau32.p);
+        c->have_tau64 = c->have_tau32 = true;
+    } else {
+        Dev<float> p32, pf32;
+        p32.alloc((size_t)n_pdep * npw1);
+        pf32.alloc((size_t)n_pdep * npw1);
+        convert<double, float>(phi, p32.p, (long long)n_pdep * npw1, c->stream);
+        convert<double, float>(phif.p, pf32.p, (long long)n_pdep * npw1, c->stream);
+        c->tau64.free();
+        c->have_tau64 = false;
+        c->tau32.alloc(P * nr);
+        screen_impl<float>(c, p32.p, pf32.p, n_pdep, prec == BSE_BF16X3, c->tau32.p, nullptr);
+        c->have_tau32 = true;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the Liouville apply (Eq. evp with Eqs. d, k1e, k1d)
+// ---------------------------------------------------------------------------
+template <typename T>
+static void ensure_ws(bse_ctx *c, ApplyWs<T> &w, int nvec) {
+    if (w.cap >= nvec) return;
+    const size_t no = c->n_occ, nr = c->nr, n = c->n;
+    const size_t norb = (size_t)nvec * no;
+    const size_t nq = (norb + 1) / 2;
+    w.Ar.alloc(norb * nr);
+    w.Cr.alloc(norb * nr);
+    w.S.alloc(norb * no);
+    w.T1.alloc(nq * c->maps.ncol * n);
+    w.T2.alloc(nq * c->maps.nxp * n * n);
+    w.Hc.alloc((size_t)((nvec + 1) / 2) * nr);
+    w.Dp.alloc((size_t)((no + K1D_BI - 1) / K1D_BI) * nvec * nr);
+    w.cap = nvec;
+    ++w.gen;
+}
+
+template <typename T>
+static void gemm_p(bse_ctx *c, bool bf, bool nt, int M, int N, int K, T alpha, const T *A,
+                   long long lda, long long sA, const T *B, long long ldb, long long sB, T beta,
+                   T *C, long long ldc, long long sC, int batch, Workspace &ws) {
+    if (bf)
+        gemm_bf16x3(nt, M, N, K, (float)alpha, (const float *)A, lda, sA, (const float *)B, ldb, sB,
+                    (float)beta, (float *)C, ldc, sC, batch, ws, c->stream);
+    else
+        gemm<T>(nt, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, ws,
+                c->stream);
+}
+
+// P_c on a block in place: Y -= (Y Psi^T) Psi
+template <typename T>
+static void project_c(bse_ctx *c, bool bf, int norb, T *Y, T *S, const T *psi, Workspace &ws) {
+    const int no = c->n_occ, npw = c->npw;
+    gemm_p<T>(c, bf, true, norb, no, npw, (T)1, Y, npw, 0, psi, npw, 0, (T)0, S, no, 0, 1, ws);
+    gemm_p<T>(c, bf, false, norb, npw, no, (T)-1, S, no, 0, psi, npw, 0, (T)1, Y, npw, 0, 1, ws);
+}
+
+// ev (optional): 11 events, [0] before the first launch, then one after each
+// of the ten stages (inv z, inv y, inv x, k1d, hartree, fwd x, fwd y, fwd z,
+// eps gemm, P_c gemms)
+template <typename T>
+static void apply_impl(bse_ctx *c, int nvec, const T *X, T *Y, bool bf, hipEvent_t *ev = nullptr) {
+    const bool dbl = std::is_same<T, double>::value;
+    ApplyWs<T> &w = *reinterpret_cast<ApplyWs<T> *>(dbl ? (void *)&c->ws64 : (void *)&c->ws32);
+    ensure_ws<T>(c, w, nvec);
+    const int no = c->n_occ, npw = c->npw;
+    const int norb = nvec * no;
+    const long long nr = c->nr;
+    const T *u = dbl ? (const T *)c->u64.p : (const T *)c->u32.p;
+    const T *V = dbl ? (const T *)c->V64.p : (const T *)c->V32.p;
+    const T *vc = dbl ? (const T *)c->vc64.p : (const T *)c->vc32.p;
+    const T *tau = dbl ? (const T *)c->tau64.p : (const T *)c->tau32.p;
+    const T *psi = dbl ? (const T *)c->psi64.p : (const T *)c->psi32.p;
+    const T *eps = dbl ? (const T *)c->eps64.p : (const T *)c->eps32.p;
+    const cplx<T> *tw = dbl ? (const cplx<T> *)c->tw64.p : (const cplx<T> *)c->tw32.p;
+    hipStream_t st = c->stream;
+    auto rec = [&](int i) {
+        if (ev) BSE_HIP(hipEventRecord(ev[i], st));
+    };
+    rec(0);
+    // a1: sphere -> grid for every (s, v)
+    sph_inverse<T>(c->maps, X, norb, w.Ar.p, w.T1.p, w.T2.p, tw, st, ev ? ev + 1 : nullptr);
+    // a4 (+ V a of a2, + the K1e density of a3)
+    k1d_apply<T>(w.Ar.p, tau, V, u, c->csr, no, nvec, nr, (T)c->k1d, (T)(1.0 / c->omega), w.Cr.p,
+                 w.Hc.p, w.Dp.p, st);
+    rec(4);
+    // a3: Hartree potential of every trial vector's density
+    const int nbh = (nvec + 1) / 2;
+    grid_fft<T>(c->plan, w.Hc.p, nbh, (T)-1, tw, st);
+    scale_grid<T>(w.Hc.p, vc, nr, nbh, st);
+    grid_fft<T>(c->plan, w.Hc.p, nbh, (T)1, tw, st);
+    rec(5);
+    // a5: combine, grid -> sphere, kinetic
+    sph_forward<T>(c->maps, w.Cr.p, u, w.Hc.p, (T)c->k1e, norb, no, X, (T)1, Y, w.T1.p, w.T2.p, tw,
+                   st, ev ? ev + 6 : nullptr);
+    // a2: - (eps - scissor) a, batched over trial vectors
+    gemm_p<T>(c, bf, false, no, npw, no, (T)-1, eps, no, 0, X, npw, (long long)no * npw, (T)1, Y,
+              npw, (long long)no * npw, nvec, c->aws);
+    rec(9);
+    // a6: P_c
+    project_c<T>(c, bf, norb, Y, w.S.p, psi, c->aws);
+    rec(10);
+}
+
+void ctx_profile_apply(bse_ctx *c, int n_vec, const void *in, void *out, int prec, int n_rep,
+                       double *ms) {
+    BSE_REQUIRE(n_rep >= 1, BSE_ERR_ARG, "n_rep must be >= 1");
+    ctx_apply(c, n_vec, in, out, prec);  // sizes the workspaces
+    hipEvent_t ev[11];
+    for (auto &e : ev) BSE_HIP(hipEventCreate(&e));
+    for (int s = 0; s < 10; ++s) ms[s] = 0;
+    try {
+        for (int r = 0; r < n_rep; ++r) {
+            if (prec == BSE_FP64)
+                apply_impl<double>(c, n_vec, (const double *)in, (double *)out, false, ev);
+            else
+                apply_impl<float>(c, n_vec, (const float *)in, (float *)out, prec == BSE_BF16X3, ev);
+            BSE_HIP(hipEventSynchronize(ev[10]));
+            for (int s = 0; s < 10; ++s) {
+                float t = 0;
+                BSE_HIP(hipEventElapsedTime(&t, ev[s], ev[s + 1]));
+                ms[s] += t / n_rep;
+            }
+        }
+    } catch (...) {
+        for (auto &e : ev) (void)hipEventDestroy(e);
+        throw;
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+}
+
+void ctx_project_c64(bse_ctx *c, int n_vec, double *Y) {
+    Dev<double> S;
+    // reuse the FP64 S buffer when large enough
+    S.alloc((size_t)n_vec * c->n_occ * c->n_occ);
+    project_c<double>(c, false, n_vec * c->n_occ, Y, S.p, c->psi64.p, c->gws);
+    BSE_HIP(hipStreamSynchronize(c->stream));
+}
+
+void ctx_apply(bse_ctx *c, int n_vec, const void *in, void *out, int prec) {
+    BSE_REQUIRE(prec == BSE_FP64 || prec == BSE_FP32 || prec == BSE_BF16X3, BSE_ERR_ARG,
+                "unknown precision %d", prec);
+    BSE_REQUIRE(n_vec >= 1, BSE_ERR_ARG, "n_vec must be >= 1");
+    BSE_REQUIRE(in && out && in != out, BSE_ERR_ARG, "A_in/A_out must be distinct device buffers");
+    if (prec == BSE_FP64) {
+        BSE_REQUIRE(c->have_tau64, BSE_ERR_STATE, "FP64 apply needs bse_screen_pairs in FP64");
+        apply_impl<double>(c, n_vec, (const double *)in, (double *)out, false);
+    } else {
+        BSE_REQUIRE(c->have_tau32, BSE_ERR_STATE, "FP32 apply needs bse_screen_pairs");
+        apply_impl<float>(c, n_vec, (const float *)in, (float *)out, prec == BSE_BF16X3);
+    }
+}
+
+// entry with optional graph capture / replay
+void ctx_apply_entry(bse_ctx *c, int n_vec, const void *in, void *out, int prec) {
+    if (!c->use_graph) {
+        ctx_apply(c, n_vec, in, out, prec);
+        return;
+    }
+    BSE_REQUIRE(c->stream != nullptr, BSE_ERR_ARG, "graph capture needs a non-default stream");
+    auto ws_gen = [c]() { return c->ws64.gen + c->ws32.gen + c->aws.gen; };
+    if (c->gexec && c->g_nvec == n_vec && c->g_prec == prec && c->g_in == in && c->g_out == out &&
+        c->g_gen == ws_gen()) {
+        BSE_HIP(hipGraphLaunch(c->gexec, c->stream));
+        return;
+    }
+    // eager run sizes every workspace; then capture the same launches
+    ctx_apply(c, n_vec, in, out, prec);
+    BSE_HIP(hipStreamSynchronize(c->stream));
+    drop_graph(c);
+    const int gen = ws_gen();
+    BSE_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    try {
+        ctx_apply(c, n_vec, in, out, prec);
+    } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(c->stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    BSE_HIP(hipStreamEndCapture(c->stream, &c->graph));
+    BSE_HIP(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+    BSE_REQUIRE(ws_gen() == gen, BSE_ERR_HIP,
+                "apply workspaces changed during capture");
+    c->g_gen = gen;
+    c->g_nvec = n_vec;
+    c->g_prec = prec;
+    c->g_in = in;
+    c->g_out = out;
+}
+
+}  // namespace bse

@@ -1,0 +1,125 @@
+// Context of one cell: device-resident inputs, index maps, pair list, tau,
+// workspaces and the captured apply graph.
+#pragma once
+
+#include <vector>
+
+#include "fft.hpp"
+#include "kernels.hpp"
+
+namespace bse {
+
+template <typename T>
+struct Dev {
+    T *p = nullptr;
+    size_t n = 0;
+    Dev() = default;
+    Dev(const Dev &) = delete;
+    Dev &operator=(const Dev &) = delete;
+    ~Dev() { free(); }
+    void alloc(size_t count) {
+        if (count <= n && p) return;
+        free();
+        if (count == 0) return;
+        hipError_t e = hipMalloc(&p, count * sizeof(T));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            set_error("device allocation of %zu bytes failed", count * sizeof(T));
+            throw Err{BSE_ERR_OOM};
+        }
+        n = count;
+    }
+    void free() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+// per-precision apply workspaces
+template <typename T>
+struct ApplyWs {
+    int cap = 0;              // trial vectors the buffers hold
+    int gen = 0;              // bumped when the buffers are reallocated
+    Dev<T> Ar, Cr, S, Dp;
+    Dev<cplx<T>> T1, T2, Hc;
+};
+
+struct LearnedPre {
+    bool loaded = false;
+    int K = 0;                 // window of low-|G| packed coefficients
+    Dev<unsigned short> W1, W2, W3;   // bf16 weights, [in][out]
+    Dev<float> b1, b2, b3;
+    Dev<int> win;              // packed indices of the window
+    Dev<float> feat, h1, h2, out;
+};
+
+}  // namespace bse
+
+struct bse_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    double L = 0, omega = 0;
+    int n = 0;
+    long long nr = 0;
+    int nh = 0, npw = 0, n_occ = 0;
+    std::vector<int> miller;
+    bse::SphereMaps maps;
+    bse::FftPlan plan{};
+    bse::Dev<double2> tw64;
+    bse::Dev<float2> tw32;
+    bse::Dev<int2> ent;
+    bse::Dev<int> col_ptr, colmap, xlist, xinv;
+    bse::Dev<double> kin;
+    // cell inputs
+    bse::Dev<double> psi64, u64, V64, vc64, sqv64, eps64, epsd;
+    bse::Dev<float> psi32, u32, V32, vc32, sqv32, eps32;
+    bse::Dev<int> idx_p, idx_m;
+    std::vector<double> eps_h;
+    double vbar = 0;
+    double k1e = 2.0, k1d = 1.0, scissor = 0.0;
+    // pairs and tau
+    std::vector<int> pairs_h;  // [P][2]
+    bse::Dev<int2> pairs_d;
+    bse::Dev<int> csr_col, csr_pidx, csr_lo, csr_hi;
+    bse::Dev<unsigned char> csr_nz;
+    bse::PairCSR csr;
+    long long n_pairs = 0;
+    bool have_tau64 = false, have_tau32 = false;
+    bse::Dev<double> tau64;
+    bse::Dev<float> tau32;
+    // workspaces
+    bse::ApplyWs<double> ws64;
+    bse::ApplyWs<float> ws32;
+    bse::Workspace gws;       // GEMM split-K partials of everything but the apply
+    bse::Workspace aws;       // GEMM split-K partials of the apply (captured in graphs)
+    // graph
+    bool use_graph = false;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    int g_nvec = -1, g_prec = -1, g_gen = -1;
+    const void *g_in = nullptr;
+    void *g_out = nullptr;
+    // learned preconditioner
+    bse::LearnedPre lp;
+};
+
+namespace bse {
+void ctx_setup(bse_ctx *c, const bse_cell *cell, const double *psi, const double *eps,
+               const double *V);
+void ctx_free(bse_ctx *c);
+void ctx_set_terms(bse_ctx *c, double k1e, double k1d, double scissor);
+void ctx_measure(bse_ctx *c, int kind, double *m_host);
+void ctx_build_pairs(bse_ctx *c, int kind, double thr);
+void ctx_screen(bse_ctx *c, const double *phi, const double *lam, int n_pdep, int prec);
+void ctx_apply(bse_ctx *c, int n_vec, const void *in, void *out, int prec);
+void ctx_apply_entry(bse_ctx *c, int n_vec, const void *in, void *out, int prec);
+void ctx_profile_apply(bse_ctx *c, int n_vec, const void *in, void *out, int prec, int n_rep,
+                       double *ms);
+void ctx_project_c64(bse_ctx *c, int n_vec, double *Y);
+void ctx_davidson(bse_ctx *c, const bse_davidson_opts *o, const double *X0, double *omega,
+                  double *X, bse_davidson_stats *stats);
+void learned_correction(bse_ctx *c, const double *R, const double *theta, int k, double *Tn,
+                        int *used, int *rejected);
+}  // namespace bse

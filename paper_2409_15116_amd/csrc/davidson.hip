@@ -1,0 +1,328 @@
+// Block Davidson for the lowest eigenpairs of the Liouville operator
+// (Sec. 3: the operator is applied to a block of trial vectors per iteration;
+// Davidson 1975).  The basis, Rayleigh-Ritz matrix, residual norms and the
+// orthogonalisation are FP64 on the device; the apply runs in the requested
+// precision.  The only host work is the small symmetric eigenproblem and the
+// small Cholesky factor, once per iteration.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "ctx.hpp"
+
+namespace bse {
+
+// cyclic Jacobi eigen-decomposition of a small symmetric matrix (row-major),
+// eigenvalues ascending, eigenvectors in the columns of Z
+static void jacobi_eigh(int n, std::vector<double> A, std::vector<double> &w,
+                        std::vector<double> &Z) {
+    Z.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) Z[(size_t)i * n + i] = 1.0;
+    auto at = [&](int i, int j) -> double & { return A[(size_t)i * n + j]; };
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0, tot = 0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                tot += at(i, j) * at(i, j);
+                if (i != j) off += at(i, j) * at(i, j);
+            }
+        if (off <= 1e-30 * tot || off == 0) break;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = at(p, q);
+                if (std::fabs(apq) < 1e-300) continue;
+                const double theta = (at(q, q) - at(p, p)) / (2.0 * apq);
+                const double t = (theta >= 0 ? 1.0 : -1.0) /
+                                 (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+                for (int k = 0; k < n; ++k) {
+                    const double akp = at(k, p), akq = at(k, q);
+                    at(k, p) = cs * akp - sn * akq;
+                    at(k, q) = sn * akp + cs * akq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double apk = at(p, k), aqk = at(q, k);
+                    at(p, k) = cs * apk - sn * aqk;
+                    at(q, k) = sn * apk + cs * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double zkp = Z[(size_t)k * n + p], zkq = Z[(size_t)k * n + q];
+                    Z[(size_t)k * n + p] = cs * zkp - sn * zkq;
+                    Z[(size_t)k * n + q] = sn * zkp + cs * zkq;
+                }
+            }
+    }
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](int a, int b) { return at(a, a) < at(b, b); });
+    w.resize(n);
+    std::vector<double> Zs((size_t)n * n);
+    for (int j = 0; j < n; ++j) {
+        w[j] = at(idx[j], idx[j]);
+        for (int i = 0; i < n; ++i) Zs[(size_t)i * n + j] = Z[(size_t)i * n + idx[j]];
+    }
+    Z.swap(Zs);
+}
+
+struct DavState {
+    bse_ctx *c;
+    long long n;  // n_occ * npw
+    Dev<double> V, W, X, LX, R, Tn, tmp, small, part, norms, theta;
+    Dev<double> in64, out64;
+    Dev<float> in32, out32;
+    int B = 0;  // rows of the fixed apply buffers
+};
+
+// stream-ordered upload of a small host matrix; returns once the host copy is consumed
+static void upload(bse_ctx *c, Dev<double> &d, const std::vector<double> &h) {
+    d.alloc(std::max<size_t>(h.size(), 1));
+    BSE_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * 8, hipMemcpyHostToDevice, c->stream));
+    BSE_HIP(hipStreamSynchronize(c->stream));
+}
+
+// rows of Y (k x n) -> C (m x n) = M (m x k) Y, M a small host matrix
+static void small_times(DavState &s, int m, int k, const std::vector<double> &M, const double *Y,
+                        double *C) {
+    upload(s.c, s.small, M);
+    gemm<double>(false, m, (int)s.n, k, 1.0, s.small.p, k, 0, Y, s.n, 0, 0.0, C, s.n, 0, 1,
+                 s.c->gws, s.c->stream);
+}
+
+// G = A B^T (m x k) to host
+static std::vector<double> gram(DavState &s, int m, const double *A, int k, const double *B) {
+    Dev<double> &g = s.small;
+    g.alloc((size_t)std::max(1, m * k));
+    gemm<double>(true, m, k, (int)s.n, 1.0, A, s.n, 0, B, s.n, 0, 0.0, g.p, k, 0, 1, s.c->gws,
+                 s.c->stream);
+    std::vector<double> h((size_t)m * k);
+    BSE_HIP(hipMemcpyAsync(h.data(), g.p, h.size() * 8, hipMemcpyDeviceToHost, s.c->stream));
+    BSE_HIP(hipStreamSynchronize(s.c->stream));
+    return h;
+}
+
+// Tn (k rows) -= (Tn V^T) V over the nb basis rows
+static void orth_against(DavState &s, int nb, int k) {
+    if (nb == 0 || k == 0) return;
+    Dev<double> sm;
+    sm.alloc((size_t)k * nb);
+    gemm<double>(true, k, nb, (int)s.n, 1.0, s.Tn.p, s.n, 0, s.V.p, s.n, 0, 0.0, sm.p, nb, 0, 1,
+                 s.c->gws, s.c->stream);
+    gemm<double>(false, k, (int)s.n, nb, -1.0, sm.p, nb, 0, s.V.p, s.n, 0, 1.0, s.Tn.p, s.n, 0, 1,
+                 s.c->gws, s.c->stream);
+    BSE_HIP(hipStreamSynchronize(s.c->stream));
+}
+
+// Orthonormalise the k rows of Tn: Cholesky-QR of the Gram matrix; when it
+// is numerically singular, an eigen-decomposition drops the collapsed
+// directions.  Returns the number of rows kept (packed to the front).
+static int orthonormalize(DavState &s, int k, double drop2) {
+    if (k == 0) return 0;
+    std::vector<double> G = gram(s, k, s.Tn.p, k, s.Tn.p);
+    double gmax = 0;
+    for (int i = 0; i < k; ++i) gmax = std::max(gmax, G[(size_t)i * k + i]);
+    // Cholesky G = L L^T
+    std::vector<double> Lm((size_t)k * k, 0.0);
+    bool ok = gmax > 0;
+    for (int j = 0; j < k && ok; ++j) {
+        double d = G[(size_t)j * k + j];
+        for (int p = 0; p < j; ++p) d -= Lm[(size_t)j * k + p] * Lm[(size_t)j * k + p];
+        if (!(d > drop2 * gmax)) {
+            ok = false;
+            break;
+        }
+        const double ljj = std::sqrt(d);
+        Lm[(size_t)j * k + j] = ljj;
+        for (int i = j + 1; i < k; ++i) {
+            double v = G[(size_t)i * k + j];
+            for (int p = 0; p < j; ++p) v -= Lm[(size_t)i * k + p] * Lm[(size_t)j * k + p];
+            Lm[(size_t)i * k + j] = v / ljj;
+        }
+    }
+    std::vector<double> Minv;
+    int kk = k;
+    if (ok) {
+        // L^{-1} by forward substitution
+        Minv.assign((size_t)k * k, 0.0);
+        for (int col = 0; col < k; ++col) {
+            for (int i = 0; i < k; ++i) {
+                double v = (i == col) ? 1.0 : 0.0;
+                for (int p = 0; p < i; ++p) v -= Lm[(size_t)i * k + p] * Minv[(size_t)p * k + col];
+                Minv[(size_t)i * k + col] = v / Lm[(size_t)i * k + i];
+            }
+        }
+    } else {
+        std::vector<double> w, Z;
+        jacobi_eigh(k, G, w, Z);
+        std::vector<int> keep;
+        for (int i = k - 1; i >= 0; --i)
+            if (w[i] > drop2 * gmax) keep.push_back(i);
+        kk = (int)keep.size();
+        Minv.assign((size_t)std::max(1, kk) * k, 0.0);
+        for (int r = 0; r < kk; ++r) {
+            const int i = keep[r];
+            const double sc = 1.0 / std::sqrt(w[i]);
+            for (int j = 0; j < k; ++j) Minv[(size_t)r * k + j] = Z[(size_t)j * k + i] * sc;
+        }
+        if (kk == 0) return 0;
+    }
+    small_times(s, kk, k, Minv, s.Tn.p, s.tmp.p);
+    BSE_HIP(hipMemcpyAsync(s.Tn.p, s.tmp.p, (size_t)kk * s.n * 8, hipMemcpyDeviceToDevice,
+                           s.c->stream));
+    BSE_HIP(hipStreamSynchronize(s.c->stream));
+    return kk;
+}
+
+static void apply_block(DavState &s, int k, const double *in, double *out, int prec) {
+    bse_ctx *c = s.c;
+    const long long len = (long long)k * s.n;
+    const int B = s.B;
+    // fixed buffers keep a captured apply valid across iterations
+    if (prec == BSE_FP64) {
+        BSE_HIP(hipMemcpyAsync(s.in64.p, in, len * 8, hipMemcpyDeviceToDevice, c->stream));
+        if (k < B) zero<double>(s.in64.p + len, (long long)(B - k) * s.n, c->stream);
+        ctx_apply_entry(c, B, s.in64.p, s.out64.p, prec);
+        BSE_HIP(hipMemcpyAsync(out, s.out64.p, len * 8, hipMemcpyDeviceToDevice, c->stream));
+    } else {
+        convert<double, float>(in, s.in32.p, len, c->stream);
+        if (k < B) zero<float>(s.in32.p + len, (long long)(B - k) * s.n, c->stream);
+        ctx_apply_entry(c, B, s.in32.p, s.out32.p, prec);
+        convert<float, double>(s.out32.p, out, len, c->stream);
+    }
+}
+
+void ctx_davidson(bse_ctx *c, const bse_davidson_opts *o, const double *X0, double *omega,
+                  double *Xout, bse_davidson_stats *stats) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int B = o->block, ne = o->n_eig;
+    BSE_REQUIRE(ne >= 1 && ne <= B && B <= 64, BSE_ERR_ARG, "need 1 <= n_eig <= block <= 64");
+    const int maxb = o->max_basis > 0 ? o->max_basis : 4 * B;
+    const int rst = o->restart > 0 ? o->restart : 2 * B;
+    BSE_REQUIRE(maxb >= 2 * B && rst >= ne && rst <= maxb - B, BSE_ERR_ARG,
+                "need max_basis >= 2 block and n_eig <= restart <= max_basis - block");
+    BSE_REQUIRE(o->tol > 0, BSE_ERR_ARG, "tol must be > 0");
+    const int prec = o->precision;
+    BSE_REQUIRE(prec == BSE_FP64 || prec == BSE_FP32 || prec == BSE_BF16X3, BSE_ERR_ARG,
+                "unknown precision");
+    BSE_REQUIRE(prec == BSE_FP64 ? c->have_tau64 : c->have_tau32, BSE_ERR_STATE,
+                "Davidson needs bse_screen_pairs in the requested precision");
+    const double delta = o->delta > 0 ? o->delta : 0.05;
+    DavState s;
+    s.c = c;
+    s.n = (long long)c->n_occ * c->npw;
+    const size_t n = s.n;
+    s.V.alloc((size_t)maxb * n);
+    s.W.alloc((size_t)maxb * n);
+    s.X.alloc((size_t)B * n);
+    s.LX.alloc((size_t)B * n);
+    s.R.alloc((size_t)B * n);
+    s.Tn.alloc((size_t)B * n);
+    s.tmp.alloc((size_t)maxb * n);
+    s.part.alloc((size_t)B * 256);
+    s.norms.alloc(B);
+    s.theta.alloc(maxb);
+    if (prec == BSE_FP64) {
+        s.in64.alloc((size_t)B * n);
+        s.out64.alloc((size_t)B * n);
+    } else {
+        s.in32.alloc((size_t)B * n);
+        s.out32.alloc((size_t)B * n);
+    }
+    s.B = B;
+    int n_apply = 0, used = 0, rejected = 0;
+    const double drop2 = 1e-20;
+    // start block
+    BSE_HIP(hipMemcpyAsync(s.Tn.p, X0, (size_t)B * n * 8, hipMemcpyDeviceToDevice, c->stream));
+    ctx_project_c64(c, B, s.Tn.p);
+    int k = orthonormalize(s, B, drop2);
+    k = orthonormalize(s, k, drop2);
+    BSE_REQUIRE(k > 0, BSE_ERR_ARG, "start block has no component in the P_c space");
+    BSE_HIP(hipMemcpyAsync(s.V.p, s.Tn.p, (size_t)k * n * 8, hipMemcpyDeviceToDevice, c->stream));
+    apply_block(s, k, s.V.p, s.W.p, prec);
+    n_apply += k;
+    int nb = k;
+    std::vector<double> theta, Y, rn(B);
+    int it = 0;
+    bse_status result = BSE_ERR_NOCONV;
+    int kr = 0;
+    for (it = 1; it <= o->max_iter; ++it) {
+        std::vector<double> T = gram(s, nb, s.V.p, nb, s.W.p);
+        for (int i = 0; i < nb; ++i)
+            for (int j = i + 1; j < nb; ++j) {
+                const double a = 0.5 * (T[(size_t)i * nb + j] + T[(size_t)j * nb + i]);
+                T[(size_t)i * nb + j] = T[(size_t)j * nb + i] = a;
+            }
+        jacobi_eigh(nb, T, theta, Y);
+        kr = std::min(B, nb);
+        std::vector<double> Yk((size_t)kr * nb);
+        for (int r = 0; r < kr; ++r)
+            for (int j = 0; j < nb; ++j) Yk[(size_t)r * nb + j] = Y[(size_t)j * nb + r];
+        small_times(s, kr, nb, Yk, s.V.p, s.X.p);
+        small_times(s, kr, nb, Yk, s.W.p, s.LX.p);
+        std::vector<double> th(theta.begin(), theta.begin() + kr);
+        upload(c, s.theta, th);
+        residual(s.LX.p, s.X.p, s.theta.p, n, kr, s.R.p, c->stream);
+        row_norm2(s.R.p, n, kr, s.part.p, s.norms.p, c->stream);
+        BSE_HIP(hipMemcpyAsync(rn.data(), s.norms.p, kr * 8, hipMemcpyDeviceToHost, c->stream));
+        BSE_HIP(hipStreamSynchronize(c->stream));
+        bool conv = true;
+        for (int i = 0; i < kr; ++i) rn[i] = std::sqrt(rn[i]);
+        for (int i = 0; i < ne; ++i) conv = conv && (i < kr) && rn[i] <= o->tol;
+        if (o->verbose)
+            fprintf(stderr, "[bse_davidson] it %d nb %d theta0 %.10f res0 %.3e res_max %.3e\n", it,
+                    nb, theta[0], rn[0], *std::max_element(rn.begin(), rn.begin() + ne));
+        if (conv) {
+            result = BSE_OK;
+            break;
+        }
+        // preconditioned residuals
+        precond_diag(s.R.p, s.theta.p, c->kin.p, c->epsd.p, c->vbar, delta, c->n_occ, c->npw, kr,
+                     s.Tn.p, c->stream);
+        if (o->precond == 1 && c->lp.loaded) learned_correction(c, s.R.p, s.theta.p, kr, s.Tn.p,
+                                                                &used, &rejected);
+        ctx_project_c64(c, kr, s.Tn.p);
+        if (nb + kr > maxb) {
+            const int m = std::min(rst, nb);
+            std::vector<double> Ym((size_t)m * nb);
+            for (int r = 0; r < m; ++r)
+                for (int j = 0; j < nb; ++j) Ym[(size_t)r * nb + j] = Y[(size_t)j * nb + r];
+            small_times(s, m, nb, Ym, s.V.p, s.tmp.p);
+            BSE_HIP(hipMemcpyAsync(s.V.p, s.tmp.p, (size_t)m * n * 8, hipMemcpyDeviceToDevice,
+                                   c->stream));
+            small_times(s, m, nb, Ym, s.W.p, s.tmp.p);
+            BSE_HIP(hipMemcpyAsync(s.W.p, s.tmp.p, (size_t)m * n * 8, hipMemcpyDeviceToDevice,
+                                   c->stream));
+            nb = m;
+        }
+        orth_against(s, nb, kr);
+        int kk = orthonormalize(s, kr, drop2);
+        orth_against(s, nb, kk);
+        kk = orthonormalize(s, kk, drop2);
+        BSE_REQUIRE(kk > 0, BSE_ERR_NOCONV, "Davidson: no new directions");
+        BSE_HIP(hipMemcpyAsync(s.V.p + (size_t)nb * n, s.Tn.p, (size_t)kk * n * 8,
+                               hipMemcpyDeviceToDevice, c->stream));
+        apply_block(s, kk, s.V.p + (size_t)nb * n, s.W.p + (size_t)nb * n, prec);
+        n_apply += kk;
+        nb += kk;
+    }
+    const int nout = std::min(ne, kr);
+    for (int i = 0; i < nout; ++i) omega[i] = theta[i];
+    BSE_HIP(hipMemcpyAsync(Xout, s.X.p, (size_t)nout * n * 8, hipMemcpyDeviceToDevice, c->stream));
+    BSE_HIP(hipStreamSynchronize(c->stream));
+    if (stats) {
+        stats->iterations = std::min(it, o->max_iter);
+        stats->n_apply = n_apply;
+        stats->learned_used = used;
+        stats->learned_rejected = rejected;
+        stats->seconds =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        for (int i = 0; i < 64; ++i) stats->resid[i] = i < nout ? rn[i] : 0.0;
+    }
+    if (result != BSE_OK) {
+        set_error("bse_davidson: not converged in %d iterations", o->max_iter);
+        throw Err{BSE_ERR_NOCONV};
+    }
+}
+
+}  // namespace bse

@@ -1,0 +1,157 @@
+// Dense GEMMs: C = alpha * A * op(B) + beta * C, row-major, strided batches.
+//   NN: B is [K][N];  NT: B is [N][K].
+// The vector-FMA kernel serves FP64 and FP32; the FP32 path can instead run
+// on MFMA as split-BF16x3 (gemm_bf16x3 in mfma.hip).
+#include "kernels.hpp"
+
+namespace bse {
+
+constexpr int BM = 64, BN = 64, BK = 16;
+
+template <typename T, bool NT>
+__global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, T alpha, const T *__restrict__ A,
+                                              long long lda, long long sA, const T *__restrict__ Bm,
+                                              long long ldb, long long sB, T beta, T *__restrict__ C,
+                                              long long ldc, long long sC, int kchunk,
+                                              int nsplit) {
+    __shared__ T As[BK][BM + 1];
+    __shared__ T Bs[BK][BN + 1];
+    const int bz = blockIdx.z;
+    const int batch = bz / nsplit;
+    const int split = bz - batch * nsplit;
+    A += batch * sA;
+    Bm += batch * sB;
+    // split-K partial sums go to a workspace laid out [batch][split][M][N]
+    C += nsplit > 1 ? ((size_t)batch * nsplit + split) * (size_t)M * N : (size_t)(batch * sC);
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int kbeg = split * kchunk;
+    const int kend = min(K, kbeg + kchunk);
+    const int tid = threadIdx.x;
+    const int tm = tid >> 4, tn = tid & 15;
+    T acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0;
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+        // A tile: 64 x 16, k fastest
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            const int idx = tid + l * 256;
+            const int mm = idx >> 4, kk = idx & 15;
+            const int gm = m0 + mm, gk = k0 + kk;
+            As[kk][mm] = (gm < M && gk < kend) ? A[(size_t)gm * lda + gk] : (T)0;
+        }
+        if (NT) {
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                const int idx = tid + l * 256;
+                const int nn = idx >> 4, kk = idx & 15;
+                const int gn = n0 + nn, gk = k0 + kk;
+                Bs[kk][nn] = (gn < N && gk < kend) ? Bm[(size_t)gn * ldb + gk] : (T)0;
+            }
+        } else {
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                const int idx = tid + l * 256;
+                const int kk = idx >> 6, nn = idx & 63;
+                const int gn = n0 + nn, gk = k0 + kk;
+                Bs[kk][nn] = (gn < N && gk < kend) ? Bm[(size_t)gk * ldb + gn] : (T)0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < BK; ++kk) {
+            T a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[kk][tm + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tn + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int gm = m0 + tm + 16 * i;
+        if (gm >= M) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int gn = n0 + tn + 16 * j;
+            if (gn >= N) continue;
+            T *c = C + (size_t)gm * ldc + gn;
+            if (nsplit > 1) {
+                *c = acc[i][j];
+            } else {
+                *c = beta == (T)0 ? alpha * acc[i][j] : alpha * acc[i][j] + beta * *c;
+            }
+        }
+    }
+}
+
+template <typename T>
+__global__ void k_splitk_reduce(const T *__restrict__ part, int nsplit, int M, int N, T alpha,
+                                T beta, T *__restrict__ C, long long ldc, long long sC,
+                                int nbatch) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long mn = (long long)M * N;
+    if (i >= mn * nbatch) return;
+    const int b = (int)(i / mn);
+    const long long j = i - b * mn;
+    const int m = (int)(j / N), n = (int)(j - (long long)m * N);
+    T s = 0;
+    for (int k = 0; k < nsplit; ++k) s += part[((size_t)b * nsplit + k) * mn + j];
+    T *c = C + b * sC + (size_t)m * ldc + n;
+    *c = beta == (T)0 ? alpha * s : alpha * s + beta * *c;
+}
+
+template <typename T>
+void gemm(bool nt, int M, int N, int K, T alpha, const T *A, long long lda, long long sA,
+          const T *B, long long ldb, long long sB, T beta, T *C, long long ldc, long long sC,
+          int batch, Workspace &ws, hipStream_t st) {
+    if (M <= 0 || N <= 0 || batch <= 0) return;
+    const int tiles = div_up(M, BM) * div_up(N, BN) * batch;
+    int nsplit = 1;
+    if (K > 4 * BK && tiles < 512) {
+        nsplit = std::min(div_up(1024, tiles), div_up(K, 256));
+        nsplit = std::max(1, nsplit);
+    }
+    int kchunk = div_up(div_up(K, nsplit), BK) * BK;
+    nsplit = std::max(1, (int)div_up(K, kchunk));
+    dim3 grid(div_up(N, BN), div_up(M, BM), batch * nsplit);
+    if (nsplit == 1) {
+        if (nt)
+            k_gemm<T, true><<<grid, 256, 0, st>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C,
+                                                  ldc, sC, kchunk, 1);
+        else
+            k_gemm<T, false><<<grid, 256, 0, st>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C,
+                                                   ldc, sC, kchunk, 1);
+        BSE_LAUNCH_CHECK();
+        return;
+    }
+    const size_t mn = (size_t)M * N;
+    T *part = (T *)ws.get(mn * nsplit * batch * sizeof(T));
+    if (nt)
+        k_gemm<T, true><<<grid, 256, 0, st>>>(M, N, K, (T)1, A, lda, sA, B, ldb, sB, (T)0, part, N,
+                                              0, kchunk, nsplit);
+    else
+        k_gemm<T, false><<<grid, 256, 0, st>>>(M, N, K, (T)1, A, lda, sA, B, ldb, sB, (T)0, part,
+                                               N, 0, kchunk, nsplit);
+    BSE_LAUNCH_CHECK();
+    const long long tot = (long long)mn * batch;
+    k_splitk_reduce<T><<<div_up(tot, 256), 256, 0, st>>>(part, nsplit, M, N, alpha, beta, C, ldc,
+                                                         sC, batch);
+    BSE_LAUNCH_CHECK();
+}
+
+template void gemm<float>(bool, int, int, int, float, const float *, long long, long long,
+                          const float *, long long, long long, float, float *, long long,
+                          long long, int, Workspace &, hipStream_t);
+template void gemm<double>(bool, int, int, int, double, const double *, long long, long long,
+                           const double *, long long, long long, double, double *, long long,
+                           long long, int, Workspace &, hipStream_t);
+
+}  // namespace bse

@@ -1,0 +1,99 @@
+// Launch wrappers of the real-space, elementwise and GEMM kernels.
+#pragma once
+
+#include <algorithm>
+
+#include "common.hpp"
+
+namespace bse {
+
+// Grow-only device scratch owned by a context.
+struct Workspace {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    int gen = 0;  // bumped on every reallocation
+    Workspace() = default;
+    Workspace(const Workspace &) = delete;
+    Workspace &operator=(const Workspace &) = delete;
+    ~Workspace() { release(); }
+    void *get(size_t need) {
+        if (need > bytes) {
+            if (ptr) BSE_HIP(hipFree(ptr));
+            ptr = nullptr;
+            bytes = 0;
+            hipError_t e = hipMalloc(&ptr, need);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                set_error("workspace allocation of %zu bytes failed", need);
+                throw Err{BSE_ERR_OOM};
+            }
+            bytes = need;
+            ++gen;
+        }
+        return ptr;
+    }
+    void release() {
+        if (ptr) (void)hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+    }
+};
+
+// Symmetric pair list as CSR over rows v: entries (w, tau slot) with w
+// sorted.  The K1d kernel stages the columns in blocks of `chunk` orbitals;
+// lo/hi are [nchunk][n_occ] offsets of each row's entries inside each column
+// block, and blk_nz[ib][jb] marks (row block of K1D_BI rows, column block)
+// pairs that hold any entry.
+constexpr int K1D_BI = 32;
+struct PairCSR {
+    int *col = nullptr;
+    int *pidx = nullptr;
+    int nnz = 0;
+    int chunk = 16;
+    int nchunk = 0;
+    int *lo = nullptr;
+    int *hi = nullptr;
+    unsigned char *blk_nz = nullptr;
+};
+
+// Dp: [ceil(n_occ / K1D_BI)][B][nr] partial K1e densities
+template <typename T>
+void k1d_apply(const T *A, const T *tau, const T *V, const T *u, const PairCSR &csr, int n_occ,
+               int B, long long nr, T k1d, T inv_omega, T *Cr, cplx<T> *Hc, T *Dp,
+               hipStream_t st);
+template <typename T>
+void scale_grid(cplx<T> *Hc, const T *w, long long nr, int nb, hipStream_t st);
+template <typename T>
+void pair_density(const T *u, const int2 *pairs, int p0, int count, long long nr, T inv_omega,
+                  cplx<T> *Hc, hipStream_t st);
+template <typename T>
+void pdep_gather(const cplx<T> *Hc, int count, long long nr, const int *idx_p, const int *idx_m,
+                 const T *sqv, int nh, T *out, hipStream_t st);
+template <typename T>
+void pdep_scatter(cplx<T> *Hc, int count, long long nr, const int *idx_p, const int *idx_m,
+                  const T *sqv, int nh, const T *D, hipStream_t st);
+template <typename T, typename TS>
+void store_tau(const cplx<T> *Hc, int count, long long nr, TS *tau, hipStream_t st);
+template <typename TI, typename TO>
+void convert(const TI *a, TO *b, long long n, hipStream_t st);
+template <typename T>
+void zero(T *a, long long n, hipStream_t st);
+void measure_prep(const double *u, long long n, int kind, double *out, hipStream_t st);
+void residual(const double *LX, const double *X, const double *theta, long long n, int k,
+              double *R, hipStream_t st);
+void row_norm2(const double *X, long long n, int k, double *part, double *out, hipStream_t st);
+void precond_diag(const double *R, const double *theta, const double *kin, const double *epsd,
+                  double vbar, double delta, int n_occ, int npw, int k, double *Tn,
+                  hipStream_t st);
+
+template <typename T>
+void gemm(bool nt, int M, int N, int K, T alpha, const T *A, long long lda, long long sA,
+          const T *B, long long ldb, long long sB, T beta, T *C, long long ldc, long long sC,
+          int batch, Workspace &ws, hipStream_t st);
+
+// split-BF16x3 MFMA GEMM with FP32 accumulate (same conventions as gemm<float>)
+void gemm_bf16x3(bool nt, int M, int N, int K, float alpha, const float *A, long long lda,
+                 long long sA, const float *B, long long ldb, long long sB, float beta, float *C,
+                 long long ldc, long long sC, int batch, Workspace &ws, hipStream_t st);
+
+}  // namespace bse

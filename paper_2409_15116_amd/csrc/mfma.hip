@@ -1,0 +1,184 @@
+// Split-BF16x3 GEMM on the gfx950 matrix cores (FP32 in, FP32 accumulate).
+//
+// Each FP32 operand x is split into hi = bf16(x) and lo = bf16(x - hi), and
+// A B is taken as Ahi Bhi + Ahi Blo + Alo Bhi (the lo*lo term is below the
+// FP32 accumulation error), so three 16x16x16 bf16 MFMAs replace one FP32 FMA
+// chain with a relative error of about 2^-16 instead of 2^-8.
+//
+// Tile: 64 x 64 per workgroup of 4 waves, each wave a 32 x 32 quadrant made
+// of 2 x 2 MFMA blocks; K steps of 16 staged through LDS as bf16 hi/lo pairs.
+// Lane layout of v_mfma_f32_16x16x16_bf16 (64 lanes): A element i of lane l is
+// A[l % 16][4 (l / 16) + i], B element i is B[4 (l / 16) + i][l % 16], and
+// accumulator element i is D[4 (l / 16) + i][l % 16].
+#include "kernels.hpp"
+
+namespace bse {
+
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ inline unsigned short bf16_rne(float x) {
+    unsigned int u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ inline float bf16_to_f32(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+
+constexpr int TB = 64, TK = 16, PADK = 4;
+
+template <bool NT>
+__global__ void __launch_bounds__(256) k_gemm_bf16x3(int M, int N, int K, float alpha,
+                                                     const float *__restrict__ A, long long lda,
+                                                     long long sA, const float *__restrict__ Bm,
+                                                     long long ldb, long long sB, float beta,
+                                                     float *__restrict__ C, long long ldc,
+                                                     long long sC, int kchunk, int nsplit) {
+    __shared__ unsigned short Ah[TB][TK + PADK], Al[TB][TK + PADK];
+    __shared__ unsigned short Bh[TB][TK + PADK], Bl[TB][TK + PADK];  // [n][k]
+    const int bz = blockIdx.z;
+    const int batch = bz / nsplit;
+    const int split = bz - batch * nsplit;
+    A += batch * sA;
+    Bm += batch * sB;
+    C += nsplit > 1 ? ((size_t)batch * nsplit + split) * (size_t)M * N : (size_t)(batch * sC);
+    const int m0 = blockIdx.y * TB, n0 = blockIdx.x * TB;
+    const int kbeg = split * kchunk;
+    const int kend = min(K, kbeg + kchunk);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    f32x4_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4_t){0.f, 0.f, 0.f, 0.f};
+    for (int k0 = kbeg; k0 < kend; k0 += TK) {
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            const int idx = tid + l * 256;
+            const int mm = idx >> 4, kk = idx & 15;
+            const int gm = m0 + mm, gk = k0 + kk;
+            const float x = (gm < M && gk < kend) ? A[(size_t)gm * lda + gk] : 0.f;
+            const unsigned short h = bf16_rne(x);
+            Ah[mm][kk] = h;
+            Al[mm][kk] = bf16_rne(x - bf16_to_f32(h));
+        }
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            const int idx = tid + l * 256;
+            int nn, kk;
+            float x;
+            if (NT) {
+                nn = idx >> 4;
+                kk = idx & 15;
+                const int gn = n0 + nn, gk = k0 + kk;
+                x = (gn < N && gk < kend) ? Bm[(size_t)gn * ldb + gk] : 0.f;
+            } else {
+                kk = idx >> 6;
+                nn = idx & 63;
+                const int gn = n0 + nn, gk = k0 + kk;
+                x = (gn < N && gk < kend) ? Bm[(size_t)gk * ldb + gn] : 0.f;
+            }
+            const unsigned short h = bf16_rne(x);
+            Bh[nn][kk] = h;
+            Bl[nn][kk] = bf16_rne(x - bf16_to_f32(h));
+        }
+        __syncthreads();
+        const int r16 = lane & 15, kq = (lane >> 4) * 4;
+        bf16x4_t ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int row = wm + i * 16 + r16;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                ah[i][e] = (short)Ah[row][kq + e];
+                al[i][e] = (short)Al[row][kq + e];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int col = wn + j * 16 + r16;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                bh[j][e] = (short)Bh[col][kq + e];
+                bl[j][e] = (short)Bl[col][kq + e];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
+            }
+        __syncthreads();
+    }
+    const int c16 = lane & 15, rq = (lane >> 4) * 4;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int gm = m0 + wm + i * 16 + rq + e;
+                const int gn = n0 + wn + j * 16 + c16;
+                if (gm < M && gn < N) {
+                    float *c = C + (size_t)gm * ldc + gn;
+                    const float v = acc[i][j][e];
+                    if (nsplit > 1) *c = v;
+                    else *c = beta == 0.f ? alpha * v : alpha * v + beta * *c;
+                }
+            }
+}
+
+__global__ void k_splitk_reduce_f(const float *__restrict__ part, int nsplit, int M, int N,
+                                  float alpha, float beta, float *__restrict__ C, long long ldc,
+                                  long long sC, int nbatch) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long mn = (long long)M * N;
+    if (i >= mn * nbatch) return;
+    const int b = (int)(i / mn);
+    const long long j = i - b * mn;
+    const int m = (int)(j / N), n = (int)(j - (long long)m * N);
+    float s = 0;
+    for (int k = 0; k < nsplit; ++k) s += part[((size_t)b * nsplit + k) * mn + j];
+    float *c = C + b * sC + (size_t)m * ldc + n;
+    *c = beta == 0.f ? alpha * s : alpha * s + beta * *c;
+}
+
+void gemm_bf16x3(bool nt, int M, int N, int K, float alpha, const float *A, long long lda,
+                 long long sA, const float *B, long long ldb, long long sB, float beta, float *C,
+                 long long ldc, long long sC, int batch, Workspace &ws, hipStream_t st) {
+    if (M <= 0 || N <= 0 || batch <= 0) return;
+    const int tiles = div_up(M, TB) * div_up(N, TB) * batch;
+    int nsplit = 1;
+    if (K > 4 * TK && tiles < 512) nsplit = std::max(1, (int)std::min(div_up(1024, tiles), div_up(K, 256)));
+    const int kchunk = div_up(div_up(K, nsplit), TK) * TK;
+    nsplit = std::max(1, (int)div_up(K, kchunk));
+    dim3 grid(div_up(N, TB), div_up(M, TB), batch * nsplit);
+    if (nsplit == 1) {
+        if (nt)
+            k_gemm_bf16x3<true><<<grid, 256, 0, st>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta,
+                                                      C, ldc, sC, kchunk, 1);
+        else
+            k_gemm_bf16x3<false><<<grid, 256, 0, st>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta,
+                                                       C, ldc, sC, kchunk, 1);
+        BSE_LAUNCH_CHECK();
+        return;
+    }
+    const size_t mn = (size_t)M * N;
+    float *part = (float *)ws.get(mn * nsplit * batch * sizeof(float));
+    if (nt)
+        k_gemm_bf16x3<true><<<grid, 256, 0, st>>>(M, N, K, 1.f, A, lda, sA, B, ldb, sB, 0.f, part,
+                                                  N, 0, kchunk, nsplit);
+    else
+        k_gemm_bf16x3<false><<<grid, 256, 0, st>>>(M, N, K, 1.f, A, lda, sA, B, ldb, sB, 0.f, part,
+                                                   N, 0, kchunk, nsplit);
+    BSE_LAUNCH_CHECK();
+    const long long tot = (long long)mn * batch;
+    k_splitk_reduce_f<<<div_up(tot, 256), 256, 0, st>>>(part, nsplit, M, N, alpha, beta, C, ldc, sC,
+                                                        batch);
+    BSE_LAUNCH_CHECK();
+}
+
+}  // namespace bse

@@ -1,0 +1,230 @@
+"""ctypes binding of libbse.so (argument marshalling only).
+
+Every call goes straight to the C ABI declared in include/bse.h; device
+buffers are torch tensors on the GPU, used only for memory and streams.
+There is no CPU path: when the library or a GPU is missing, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbse.so")
+
+FP64, FP32, BF16X3 = 0, 1, 2
+MEASURE_ABS_L1, MEASURE_OVERLAP = 0, 1
+_STATUS = {0: "ok", 1: "invalid argument", 2: "HIP error", 3: "out of device memory",
+           4: "not converged", 5: "call out of order"}
+
+
+class BseError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Cell(C.Structure):
+    _fields_ = [("L", C.c_double), ("n", C.c_int32), ("n_half", C.c_int32),
+                ("miller", C.POINTER(C.c_int32)), ("n_occ", C.c_int32)]
+
+
+class DavidsonOpts(C.Structure):
+    _fields_ = [("n_eig", C.c_int32), ("block", C.c_int32), ("max_basis", C.c_int32),
+                ("restart", C.c_int32), ("max_iter", C.c_int32), ("precision", C.c_int32),
+                ("tol", C.c_double), ("delta", C.c_double), ("precond", C.c_int32),
+                ("verbose", C.c_int32)]
+
+
+class DavidsonStats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("n_apply", C.c_int32),
+                ("learned_used", C.c_int32), ("learned_rejected", C.c_int32),
+                ("seconds", C.c_double), ("resid", C.c_double * 64)]
+
+
+_lib = None
+
+
+def load():
+    """Load the in-tree libbse.so; raise when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library missing: {LIB_PATH} (run __graft_entry__.build())")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int, C.c_int64, C.c_double
+    sig = {
+        "bse_create": (i32, [C.POINTER(vp), C.POINTER(_Cell), vp, vp, vp, vp]),
+        "bse_destroy": (i32, [vp]),
+        "bse_set_terms": (i32, [vp, dbl, dbl, dbl]),
+        "bse_pair_measure": (i32, [vp, i32, vp]),
+        "bse_build_pairs": (i32, [vp, i32, dbl, C.POINTER(i64)]),
+        "bse_threshold_for_fraction": (dbl, [vp, i32, dbl]),
+        "bse_get_pairs": (i32, [vp, vp]),
+        "bse_screen_pairs": (i32, [vp, vp, vp, i32, i32]),
+        "bse_copy_tau": (i32, [vp, i64, i64, vp]),
+        "bse_apply_liouville": (i32, [vp, i32, vp, vp, i32]),
+        "bse_set_graph": (i32, [vp, i32]),
+        "bse_profile_apply": (i32, [vp, i32, vp, vp, i32, i32, vp]),
+        "bse_davidson": (i32, [vp, C.POINTER(DavidsonOpts), vp, vp, vp,
+                               C.POINTER(DavidsonStats)]),
+        "bse_debug_to_grid": (i32, [vp, i32, vp, vp, i32]),
+        "bse_debug_gemm": (i32, [vp, i32, i32, i32, i32, dbl, vp, vp, dbl, vp, i32]),
+        "bse_status_str": (C.c_char_p, [i32]),
+        "bse_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return ["bse_create", "bse_destroy", "bse_set_terms", "bse_pair_measure", "bse_build_pairs",
+            "bse_threshold_for_fraction", "bse_get_pairs", "bse_screen_pairs", "bse_copy_tau",
+            "bse_apply_liouville", "bse_set_graph", "bse_davidson", "bse_status_str",
+            "bse_last_error", "bse_debug_to_grid", "bse_debug_gemm", "bse_profile_apply"]
+
+
+def _check(st):
+    if st != 0:
+        raise BseError(st, load().bse_last_error().decode())
+
+
+def _dptr(t, dtype, shape=None):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"expected a contiguous CUDA tensor of {dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+def threshold_for_fraction(m: np.ndarray, fraction: float) -> float:
+    m = np.ascontiguousarray(m, dtype=np.float64)
+    return float(load().bse_threshold_for_fraction(m.ctypes.data, m.shape[0], float(fraction)))
+
+
+class BseContext:
+    """One cell on one GPU; wraps a bse_ctx."""
+
+    def __init__(self, L, n, miller, psi, eps, V, stream=None):
+        import torch
+        lib = load()
+        self.torch = torch
+        self.miller = np.ascontiguousarray(miller, dtype=np.int32)
+        self.n_occ, self.npw = psi.shape
+        self.n = int(n)
+        self.nr = self.n ** 3
+        self.stream = stream
+        self._eps = np.ascontiguousarray(eps, dtype=np.float64)
+        cell = _Cell(float(L), self.n, len(self.miller),
+                     self.miller.ctypes.data_as(C.POINTER(C.c_int32)), self.n_occ)
+        h = C.c_void_p()
+        sp = C.c_void_p(stream.cuda_stream if stream is not None else 0)
+        _check(lib.bse_create(C.byref(h), C.byref(cell), _dptr(psi, torch.float64),
+                              self._eps.ctypes.data, _dptr(V, torch.float64), sp))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().bse_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_terms(self, k1e=2.0, k1d=1.0, scissor=0.0):
+        _check(load().bse_set_terms(self.h, k1e, k1d, scissor))
+
+    def pair_measure(self, kind=MEASURE_ABS_L1):
+        m = np.empty((self.n_occ, self.n_occ))
+        _check(load().bse_pair_measure(self.h, kind, m.ctypes.data))
+        return m
+
+    def build_pairs(self, kind=MEASURE_ABS_L1, threshold=-1.0):
+        P = C.c_int64()
+        _check(load().bse_build_pairs(self.h, kind, float(threshold), C.byref(P)))
+        self.n_pairs = int(P.value)
+        return self.n_pairs
+
+    def get_pairs(self):
+        out = np.empty((self.n_pairs, 2), dtype=np.int32)
+        _check(load().bse_get_pairs(self.h, out.ctypes.data))
+        return out
+
+    def screen_pairs(self, phi, lam, precision=FP64):
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        _check(load().bse_screen_pairs(self.h, _dptr(phi, self.torch.float64), lam.ctypes.data,
+                                       len(lam), precision))
+
+    def copy_tau(self, p0, count):
+        out = self.torch.empty((count, self.nr), dtype=self.torch.float64, device="cuda")
+        _check(load().bse_copy_tau(self.h, p0, count, _dptr(out, self.torch.float64)))
+        return out
+
+    def apply(self, A_in, A_out, precision=FP64):
+        dt = self.torch.float64 if precision == FP64 else self.torch.float32
+        nv = A_in.shape[0]
+        shp = (nv, self.n_occ, self.npw)
+        _check(load().bse_apply_liouville(self.h, nv, _dptr(A_in, dt, shp), _dptr(A_out, dt, shp),
+                                          precision))
+        return A_out
+
+    def debug_to_grid(self, X, precision=FP64):
+        dt = self.torch.float64 if precision == FP64 else self.torch.float32
+        out = self.torch.empty((X.shape[0], self.nr), dtype=dt, device="cuda")
+        _check(load().bse_debug_to_grid(self.h, X.shape[0], _dptr(X, dt), _dptr(out, dt),
+                                        precision))
+        return out
+
+    def debug_gemm(self, A, B, nt, precision=FP64, alpha=1.0, beta=0.0, Cm=None):
+        dt = self.torch.float64 if precision == FP64 else self.torch.float32
+        M, K = A.shape
+        N = B.shape[0] if nt else B.shape[1]
+        if Cm is None:
+            Cm = self.torch.zeros((M, N), dtype=dt, device="cuda")
+        _check(load().bse_debug_gemm(self.h, int(nt), M, N, K, alpha, _dptr(A, dt), _dptr(B, dt),
+                                     beta, _dptr(Cm, dt, (M, N)), precision))
+        return Cm
+
+    STAGES = ("inv_z", "inv_y", "inv_x", "k1d", "hartree", "fwd_x", "fwd_y", "fwd_z",
+              "eps_gemm", "pc_gemm")
+
+    def profile_apply(self, A_in, A_out, precision=FP64, n_rep=3):
+        dt = self.torch.float64 if precision == FP64 else self.torch.float32
+        nv = A_in.shape[0]
+        shp = (nv, self.n_occ, self.npw)
+        ms = np.zeros(10)
+        _check(load().bse_profile_apply(self.h, nv, _dptr(A_in, dt, shp), _dptr(A_out, dt, shp),
+                                        precision, n_rep, ms.ctypes.data))
+        return dict(zip(self.STAGES, ms))
+
+    def set_graph(self, enable=True):
+        _check(load().bse_set_graph(self.h, 1 if enable else 0))
+
+    def davidson(self, X0, n_eig, *, block=None, max_basis=0, restart=0, max_iter=200,
+                 precision=FP64, tol=1e-6, delta=0.05, precond=0, verbose=0):
+        torch = self.torch
+        B = block or X0.shape[0]
+        o = DavidsonOpts(n_eig, B, max_basis, restart, max_iter, precision, tol, delta, precond,
+                         verbose)
+        om = np.zeros(n_eig)
+        X = torch.empty((n_eig, self.n_occ, self.npw), dtype=torch.float64, device="cuda")
+        st = DavidsonStats()
+        status = load().bse_davidson(self.h, C.byref(o), _dptr(X0, torch.float64,
+                                                                (B, self.n_occ, self.npw)),
+                                     om.ctypes.data, _dptr(X, torch.float64), C.byref(st))
+        stats = {"iterations": st.iterations, "n_apply": st.n_apply, "seconds": st.seconds,
+                 "learned_used": st.learned_used, "learned_rejected": st.learned_rejected,
+                 "resid": np.array(st.resid[:n_eig]), "status": status}
+        _check(status)
+        return om, X, stats

@@ -33,7 +33,16 @@ import scipy.fft as sfft
 from scipy.sparse.linalg import LinearOperator, eigsh
 
 SQRT2 = np.sqrt(2.0)
+GENERATOR_VERSION = 2        # part of the cache key: bump when generated data change
 _WORKERS = max(1, min(16, os.cpu_count() or 1))
+
+
+def _progress(msg):
+    """Work-step progress lines of long generations (stderr)."""
+    if os.environ.get("BSE_SYNTH_QUIET") != "1":
+        import sys
+        import time
+        print(f"[synth {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 # --------------------------------------------------------------------------
@@ -57,7 +66,7 @@ class CellSpec:
     localize: bool = True    # JADE-localise the occupied orbitals
 
     def key(self) -> str:
-        s = repr(sorted(asdict(self).items())).encode()
+        s = repr((GENERATOR_VERSION, sorted(asdict(self).items()))).encode()
         return hashlib.sha1(s).hexdigest()[:12]
 
 
@@ -229,39 +238,102 @@ class _RealBasis:
         return 0.5 * self.g2 * p + self.to_packed(V * self.to_grid(p))
 
 
+def _dense_ham(basis: _RealBasis, V: np.ndarray) -> np.ndarray:
+    npw = basis.npw
+    H = np.empty((npw, npw))
+    step = max(1, int(2e8 // (basis.nr * 16)))
+    for i in range(0, npw, step):
+        j = min(npw, i + step)
+        E = np.zeros((j - i, npw))
+        E[np.arange(j - i), np.arange(i, j)] = 1.0
+        H[i:j] = basis.ham(E, V)
+    return 0.5 * (H + H.T)
+
+
 def _ground_state(basis: _RealBasis, V: np.ndarray, k: int, seed: int):
+    """Lowest k eigenpairs of H = -1/2 nabla^2 + V in the sphere.
+
+    Small spheres: dense eigh.  Large ones: dense eigh in a low-cut-off
+    sub-sphere gives the start block of a preconditioned block solver
+    (scipy LOBPCG) in the full sphere."""
     npw = basis.npw
     if npw <= 3200:
-        H = np.empty((npw, npw))
-        step = max(1, int(2e8 // (basis.nr * 16)))
-        for i in range(0, npw, step):
-            j = min(npw, i + step)
-            E = np.zeros((j - i, npw))
-            E[np.arange(j - i), np.arange(i, j)] = 1.0
-            H[i:j] = basis.ham(E, V)
-        H = 0.5 * (H + H.T)
-        w, X = np.linalg.eigh(H)
+        w, X = np.linalg.eigh(_dense_ham(basis, V))
         return w[:k], np.ascontiguousarray(X[:, :k].T)
-    rng = np.random.default_rng(seed + 12345)
-    v0 = rng.standard_normal(npw)
-    op = LinearOperator((npw, npw), matvec=lambda x: basis.ham(x, V), dtype=np.float64)
-    w, X = eigsh(op, k=k, which="SA", v0=v0, tol=1e-12, ncv=min(npw, max(2 * k + 1, k + 64)))
+    from scipy.sparse.linalg import lobpcg
+    b = 2.0 * np.pi / basis.L
+    g2h = (b * b) * (basis.miller.astype(np.float64) ** 2).sum(1)
+    # sub-sphere with about 2500 packed dofs
+    ec = np.sort(g2h)[min(len(g2h) - 1, 1250)]
+    sel = np.nonzero(g2h <= ec)[0]
+    sub = _RealBasis(basis.L, basis.n, basis.miller[sel])
+    w0, X0 = np.linalg.eigh(_dense_ham(sub, V))
+    _progress(f"sub-sphere eigh done ({sub.npw} dofs); LOBPCG on {npw} dofs, {k} states")
+    m = min(sub.npw, k + max(16, k // 4))
+    idx = np.concatenate([[0], 1 + 2 * sel, 2 + 2 * sel])
+    order = np.argsort(idx)
+    start = np.zeros((npw, m))
+    start[idx[order]] = X0[order, :m]
+    prec = 1.0 / (0.5 * basis.g2 + 1.0)
+
+    calls = [0]
+
+    def A(X):
+        X = X.reshape(npw, -1)
+        calls[0] += 1
+        if calls[0] % 10 == 0:
+            _progress(f"LOBPCG operator block {calls[0]}")
+        return basis.ham(np.ascontiguousarray(X.T), V).T
+
+    def M(X):
+        return prec.reshape(-1, 1) * X.reshape(npw, -1)
+
+    import warnings
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        w, X = lobpcg(A, start, M=M, largest=False, tol=1e-7, maxiter=80)
     o = np.argsort(w)
-    return w[o], np.ascontiguousarray(X[:, o].T)
+    w, X = w[o], X[:, o]
+    # final Rayleigh-Ritz and accuracy check
+    HX = A(X)
+    T = X.T @ HX
+    S = X.T @ X
+    from scipy.linalg import eigh as geigh
+    ww, Y = geigh(0.5 * (T + T.T), 0.5 * (S + S.T))
+    X = X @ Y
+    res = np.linalg.norm(A(X[:, :k]) - X[:, :k] * ww[:k], axis=0).max()
+    if res > 1e-6:
+        raise RuntimeError(f"ground state not converged (residual {res:.2e})")
+    return ww[:k], np.ascontiguousarray(X[:, :k].T)
 
 
 # --------------------------------------------------------------------------
 # JADE localisation (input preparation, Sec. 2 Eq. (wannier), Eq. (spread))
 # --------------------------------------------------------------------------
+def _round_robin(N):
+    """N-1 (N even) or N (odd) rounds of disjoint pairs covering every pair once."""
+    players = list(range(N)) + ([-1] if N % 2 else [])
+    M = len(players)
+    rounds = []
+    for r in range(M - 1):
+        p = [players[0]] + players[1:][r:] + players[1:][:r]
+        pr = [(p[i], p[M - 1 - i]) for i in range(M // 2)]
+        pr = [(min(a, b), max(a, b)) for a, b in pr if a >= 0 and b >= 0]
+        rounds.append((np.array([a for a, _ in pr]), np.array([b for _, b in pr])))
+    return rounds
+
+
 def jade(A: np.ndarray, tol: float = 1e-7, max_sweeps: int = 60):
     """Joint approximate diagonalisation of the real symmetric matrices A[n].
 
     Returns (Q, history) with Q orthogonal such that Q^T A[n] Q are as
     diagonal as the Jacobi sweeps reach; history holds the off-diagonal sum
     sum_n sum_{v != w} (Q^T A[n] Q)_{vw}^2 after the start and each sweep.
-    Start: eigenvectors of A[0].  Pair rotation angle: the principal
+    Start: eigenvectors of A[0] (Sec. 2).  Pair rotation angle: the principal
     eigenvector of G = sum_n h_n h_n^T, h_n = (A_pp - A_qq, 2 A_pq), gives
-    (cos 2t, sin 2t) (Cardoso & Souloumiac).
+    (cos 2t, sin 2t) (Cardoso & Souloumiac).  Each sweep visits the pairs in
+    rounds of disjoint pairs whose 2x2 rotations commute and are applied
+    together (the concurrent-rotation form of Sec. 2).
     """
     A = np.array(A, dtype=np.float64, copy=True)
     nm, N, _ = A.shape
@@ -273,32 +345,36 @@ def jade(A: np.ndarray, tol: float = 1e-7, max_sweeps: int = 60):
         return float((A * A).sum() - (d * d).sum())
 
     hist = [offsum(A)]
+    rounds = _round_robin(N) if N > 1 else []
     for _ in range(max_sweeps):
         smax = 0.0
-        for p in range(N - 1):
-            for q in range(p + 1, N):
-                h0 = A[:, p, p] - A[:, q, q]
-                h1 = 2.0 * A[:, p, q]
-                g00 = h0 @ h0
-                g11 = h1 @ h1
-                g01 = h0 @ h1
-                t = 0.25 * np.arctan2(2.0 * g01, g00 - g11)
-                c, s = np.cos(t), np.sin(t)
-                if abs(s) < tol:
-                    continue
-                smax = max(smax, abs(s))
-                ap = A[:, :, p].copy()
-                aq = A[:, :, q]
-                A[:, :, p] = c * ap + s * aq
-                A[:, :, q] = -s * ap + c * aq
-                ap = A[:, p, :].copy()
-                aq = A[:, q, :]
-                A[:, p, :] = c * ap + s * aq
-                A[:, q, :] = -s * ap + c * aq
-                qp = Q[:, p].copy()
-                Q[:, p] = c * qp + s * Q[:, q]
-                Q[:, q] = -s * qp + c * Q[:, q]
+        for P, R in rounds:
+            h0 = A[:, P, P] - A[:, R, R]
+            h1 = 2.0 * A[:, P, R]
+            g00 = (h0 * h0).sum(0)
+            g11 = (h1 * h1).sum(0)
+            g01 = (h0 * h1).sum(0)
+            t = 0.25 * np.arctan2(2.0 * g01, g00 - g11)
+            c, s = np.cos(t), np.sin(t)
+            skip = np.abs(s) < tol
+            c[skip], s[skip] = 1.0, 0.0
+            if not skip.all():
+                smax = max(smax, float(np.abs(s).max()))
+            ap = A[:, :, P].copy()
+            aq = A[:, :, R].copy()
+            A[:, :, P] = c * ap + s * aq
+            A[:, :, R] = -s * ap + c * aq
+            ap = A[:, P, :].copy()
+            aq = A[:, R, :].copy()
+            A[:, P, :] = c[:, None] * ap + s[:, None] * aq
+            A[:, R, :] = -s[:, None] * ap + c[:, None] * aq
+            qp = Q[:, P].copy()
+            qq = Q[:, R].copy()
+            Q[:, P] = c * qp + s * qq
+            Q[:, R] = -s * qp + c * qq
         hist.append(offsum(A))
+        if N >= 64:
+            _progress(f"JADE sweep {len(hist) - 1}: off-diagonal {hist[-1]:.4g}")
         if smax < tol:
             break
     return Q, hist
@@ -392,7 +468,9 @@ def make_cell(spec: CellSpec | str, cache: bool = True) -> Cell:
         kw = {f: z[f] for f in _FIELDS}
         return Cell(spec=spec, L=spec.L, n=spec.n, omega=spec.L ** 3,
                     eps_next=float(z["eps_next"]), jade_history=list(z["jade_history"]), **kw)
+    _progress(f"building cell {spec.name}")
     cell = _build_cell(spec)
+    _progress(f"cell {spec.name} ready (gap {cell.gap:.4f} Ha)")
     if cache:
         tmp = path + ".tmp.npz"
         np.savez(tmp, eps_next=cell.eps_next, jade_history=np.array(cell.jade_history),

@@ -1,0 +1,91 @@
+"""GPU parity at the benchmark's full size and launch configuration.
+
+64-well cell at its literal filling (N_occ = 128, 72^3 grid, 25 Ry, 256 PDEP,
+~40 % pairs), a block of 16 trial vectors (bench.py's seed), hipGraph replay.
+The oracle cannot apply the whole operator at this size within a test, so it
+computes sampled output orbitals one by one: each orbital slot of the output
+needs only the pairs that touch it (oracle apply with ``rows``).  Properties
+that hold at any size are checked on the whole output.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle.liouville import Basis, LiouvilleOracle  # noqa: E402
+from oracle.pairs import MEASURE_ABS_L1, build_pairs, pair_measure  # noqa: E402
+from oracle.screening import screened_integrals  # noqa: E402
+from synth import trial_block  # noqa: E402
+from tests.gpu_common import rel_err, say  # noqa: E402
+from tests.oracle_setup import cell  # noqa: E402
+
+ROWS = [0, 77]
+VECS = [0, 15]
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2409_15116_amd as pkg
+    say("fullsize: cell")
+    c = cell("c2_lit")
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        ctx = pkg.context_for(c, stream=st)
+        thr = pkg.setup_pairs_and_screen(ctx, c, fraction=0.4, precision=pkg.FP64)
+    st.synchronize()
+    say("fullsize: oracle subset")
+    b = Basis(c.L, c.n, c.miller)
+    u = b.to_grid(c.psi)
+    m = pair_measure(u, MEASURE_ABS_L1)
+    pairs = build_pairs(m, thr)
+    sub = [p for p in pairs if p[0] in ROWS or p[1] in ROWS]
+    tau = screened_integrals(b, u, sub, c.phi, c.lam)
+    op = LiouvilleOracle(b, c.psi, c.eps_mat, c.V, sub, tau)
+    X = trial_block(c, 16, seed=1234)
+    ref = op.apply(X[VECS], rows=ROWS)
+    yield pkg, c, ctx, st, pairs, sub, tau, X, ref
+    ctx.close()
+
+
+def test_pairs_match(setup):
+    pkg, c, ctx, st, pairs, *_ = setup
+    assert [tuple(p) for p in ctx.get_pairs()] == pairs
+    n = c.n_occ
+    frac = (len(pairs) - n) / (n * (n - 1) / 2)
+    assert 0.3 < frac < 0.5
+
+
+def test_tau_sampled(setup):
+    pkg, c, ctx, st, pairs, sub, tau, X, ref = setup
+    idx = {p: i for i, p in enumerate(pairs)}
+    for k in (0, len(sub) // 2, len(sub) - 1):
+        p = idx[sub[k]]
+        got = ctx.copy_tau(p, 1).cpu().numpy()[0]
+        assert rel_err(got, tau[k].reshape(-1)) < 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 2e-5), (2, 1e-4)])
+def test_apply_sampled_graph(setup, prec, tol):
+    pkg, c, ctx, st, pairs, sub, tau, X, ref = setup
+    say("fullsize apply", prec)
+    dt = torch.float64 if prec == 0 else torch.float32
+    with torch.cuda.stream(st):
+        Xd = torch.from_numpy(X).to("cuda", dtype=dt)
+        Y = torch.empty_like(Xd)
+        ctx.set_graph(True)
+        for _ in range(3):                         # capture, then replays
+            Y.fill_(float("nan"))
+            ctx.apply(Xd, Y, prec)
+        ctx.set_graph(False)
+    st.synchronize()
+    got = Y.double().cpu().numpy()
+    assert np.isfinite(got).all()
+    for k, s in enumerate(VECS):
+        assert rel_err(got[s][ROWS], ref[k][ROWS]) < tol, (s, prec)
+    # any size: the output lies in the P_c space
+    ov = np.einsum("svg,wg->svw", got, c.psi)
+    assert np.abs(ov).max() < (1e-10 if prec == 0 else 2e-4) * np.abs(got).max()
