@@ -158,6 +158,9 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tts", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 1 GiB read + 1 GiB write elementwise kernel first "
+                         "(scale reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -175,6 +178,13 @@ def main():
     esz = 8 if prec == pkg.FP64 else 4
     B = args.block
 
+    if args.calib_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        log("calibration kernel: 1 GiB read, 1 GiB written")
+        del a, b
     log("generating cell", args.cell)
     t = time.time()
     cell = make_cell(args.cell)

@@ -180,6 +180,64 @@ typedef struct {
 bse_status bse_davidson(bse_ctx *ctx, const bse_davidson_opts *opts, const double *X0,
                         double *omega, double *X, bse_davidson_stats *stats);
 
+/* ---------------------------------------------------------------- learned
+ * Learned correction of the diagonal Davidson preconditioner.  Not in the
+ * paper.  A network maps, per orbital slot v of a residual r, the packed
+ * coefficients of r_v on a window (G = 0 and the n_window_pw lowest-|G|
+ * plane waves: Kw = 1 + 2 n_window_pw values), phase-shifted to the Wannier
+ * centre of orbital v and divided by |r_v|, plus (theta - eps_vv,
+ * eps_vv - mean V, log |r_v|), to a correction of the diagonally
+ * preconditioned residual on the same window.  Davidson with precond = 1
+ * adds it behind a safeguard: a slot's correction is dropped when it is
+ * more than 10x the diagonal one on the window, a vector's corrections are
+ * all dropped when the corrected block no longer has a positive projection
+ * on its residual, and the solve returns to the diagonal preconditioner for
+ * good once a corrected step fails to lower the largest wanted residual.
+ * The converged eigenvalues are those of the operator; only the iteration
+ * count may change. */
+typedef struct bse_mlp bse_mlp;
+
+/* Network f_in -> hidden -> hidden -> k_out (ReLU), trained with Adam.
+ *   w  host FP32 flat initial weights [W1 (f_in x hidden) | b1 | W2 (hidden x
+ *      hidden) | b2 | W3 (hidden x k_out) | b3], row-major [in][out].
+ * Forward and backward run on the matrix cores with bf16 weights and
+ * activations and FP32 accumulation; Adam keeps FP32 master weights. */
+bse_status bse_mlp_create(bse_mlp **mlp, int f_in, int hidden, int k_out, const float *w,
+                          void *stream);
+bse_status bse_mlp_destroy(bse_mlp *mlp);
+long long bse_mlp_num_params(const bse_mlp *mlp);
+bse_status bse_mlp_get_weights(bse_mlp *mlp, float *w);          /* host out */
+bse_status bse_mlp_set_weights(bse_mlp *mlp, const float *w);    /* host in; resets Adam */
+/* Y dev [n][k_out] = network(X dev [n][f_in]).  Synchronises. */
+bse_status bse_mlp_forward(bse_mlp *mlp, int n, const float *X, float *Y);
+/* Gradients (host, flat like the weights) of the mean-squared error of
+ * network(X) against T dev [n][k_out]; loss (host) optional.  Synchronises. */
+bse_status bse_mlp_gradients(bse_mlp *mlp, int n, const float *X, const float *T, float *g,
+                             double *loss);
+/* Adam (lr, beta 0.9 / 0.999) on shuffled minibatches of `batch` rows for
+ * `epochs` passes; the shuffle is drawn from `seed`.  losses host [epochs]
+ * (optional): mean minibatch loss per epoch.  Synchronises. */
+bse_status bse_mlp_train(bse_mlp *mlp, int n, const float *X, const float *T, int epochs,
+                         int batch, float lr, uint64_t seed, double *losses);
+/* Attach (mlp, not owned) or detach (NULL) the network used by precond = 1;
+ * f_in must be Kw + 3 and k_out Kw for Kw = 1 + 2 n_window_pw. */
+bse_status bse_set_learned(bse_ctx *ctx, bse_mlp *mlp, int n_window_pw);
+/* Wannier centres (host [n_occ][3], bohr) of the window set-up. */
+bse_status bse_learned_centers(bse_ctx *ctx, double *centers);
+/* bse_davidson that also writes training rows: for every iteration and each
+ * of the n_eig lowest Ritz vectors x_s, the slot features (as above) and the
+ * label (alpha t*_v - M r_v) on the window (same frame and scale), where
+ * t* = sigma x*_s - sum_j x_j <x_j, sigma x*_s> is the part of the s-th
+ * reference eigenvector (Xref dev [n_ref][n_occ][n_pw], sigma aligning its
+ * sign) outside the span of the current Ritz vectors x_j, and alpha the
+ * least-squares scale of t* onto the diagonal correction M r.
+ *   feat  dev [max_rows][Kw + 3] FP32,  label dev [max_rows][Kw] FP32
+ *   n_rows host out: rows written (recording stops when full). */
+bse_status bse_davidson_record(bse_ctx *ctx, const bse_davidson_opts *opts, const double *X0,
+                               const double *Xref, int n_ref, int n_window_pw, float *feat,
+                               float *label, int64_t max_rows, int64_t *n_rows, double *omega,
+                               double *X, bse_davidson_stats *stats);
+
 const char *bse_status_str(bse_status s);
 const char *bse_last_error(void);
 

@@ -220,6 +220,36 @@ bse_status bse_davidson(bse_ctx *c, const bse_davidson_opts *opts, const double 
     BSE_GUARD(bse::ctx_davidson(c, opts, X0, omega, X, stats))
 }
 
+bse_status bse_davidson_record(bse_ctx *c, const bse_davidson_opts *opts, const double *X0,
+                               const double *Xref, int n_ref, int n_window_pw, float *feat,
+                               float *label, int64_t max_rows, int64_t *n_rows, double *omega,
+                               double *X, bse_davidson_stats *stats) {
+    CHECK_CTX(c);
+    if (!opts || !X0 || !Xref || !feat || !label || !n_rows || !omega || !X || n_ref < 1 ||
+        max_rows < 0) {
+        set_error("bse_davidson_record: bad argument");
+        return BSE_ERR_ARG;
+    }
+    BSE_GUARD({
+        if (c->lp.nwg != n_window_pw) bse::learned_setup(c, n_window_pw);
+        bse::RecordSpec r;
+        r.Xref = Xref;
+        r.n_ref = n_ref;
+        r.feat = feat;
+        r.lab = label;
+        r.max_rows = max_rows;
+        r.n_rows = 0;
+        bse_status st = BSE_OK;
+        try {
+            bse::ctx_davidson(c, opts, X0, omega, X, stats, &r);
+        } catch (const Err &e) {
+            st = e.st;
+        }
+        *n_rows = r.n_rows;
+        if (st != BSE_OK) throw Err{st};
+    })
+}
+
 const char *bse_status_str(bse_status s) {
     switch (s) {
         case BSE_OK: return "ok";

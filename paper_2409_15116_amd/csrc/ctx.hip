@@ -435,7 +435,7 @@ static void ensure_ws(bse_ctx *c, ApplyWs<T> &w, int nvec) {
     if (w.cap >= nvec) return;
     const size_t no = c->n_occ, nr = c->nr, n = c->n;
     const size_t norb = (size_t)nvec * no;
-    const size_t nq = (norb + 1) / 2;
+    const size_t nq = (size_t)((nvec + 1) / 2) * no;  // trial-vector pairs x orbital slots
     w.Ar.alloc(norb * nr);
     w.Cr.alloc(norb * nr);
     w.S.alloc(norb * no);
@@ -491,7 +491,7 @@ static void apply_impl(bse_ctx *c, int nvec, const T *X, T *Y, bool bf, hipEvent
     };
     rec(0);
     // a1: sphere -> grid for every (s, v)
-    sph_inverse<T>(c->maps, X, norb, w.Ar.p, w.T1.p, w.T2.p, tw, st, ev ? ev + 1 : nullptr);
+    sph_inverse<T>(c->maps, X, norb, w.Ar.p, w.T1.p, w.T2.p, tw, st, ev ? ev + 1 : nullptr, no);
     // a4 (+ V a of a2, + the K1e density of a3)
     k1d_apply<T>(w.Ar.p, tau, V, u, c->csr, no, nvec, nr, (T)c->k1d, (T)(1.0 / c->omega), w.Cr.p,
                  w.Hc.p, w.Dp.p, st);

@@ -5,6 +5,8 @@
 #include <vector>
 
 #include "fft.hpp"
+
+struct bse_mlp;
 #include "kernels.hpp"
 
 namespace bse {
@@ -47,12 +49,24 @@ struct ApplyWs {
 };
 
 struct LearnedPre {
-    bool loaded = false;
-    int K = 0;                 // window of low-|G| packed coefficients
-    Dev<unsigned short> W1, W2, W3;   // bf16 weights, [in][out]
-    Dev<float> b1, b2, b3;
-    Dev<int> win;              // packed indices of the window
-    Dev<float> feat, h1, h2, out;
+    bse_mlp *net = nullptr;    // attached network (not owned)
+    int nwg = 0;               // window: G = 0 and the nwg lowest-|G| plane waves
+    Dev<int> wk;               // half-space index of each window plane wave
+    Dev<double> wg;            // its G vector (bohr^-1)
+    Dev<double> cen;           // Wannier centres [n_occ][3] (bohr)
+    std::vector<double> cen_h;
+    Dev<double> rn2, part, D, stats;
+    Dev<float> feat, out;
+    Dev<int> ok;
+};
+
+struct RecordSpec {
+    const double *Xref = nullptr;  // dev [n_ref][n_occ * npw] converged eigenvectors
+    int n_ref = 0;
+    float *feat = nullptr;         // dev [max_rows][Kw + 3]
+    float *lab = nullptr;          // dev [max_rows][Kw]
+    long long max_rows = 0;
+    long long n_rows = 0;
 };
 
 }  // namespace bse
@@ -119,7 +133,12 @@ void ctx_profile_apply(bse_ctx *c, int n_vec, const void *in, void *out, int pre
                        double *ms);
 void ctx_project_c64(bse_ctx *c, int n_vec, double *Y);
 void ctx_davidson(bse_ctx *c, const bse_davidson_opts *o, const double *X0, double *omega,
-                  double *X, bse_davidson_stats *stats);
+                  double *X, bse_davidson_stats *stats, RecordSpec *rec = nullptr);
+void learned_setup(bse_ctx *c, int nwg);
+void learned_record(bse_ctx *c, const double *X, const double *R, const double *theta,
+                    const double *Tn, int n_rec, int n_ritz, const double *Xref, int n_ref,
+                    Workspace &ws, float *feat, float *lab, long long max_rows,
+                    long long *n_rows);
 void learned_correction(bse_ctx *c, const double *R, const double *theta, int k, double *Tn,
                         int *used, int *rejected);
 }  // namespace bse

@@ -193,7 +193,7 @@ static void apply_block(DavState &s, int k, const double *in, double *out, int p
 }
 
 void ctx_davidson(bse_ctx *c, const bse_davidson_opts *o, const double *X0, double *omega,
-                  double *Xout, bse_davidson_stats *stats) {
+                  double *Xout, bse_davidson_stats *stats, RecordSpec *rec) {
     const auto t0 = std::chrono::steady_clock::now();
     const int B = o->block, ne = o->n_eig;
     BSE_REQUIRE(ne >= 1 && ne <= B && B <= 64, BSE_ERR_ARG, "need 1 <= n_eig <= block <= 64");
@@ -246,6 +246,9 @@ void ctx_davidson(bse_ctx *c, const bse_davidson_opts *o, const double *X0, doub
     int it = 0;
     bse_status result = BSE_ERR_NOCONV;
     int kr = 0;
+    bool learned_on = o->precond == 1 && c->lp.net != nullptr;
+    bool learned_last = false;
+    double res_prev = INFINITY;
     for (it = 1; it <= o->max_iter; ++it) {
         std::vector<double> T = gram(s, nb, s.V.p, nb, s.W.p);
         for (int i = 0; i < nb; ++i)
@@ -279,8 +282,19 @@ void ctx_davidson(bse_ctx *c, const bse_davidson_opts *o, const double *X0, doub
         // preconditioned residuals
         precond_diag(s.R.p, s.theta.p, c->kin.p, c->epsd.p, c->vbar, delta, c->n_occ, c->npw, kr,
                      s.Tn.p, c->stream);
-        if (o->precond == 1 && c->lp.loaded) learned_correction(c, s.R.p, s.theta.p, kr, s.Tn.p,
-                                                                &used, &rejected);
+        if (rec)
+            learned_record(c, s.X.p, s.R.p, s.theta.p, s.Tn.p, std::min(ne, kr), kr, rec->Xref,
+                           rec->n_ref, c->gws, rec->feat, rec->lab, rec->max_rows, &rec->n_rows);
+        // learned correction; the diagonal preconditioner takes over for good
+        // once a corrected step fails to lower the largest wanted residual
+        const double res_max = *std::max_element(rn.begin(), rn.begin() + ne);
+        if (learned_last && !(res_max < res_prev)) learned_on = false;
+        res_prev = res_max;
+        learned_last = false;
+        if (learned_on) {
+            learned_correction(c, s.R.p, s.theta.p, kr, s.Tn.p, &used, &rejected);
+            learned_last = true;
+        }
         ctx_project_c64(c, kr, s.Tn.p);
         if (nb + kr > maxb) {
             const int m = std::min(rst, nb);

@@ -62,59 +62,81 @@ __device__ inline void bfly5(C2 *v, T s) {
     v[3] = csub(a2, b2);
 }
 
-template <int R, typename T>
+constexpr int fft_nfactors(int n) {
+    int c = 0;
+    const int order[4] = {4, 2, 3, 5};
+    for (int i = 0; i < 4; ++i)
+        while (n % order[i] == 0) {
+            n /= order[i];
+            ++c;
+        }
+    return c;
+}
+constexpr int fft_factor(int n, int at) {
+    int c = 0;
+    const int order[4] = {4, 2, 3, 5};
+    for (int i = 0; i < 4; ++i)
+        while (n % order[i] == 0) {
+            if (c == at) return order[i];
+            n /= order[i];
+            ++c;
+        }
+    return 1;
+}
+
+// One Stockham stage of radix R for lines of compile-time length N after
+// stages whose radices multiply to NS; C (a power of two, 1 << lc) lines in
+// LDS at addr = e * C + c.
+template <int R, int N, int NS, typename T>
 __device__ inline void stage(const cplx<T> *__restrict__ src, cplx<T> *__restrict__ dst,
-                             const cplx<T> *__restrict__ tw, int n, int Ns, int C, T sign) {
+                             const cplx<T> *__restrict__ tw, int lc, T sign) {
     using C2 = cplx<T>;
-    const int nR = n / R;
-    const int twstep = n / (Ns * R);
-    const int total = nR * C;
+    constexpr int nR = N / R;
+    constexpr int twstep = N / (NS * R);
+    const int C = 1 << lc;
+    const int total = nR << lc;
     for (int b = threadIdx.x; b < total; b += blockDim.x) {
-        const int j = b / C;
-        const int c = b - j * C;
-        const int k = j % Ns;
+        const int j = b >> lc;
+        const int c = b & (C - 1);
+        const int k = j % NS;
         C2 v[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = src[(j + r * nR) * C + c];
-        const int base = k * twstep;
+        for (int r = 0; r < R; ++r) v[r] = src[((j + r * nR) << lc) + c];
+        const int base = k * twstep;  // r * base < N
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-            C2 w = tw[(r * base) % n];
-            w.y *= -sign;  // table holds exp(-2 pi i m / n); inverse takes the conjugate
+            C2 w = tw[r * base];
+            w.y *= -sign;  // table holds exp(-2 pi i m / N); inverse takes the conjugate
             v[r] = cmul(v[r], w);
         }
         if (R == 2) bfly2<C2, T>(v, sign);
         if (R == 3) bfly3<C2, T>(v, sign);
         if (R == 4) bfly4<C2, T>(v, sign);
         if (R == 5) bfly5<C2, T>(v, sign);
-        const int idxD = (j / Ns) * Ns * R + k;
+        const int idxD = (j / NS) * NS * R + k;
 #pragma unroll
-        for (int r = 0; r < R; ++r) dst[(idxD + r * Ns) * C + c] = v[r];
+        for (int r = 0; r < R; ++r) dst[((idxD + r * NS) << lc) + c] = v[r];
     }
 }
 
-// FFT of C lines held in LDS buffer a (layout e*C + c); b is scratch of the
-// same size.  sign = -1 forward, +1 inverse (unnormalised).  Returns the
-// buffer holding the result.  Ends with a barrier.
-template <typename T>
-__device__ cplx<T> *lds_fft(cplx<T> *a, cplx<T> *b, const cplx<T> *tw, const FftPlan &pl, int C,
-                            T sign) {
-    int Ns = 1;
-    for (int st = 0; st < pl.nst; ++st) {
-        const int R = pl.radix[st];
-        switch (R) {
-            case 2: stage<2, T>(a, b, tw, pl.n, Ns, C, sign); break;
-            case 3: stage<3, T>(a, b, tw, pl.n, Ns, C, sign); break;
-            case 4: stage<4, T>(a, b, tw, pl.n, Ns, C, sign); break;
-            default: stage<5, T>(a, b, tw, pl.n, Ns, C, sign); break;
-        }
+template <typename T, int N, int ST, int NS>
+__device__ inline cplx<T> *fft_stages(cplx<T> *a, cplx<T> *b, const cplx<T> *tw, int lc, T sign) {
+    if constexpr (ST < fft_nfactors(N)) {
+        constexpr int R = fft_factor(N, ST);
+        stage<R, N, NS, T>(a, b, tw, lc, sign);
         __syncthreads();
-        cplx<T> *t = a;
-        a = b;
-        b = t;
-        Ns *= R;
+        return fft_stages<T, N, ST + 1, NS * R>(b, a, tw, lc, sign);
+    } else {
+        return a;
     }
-    return a;
+}
+
+// FFT of 1 << lc lines of length N held in LDS buffer a (layout e*C + c); b is
+// scratch of the same size.  sign = -1 forward, +1 inverse (unnormalised).
+// Returns the buffer holding the result.  Ends with a barrier.
+template <typename T, int N>
+__device__ cplx<T> *lds_fft(cplx<T> *a, cplx<T> *b, const cplx<T> *tw, int lc, T sign) {
+    return fft_stages<T, N, 0, 1>(a, b, tw, lc, sign);
 }
 
 template <typename T>
@@ -122,19 +144,28 @@ __device__ inline void load_twiddles(cplx<T> *tw_lds, const cplx<T> *tw, int n) 
     for (int i = threadIdx.x; i < n; i += blockDim.x) tw_lds[i] = tw[i];
 }
 
+// Pairing of real orbitals into complex transforms: line q holds orbitals
+// o1 = (q / ps) * 2 ps + q % ps and o2 = o1 + ps (ps = 1: neighbours; ps =
+// n_occ: the same orbital slot of two consecutive trial vectors).
+__device__ inline void pair_of(int q, int ps, int &o1, int &o2) {
+    const int g = q / ps;
+    o1 = g * 2 * ps + (q - g * ps);
+    o2 = o1 + ps;
+}
+
 // ============================================================ sphere -> grid
 // z-lines of the columns that hold sphere points.  Line L = q * ncol + col.
-template <typename T>
+template <typename T, int N>
 __global__ void __launch_bounds__(256) k_sph_inv_z(const T *__restrict__ X, int n_orb, int npw,
                                                    const int2 *__restrict__ ent,
                                                    const int *__restrict__ col_ptr, int ncol,
                                                    int n_lines, cplx<T> *__restrict__ T1,
-                                                   const cplx<T> *__restrict__ tw, FftPlan pl,
-                                                   int C) {
+                                                   const cplx<T> *__restrict__ tw, int lc, int ps) {
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
-    const int n = pl.n;
+    constexpr int n = N;
+    const int C = 1 << lc;
     C2 *sb = sa + n * C;
     C2 *stw = sb + n * C;
     load_twiddles<T>(stw, tw, n);
@@ -147,7 +178,8 @@ __global__ void __launch_bounds__(256) k_sph_inv_z(const T *__restrict__ X, int 
         const int L = L0 + c;
         if (L >= n_lines) break;
         const int q = L / ncol, col = L - q * ncol;
-        const int o1 = 2 * q, o2 = 2 * q + 1;
+        int o1, o2;
+        pair_of(q, ps, o1, o2);
         const T *x1 = X + (size_t)o1 * npw;
         const T *x2 = X + (size_t)o2 * npw;
         const bool has2 = o2 < n_orb;
@@ -168,7 +200,7 @@ __global__ void __launch_bounds__(256) k_sph_inv_z(const T *__restrict__ X, int 
         }
     }
     __syncthreads();
-    C2 *res = lds_fft<T>(sa, sb, stw, pl, C, (T)1);
+    C2 *res = lds_fft<T, N>(sa, sb, stw, lc, (T)1);
     for (int i = threadIdx.x; i < n * C; i += blockDim.x) {
         const int c = i / n, z = i - c * n;
         const int L = L0 + c;
@@ -177,16 +209,16 @@ __global__ void __launch_bounds__(256) k_sph_inv_z(const T *__restrict__ X, int 
 }
 
 // y-lines of the x-planes that hold sphere points.  Block: (q, ix, z-tile).
-template <typename T>
+template <typename T, int N>
 __global__ void __launch_bounds__(256) k_sph_inv_y(const cplx<T> *__restrict__ T1,
                                                    const int *__restrict__ colmap,
                                                    const int *__restrict__ xlist, int nxp, int ncol,
                                                    cplx<T> *__restrict__ T2,
-                                                   const cplx<T> *__restrict__ tw, FftPlan pl,
-                                                   int C, int nzt) {
+                                                   const cplx<T> *__restrict__ tw, int lc, int nzt) {
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
-    const int n = pl.n;
+    constexpr int n = N;
+    const int C = 1 << lc;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
     C2 *sb = sa + n * C;
     C2 *stw = sb + n * C;
@@ -206,7 +238,7 @@ __global__ void __launch_bounds__(256) k_sph_inv_y(const cplx<T> *__restrict__ T
         sa[i] = (col >= 0 && z < n) ? t1[(size_t)col * n + z] : cmake<C2>(0, 0);
     }
     __syncthreads();
-    C2 *res = lds_fft<T>(sa, sb, stw, pl, C, (T)1);
+    C2 *res = lds_fft<T, N>(sa, sb, stw, lc, (T)1);
     C2 *t2 = T2 + ((size_t)q * nxp + ix) * n * n;
     for (int i = threadIdx.x; i < n * C; i += blockDim.x) {
         const int y = i / C, c = i - y * C;
@@ -216,15 +248,16 @@ __global__ void __launch_bounds__(256) k_sph_inv_y(const cplx<T> *__restrict__ T
 }
 
 // Full x-lines, then split a + i b into two real orbitals on the grid.
-template <typename T>
+template <typename T, int N>
 __global__ void __launch_bounds__(256) k_sph_inv_x(const cplx<T> *__restrict__ T2,
                                                    const int *__restrict__ xinv, int nxp,
                                                    int n_orb, T *__restrict__ out,
-                                                   const cplx<T> *__restrict__ tw, FftPlan pl,
-                                                   int C, int nyzt) {
+                                                   const cplx<T> *__restrict__ tw, int lc, int nyzt,
+                                                   int ps) {
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
-    const int n = pl.n;
+    constexpr int n = N;
+    const int C = 1 << lc;
     const int n2 = n * n;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
     C2 *sb = sa + n * C;
@@ -241,11 +274,13 @@ __global__ void __launch_bounds__(256) k_sph_inv_x(const cplx<T> *__restrict__ T
         sa[i] = (ix >= 0 && yz < n2) ? t2[(size_t)ix * n2 + yz] : cmake<C2>(0, 0);
     }
     __syncthreads();
-    C2 *res = lds_fft<T>(sa, sb, stw, pl, C, (T)1);
+    C2 *res = lds_fft<T, N>(sa, sb, stw, lc, (T)1);
     const size_t nr = (size_t)n2 * n;
-    T *o1 = out + (size_t)(2 * q) * nr;
-    T *o2 = out + (size_t)(2 * q + 1) * nr;
-    const bool has2 = 2 * q + 1 < n_orb;
+    int i1, i2;
+    pair_of(q, ps, i1, i2);
+    T *o1 = out + (size_t)i1 * nr;
+    T *o2 = out + (size_t)i2 * nr;
+    const bool has2 = i2 < n_orb;
     for (int i = threadIdx.x; i < n * C; i += blockDim.x) {
         const int x = i / C, c = i - x * C;
         const int yz = yz0 + c;
@@ -257,54 +292,56 @@ __global__ void __launch_bounds__(256) k_sph_inv_x(const cplx<T> *__restrict__ T
 }
 
 // ============================================================ grid -> sphere
-// x-lines of f_o(r) = Cr_o(r) + k1e u_v(r) vH_s(r) for two orbitals o = 2q, 2q+1
-// (o = s * n_occ + v), keeping only the x-frequencies of the sphere.
-template <typename T>
+// x-lines of f_o(r) = Cr_o(r) + k1e u_v(r) vH_s(r) for the two orbitals
+// o1 = (s, v), o2 = (s + 1, v) of line q (s even, o = s * n_occ + v), read as
+// one complex expression (Cr_o1 + i Cr_o2) + k1e u_v (vH_s + i vH_{s+1}):
+// the Hartree grid of a trial-vector pair is one complex grid, and u_v is
+// read once for both.  Only the x-frequencies of the sphere are kept.
+template <typename T, int N>
 __global__ void __launch_bounds__(256) k_sph_fwd_x(const T *__restrict__ Cr, const T *__restrict__ u,
                                                    const cplx<T> *__restrict__ vH, T k1e,
                                                    int n_orb, int n_occ, const int *__restrict__ xlist,
                                                    int nxp, cplx<T> *__restrict__ T2,
-                                                   const cplx<T> *__restrict__ tw, FftPlan pl, int C,
+                                                   const cplx<T> *__restrict__ tw, int lc,
                                                    int nyzt) {
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
-    const int n = pl.n;
+    constexpr int n = N;
+    const int C = 1 << lc;
     const int n2 = n * n;
     const size_t nr = (size_t)n2 * n;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
     C2 *sb = sa + n * C;
     C2 *stw = sb + n * C;
     load_twiddles<T>(stw, tw, n);
-    const int t = blockIdx.x % nyzt;
-    const int q = blockIdx.x / nyzt;
+    // q fastest: the orbital slots sharing one Hartree tile run back to back
+    const int nq = gridDim.x / nyzt;
+    const int q = blockIdx.x % nq;
+    const int t = blockIdx.x / nq;
     const int yz0 = t * C;
-    const int o1 = 2 * q, o2 = 2 * q + 1;
+    int o1, o2;
+    pair_of(q, n_occ, o1, o2);
     const bool has2 = o2 < n_orb;
-    const int s1 = o1 / n_occ, v1 = o1 - s1 * n_occ;
-    const int s2 = o2 / n_occ, v2 = o2 - s2 * n_occ;
+    const int s1 = o1 / n_occ, v = o1 - s1 * n_occ;  // s1 even
     const T *c1 = Cr + (size_t)o1 * nr;
     const T *c2 = Cr + (size_t)o2 * nr;
-    const T *u1 = u + (size_t)v1 * nr;
-    const T *u2 = u + (size_t)v2 * nr;
-    const C2 *h1 = vH + (size_t)(s1 >> 1) * nr;
-    const C2 *h2 = vH + (size_t)(s2 >> 1) * nr;
+    const T *uv = u + (size_t)v * nr;
+    const C2 *h = vH + (size_t)(s1 >> 1) * nr;
     for (int i = threadIdx.x; i < n * C; i += blockDim.x) {
         const int x = i / C, c = i - x * C;
         const int yz = yz0 + c;
         C2 val = cmake<C2>(0, 0);
         if (yz < n2) {
             const size_t r = (size_t)x * n2 + yz;
-            const C2 hv1 = h1[r];
-            val.x = c1[r] + k1e * u1[r] * ((s1 & 1) ? hv1.y : hv1.x);
-            if (has2) {
-                const C2 hv2 = h2[r];
-                val.y = c2[r] + k1e * u2[r] * ((s2 & 1) ? hv2.y : hv2.x);
-            }
+            const C2 hv = h[r];
+            const T ku = k1e * uv[r];
+            val.x = c1[r] + ku * hv.x;
+            val.y = has2 ? c2[r] + ku * hv.y : (T)0;
         }
         sa[i] = val;
     }
     __syncthreads();
-    C2 *res = lds_fft<T>(sa, sb, stw, pl, C, (T)-1);
+    C2 *res = lds_fft<T, N>(sa, sb, stw, lc, (T)-1);
     C2 *t2 = T2 + (size_t)q * nxp * n2;
     for (int i = threadIdx.x; i < nxp * C; i += blockDim.x) {
         const int ix = i / C, c = i - ix * C;
@@ -314,16 +351,16 @@ __global__ void __launch_bounds__(256) k_sph_fwd_x(const T *__restrict__ Cr, con
 }
 
 // y-lines of each sphere x-plane, keeping the columns of the sphere.
-template <typename T>
+template <typename T, int N>
 __global__ void __launch_bounds__(256) k_sph_fwd_y(const cplx<T> *__restrict__ T2,
                                                    const int *__restrict__ colmap,
                                                    const int *__restrict__ xlist, int nxp, int ncol,
                                                    cplx<T> *__restrict__ T1,
-                                                   const cplx<T> *__restrict__ tw, FftPlan pl,
-                                                   int C, int nzt) {
+                                                   const cplx<T> *__restrict__ tw, int lc, int nzt) {
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
-    const int n = pl.n;
+    constexpr int n = N;
+    const int C = 1 << lc;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
     C2 *sb = sa + n * C;
     C2 *stw = sb + n * C;
@@ -342,7 +379,7 @@ __global__ void __launch_bounds__(256) k_sph_fwd_y(const cplx<T> *__restrict__ T
         sa[i] = (z < n) ? t2[(size_t)y * n + z] : cmake<C2>(0, 0);
     }
     __syncthreads();
-    C2 *res = lds_fft<T>(sa, sb, stw, pl, C, (T)-1);
+    C2 *res = lds_fft<T, N>(sa, sb, stw, lc, (T)-1);
     C2 *t1 = T1 + (size_t)q * ncol * n;
     for (int i = threadIdx.x; i < n * C; i += blockDim.x) {
         const int y = i / C, c = i - y * C;
@@ -355,7 +392,7 @@ __global__ void __launch_bounds__(256) k_sph_fwd_y(const cplx<T> *__restrict__ T
 // z-lines of the sphere columns; extract the two real orbitals' packed
 // coefficients (Gamma reality: F(G) and F(-G) of a + i b), scale by 1/N_r,
 // add the kinetic term 1/2|G|^2 X.  Tiles hold a column and its mirror.
-template <typename T>
+template <typename T, int N>
 __global__ void __launch_bounds__(256) k_sph_fwd_z(const cplx<T> *__restrict__ T1,
                                                    const int2 *__restrict__ ent,
                                                    const int *__restrict__ col_ptr, int ncol,
@@ -363,10 +400,11 @@ __global__ void __launch_bounds__(256) k_sph_fwd_z(const cplx<T> *__restrict__ T
                                                    const T *__restrict__ X,
                                                    const double *__restrict__ kin, T kin_scale,
                                                    T *__restrict__ Y, const cplx<T> *__restrict__ tw,
-                                                   FftPlan pl, int C) {
+                                                   int lc, int ps) {
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
-    const int n = pl.n;
+    constexpr int n = N;
+    const int C = 1 << lc;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
     C2 *sb = sa + n * C;
     C2 *stw = sb + n * C;
@@ -378,7 +416,7 @@ __global__ void __launch_bounds__(256) k_sph_fwd_z(const cplx<T> *__restrict__ T
         sa[z * C + c] = (L < n_lines) ? T1[(size_t)L * n + z] : cmake<C2>(0, 0);
     }
     __syncthreads();
-    C2 *res = lds_fft<T>(sa, sb, stw, pl, C, (T)-1);
+    C2 *res = lds_fft<T, N>(sa, sb, stw, lc, (T)-1);
     const T inv_nr = (T)1 / ((T)n * (T)n * (T)n);
     const T sq2 = (T)1.41421356237309504880;
     const int nwave = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -388,7 +426,8 @@ __global__ void __launch_bounds__(256) k_sph_fwd_z(const cplx<T> *__restrict__ T
         const int q = L / ncol, col = L - q * ncol;
         const int mcol = col < 2 ? col : (col ^ 1);
         const int cm = c + (mcol - col);
-        const int o1 = 2 * q, o2 = 2 * q + 1;
+        int o1, o2;
+        pair_of(q, ps, o1, o2);
         const bool has2 = o2 < n_orb;
         T *y1 = Y + (size_t)o1 * npw;
         T *y2 = Y + (size_t)o2 * npw;
@@ -422,13 +461,14 @@ __global__ void __launch_bounds__(256) k_sph_fwd_z(const cplx<T> *__restrict__ T
 
 // ============================================================ full grid, in place
 // axis 2 (z): contiguous lines; line L = b * n^2 + (x * n + y)
-template <typename T>
+template <typename T, int N>
 __global__ void __launch_bounds__(256) k_grid_z(cplx<T> *__restrict__ A, int n_lines,
-                                                const cplx<T> *__restrict__ tw, FftPlan pl, int C,
+                                                const cplx<T> *__restrict__ tw, int lc,
                                                 T sign) {
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
-    const int n = pl.n;
+    constexpr int n = N;
+    const int C = 1 << lc;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
     C2 *sb = sa + n * C;
     C2 *stw = sb + n * C;
@@ -440,7 +480,7 @@ __global__ void __launch_bounds__(256) k_grid_z(cplx<T> *__restrict__ A, int n_l
         sa[z * C + c] = (L < n_lines) ? A[(size_t)L * n + z] : cmake<C2>(0, 0);
     }
     __syncthreads();
-    C2 *res = lds_fft<T>(sa, sb, stw, pl, C, sign);
+    C2 *res = lds_fft<T, N>(sa, sb, stw, lc, sign);
     for (int i = threadIdx.x; i < n * C; i += blockDim.x) {
         const int c = i / n, z = i - c * n;
         const int L = L0 + c;
@@ -449,13 +489,14 @@ __global__ void __launch_bounds__(256) k_grid_z(cplx<T> *__restrict__ A, int n_l
 }
 
 // axis 1 (y): block (b, x, z-tile)
-template <typename T>
+template <typename T, int N>
 __global__ void __launch_bounds__(256) k_grid_y(cplx<T> *__restrict__ A,
-                                                const cplx<T> *__restrict__ tw, FftPlan pl, int C,
+                                                const cplx<T> *__restrict__ tw, int lc,
                                                 int nzt, T sign) {
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
-    const int n = pl.n;
+    constexpr int n = N;
+    const int C = 1 << lc;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
     C2 *sb = sa + n * C;
     C2 *stw = sb + n * C;
@@ -470,7 +511,7 @@ __global__ void __launch_bounds__(256) k_grid_y(cplx<T> *__restrict__ A,
         sa[i] = (z < n) ? p[(size_t)y * n + z] : cmake<C2>(0, 0);
     }
     __syncthreads();
-    C2 *res = lds_fft<T>(sa, sb, stw, pl, C, sign);
+    C2 *res = lds_fft<T, N>(sa, sb, stw, lc, sign);
     for (int i = threadIdx.x; i < n * C; i += blockDim.x) {
         const int y = i / C, c = i - y * C;
         const int z = z0 + c;
@@ -479,13 +520,14 @@ __global__ void __launch_bounds__(256) k_grid_y(cplx<T> *__restrict__ A,
 }
 
 // axis 0 (x): block (b, yz-tile)
-template <typename T>
+template <typename T, int N>
 __global__ void __launch_bounds__(256) k_grid_x(cplx<T> *__restrict__ A,
-                                                const cplx<T> *__restrict__ tw, FftPlan pl, int C,
+                                                const cplx<T> *__restrict__ tw, int lc,
                                                 int nyzt, T sign) {
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
-    const int n = pl.n;
+    constexpr int n = N;
+    const int C = 1 << lc;
     const int n2 = n * n;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
     C2 *sb = sa + n * C;
@@ -501,7 +543,7 @@ __global__ void __launch_bounds__(256) k_grid_x(cplx<T> *__restrict__ A,
         sa[i] = (yz < n2) ? p[(size_t)x * n2 + yz] : cmake<C2>(0, 0);
     }
     __syncthreads();
-    C2 *res = lds_fft<T>(sa, sb, stw, pl, C, sign);
+    C2 *res = lds_fft<T, N>(sa, sb, stw, lc, sign);
     for (int i = threadIdx.x; i < n * C; i += blockDim.x) {
         const int x = i / C, c = i - x * C;
         const int yz = yz0 + c;
@@ -523,48 +565,128 @@ FftPlan make_plan(int n) {
         }
     }
     BSE_REQUIRE(m == 1, BSE_ERR_ARG, "grid size %d is not a product of 2, 3 and 5", n);
+    bool ok = false;
+#define BSE_N_CHECK(NN) ok = ok || n == NN;
+    BSE_FFT_SIZES(BSE_N_CHECK)
+#undef BSE_N_CHECK
+    BSE_REQUIRE(ok, BSE_ERR_ARG, "grid size %d is not one of the compiled FFT lengths", n);
     return p;
 }
 
 static size_t lds_bytes(int n, int C, size_t esz) { return (size_t)(2 * n * C + n) * esz; }
 
-// lines per workgroup: as many as fit a 64 KB (or 96 KB) tile, at most 64
+// lines per workgroup: a power of two, as many as fit a 64 KB tile, at most cap
 int fft_tile(int n, size_t esz, int cap) {
     int C = cap;
     while (C > 2 && lds_bytes(n, C, esz) > 64 * 1024) C /= 2;
     return C;
 }
+static int ilog2(int c) {
+    int l = 0;
+    while ((1 << l) < c) ++l;
+    return l;
+}
 
-template <typename T>
-void sph_inverse(const SphereMaps &m, const T *X, int n_orb, T *out, cplx<T> *T1, cplx<T> *T2,
-                 const cplx<T> *tw, hipStream_t st, hipEvent_t *ev) {
+static int n_lines_for(int n_orb, int ps) {
+    return (int)div_up((size_t)n_orb, (size_t)2 * ps) * ps;
+}
+
+template <typename T, int N>
+static void sph_inverse_n(const SphereMaps &m, const T *X, int n_orb, T *out, cplx<T> *T1,
+                          cplx<T> *T2, const cplx<T> *tw, hipStream_t st, hipEvent_t *ev, int ps) {
     using C2 = cplx<T>;
-    const int n = m.n;
-    const int nq = (n_orb + 1) / 2;
+    constexpr int n = N;
+    const int nq = n_lines_for(n_orb, ps);
     const size_t esz = sizeof(C2);
+    const int C = fft_tile(n, esz, 64);  // even, so a column and its mirror share a tile
+    const int lc = ilog2(C);
     {
-        const int C = fft_tile(n, esz, 64);  // even, so a column and its mirror share a tile
         const int n_lines = nq * m.ncol;
-        k_sph_inv_z<T><<<div_up(n_lines, C), 256, lds_bytes(n, C, esz), st>>>(
-            X, n_orb, m.npw, m.ent, m.col_ptr, m.ncol, n_lines, T1, tw, m.plan, C);
+        k_sph_inv_z<T, N><<<div_up(n_lines, C), 256, lds_bytes(n, C, esz), st>>>(
+            X, n_orb, m.npw, m.ent, m.col_ptr, m.ncol, n_lines, T1, tw, lc, ps);
         BSE_LAUNCH_CHECK();
         if (ev) BSE_HIP(hipEventRecord(ev[0], st));
     }
     {
-        const int C = fft_tile(n, esz, 64);
         const int nzt = div_up(n, C);
-        k_sph_inv_y<T><<<(unsigned)nq * m.nxp * nzt, 256, lds_bytes(n, C, esz), st>>>(
-            T1, m.colmap, m.xlist, m.nxp, m.ncol, T2, tw, m.plan, C, nzt);
+        k_sph_inv_y<T, N><<<(unsigned)nq * m.nxp * nzt, 256, lds_bytes(n, C, esz), st>>>(
+            T1, m.colmap, m.xlist, m.nxp, m.ncol, T2, tw, lc, nzt);
         BSE_LAUNCH_CHECK();
         if (ev) BSE_HIP(hipEventRecord(ev[1], st));
     }
     {
-        const int C = fft_tile(n, esz, 64);
         const int nyzt = div_up((size_t)n * n, C);
-        k_sph_inv_x<T><<<(unsigned)nq * nyzt, 256, lds_bytes(n, C, esz), st>>>(
-            T2, m.xinv, m.nxp, n_orb, out, tw, m.plan, C, nyzt);
+        k_sph_inv_x<T, N><<<(unsigned)nq * nyzt, 256, lds_bytes(n, C, esz), st>>>(
+            T2, m.xinv, m.nxp, n_orb, out, tw, lc, nyzt, ps);
         BSE_LAUNCH_CHECK();
         if (ev) BSE_HIP(hipEventRecord(ev[2], st));
+    }
+}
+
+template <typename T, int N>
+static void sph_forward_n(const SphereMaps &m, const T *Cr, const T *u, const cplx<T> *vH, T k1e,
+                          int n_orb, int n_occ, const T *X, T kin_scale, T *Y, cplx<T> *T1,
+                          cplx<T> *T2, const cplx<T> *tw, hipStream_t st, hipEvent_t *ev) {
+    using C2 = cplx<T>;
+    constexpr int n = N;
+    const int nq = n_lines_for(n_orb, n_occ);
+    const size_t esz = sizeof(C2);
+    const int C = fft_tile(n, esz, 64);
+    const int lc = ilog2(C);
+    {
+        const int nyzt = div_up((size_t)n * n, C);
+        k_sph_fwd_x<T, N><<<(unsigned)nq * nyzt, 256, lds_bytes(n, C, esz), st>>>(
+            Cr, u, vH, k1e, n_orb, n_occ, m.xlist, m.nxp, T2, tw, lc, nyzt);
+        BSE_LAUNCH_CHECK();
+        if (ev) BSE_HIP(hipEventRecord(ev[0], st));
+    }
+    {
+        const int nzt = div_up(n, C);
+        k_sph_fwd_y<T, N><<<(unsigned)nq * m.nxp * nzt, 256, lds_bytes(n, C, esz), st>>>(
+            T2, m.colmap, m.xlist, m.nxp, m.ncol, T1, tw, lc, nzt);
+        BSE_LAUNCH_CHECK();
+        if (ev) BSE_HIP(hipEventRecord(ev[1], st));
+    }
+    {
+        const int n_lines = nq * m.ncol;
+        k_sph_fwd_z<T, N><<<div_up(n_lines, C), 256, lds_bytes(n, C, esz), st>>>(
+            T1, m.ent, m.col_ptr, m.ncol, n_lines, n_orb, m.npw, X, m.kin, kin_scale, Y, tw, lc,
+            n_occ);
+        BSE_LAUNCH_CHECK();
+        if (ev) BSE_HIP(hipEventRecord(ev[2], st));
+    }
+}
+
+template <typename T, int N>
+static void grid_fft_n(cplx<T> *A, int nb, T sign, const cplx<T> *tw, hipStream_t st) {
+    using C2 = cplx<T>;
+    constexpr int n = N;
+    const size_t esz = sizeof(C2);
+    const int C = fft_tile(n, esz, 64);
+    const int lc = ilog2(C);
+    const int n_lines = nb * n * n;
+    k_grid_z<T, N><<<div_up(n_lines, C), 256, lds_bytes(n, C, esz), st>>>(A, n_lines, tw, lc, sign);
+    BSE_LAUNCH_CHECK();
+    const int nzt = div_up(n, C);
+    k_grid_y<T, N><<<(unsigned)nb * n * nzt, 256, lds_bytes(n, C, esz), st>>>(A, tw, lc, nzt, sign);
+    BSE_LAUNCH_CHECK();
+    const int nyzt = div_up((size_t)n * n, C);
+    k_grid_x<T, N><<<(unsigned)nb * nyzt, 256, lds_bytes(n, C, esz), st>>>(A, tw, lc, nyzt, sign);
+    BSE_LAUNCH_CHECK();
+}
+
+#define BSE_FFT_DISPATCH(NN, CALL) \
+    case NN: CALL; break;
+
+template <typename T>
+void sph_inverse(const SphereMaps &m, const T *X, int n_orb, T *out, cplx<T> *T1, cplx<T> *T2,
+                 const cplx<T> *tw, hipStream_t st, hipEvent_t *ev, int ps) {
+    BSE_REQUIRE(ps >= 1 && (ps == 1 || n_orb % ps == 0), BSE_ERR_ARG, "bad orbital pairing");
+    switch (m.n) {
+#define BSE_CASE(NN) case NN: sph_inverse_n<T, NN>(m, X, n_orb, out, T1, T2, tw, st, ev, ps); break;
+        BSE_FFT_SIZES(BSE_CASE)
+#undef BSE_CASE
+        default: BSE_REQUIRE(false, BSE_ERR_ARG, "unsupported grid size %d", m.n);
     }
 }
 
@@ -572,72 +694,34 @@ template <typename T>
 void sph_forward(const SphereMaps &m, const T *Cr, const T *u, const cplx<T> *vH, T k1e, int n_orb,
                  int n_occ, const T *X, T kin_scale, T *Y, cplx<T> *T1, cplx<T> *T2,
                  const cplx<T> *tw, hipStream_t st, hipEvent_t *ev) {
-    using C2 = cplx<T>;
-    const int n = m.n;
-    const int nq = (n_orb + 1) / 2;
-    const size_t esz = sizeof(C2);
-    {
-        const int C = fft_tile(n, esz, 64);
-        const int nyzt = div_up((size_t)n * n, C);
-        k_sph_fwd_x<T><<<(unsigned)nq * nyzt, 256, lds_bytes(n, C, esz), st>>>(
-            Cr, u, vH, k1e, n_orb, n_occ, m.xlist, m.nxp, T2, tw, m.plan, C, nyzt);
-        BSE_LAUNCH_CHECK();
-        if (ev) BSE_HIP(hipEventRecord(ev[0], st));
-    }
-    {
-        const int C = fft_tile(n, esz, 64);
-        const int nzt = div_up(n, C);
-        k_sph_fwd_y<T><<<(unsigned)nq * m.nxp * nzt, 256, lds_bytes(n, C, esz), st>>>(
-            T2, m.colmap, m.xlist, m.nxp, m.ncol, T1, tw, m.plan, C, nzt);
-        BSE_LAUNCH_CHECK();
-        if (ev) BSE_HIP(hipEventRecord(ev[1], st));
-    }
-    {
-        const int C = fft_tile(n, esz, 64);
-        const int n_lines = nq * m.ncol;
-        k_sph_fwd_z<T><<<div_up(n_lines, C), 256, lds_bytes(n, C, esz), st>>>(
-            T1, m.ent, m.col_ptr, m.ncol, n_lines, n_orb, m.npw, X, m.kin, kin_scale, Y, tw,
-            m.plan, C);
-        BSE_LAUNCH_CHECK();
-        if (ev) BSE_HIP(hipEventRecord(ev[2], st));
+    switch (m.n) {
+#define BSE_CASE(NN)                                                                          \
+    case NN:                                                                                  \
+        sph_forward_n<T, NN>(m, Cr, u, vH, k1e, n_orb, n_occ, X, kin_scale, Y, T1, T2, tw, st, \
+                             ev);                                                             \
+        break;
+        BSE_FFT_SIZES(BSE_CASE)
+#undef BSE_CASE
+        default: BSE_REQUIRE(false, BSE_ERR_ARG, "unsupported grid size %d", m.n);
     }
 }
 
 template <typename T>
 void grid_fft(const FftPlan &pl, cplx<T> *A, int nb, T sign, const cplx<T> *tw, hipStream_t st) {
-    using C2 = cplx<T>;
-    const int n = pl.n;
-    const size_t esz = sizeof(C2);
-    const int C = fft_tile(n, esz, 64);
-    auto z = [&]() {
-        const int n_lines = nb * n * n;
-        k_grid_z<T><<<div_up(n_lines, C), 256, lds_bytes(n, C, esz), st>>>(A, n_lines, tw, pl, C,
-                                                                           sign);
-        BSE_LAUNCH_CHECK();
-    };
-    auto y = [&]() {
-        const int nzt = div_up(n, C);
-        k_grid_y<T><<<(unsigned)nb * n * nzt, 256, lds_bytes(n, C, esz), st>>>(A, tw, pl, C, nzt,
-                                                                               sign);
-        BSE_LAUNCH_CHECK();
-    };
-    auto x = [&]() {
-        const int nyzt = div_up((size_t)n * n, C);
-        k_grid_x<T><<<(unsigned)nb * nyzt, 256, lds_bytes(n, C, esz), st>>>(A, tw, pl, C, nyzt,
-                                                                            sign);
-        BSE_LAUNCH_CHECK();
-    };
-    // separable: order of the axes does not matter
-    z();
-    y();
-    x();
+    switch (pl.n) {
+#define BSE_CASE(NN) case NN: grid_fft_n<T, NN>(A, nb, sign, tw, st); break;
+        BSE_FFT_SIZES(BSE_CASE)
+#undef BSE_CASE
+        default: BSE_REQUIRE(false, BSE_ERR_ARG, "unsupported grid size %d", pl.n);
+    }
 }
 
 template void sph_inverse<float>(const SphereMaps &, const float *, int, float *, cplx<float> *,
-                                 cplx<float> *, const cplx<float> *, hipStream_t, hipEvent_t *);
+                                 cplx<float> *, const cplx<float> *, hipStream_t, hipEvent_t *,
+                                 int);
 template void sph_inverse<double>(const SphereMaps &, const double *, int, double *,
                                   cplx<double> *, cplx<double> *, const cplx<double> *,
-                                  hipStream_t, hipEvent_t *);
+                                  hipStream_t, hipEvent_t *, int);
 template void sph_forward<float>(const SphereMaps &, const float *, const float *,
                                  const cplx<float> *, float, int, int, const float *, float,
                                  float *, cplx<float> *, cplx<float> *, const cplx<float> *,

@@ -5,6 +5,9 @@
 
 namespace bse {
 
+// FFT lengths compiled into the library (products of 2, 3 and 5)
+#define BSE_FFT_SIZES(X) X(16) X(24) X(32) X(36) X(48) X(60) X(64) X(72) X(80) X(96) X(120) X(128)
+
 struct FftPlan {
     int n;
     int nst;
@@ -29,11 +32,15 @@ struct SphereMaps {
 FftPlan make_plan(int n);
 int fft_tile(int n, size_t esz, int cap);
 
-// ev (optional): three events recorded after the three passes
+// ev (optional): three events recorded after the three passes.
+// Two real orbitals share a complex transform: o and o + ps (ps = 1 pairs
+// neighbours; ps = n_occ pairs the same slot of consecutive trial vectors,
+// n_orb a multiple of ps).  Workspaces hold ceil(n_orb / 2ps) * ps lines.
 template <typename T>
 void sph_inverse(const SphereMaps &m, const T *X, int n_orb, T *out, cplx<T> *T1, cplx<T> *T2,
-                 const cplx<T> *tw, hipStream_t st, hipEvent_t *ev = nullptr);
+                 const cplx<T> *tw, hipStream_t st, hipEvent_t *ev = nullptr, int ps = 1);
 
+// pairs the same orbital slot of consecutive trial vectors (ps = n_occ)
 template <typename T>
 void sph_forward(const SphereMaps &m, const T *Cr, const T *u, const cplx<T> *vH, T k1e, int n_orb,
                  int n_occ, const T *X, T kin_scale, T *Y, cplx<T> *T1, cplx<T> *T2,

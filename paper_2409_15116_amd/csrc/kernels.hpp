@@ -49,7 +49,7 @@ struct PairCSR {
     int *col = nullptr;
     int *pidx = nullptr;
     int nnz = 0;
-    int chunk = 16;
+    int chunk = 8;
     int nchunk = 0;
     int *lo = nullptr;
     int *hi = nullptr;
@@ -95,5 +95,11 @@ void gemm(bool nt, int M, int N, int K, T alpha, const T *A, long long lda, long
 void gemm_bf16x3(bool nt, int M, int N, int K, float alpha, const float *A, long long lda,
                  long long sA, const float *B, long long ldb, long long sB, float beta, float *C,
                  long long ldc, long long sC, int batch, Workspace &ws, hipStream_t st);
+
+// plain bf16 x bf16 MFMA GEMM with FP32 accumulate (operands rounded to bf16);
+// ta: A stored [K][M]
+void gemm_bf16(bool ta, bool nt, int M, int N, int K, float alpha, const float *A, long long lda,
+               const float *B, long long ldb, float beta, float *C, long long ldc, Workspace &ws,
+               hipStream_t st);
 
 }  // namespace bse

@@ -26,7 +26,9 @@ __device__ inline float bf16_to_f32(unsigned short h) { return __uint_as_float((
 
 constexpr int TB = 64, TK = 16, PADK = 4;
 
-template <bool NT>
+// TA: A is stored [K][M] (C = A^T op(B)); SPLIT: hi/lo split (BF16x3),
+// otherwise one plain bf16 x bf16 product with FP32 accumulate.
+template <bool TA, bool NT, bool SPLIT>
 __global__ void __launch_bounds__(256) k_gemm_bf16x3(int M, int N, int K, float alpha,
                                                      const float *__restrict__ A, long long lda,
                                                      long long sA, const float *__restrict__ Bm,
@@ -55,12 +57,22 @@ __global__ void __launch_bounds__(256) k_gemm_bf16x3(int M, int N, int K, float 
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
             const int idx = tid + l * 256;
-            const int mm = idx >> 4, kk = idx & 15;
-            const int gm = m0 + mm, gk = k0 + kk;
-            const float x = (gm < M && gk < kend) ? A[(size_t)gm * lda + gk] : 0.f;
+            int mm, kk;
+            float x;
+            if (TA) {
+                kk = idx >> 6;
+                mm = idx & 63;
+                const int gm = m0 + mm, gk = k0 + kk;
+                x = (gm < M && gk < kend) ? A[(size_t)gk * lda + gm] : 0.f;
+            } else {
+                mm = idx >> 4;
+                kk = idx & 15;
+                const int gm = m0 + mm, gk = k0 + kk;
+                x = (gm < M && gk < kend) ? A[(size_t)gm * lda + gk] : 0.f;
+            }
             const unsigned short h = bf16_rne(x);
             Ah[mm][kk] = h;
-            Al[mm][kk] = bf16_rne(x - bf16_to_f32(h));
+            if (SPLIT) Al[mm][kk] = bf16_rne(x - bf16_to_f32(h));
         }
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
@@ -80,7 +92,7 @@ __global__ void __launch_bounds__(256) k_gemm_bf16x3(int M, int N, int K, float 
             }
             const unsigned short h = bf16_rne(x);
             Bh[nn][kk] = h;
-            Bl[nn][kk] = bf16_rne(x - bf16_to_f32(h));
+            if (SPLIT) Bl[nn][kk] = bf16_rne(x - bf16_to_f32(h));
         }
         __syncthreads();
         const int r16 = lane & 15, kq = (lane >> 4) * 4;
@@ -91,7 +103,7 @@ __global__ void __launch_bounds__(256) k_gemm_bf16x3(int M, int N, int K, float 
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 ah[i][e] = (short)Ah[row][kq + e];
-                al[i][e] = (short)Al[row][kq + e];
+                al[i][e] = SPLIT ? (short)Al[row][kq + e] : (short)0;
             }
         }
 #pragma unroll
@@ -100,15 +112,17 @@ __global__ void __launch_bounds__(256) k_gemm_bf16x3(int M, int N, int K, float 
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 bh[j][e] = (short)Bh[col][kq + e];
-                bl[j][e] = (short)Bl[col][kq + e];
+                bl[j][e] = SPLIT ? (short)Bl[col][kq + e] : (short)0;
             }
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                if (SPLIT) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                }
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
             }
         __syncthreads();
@@ -146,9 +160,19 @@ __global__ void k_splitk_reduce_f(const float *__restrict__ part, int nsplit, in
     *c = beta == 0.f ? alpha * s : alpha * s + beta * *c;
 }
 
-void gemm_bf16x3(bool nt, int M, int N, int K, float alpha, const float *A, long long lda,
-                 long long sA, const float *B, long long ldb, long long sB, float beta, float *C,
-                 long long ldc, long long sC, int batch, Workspace &ws, hipStream_t st) {
+template <bool TA, bool NT, bool SPLIT>
+static void launch_bf16(dim3 grid, hipStream_t st, int M, int N, int K, float alpha, const float *A,
+                        long long lda, long long sA, const float *B, long long ldb, long long sB,
+                        float beta, float *C, long long ldc, long long sC, int kchunk, int nsplit) {
+    k_gemm_bf16x3<TA, NT, SPLIT><<<grid, 256, 0, st>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta,
+                                                       C, ldc, sC, kchunk, nsplit);
+    BSE_LAUNCH_CHECK();
+}
+
+static void gemm_bf16_any(bool ta, bool nt, bool split, int M, int N, int K, float alpha,
+                          const float *A, long long lda, long long sA, const float *B,
+                          long long ldb, long long sB, float beta, float *C, long long ldc,
+                          long long sC, int batch, Workspace &ws, hipStream_t st) {
     if (M <= 0 || N <= 0 || batch <= 0) return;
     const int tiles = div_up(M, TB) * div_up(N, TB) * batch;
     int nsplit = 1;
@@ -156,29 +180,46 @@ void gemm_bf16x3(bool nt, int M, int N, int K, float alpha, const float *A, long
     const int kchunk = div_up(div_up(K, nsplit), TK) * TK;
     nsplit = std::max(1, (int)div_up(K, kchunk));
     dim3 grid(div_up(N, TB), div_up(M, TB), batch * nsplit);
-    if (nsplit == 1) {
-        if (nt)
-            k_gemm_bf16x3<true><<<grid, 256, 0, st>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta,
-                                                      C, ldc, sC, kchunk, 1);
-        else
-            k_gemm_bf16x3<false><<<grid, 256, 0, st>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta,
-                                                       C, ldc, sC, kchunk, 1);
-        BSE_LAUNCH_CHECK();
-        return;
+    float *Cw = C;
+    float a = alpha, b = beta;
+    long long ldw = ldc, sw = sC;
+    if (nsplit > 1) {
+        Cw = (float *)ws.get((size_t)M * N * nsplit * batch * sizeof(float));
+        a = 1.f;
+        b = 0.f;
+        ldw = N;
+        sw = 0;
     }
-    const size_t mn = (size_t)M * N;
-    float *part = (float *)ws.get(mn * nsplit * batch * sizeof(float));
-    if (nt)
-        k_gemm_bf16x3<true><<<grid, 256, 0, st>>>(M, N, K, 1.f, A, lda, sA, B, ldb, sB, 0.f, part,
-                                                  N, 0, kchunk, nsplit);
-    else
-        k_gemm_bf16x3<false><<<grid, 256, 0, st>>>(M, N, K, 1.f, A, lda, sA, B, ldb, sB, 0.f, part,
-                                                   N, 0, kchunk, nsplit);
-    BSE_LAUNCH_CHECK();
-    const long long tot = (long long)mn * batch;
-    k_splitk_reduce_f<<<div_up(tot, 256), 256, 0, st>>>(part, nsplit, M, N, alpha, beta, C, ldc, sC,
-                                                        batch);
-    BSE_LAUNCH_CHECK();
+#define BSE_BF16_CASE(TA_, NT_, SP_)                                                          \
+    if (ta == TA_ && nt == NT_ && split == SP_)                                               \
+        launch_bf16<TA_, NT_, SP_>(grid, st, M, N, K, a, A, lda, sA, B, ldb, sB, b, Cw, ldw, sw, \
+                                   kchunk, nsplit);
+    BSE_BF16_CASE(false, false, true)
+    BSE_BF16_CASE(false, true, true)
+    BSE_BF16_CASE(false, false, false)
+    BSE_BF16_CASE(false, true, false)
+    BSE_BF16_CASE(true, false, false)
+    BSE_BF16_CASE(true, true, false)
+#undef BSE_BF16_CASE
+    if (nsplit > 1) {
+        const long long tot = (long long)M * N * batch;
+        k_splitk_reduce_f<<<div_up(tot, 256), 256, 0, st>>>(Cw, nsplit, M, N, alpha, beta, C, ldc,
+                                                            sC, batch);
+        BSE_LAUNCH_CHECK();
+    }
+}
+
+void gemm_bf16x3(bool nt, int M, int N, int K, float alpha, const float *A, long long lda,
+                 long long sA, const float *B, long long ldb, long long sB, float beta, float *C,
+                 long long ldc, long long sC, int batch, Workspace &ws, hipStream_t st) {
+    gemm_bf16_any(false, nt, true, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch,
+                  ws, st);
+}
+
+void gemm_bf16(bool ta, bool nt, int M, int N, int K, float alpha, const float *A, long long lda,
+               const float *B, long long ldb, float beta, float *C, long long ldc, Workspace &ws,
+               hipStream_t st) {
+    gemm_bf16_any(ta, nt, false, M, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1, ws, st);
 }
 
 }  // namespace bse

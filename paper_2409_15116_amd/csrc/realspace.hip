@@ -73,20 +73,21 @@ __global__ void __launch_bounds__(256) k_k1d(const T *__restrict__ A, const T *_
         const int *hi_b = hi + (size_t)jb * n_occ;
 #pragma unroll
         for (int i = 0; i < BI; ++i) {
+            // no early exit: a constant trip count keeps acc[][] in registers
             const int v = v0 + i;
-            if (v >= n_occ) break;
-            int e = lo_b[v];
-            const int e1 = hi_b[v];
-            for (; e + 4 <= e1; e += 4) {
-                T t[4];
-                int c[4];
+            int e = v < n_occ ? lo_b[v] : 0;
+            const int e1 = v < n_occ ? hi_b[v] : 0;
+            // eight independent tau loads in flight per wave
+            for (; e + 8 <= e1; e += 8) {
+                T t[8];
+                int c[8];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < 8; ++q) {
                     c[q] = pcol[e + q] - j0;
                     t[q] = rok ? tau[(size_t)pidx[e + q] * nr + rr] : (T)0;
                 }
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
+                for (int q = 0; q < 8; ++q)
 #pragma unroll
                     for (int j = 0; j < SPL; ++j)
                         acc[i][j] += t[q] * tl[(c[q] * S + j) * K1D_R];
@@ -109,11 +110,12 @@ __global__ void __launch_bounds__(256) k_k1d(const T *__restrict__ A, const T *_
 #pragma unroll
         for (int i = 0; i < BI; ++i) {
             const int v = v0 + i;
-            if (v >= n_occ) break;
-            const size_t off = (size_t)s * sstride + (size_t)v * nr + rr;
-            const T av = A[off];
-            Cr[off] = vr * av - k1d * acc[i][j];
-            dn += u[(size_t)v * nr + rr] * av;
+            if (v < n_occ) {
+                const size_t off = (size_t)s * sstride + (size_t)v * nr + rr;
+                const T av = A[off];
+                Cr[off] = vr * av - k1d * acc[i][j];
+                dn += u[(size_t)v * nr + rr] * av;
+            }
         }
         Dp[((size_t)ib * B + s) * nr + rr] = dn * inv_omega;
     }

@@ -73,6 +73,18 @@ def load():
                                C.POINTER(DavidsonStats)]),
         "bse_debug_to_grid": (i32, [vp, i32, vp, vp, i32]),
         "bse_debug_gemm": (i32, [vp, i32, i32, i32, i32, dbl, vp, vp, dbl, vp, i32]),
+        "bse_mlp_create": (i32, [C.POINTER(vp), i32, i32, i32, vp, vp]),
+        "bse_mlp_destroy": (i32, [vp]),
+        "bse_mlp_num_params": (C.c_longlong, [vp]),
+        "bse_mlp_get_weights": (i32, [vp, vp]),
+        "bse_mlp_set_weights": (i32, [vp, vp]),
+        "bse_mlp_forward": (i32, [vp, i32, vp, vp]),
+        "bse_mlp_gradients": (i32, [vp, i32, vp, vp, vp, vp]),
+        "bse_mlp_train": (i32, [vp, i32, vp, vp, i32, i32, C.c_float, C.c_uint64, vp]),
+        "bse_set_learned": (i32, [vp, vp, i32]),
+        "bse_learned_centers": (i32, [vp, vp]),
+        "bse_davidson_record": (i32, [vp, C.POINTER(DavidsonOpts), vp, vp, i32, i32, vp, vp, i64,
+                                      C.POINTER(i64), vp, vp, C.POINTER(DavidsonStats)]),
         "bse_status_str": (C.c_char_p, [i32]),
         "bse_last_error": (C.c_char_p, []),
     }
@@ -88,7 +100,10 @@ def exported_symbols():
     return ["bse_create", "bse_destroy", "bse_set_terms", "bse_pair_measure", "bse_build_pairs",
             "bse_threshold_for_fraction", "bse_get_pairs", "bse_screen_pairs", "bse_copy_tau",
             "bse_apply_liouville", "bse_set_graph", "bse_davidson", "bse_status_str",
-            "bse_last_error", "bse_debug_to_grid", "bse_debug_gemm", "bse_profile_apply"]
+            "bse_last_error", "bse_debug_to_grid", "bse_debug_gemm", "bse_profile_apply",
+            "bse_mlp_create", "bse_mlp_destroy", "bse_mlp_num_params", "bse_mlp_get_weights",
+            "bse_mlp_set_weights", "bse_mlp_forward", "bse_mlp_gradients", "bse_mlp_train",
+            "bse_set_learned", "bse_learned_centers", "bse_davidson_record"]
 
 
 def _check(st):
@@ -211,6 +226,36 @@ class BseContext:
     def set_graph(self, enable=True):
         _check(load().bse_set_graph(self.h, 1 if enable else 0))
 
+    def set_learned(self, mlp, n_window_pw):
+        _check(load().bse_set_learned(self.h, mlp.h if mlp is not None else None, n_window_pw))
+
+    def learned_centers(self):
+        out = np.empty((self.n_occ, 3))
+        _check(load().bse_learned_centers(self.h, out.ctypes.data))
+        return out
+
+    def davidson_record(self, X0, Xref, n_eig, n_window_pw, max_rows, *, block=None,
+                        max_basis=0, restart=0, max_iter=200, precision=FP64, tol=1e-6,
+                        delta=0.05):
+        """Plain Davidson that records (features, labels) rows for training."""
+        torch = self.torch
+        B = block or X0.shape[0]
+        kw = 1 + 2 * n_window_pw
+        feat = torch.zeros((max_rows, kw + 3), dtype=torch.float32, device="cuda")
+        lab = torch.zeros((max_rows, kw), dtype=torch.float32, device="cuda")
+        o = DavidsonOpts(n_eig, B, max_basis, restart, max_iter, precision, tol, delta, 0, 0)
+        om = np.zeros(n_eig)
+        X = torch.empty((n_eig, self.n_occ, self.npw), dtype=torch.float64, device="cuda")
+        st = DavidsonStats()
+        nr = C.c_int64()
+        _check(load().bse_davidson_record(self.h, C.byref(o), _dptr(X0, torch.float64),
+                                          _dptr(Xref, torch.float64), Xref.shape[0], n_window_pw,
+                                          _dptr(feat, torch.float32), _dptr(lab, torch.float32),
+                                          max_rows, C.byref(nr), om.ctypes.data,
+                                          _dptr(X, torch.float64), C.byref(st)))
+        n = int(nr.value)
+        return feat[:n], lab[:n], om, {"iterations": st.iterations, "n_apply": st.n_apply}
+
     def davidson(self, X0, n_eig, *, block=None, max_basis=0, restart=0, max_iter=200,
                  precision=FP64, tol=1e-6, delta=0.05, precond=0, verbose=0):
         torch = self.torch
@@ -228,3 +273,77 @@ class BseContext:
                  "resid": np.array(st.resid[:n_eig]), "status": status}
         _check(status)
         return om, X, stats
+
+
+class Mlp:
+    """The learned preconditioner's network on the GPU (bse_mlp)."""
+
+    def __init__(self, f_in, hidden, k_out, weights, stream=None):
+        import torch
+        self.torch = torch
+        self.shape = (f_in, hidden, k_out)
+        w = np.ascontiguousarray(weights, dtype=np.float32)
+        h = C.c_void_p()
+        sp = C.c_void_p(stream.cuda_stream if stream is not None else 0)
+        _check(load().bse_mlp_create(C.byref(h), f_in, hidden, k_out, w.ctypes.data, sp))
+        self.h = h
+        self.n_params = int(load().bse_mlp_num_params(h))
+        assert self.n_params == w.size
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().bse_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def weights(self):
+        w = np.empty(self.n_params, dtype=np.float32)
+        _check(load().bse_mlp_get_weights(self.h, w.ctypes.data))
+        return w
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        _check(load().bse_mlp_set_weights(self.h, w.ctypes.data))
+
+    def forward(self, X):
+        t = self.torch
+        Y = t.empty((X.shape[0], self.shape[2]), dtype=t.float32, device="cuda")
+        _check(load().bse_mlp_forward(self.h, X.shape[0], _dptr(X, t.float32),
+                                      _dptr(Y, t.float32)))
+        return Y
+
+    def gradients(self, X, T):
+        t = self.torch
+        g = np.empty(self.n_params, dtype=np.float32)
+        loss = C.c_double()
+        _check(load().bse_mlp_gradients(self.h, X.shape[0], _dptr(X, t.float32),
+                                        _dptr(T, t.float32), g.ctypes.data, C.byref(loss)))
+        return g, float(loss.value)
+
+    def train(self, X, T, epochs, batch, lr, seed=0):
+        t = self.torch
+        losses = np.zeros(epochs)
+        _check(load().bse_mlp_train(self.h, X.shape[0], _dptr(X, t.float32), _dptr(T, t.float32),
+                                    epochs, batch, lr, seed, losses.ctypes.data))
+        return losses
+
+
+def pack_params(p):
+    """Flat weight vector of a dict of W1, b1, W2, b2, W3, b3."""
+    return np.concatenate([np.asarray(p[k], dtype=np.float32).ravel()
+                           for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+
+
+def unpack_params(w, f_in, hidden, k_out):
+    out, o = {}, 0
+    for k, shp in (("W1", (f_in, hidden)), ("b1", (hidden,)), ("W2", (hidden, hidden)),
+                   ("b2", (hidden,)), ("W3", (hidden, k_out)), ("b3", (k_out,))):
+        n = int(np.prod(shp))
+        out[k] = np.asarray(w[o:o + n], dtype=np.float64).reshape(shp)
+        o += n
+    return out
