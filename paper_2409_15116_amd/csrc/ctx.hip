@@ -275,57 +275,33 @@ void ctx_build_pairs(bse_ctx *c, int kind, double thr) {
     c->tau64.free();
     c->tau32.free();
     drop_graph(c);
-    // symmetric CSR: row v holds (w, p) for every pair touching v, sorted by w
-    std::vector<std::vector<std::pair<int, int>>> rows(no);
-    for (long long p = 0; p < c->n_pairs; ++p) {
-        const int v = pr[2 * p], w = pr[2 * p + 1];
-        rows[v].push_back({w, (int)p});
-        if (w != v) rows[w].push_back({v, (int)p});
-    }
-    std::vector<int> col, pidx, rp(no + 1, 0);
-    for (int v = 0; v < no; ++v) {
-        std::sort(rows[v].begin(), rows[v].end());
-        rp[v] = (int)col.size();
-        for (auto &e : rows[v]) {
-            col.push_back(e.first);
-            pidx.push_back(e.second);
-        }
-    }
-    rp[no] = (int)col.size();
+    // dense (row block x column block) tables of tau rows for the K1d kernel;
+    // pairs that are not kept point at the zero row P
     auto up = [&](auto &dev, const auto &host) {
         dev.alloc(std::max<size_t>(1, host.size()));
         if (!host.empty())
             BSE_HIP(hipMemcpy(dev.p, host.data(), host.size() * sizeof(host[0]), hipMemcpyHostToDevice));
     };
-    up(c->csr_col, col);
-    up(c->csr_pidx, pidx);
-    c->csr.col = c->csr_col.p;
-    c->csr.pidx = c->csr_pidx.p;
-    c->csr.nnz = (int)col.size();
     {
-        const int chunk = c->csr.chunk;
-        const int nchunk = (no + chunk - 1) / chunk;
-        const int nIb = (no + K1D_BI - 1) / K1D_BI;
-        std::vector<int> lo((size_t)nchunk * no), hi((size_t)nchunk * no);
-        std::vector<unsigned char> nz((size_t)nIb * nchunk, 0);
-        for (int k = 0; k < nchunk; ++k) {
-            const int c0 = k * chunk, c1 = std::min(no, c0 + chunk);
-            for (int v = 0; v < no; ++v) {
-                int a = rp[v];
-                while (a < rp[v + 1] && col[a] < c0) ++a;
-                int b = a;
-                while (b < rp[v + 1] && col[b] < c1) ++b;
-                lo[(size_t)k * no + v] = a;
-                hi[(size_t)k * no + v] = b;
-                if (b > a) nz[(size_t)(v / K1D_BI) * nchunk + k] = 1;
-            }
+        const int BI = K1D_BI, BJ = K1D_BJ;
+        const int nIb = (no + BI - 1) / BI, nJb = (no + BJ - 1) / BJ;
+        const long long P = c->n_pairs;
+        std::vector<long long> tbl((size_t)nIb * nJb * BI * BJ, P * c->nr);
+        std::vector<unsigned char> nz((size_t)nIb * nJb, 0);
+        auto put = [&](int v, int w, long long p) {
+            const int ib = v / BI, jb = w / BJ;
+            tbl[((size_t)(ib * nJb + jb) * BJ + (w - jb * BJ)) * BI + (v - ib * BI)] = p * c->nr;
+            nz[(size_t)ib * nJb + jb] = 1;
+        };
+        for (long long p = 0; p < c->n_pairs; ++p) {
+            const int v = pr[2 * p], w = pr[2 * p + 1];
+            put(v, w, p);
+            if (w != v) put(w, v, p);
         }
-        up(c->csr_lo, lo);
-        up(c->csr_hi, hi);
+        up(c->csr_tbl, tbl);
         up(c->csr_nz, nz);
-        c->csr.nchunk = nchunk;
-        c->csr.lo = c->csr_lo.p;
-        c->csr.hi = c->csr_hi.p;
+        c->csr.nchunk = nJb;
+        c->csr.tbl = c->csr_tbl.p;
         c->csr.blk_nz = c->csr_nz.p;
     }
     std::vector<int2> pd(c->n_pairs);
@@ -408,9 +384,12 @@ void ctx_screen(bse_ctx *c, const double *phi, const double *lam, int n_pdep, in
                      npw1, n_pdep, c->gws, c->stream);
     }
     drop_graph(c);
+    // tau carries one extra all-zero row (index P) for the K1d block tables
     if (prec == BSE_FP64) {
-        c->tau64.alloc(P * nr);
-        c->tau32.alloc(P * nr);
+        c->tau64.alloc((P + 1) * nr);
+        c->tau32.alloc((P + 1) * nr);
+        zero<double>(c->tau64.p + P * nr, (long long)nr, c->stream);
+        zero<float>(c->tau32.p + P * nr, (long long)nr, c->stream);
         screen_impl<double>(c, phi, phif.p, n_pdep, false, c->tau64.p, c->tau32.p);
         c->have_tau64 = c->have_tau32 = true;
     } else {
@@ -421,7 +400,8 @@ void ctx_screen(bse_ctx *c, const double *phi, const double *lam, int n_pdep, in
         convert<double, float>(phif.p, pf32.p, (long long)n_pdep * npw1, c->stream);
         c->tau64.free();
         c->have_tau64 = false;
-        c->tau32.alloc(P * nr);
+        c->tau32.alloc((P + 1) * nr);
+        zero<float>(c->tau32.p + P * nr, (long long)nr, c->stream);
         screen_impl<float>(c, p32.p, pf32.p, n_pdep, prec == BSE_BF16X3, c->tau32.p, nullptr);
         c->have_tau32 = true;
     }

@@ -96,7 +96,7 @@ struct bse_ctx {
     // pairs and tau
     std::vector<int> pairs_h;  // [P][2]
     bse::Dev<int2> pairs_d;
-    bse::Dev<int> csr_col, csr_pidx, csr_lo, csr_hi;
+    bse::Dev<long long> csr_tbl;
     bse::Dev<unsigned char> csr_nz;
     bse::PairCSR csr;
     long long n_pairs = 0;

@@ -39,20 +39,17 @@ struct Workspace {
     }
 };
 
-// Symmetric pair list as CSR over rows v: entries (w, tau slot) with w
-// sorted.  The K1d kernel stages the columns in blocks of `chunk` orbitals;
-// lo/hi are [nchunk][n_occ] offsets of each row's entries inside each column
-// block, and blk_nz[ib][jb] marks (row block of K1D_BI rows, column block)
-// pairs that hold any entry.
+// Pair list for the K1d kernel: rows in blocks of K1D_BI, columns in blocks
+// of K1D_BJ; tbl[(ib * nchunk + jb) * BI * BJ + w * BI + i] is the element
+// offset (row * nr) of the tau row of pair (ib*BI + i, jb*BJ + w), or of the
+// zero row P when the pair is not kept;
+// blk_nz[ib * nchunk + jb] marks blocks holding any kept pair.  tau carries
+// P + 1 rows, the last one zero.
 constexpr int K1D_BI = 32;
+constexpr int K1D_BJ = 8;
 struct PairCSR {
-    int *col = nullptr;
-    int *pidx = nullptr;
-    int nnz = 0;
-    int chunk = 8;
     int nchunk = 0;
-    int *lo = nullptr;
-    int *hi = nullptr;
+    long long *tbl = nullptr;
     unsigned char *blk_nz = nullptr;
 };
 

@@ -18,19 +18,21 @@ namespace bse {
 // ---------------------------------------------------------------------------
 constexpr int K1D_R = 64;
 
-template <typename T, int BI, int SPL>
+// tbl[(ib * nJb + jb) * BI * BJ + w * BI + i] = element offset (p * nr) of the
+// tau row of pair (v0 + i, j0 + w), or of the all-zero row P for pairs that
+// are not kept; blk_nz[ib * nJb + jb] marks blocks with any kept pair.  Every
+// tau load is then unconditional and independent (a column's BI loads are
+// issued together), and a column's a values are read from LDS once for BI rows.
+template <typename T, int BI, int BJ, int SPL>
 __global__ void __launch_bounds__(256) k_k1d(const T *__restrict__ A, const T *__restrict__ tau,
                                              const T *__restrict__ V, const T *__restrict__ u,
-                                             const int *__restrict__ lo, const int *__restrict__ hi,
-                                             const unsigned char *__restrict__ blk_nz,
-                                             const int *__restrict__ pcol,
-                                             const int *__restrict__ pidx, int n_occ, int B,
-                                             long long nr, int BJ, int nIb, int nJb, int nSc,
+                                             const long long *__restrict__ tbl,
+                                             const unsigned char *__restrict__ blk_nz, int n_occ,
+                                             int B, long long nr, int nIb, int nJb, int nSc,
                                              T k1d, T inv_omega, T *__restrict__ Cr,
                                              T *__restrict__ Dp) {
     constexpr int S = 4 * SPL;
-    extern __shared__ unsigned char smem_raw[];
-    T *tile = reinterpret_cast<T *>(smem_raw);  // [BJ][S][64]
+    __shared__ T tile[BJ * S * K1D_R];
     // decode: id = 8 * (hi8 * nIb * nSc + ib * nSc + sc) + lo8, r-tile = hi8 * 8 + lo8
     const int id = blockIdx.x;
     const int lo8 = id & 7;
@@ -43,8 +45,8 @@ __global__ void __launch_bounds__(256) k_k1d(const T *__restrict__ A, const T *_
     const long long r0 = rt * K1D_R;
     if (r0 >= nr) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const long long rr = r0 + lane;
-    const bool rok = rr < nr;
+    const long long rr = r0 + lane < nr ? r0 + lane : nr - 1;  // clamp: loads stay in bounds
+    const bool rok = r0 + lane < nr;
     const int s0 = sc * S;
     const int v0 = ib * BI;
     const size_t sstride = (size_t)n_occ * nr;
@@ -68,36 +70,22 @@ __global__ void __launch_bounds__(256) k_k1d(const T *__restrict__ A, const T *_
             tile[i] = val;
         }
         __syncthreads();
-        const T *tl = tile + (wave * SPL) * K1D_R + lane;
-        const int *lo_b = lo + (size_t)jb * n_occ;
-        const int *hi_b = hi + (size_t)jb * n_occ;
+        const long long *tb = tbl + (size_t)(ib * nJb + jb) * BI * BJ;
+        const int lr = (int)rr;  // lane offset inside a tau row (nr < 2^31)
 #pragma unroll
-        for (int i = 0; i < BI; ++i) {
-            // no early exit: a constant trip count keeps acc[][] in registers
-            const int v = v0 + i;
-            int e = v < n_occ ? lo_b[v] : 0;
-            const int e1 = v < n_occ ? hi_b[v] : 0;
-            // eight independent tau loads in flight per wave
-            for (; e + 8 <= e1; e += 8) {
-                T t[8];
-                int c[8];
+        for (int w = 0; w < BJ; ++w) {
+            // all BI tau loads of this column first, then the FMAs: BI loads in flight
+            T t[BI];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    c[q] = pcol[e + q] - j0;
-                    t[q] = rok ? tau[(size_t)pidx[e + q] * nr + rr] : (T)0;
-                }
+            for (int i = 0; i < BI; ++i) t[i] = (tau + tb[w * BI + i])[lr];
+            __builtin_amdgcn_sched_barrier(0);
+            T aw[SPL];
 #pragma unroll
-                for (int q = 0; q < 8; ++q)
+            for (int j = 0; j < SPL; ++j) aw[j] = tile[(w * S + wave * SPL + j) * K1D_R + lane];
 #pragma unroll
-                    for (int j = 0; j < SPL; ++j)
-                        acc[i][j] += t[q] * tl[(c[q] * S + j) * K1D_R];
-            }
-            for (; e < e1; ++e) {
-                const int c = pcol[e] - j0;
-                const T t = rok ? tau[(size_t)pidx[e] * nr + rr] : (T)0;
+            for (int i = 0; i < BI; ++i)
 #pragma unroll
-                for (int j = 0; j < SPL; ++j) acc[i][j] += t * tl[(c * S + j) * K1D_R];
-            }
+                for (int j = 0; j < SPL; ++j) acc[i][j] += t[i] * aw[j];
         }
     }
     if (!rok) return;
@@ -141,10 +129,9 @@ void k1d_apply(const T *A, const T *tau, const T *V, const T *u, const PairCSR &
                int B, long long nr, T k1d, T inv_omega, T *Cr, cplx<T> *Hc, T *Dp,
                hipStream_t st) {
     constexpr bool dbl = sizeof(T) == 8;
-    constexpr int BI = K1D_BI;
+    constexpr int BI = K1D_BI, BJ = K1D_BJ;
     constexpr int SPL = dbl ? 2 : 4;
     constexpr int S = 4 * SPL;
-    const int BJ = csr.chunk;
     const int nJb = csr.nchunk;
     const int nIb = (n_occ + BI - 1) / BI;
     const int nSc = (B + S - 1) / S;
@@ -152,10 +139,9 @@ void k1d_apply(const T *A, const T *tau, const T *V, const T *u, const PairCSR &
     const long long nhi = (nrt + 7) / 8;
     const long long nblk = nhi * 8 * nIb * nSc;
     BSE_REQUIRE(nblk < (1LL << 31), BSE_ERR_ARG, "grid too large for the K1d kernel");
-    const size_t lds = (size_t)BJ * S * K1D_R * sizeof(T);
-    k_k1d<T, BI, SPL><<<(unsigned)nblk, 256, lds, st>>>(A, tau, V, u, csr.lo, csr.hi, csr.blk_nz,
-                                                        csr.col, csr.pidx, n_occ, B, nr, BJ, nIb,
-                                                        nJb, nSc, k1d, inv_omega, Cr, Dp);
+    k_k1d<T, BI, BJ, SPL><<<(unsigned)nblk, 256, 0, st>>>(A, tau, V, u, csr.tbl, csr.blk_nz, n_occ,
+                                                         B, nr, nIb, nJb, nSc, k1d, inv_omega, Cr,
+                                                         Dp);
     BSE_LAUNCH_CHECK();
     dim3 g2(div_up(nr, 256), (B + 1) / 2);
     k_sum_density<T><<<g2, 256, 0, st>>>(Dp, nIb, B, nr, Hc);
