@@ -174,13 +174,15 @@ bse_status bse_copy_tau(bse_ctx *c, int64_t p0, int64_t count, double *out) {
         return BSE_ERR_STATE;
     }
     BSE_GUARD({
-        const size_t len = (size_t)count * c->nr;
-        if (c->have_tau64)
-            BSE_HIP(hipMemcpyAsync(out, c->tau64.p + (size_t)p0 * c->nr, len * 8,
-                                   hipMemcpyDeviceToDevice, c->stream));
-        else
-            bse::convert<float, double>(c->tau32.p + (size_t)p0 * c->nr, out, (long long)len,
-                                        c->stream);
+        for (int64_t q = 0; q < count; q += 32768) {
+            const int64_t n = std::min<int64_t>(32768, count - q);
+            if (c->have_tau64)
+                bse::untile_tau<double>(c->tau64.p, p0 + q, n, c->n_pairs + 1, c->nr,
+                                        out + (size_t)q * c->nr, c->stream);
+            else
+                bse::untile_tau<float>(c->tau32.p, p0 + q, n, c->n_pairs + 1, c->nr,
+                                       out + (size_t)q * c->nr, c->stream);
+        }
         BSE_HIP(hipStreamSynchronize(c->stream));
     })
 }

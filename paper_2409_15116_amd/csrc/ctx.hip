@@ -286,11 +286,13 @@ void ctx_build_pairs(bse_ctx *c, int kind, double thr) {
         const int BI = K1D_BI, BJ = K1D_BJ;
         const int nIb = (no + BI - 1) / BI, nJb = (no + BJ - 1) / BJ;
         const long long P = c->n_pairs;
-        std::vector<long long> tbl((size_t)nIb * nJb * BI * BJ, P * c->nr);
+        BSE_REQUIRE((P + 1) * TAU_TILE < (1LL << 31), BSE_ERR_ARG, "too many pairs (%lld)", P);
+        std::vector<int> tbl((size_t)nIb * nJb * BI * BJ, (int)(P * TAU_TILE));
         std::vector<unsigned char> nz((size_t)nIb * nJb, 0);
         auto put = [&](int v, int w, long long p) {
             const int ib = v / BI, jb = w / BJ;
-            tbl[((size_t)(ib * nJb + jb) * BJ + (w - jb * BJ)) * BI + (v - ib * BI)] = p * c->nr;
+            tbl[((size_t)(ib * nJb + jb) * BJ + (w - jb * BJ)) * BI + (v - ib * BI)] =
+                (int)(p * TAU_TILE);
             nz[(size_t)ib * nJb + jb] = 1;
         };
         for (long long p = 0; p < c->n_pairs; ++p) {
@@ -298,11 +300,39 @@ void ctx_build_pairs(bse_ctx *c, int kind, double thr) {
             put(v, w, p);
             if (w != v) put(w, v, p);
         }
+        // visiting order: a round-robin tournament over the row blocks (circle
+        // method; an odd count gets a bye); in round r, row block I visits
+        // the column blocks of its partner's rows, and its own rows come last
+        const int nt = nIb + (nIb & 1);
+        auto partner = [&](int I, int r) {
+            if (I == nt - 1) return r;
+            if (I == r) return nt - 1;
+            return ((2 * r - I) % (nt - 1) + (nt - 1)) % (nt - 1);
+        };
+        auto group_of = [&](int jb) { return jb * BJ / BI; };
+        std::vector<int> order;
+        order.reserve((size_t)nIb * nJb);
+        for (int I = 0; I < nIb; ++I) {
+            const size_t start = order.size();
+            for (int r = 0; r < nt - 1; ++r) {
+                const int J = partner(I, r);
+                if (J >= nIb) continue;
+                for (int jb = 0; jb < nJb; ++jb)
+                    if (group_of(jb) == J) order.push_back(jb);
+            }
+            for (int jb = 0; jb < nJb; ++jb)
+                if (group_of(jb) == I) order.push_back(jb);
+            BSE_REQUIRE(order.size() - start == (size_t)nJb, BSE_ERR_STATE,
+                        "column-block order incomplete");
+        }
         up(c->csr_tbl, tbl);
         up(c->csr_nz, nz);
+        up(c->csr_order, order);
         c->csr.nchunk = nJb;
+        c->csr.n_rows = P + 1;
         c->csr.tbl = c->csr_tbl.p;
         c->csr.blk_nz = c->csr_nz.p;
+        c->csr.order = c->csr_order.p;
     }
     std::vector<int2> pd(c->n_pairs);
     for (long long p = 0; p < c->n_pairs; ++p) pd[p] = make_int2(pr[2 * p], pr[2 * p + 1]);
@@ -355,10 +385,10 @@ static void screen_impl(bse_ctx *c, const T *phi, const T *phif, int n_pdep, boo
         scale_grid<T>(Hc.p, vc, nr, nq, c->stream);
         pdep_scatter<T>(Hc.p, cnt, nr, c->idx_p.p, c->idx_m.p, sqv, nh, D.p, c->stream);
         grid_fft<T>(c->plan, Hc.p, nq, (T)1, tw, c->stream);
-        store_tau<T, T>(Hc.p, cnt, nr, tau_out + (size_t)p0 * nr, c->stream);
+        store_tau<T, T>(Hc.p, cnt, nr, tau_out, p0, P + 1, c->stream);
     }
     if (tau32_copy)
-        convert<double, float>((const double *)tau_out, tau32_copy, P * nr, c->stream);
+        convert<double, float>((const double *)tau_out, tau32_copy, tau_elems(P + 1, nr), c->stream);
     BSE_HIP(hipStreamSynchronize(c->stream));
 }
 
@@ -384,12 +414,13 @@ void ctx_screen(bse_ctx *c, const double *phi, const double *lam, int n_pdep, in
                      npw1, n_pdep, c->gws, c->stream);
     }
     drop_graph(c);
-    // tau carries one extra all-zero row (index P) for the K1d block tables
+    // tau carries one extra all-zero row (index P) for the K1d block tables;
+    // zeroing the whole tiled array also clears the padding of the last tile
+    const long long ne = tau_elems((long long)P + 1, (long long)nr);
     if (prec == BSE_FP64) {
-        c->tau64.alloc((P + 1) * nr);
-        c->tau32.alloc((P + 1) * nr);
-        zero<double>(c->tau64.p + P * nr, (long long)nr, c->stream);
-        zero<float>(c->tau32.p + P * nr, (long long)nr, c->stream);
+        c->tau64.alloc(ne);
+        c->tau32.alloc(ne);
+        zero<double>(c->tau64.p, ne, c->stream);
         screen_impl<double>(c, phi, phif.p, n_pdep, false, c->tau64.p, c->tau32.p);
         c->have_tau64 = c->have_tau32 = true;
     } else {
@@ -400,8 +431,8 @@ void ctx_screen(bse_ctx *c, const double *phi, const double *lam, int n_pdep, in
         convert<double, float>(phif.p, pf32.p, (long long)n_pdep * npw1, c->stream);
         c->tau64.free();
         c->have_tau64 = false;
-        c->tau32.alloc((P + 1) * nr);
-        zero<float>(c->tau32.p + P * nr, (long long)nr, c->stream);
+        c->tau32.alloc(ne);
+        zero<float>(c->tau32.p, ne, c->stream);
         screen_impl<float>(c, p32.p, pf32.p, n_pdep, prec == BSE_BF16X3, c->tau32.p, nullptr);
         c->have_tau32 = true;
     }

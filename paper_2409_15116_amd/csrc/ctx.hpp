@@ -96,8 +96,9 @@ struct bse_ctx {
     // pairs and tau
     std::vector<int> pairs_h;  // [P][2]
     bse::Dev<int2> pairs_d;
-    bse::Dev<long long> csr_tbl;
+    bse::Dev<int> csr_tbl;
     bse::Dev<unsigned char> csr_nz;
+    bse::Dev<int> csr_order;
     bse::PairCSR csr;
     long long n_pairs = 0;
     bool have_tau64 = false, have_tau32 = false;

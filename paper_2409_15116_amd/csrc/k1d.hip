@@ -1,0 +1,255 @@
+// The K1d product over the pair list (Eq. k1d), fused with the D potential
+// term and the K1e density (Eq. k1e):
+//   Cr[s][v](r) = V(r) a_{s,v}(r) - k1d sum_{w in N(v)} tau_{vw}(r) a_{s,w}(r)
+//   Dp[ib][s](r) = (1/Omega) sum_{v in row block ib} u_v(r) a_{s,v}(r)
+//
+// A workgroup owns 64 consecutive grid points (one per lane), a block of BI
+// output rows and S trial vectors; each of its four waves owns BI/4 of the
+// rows and all S vectors, so every tau value is loaded once per workgroup and
+// used for S products.  The (BI/4) x S accumulators of a wave live in
+// registers; the a values of BJ columns at a time are
+// staged in LDS (two buffers, one barrier per column block) and column blocks
+// without pairs in the row block are skipped.  Workgroups sharing grid points
+// are numbered so that they land on one XCD (workgroup id mod 8) close in
+// time, so their a tiles share that XCD's L2; each visits the column blocks
+// in the order order[ib][*], a round-robin schedule in which row blocks I and
+// J visit each other's columns in the same round (a kept pair's tau is then
+// read twice close in time) and the block of its own rows comes last (the
+// epilogue's a values were just staged).
+//
+// tbl[(ib * nJb + jb) * BI * BJ + w * BI + i] = offset (p * 64) inside a tau
+// tile of pair (v0 + i, j0 + w), or of the all-zero row P for pairs that are
+// not kept; blk_nz[ib * nJb + jb] marks blocks with any kept pair.  Every tau
+// load is unconditional: a buffer load whose scalar offset is the table entry
+// (in bytes) and whose vector offset is the lane, so it costs no vector
+// address arithmetic and the buffer's range check keeps it inside the tile.
+// With NBUF = 2 the tau values of two columns are in registers at once: while
+// column w is being used, column w + 1 is already in flight and column w + 2
+// is requested right after column w's last product.
+#include "kernels.hpp"
+
+namespace bse {
+
+constexpr int K1D_R = 64;
+
+template <typename T>
+__device__ inline T tau_load(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    if constexpr (sizeof(T) == 4)
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    else
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+template <typename T, int BW, int S>
+__device__ inline void k1d_column(T (&acc)[BW][S], const T (&t)[BW], const T *col, int lane) {
+    T aw[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) aw[j] = col[j * K1D_R + lane];
+#pragma unroll
+    for (int i = 0; i < BW; ++i)
+#pragma unroll
+        for (int j = 0; j < S; ++j) acc[i][j] += t[i] * aw[j];
+}
+
+template <typename T, int BW>
+__device__ inline void k1d_request(T (&t)[BW], __amdgpu_buffer_rsrc_t trs, int voff,
+                                   const int *tb) {
+#pragma unroll
+    for (int i = 0; i < BW; ++i) t[i] = tau_load<T>(trs, voff, tb[i] * (int)sizeof(T));
+}
+
+template <typename T, int BI, int BJ, int S, int NBUF>
+__global__ void __launch_bounds__(256) k_k1d(const T *__restrict__ A, const T *__restrict__ tau,
+                                             const T *__restrict__ V, const T *__restrict__ u,
+                                             const int *__restrict__ tbl,
+                                             const unsigned char *__restrict__ blk_nz,
+                                             const int *__restrict__ order, int n_occ,
+                                             int B, long long nr, long long n_rows, int nIb,
+                                             int nJb, int nSc, T k1d, T inv_omega,
+                                             T *__restrict__ Cr, T *__restrict__ Dp) {
+    static_assert(NBUF == 1 || (NBUF == 2 && BJ % 2 == 0), "NBUF 1, or 2 with an even BJ");
+    static_assert(BI % 4 == 0, "four waves share the rows");
+    constexpr int BW = BI / 4;  // rows per wave
+    constexpr int TILE = BJ * S * K1D_R;
+    constexpr int PER_T = TILE / 256;  // a values staged per thread
+    static_assert(TILE % 256 == 0 && 4 * S * K1D_R <= 2 * TILE, "tile shapes");
+    __shared__ T tile[2][TILE];
+    // decode: id = 8 * (hi8 * nIb * nSc + ib * nSc + sc) + lo8, r-tile = hi8 * 8 + lo8
+    const int id = blockIdx.x;
+    const int lo8 = id & 7;
+    int rest = id >> 3;
+    const int sc = rest % nSc;
+    rest /= nSc;
+    const int ib = rest % nIb;
+    const int hi8 = rest / nIb;
+    const long long rt = (long long)hi8 * 8 + lo8;
+    const long long r0 = rt * K1D_R;
+    if (r0 >= nr) return;
+    const int tid = threadIdx.x, lane = tid & 63;
+    // wave-uniform indices keep the a-tile and output addresses scalar
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const long long rr = r0 + lane < nr ? r0 + lane : nr - 1;  // clamp: loads stay in bounds
+    const bool rok = r0 + lane < nr;
+    const int s0 = sc * S;
+    const int v0 = ib * BI + wv * BW;  // this wave's first row
+    const size_t sstride = (size_t)n_occ * nr;
+    const __amdgpu_buffer_rsrc_t trs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(tau + rt * n_rows * TAU_TILE), (short)0, (int)(n_rows * TAU_TILE * sizeof(T)),
+        0x00020000);
+    const int voff = lane * (int)sizeof(T);
+    // this row block's tables, at this wave's rows
+    const int *tbr = tbl + (size_t)ib * nJb * BI * BJ + wv * BW;
+    const unsigned char *nzr = blk_nz + (size_t)ib * nJb;
+    const int *ordr = order + (size_t)ib * nJb;
+
+    // a values of column block jb into tile[b]: row (w * S + s) of the tile is
+    // staged by wave (w * S + s) % 4, one point per lane; rows past n_occ,
+    // vectors past B and points past nr read a clamped valid element (their
+    // products either meet a zero tau or are never stored)
+    auto stage_a = [&](int jb, int b) {
+#pragma unroll
+        for (int l = 0; l < PER_T; ++l) {
+            const int row = wv + 4 * l;
+            const int s = row % S, w = row / S;
+            const int vv = min(jb * BJ + w, n_occ - 1);
+            const int ss = min(s0 + s, B - 1);
+            const T *src = A + (size_t)ss * sstride + (size_t)vv * nr;
+            tile[b][row * K1D_R + lane] = src[rr];
+        }
+    };
+    // position of the next visited column block with kept pairs, or nJb
+    auto next_nz = [&](int k) {
+        int j = k + 1;
+        while (j < nJb && !nzr[ordr[j]]) ++j;
+        return j;
+    };
+
+    T acc[BW][S];
+#pragma unroll
+    for (int i = 0; i < BW; ++i)
+#pragma unroll
+        for (int j = 0; j < S; ++j) acc[i][j] = 0;
+
+    int kb = next_nz(-1);
+    if (kb < nJb) {
+        int jb = ordr[kb];
+        T t0[BW], t1[BW];
+        k1d_request<T, BW>(t0, trs, voff, tbr + (size_t)jb * BI * BJ);
+        if (NBUF == 2) k1d_request<T, BW>(t1, trs, voff, tbr + (size_t)jb * BI * BJ + BI);
+        stage_a(jb, 0);
+        __syncthreads();
+        int buf = 0;
+        while (kb < nJb) {
+            const int kn = next_nz(kb);
+            const int jn = kn < nJb ? ordr[kn] : nJb;
+            const int jf = kn < nJb ? jn : jb;  // past the last block: harmless reloads
+            const int *tb = tbr + (size_t)jb * BI * BJ;
+            const int *tn = tbr + (size_t)jf * BI * BJ;
+            const T *tl = tile[buf];
+            if constexpr (NBUF == 1) {
+#pragma unroll 1
+                for (int w = 0; w < BJ; ++w) {
+                    k1d_column<T, BW, S>(acc, t0, tl + w * S * K1D_R, lane);
+                    k1d_request<T, BW>(t0, trs, voff, w + 1 < BJ ? tb + (w + 1) * BI : tn);
+                }
+            } else {
+#pragma unroll 1
+                for (int w = 0; w < BJ; w += 2) {
+                    const int *n0 = w + 2 < BJ ? tb + (w + 2) * BI : tn + (w + 2 - BJ) * BI;
+                    const int *n1 = w + 3 < BJ ? tb + (w + 3) * BI : tn + (w + 3 - BJ) * BI;
+                    k1d_column<T, BW, S>(acc, t0, tl + w * S * K1D_R, lane);
+                    __builtin_amdgcn_sched_barrier(0);
+                    k1d_request<T, BW>(t0, trs, voff, n0);
+                    __builtin_amdgcn_sched_barrier(0);
+                    k1d_column<T, BW, S>(acc, t1, tl + (w + 1) * S * K1D_R, lane);
+                    __builtin_amdgcn_sched_barrier(0);
+                    k1d_request<T, BW>(t1, trs, voff, n1);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            // the other buffer was last read before the previous barrier
+            if (kn < nJb) stage_a(jn, buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
+            kb = kn;
+            jb = jn;
+        }
+    }
+    // epilogue: Cr for this wave's rows, and the K1e density of the row block
+    // summed over the four waves through LDS (the tiles are free after the
+    // loop's last barrier)
+    const T vr = V[rr];
+    T *red = &tile[0][0];  // [4][S][64]
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const int s = min(s0 + j, B - 1);
+        T dn = 0;
+#pragma unroll
+        for (int i = 0; i < BW; ++i) {
+            const int v = v0 + i;
+            if (v < n_occ) {
+                const size_t off = (size_t)s * sstride + (size_t)v * nr;
+                const T av = A[off + rr];
+                if (rok && s0 + j < B) Cr[off + rr] = vr * av - k1d * acc[i][j];
+                dn += u[(size_t)v * nr + rr] * av;
+            }
+        }
+        red[(wv * S + j) * K1D_R + lane] = dn;
+    }
+    __syncthreads();
+    for (int j = wv; j < S; j += 4) {
+        const T d = red[(0 * S + j) * K1D_R + lane] + red[(1 * S + j) * K1D_R + lane] +
+                    red[(2 * S + j) * K1D_R + lane] + red[(3 * S + j) * K1D_R + lane];
+        if (rok && s0 + j < B) Dp[((size_t)ib * B + s0 + j) * nr + rr] = d * inv_omega;
+    }
+}
+
+// Hc[s/2](r).{x|y} = sum_ib Dp[ib][s](r)  (fixed order: deterministic)
+template <typename T>
+__global__ void k_sum_density(const T *__restrict__ Dp, int nIb, int B, long long nr,
+                              cplx<T> *__restrict__ Hc) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = blockIdx.y;
+    if (i >= nr) return;
+    T a = 0, b = 0;
+    for (int ib = 0; ib < nIb; ++ib) {
+        a += Dp[((size_t)ib * B + 2 * q) * nr + i];
+        if (2 * q + 1 < B) b += Dp[((size_t)ib * B + 2 * q + 1) * nr + i];
+    }
+    Hc[(size_t)q * nr + i] = cmake<cplx<T>>(a, b);
+}
+
+template <typename T>
+void k1d_apply(const T *A, const T *tau, const T *V, const T *u, const PairCSR &csr, int n_occ,
+               int B, long long nr, T k1d, T inv_omega, T *Cr, cplx<T> *Hc, T *Dp,
+               hipStream_t st) {
+    constexpr bool dbl = sizeof(T) == 8;
+    constexpr int BI = K1D_BI, BJ = K1D_BJ;
+    constexpr int S = dbl ? K1D_S64 : K1D_S32;
+    constexpr int NBUF = dbl ? K1D_NBUF64 : K1D_NBUF32;
+    const int nJb = csr.nchunk;
+    const int nIb = (n_occ + BI - 1) / BI;
+    const int nSc = (B + S - 1) / S;
+    const long long nrt = (nr + K1D_R - 1) / K1D_R;
+    const long long nhi = (nrt + 7) / 8;
+    const long long nblk = nhi * 8 * nIb * nSc;
+    BSE_REQUIRE(nblk < (1LL << 31), BSE_ERR_ARG, "grid too large for the K1d kernel");
+    BSE_REQUIRE(csr.n_rows * TAU_TILE * (long long)sizeof(T) < (1LL << 31), BSE_ERR_ARG,
+                "too many pairs for the K1d tables");
+    k_k1d<T, BI, BJ, S, NBUF><<<(unsigned)nblk, 256, 0, st>>>(
+        A, tau, V, u, csr.tbl, csr.blk_nz, csr.order, n_occ, B, nr, csr.n_rows, nIb, nJb, nSc, k1d,
+        inv_omega, Cr, Dp);
+    BSE_LAUNCH_CHECK();
+    dim3 g2(div_up(nr, 256), (B + 1) / 2);
+    k_sum_density<T><<<g2, 256, 0, st>>>(Dp, nIb, B, nr, Hc);
+    BSE_LAUNCH_CHECK();
+}
+
+template void k1d_apply<float>(const float *, const float *, const float *, const float *,
+                               const PairCSR &, int, int, long long, float, float, float *,
+                               cplx<float> *, float *, hipStream_t);
+template void k1d_apply<double>(const double *, const double *, const double *, const double *,
+                                const PairCSR &, int, int, long long, double, double, double *,
+                                cplx<double> *, double *, hipStream_t);
+
+}  // namespace bse

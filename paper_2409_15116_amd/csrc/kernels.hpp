@@ -39,18 +39,40 @@ struct Workspace {
     }
 };
 
+// Device layout of the screened integrals: tile-major over 64-point tiles of
+// the grid, tau_p(r) at ((r / 64) * (P + 1) + p) * 64 + r % 64, with P + 1
+// rows (row P all zero) and the last tile padded to 64 points.  One grid tile
+// of every pair is one contiguous block, so the K1d kernel, which walks all
+// pairs of a row block at fixed grid points, reads a compact region.
+constexpr int TAU_TILE = 64;
+inline long long tau_elems(long long n_rows, long long nr) {
+    return (nr + TAU_TILE - 1) / TAU_TILE * TAU_TILE * n_rows;
+}
+
 // Pair list for the K1d kernel: rows in blocks of K1D_BI, columns in blocks
-// of K1D_BJ; tbl[(ib * nchunk + jb) * BI * BJ + w * BI + i] is the element
-// offset (row * nr) of the tau row of pair (ib*BI + i, jb*BJ + w), or of the
-// zero row P when the pair is not kept;
-// blk_nz[ib * nchunk + jb] marks blocks holding any kept pair.  tau carries
-// P + 1 rows, the last one zero.
-constexpr int K1D_BI = 32;
+// of K1D_BJ; tbl[(ib * nchunk + jb) * BI * BJ + w * BI + i] is the offset
+// (p * 64) inside a tau tile of pair p = (ib*BI + i, jb*BJ + w), or of the
+// zero row P when the pair is not kept; blk_nz[ib * nchunk + jb] marks blocks
+// holding any kept pair.  n_rows = P + 1.
+// Block shape of the K1d kernel (compile-time tunables): BI rows x BJ columns
+// per table block, S trial vectors per workgroup, NBUF columns of tau in flight.
+#ifndef BSE_K1D_BI
+#define BSE_K1D_BI 32
+#endif
+#ifndef BSE_K1D_NBUF32
+#define BSE_K1D_NBUF32 2
+#endif
+constexpr int K1D_BI = BSE_K1D_BI;
 constexpr int K1D_BJ = 8;
+constexpr int K1D_S32 = 16, K1D_S64 = 8;
+constexpr int K1D_NBUF32 = BSE_K1D_NBUF32, K1D_NBUF64 = 1;
+// order[ib * nchunk + k] is the k-th column block that row block ib visits.
 struct PairCSR {
     int nchunk = 0;
-    long long *tbl = nullptr;
+    long long n_rows = 0;
+    int *tbl = nullptr;
     unsigned char *blk_nz = nullptr;
+    int *order = nullptr;
 };
 
 // Dp: [ceil(n_occ / K1D_BI)][B][nr] partial K1e densities
@@ -70,7 +92,12 @@ template <typename T>
 void pdep_scatter(cplx<T> *Hc, int count, long long nr, const int *idx_p, const int *idx_m,
                   const T *sqv, int nh, const T *D, hipStream_t st);
 template <typename T, typename TS>
-void store_tau(const cplx<T> *Hc, int count, long long nr, TS *tau, hipStream_t st);
+void store_tau(const cplx<T> *Hc, int count, long long nr, TS *tau, long long p0, long long n_rows,
+               hipStream_t st);
+// out[p][r] (FP64, row-major) = tau_{p0 + p}(r) for p < count, from the tiled layout
+template <typename TS>
+void untile_tau(const TS *tau, long long p0, long long count, long long n_rows, long long nr,
+                double *out, hipStream_t st);
 template <typename TI, typename TO>
 void convert(const TI *a, TO *b, long long n, hipStream_t st);
 template <typename T>

@@ -5,150 +5,6 @@
 namespace bse {
 
 // ---------------------------------------------------------------------------
-// K1d over the pair list (Eq. k1d) fused with the D potential term and the
-// K1e density (Eq. k1e):
-//   Cr[s][v](r) = V(r) a_{s,v}(r) - k1d sum_{w in N(v)} tau_{vw}(r) a_{s,w}(r)
-//   Dp[ib][s](r) = (1/Omega) sum_{v in row block ib} u_v(r) a_{s,v}(r)
-// A workgroup owns 64 consecutive grid points (one per lane), a block of BI
-// output rows and 4*SPL trial vectors (SPL per wave).  The BI x SPL
-// accumulators live in registers; the a values of BJ columns at a time are
-// staged in LDS and column blocks without pairs in the row block are skipped.
-// Blocks sharing grid points are numbered so that they land on one XCD
-// (workgroup id mod 8) close in time, so their a tiles share that XCD's L2.
-// ---------------------------------------------------------------------------
-constexpr int K1D_R = 64;
-
-// tbl[(ib * nJb + jb) * BI * BJ + w * BI + i] = element offset (p * nr) of the
-// tau row of pair (v0 + i, j0 + w), or of the all-zero row P for pairs that
-// are not kept; blk_nz[ib * nJb + jb] marks blocks with any kept pair.  Every
-// tau load is then unconditional and independent (a column's BI loads are
-// issued together), and a column's a values are read from LDS once for BI rows.
-template <typename T, int BI, int BJ, int SPL>
-__global__ void __launch_bounds__(256) k_k1d(const T *__restrict__ A, const T *__restrict__ tau,
-                                             const T *__restrict__ V, const T *__restrict__ u,
-                                             const long long *__restrict__ tbl,
-                                             const unsigned char *__restrict__ blk_nz, int n_occ,
-                                             int B, long long nr, int nIb, int nJb, int nSc,
-                                             T k1d, T inv_omega, T *__restrict__ Cr,
-                                             T *__restrict__ Dp) {
-    constexpr int S = 4 * SPL;
-    __shared__ T tile[BJ * S * K1D_R];
-    // decode: id = 8 * (hi8 * nIb * nSc + ib * nSc + sc) + lo8, r-tile = hi8 * 8 + lo8
-    const int id = blockIdx.x;
-    const int lo8 = id & 7;
-    int rest = id >> 3;
-    const int sc = rest % nSc;
-    rest /= nSc;
-    const int ib = rest % nIb;
-    const int hi8 = rest / nIb;
-    const long long rt = (long long)hi8 * 8 + lo8;
-    const long long r0 = rt * K1D_R;
-    if (r0 >= nr) return;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const long long rr = r0 + lane < nr ? r0 + lane : nr - 1;  // clamp: loads stay in bounds
-    const bool rok = r0 + lane < nr;
-    const int s0 = sc * S;
-    const int v0 = ib * BI;
-    const size_t sstride = (size_t)n_occ * nr;
-    T acc[BI][SPL];
-#pragma unroll
-    for (int i = 0; i < BI; ++i)
-#pragma unroll
-        for (int j = 0; j < SPL; ++j) acc[i][j] = 0;
-    for (int jb = 0; jb < nJb; ++jb) {
-        if (!blk_nz[ib * nJb + jb]) continue;  // uniform across the workgroup
-        const int j0 = jb * BJ;
-        __syncthreads();
-        for (int i = threadIdx.x; i < BJ * S * K1D_R; i += 256) {
-            const int r = i & (K1D_R - 1);
-            const int s = (i / K1D_R) % S;
-            const int w = i / (K1D_R * S);
-            const long long q = r0 + r;
-            T val = 0;
-            if (j0 + w < n_occ && s0 + s < B && q < nr)
-                val = A[(size_t)(s0 + s) * sstride + (size_t)(j0 + w) * nr + q];
-            tile[i] = val;
-        }
-        __syncthreads();
-        const long long *tb = tbl + (size_t)(ib * nJb + jb) * BI * BJ;
-        const int lr = (int)rr;  // lane offset inside a tau row (nr < 2^31)
-#pragma unroll
-        for (int w = 0; w < BJ; ++w) {
-            // all BI tau loads of this column first, then the FMAs: BI loads in flight
-            T t[BI];
-#pragma unroll
-            for (int i = 0; i < BI; ++i) t[i] = (tau + tb[w * BI + i])[lr];
-            __builtin_amdgcn_sched_barrier(0);
-            T aw[SPL];
-#pragma unroll
-            for (int j = 0; j < SPL; ++j) aw[j] = tile[(w * S + wave * SPL + j) * K1D_R + lane];
-#pragma unroll
-            for (int i = 0; i < BI; ++i)
-#pragma unroll
-                for (int j = 0; j < SPL; ++j) acc[i][j] += t[i] * aw[j];
-        }
-    }
-    if (!rok) return;
-    const T vr = V[rr];
-#pragma unroll
-    for (int j = 0; j < SPL; ++j) {
-        const int s = s0 + wave * SPL + j;
-        if (s >= B) continue;
-        T dn = 0;
-#pragma unroll
-        for (int i = 0; i < BI; ++i) {
-            const int v = v0 + i;
-            if (v < n_occ) {
-                const size_t off = (size_t)s * sstride + (size_t)v * nr + rr;
-                const T av = A[off];
-                Cr[off] = vr * av - k1d * acc[i][j];
-                dn += u[(size_t)v * nr + rr] * av;
-            }
-        }
-        Dp[((size_t)ib * B + s) * nr + rr] = dn * inv_omega;
-    }
-}
-
-// Hc[s/2](r).{x|y} = sum_ib Dp[ib][s](r)  (fixed order: deterministic)
-template <typename T>
-__global__ void k_sum_density(const T *__restrict__ Dp, int nIb, int B, long long nr,
-                              cplx<T> *__restrict__ Hc) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int q = blockIdx.y;
-    if (i >= nr) return;
-    T a = 0, b = 0;
-    for (int ib = 0; ib < nIb; ++ib) {
-        a += Dp[((size_t)ib * B + 2 * q) * nr + i];
-        if (2 * q + 1 < B) b += Dp[((size_t)ib * B + 2 * q + 1) * nr + i];
-    }
-    Hc[(size_t)q * nr + i] = cmake<cplx<T>>(a, b);
-}
-
-template <typename T>
-void k1d_apply(const T *A, const T *tau, const T *V, const T *u, const PairCSR &csr, int n_occ,
-               int B, long long nr, T k1d, T inv_omega, T *Cr, cplx<T> *Hc, T *Dp,
-               hipStream_t st) {
-    constexpr bool dbl = sizeof(T) == 8;
-    constexpr int BI = K1D_BI, BJ = K1D_BJ;
-    constexpr int SPL = dbl ? 2 : 4;
-    constexpr int S = 4 * SPL;
-    const int nJb = csr.nchunk;
-    const int nIb = (n_occ + BI - 1) / BI;
-    const int nSc = (B + S - 1) / S;
-    const long long nrt = (nr + K1D_R - 1) / K1D_R;
-    const long long nhi = (nrt + 7) / 8;
-    const long long nblk = nhi * 8 * nIb * nSc;
-    BSE_REQUIRE(nblk < (1LL << 31), BSE_ERR_ARG, "grid too large for the K1d kernel");
-    k_k1d<T, BI, BJ, SPL><<<(unsigned)nblk, 256, 0, st>>>(A, tau, V, u, csr.tbl, csr.blk_nz, n_occ,
-                                                         B, nr, nIb, nJb, nSc, k1d, inv_omega, Cr,
-                                                         Dp);
-    BSE_LAUNCH_CHECK();
-    dim3 g2(div_up(nr, 256), (B + 1) / 2);
-    k_sum_density<T><<<g2, 256, 0, st>>>(Dp, nIb, B, nr, Hc);
-    BSE_LAUNCH_CHECK();
-}
-
-// ---------------------------------------------------------------------------
 // Hc[b][G] *= w[G]  (Coulomb kernel 4 pi/|G|^2 / N_r, or any real weight)
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -269,22 +125,44 @@ void pdep_scatter(cplx<T> *Hc, int count, long long nr, const int *idx_p, const 
     BSE_LAUNCH_CHECK();
 }
 
-// tau[2q] = Re Hc[q], tau[2q+1] = Im Hc[q]
+// tau_{p0+2q} = Re Hc[q], tau_{p0+2q+1} = Im Hc[q], into the tiled layout
 template <typename T, typename TS>
 __global__ void k_store_tau(const cplx<T> *__restrict__ Hc, int count, long long nr,
-                            TS *__restrict__ tau) {
+                            TS *__restrict__ tau, long long p0, long long n_rows) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int q = blockIdx.y;
     if (i >= nr) return;
     const cplx<T> h = Hc[(size_t)q * nr + i];
-    tau[(size_t)(2 * q) * nr + i] = (TS)h.x;
-    if (2 * q + 1 < count) tau[(size_t)(2 * q + 1) * nr + i] = (TS)h.y;
+    const size_t base = (size_t)(i / TAU_TILE) * n_rows * TAU_TILE + (i % TAU_TILE);
+    tau[base + (size_t)(p0 + 2 * q) * TAU_TILE] = (TS)h.x;
+    if (2 * q + 1 < count) tau[base + (size_t)(p0 + 2 * q + 1) * TAU_TILE] = (TS)h.y;
 }
 
 template <typename T, typename TS>
-void store_tau(const cplx<T> *Hc, int count, long long nr, TS *tau, hipStream_t st) {
+void store_tau(const cplx<T> *Hc, int count, long long nr, TS *tau, long long p0, long long n_rows,
+               hipStream_t st) {
     dim3 grid(div_up(nr, 256), (count + 1) / 2);
-    k_store_tau<T, TS><<<grid, 256, 0, st>>>(Hc, count, nr, tau);
+    k_store_tau<T, TS><<<grid, 256, 0, st>>>(Hc, count, nr, tau, p0, n_rows);
+    BSE_LAUNCH_CHECK();
+}
+
+template <typename TS>
+__global__ void k_untile_tau(const TS *__restrict__ tau, long long p0, long long n_rows,
+                             long long nr, double *__restrict__ out) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long p = blockIdx.y;
+    if (i >= nr) return;
+    out[(size_t)p * nr + i] =
+        (double)tau[(size_t)(i / TAU_TILE) * n_rows * TAU_TILE + (size_t)(p0 + p) * TAU_TILE + i % TAU_TILE];
+}
+
+template <typename TS>
+void untile_tau(const TS *tau, long long p0, long long count, long long n_rows, long long nr,
+                double *out, hipStream_t st) {
+    if (count <= 0) return;
+    BSE_REQUIRE(count < 65536, BSE_ERR_ARG, "copy at most 65535 pairs per call");
+    dim3 grid(div_up(nr, 256), (unsigned)count);
+    k_untile_tau<TS><<<grid, 256, 0, st>>>(tau, p0, n_rows, nr, out);
     BSE_LAUNCH_CHECK();
 }
 
@@ -408,12 +286,6 @@ void zero(T *a, long long n, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-template void k1d_apply<float>(const float *, const float *, const float *, const float *,
-                               const PairCSR &, int, int, long long, float, float, float *,
-                               cplx<float> *, float *, hipStream_t);
-template void k1d_apply<double>(const double *, const double *, const double *, const double *,
-                                const PairCSR &, int, int, long long, double, double, double *,
-                                cplx<double> *, double *, hipStream_t);
 template void scale_grid<float>(cplx<float> *, const float *, long long, int, hipStream_t);
 template void scale_grid<double>(cplx<double> *, const double *, long long, int, hipStream_t);
 template void pair_density<float>(const float *, const int2 *, int, int, long long, float,
@@ -428,11 +300,14 @@ template void pdep_scatter<float>(cplx<float> *, int, long long, const int *, co
                                   const float *, int, const float *, hipStream_t);
 template void pdep_scatter<double>(cplx<double> *, int, long long, const int *, const int *,
                                    const double *, int, const double *, hipStream_t);
-template void store_tau<float, float>(const cplx<float> *, int, long long, float *, hipStream_t);
-template void store_tau<double, double>(const cplx<double> *, int, long long, double *,
-                                        hipStream_t);
-template void store_tau<double, float>(const cplx<double> *, int, long long, float *,
-                                       hipStream_t);
+template void store_tau<float, float>(const cplx<float> *, int, long long, float *, long long,
+                                      long long, hipStream_t);
+template void store_tau<double, double>(const cplx<double> *, int, long long, double *, long long,
+                                        long long, hipStream_t);
+template void untile_tau<float>(const float *, long long, long long, long long, long long, double *,
+                                hipStream_t);
+template void untile_tau<double>(const double *, long long, long long, long long, long long,
+                                 double *, hipStream_t);
 template void convert<double, float>(const double *, float *, long long, hipStream_t);
 template void convert<float, double>(const float *, double *, long long, hipStream_t);
 template void convert<double, double>(const double *, double *, long long, hipStream_t);

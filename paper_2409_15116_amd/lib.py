@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libbse.so")
+# BSE_LIBRARY selects another build of the same library (e.g. other tunables)
+LIB_PATH = os.environ.get("BSE_LIBRARY") or os.path.join(HERE, "libbse.so")
 
 FP64, FP32, BF16X3 = 0, 1, 2
 MEASURE_ABS_L1, MEASURE_OVERLAP = 0, 1
