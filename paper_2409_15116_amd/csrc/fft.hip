@@ -16,6 +16,44 @@
 
 namespace bse {
 
+// Threads per workgroup of every FFT kernel.
+constexpr int FFT_NT = 256;
+
+// Lines per workgroup: a power of two, as many as fit a 64 KB LDS tile (two
+// buffers of n * C elements plus n twiddles), at most 64.  Compile-time, so
+// that every staging loop has a constant trip count and unrolls.
+template <typename T, int N>
+struct FftTile {
+    static constexpr size_t esz = 2 * sizeof(T);
+    static constexpr int pick() {
+        int c = 64;
+        while (c > 2 && (size_t)(2 * N * c + N) * esz > 64 * 1024) c /= 2;
+        return c;
+    }
+    static constexpr int C = pick();
+    static constexpr int lc = C == 64 ? 6 : C == 32 ? 5 : C == 16 ? 4 : C == 8 ? 3 : C == 4 ? 2 : 1;
+    static constexpr size_t lds = (size_t)(2 * N * C + N) * esz;
+    static_assert((1 << lc) == C, "tile width");
+};
+
+// Element loop of a staging pass: i = k * FFT_NT + threadIdx.x for every
+// i < TOTAL, with a compile-time trip count so that it unrolls and all of a
+// thread's global loads are issued before the first is waited on.
+#define FFT_FOR(i, TOTAL)                                                                 \
+    _Pragma("unroll") for (int k_##i = 0; k_##i < ((TOTAL) + FFT_NT - 1) / FFT_NT; ++k_##i) \
+        if (const int i = k_##i * FFT_NT + (int)threadIdx.x; (TOTAL) % FFT_NT == 0 || i < (TOTAL))
+
+// v if ok, else 0, as a product with a 0/1 mask: the load of v (made at a
+// clamped, in-bounds address, so v is finite) stays unconditional and can be
+// issued together with the other loads of the staging pass, instead of being
+// moved behind a branch
+template <typename C2>
+__device__ inline C2 keep_if(C2 v, bool ok) {
+    using T = decltype(v.x);
+    const T m = ok ? (T)1 : (T)0;
+    return cmake<C2>(v.x * m, v.y * m);
+}
+
 // ------------------------------------------------------------------ butterflies
 template <typename C2, typename T>
 __device__ inline void bfly2(C2 *v, T) {
@@ -87,15 +125,19 @@ constexpr int fft_factor(int n, int at) {
 // One Stockham stage of radix R for lines of compile-time length N after
 // stages whose radices multiply to NS; C (a power of two, 1 << lc) lines in
 // LDS at addr = e * C + c.
-template <int R, int N, int NS, typename T>
-__device__ inline void stage(const cplx<T> *__restrict__ src, cplx<T> *__restrict__ dst,
-                             const cplx<T> *__restrict__ tw, int lc, T sign) {
+template <int R, int N, int NS, int LC, typename T>
+__device__ __forceinline__ void stage(const cplx<T> *__restrict__ src, cplx<T> *__restrict__ dst,
+                             const cplx<T> *__restrict__ tw, T sign) {
     using C2 = cplx<T>;
     constexpr int nR = N / R;
     constexpr int twstep = N / (NS * R);
-    const int C = 1 << lc;
-    const int total = nR << lc;
-    for (int b = threadIdx.x; b < total; b += blockDim.x) {
+    constexpr int lc = LC;
+    constexpr int C = 1 << lc;
+    constexpr int total = nR << lc;
+#pragma unroll
+    for (int b0 = 0; b0 < total; b0 += FFT_NT) {
+        const int b = b0 + (int)threadIdx.x;
+        if (total % FFT_NT != 0 && b >= total) continue;
         const int j = b >> lc;
         const int c = b & (C - 1);
         const int k = j % NS;
@@ -119,29 +161,30 @@ __device__ inline void stage(const cplx<T> *__restrict__ src, cplx<T> *__restric
     }
 }
 
-template <typename T, int N, int ST, int NS>
-__device__ inline cplx<T> *fft_stages(cplx<T> *a, cplx<T> *b, const cplx<T> *tw, int lc, T sign) {
+template <typename T, int N, int ST, int NS, int LC>
+__device__ __forceinline__ cplx<T> *fft_stages(cplx<T> *a, cplx<T> *b, const cplx<T> *tw, T sign) {
     if constexpr (ST < fft_nfactors(N)) {
         constexpr int R = fft_factor(N, ST);
-        stage<R, N, NS, T>(a, b, tw, lc, sign);
+        stage<R, N, NS, LC, T>(a, b, tw, sign);
         __syncthreads();
-        return fft_stages<T, N, ST + 1, NS * R>(b, a, tw, lc, sign);
+        return fft_stages<T, N, ST + 1, NS * R, LC>(b, a, tw, sign);
     } else {
         return a;
     }
 }
 
-// FFT of 1 << lc lines of length N held in LDS buffer a (layout e*C + c); b is
-// scratch of the same size.  sign = -1 forward, +1 inverse (unnormalised).
-// Returns the buffer holding the result.  Ends with a barrier.
+// FFT of the C = FftTile<T, N>::C lines of length N held in LDS buffer a
+// (layout e*C + c); b is scratch of the same size.  sign = -1 forward, +1
+// inverse (unnormalised).  Returns the buffer holding the result.  Ends with a
+// barrier.
 template <typename T, int N>
-__device__ cplx<T> *lds_fft(cplx<T> *a, cplx<T> *b, const cplx<T> *tw, int lc, T sign) {
-    return fft_stages<T, N, 0, 1>(a, b, tw, lc, sign);
+__device__ __forceinline__ cplx<T> *lds_fft(cplx<T> *a, cplx<T> *b, const cplx<T> *tw, T sign) {
+    return fft_stages<T, N, 0, 1, FftTile<T, N>::lc>(a, b, tw, sign);
 }
 
 template <typename T>
 __device__ inline void load_twiddles(cplx<T> *tw_lds, const cplx<T> *tw, int n) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) tw_lds[i] = tw[i];
+    for (int i = threadIdx.x; i < n; i += FFT_NT) tw_lds[i] = tw[i];
 }
 
 // Pairing of real orbitals into complex transforms: line q holds orbitals
@@ -160,20 +203,21 @@ __global__ void __launch_bounds__(256) k_sph_inv_z(const T *__restrict__ X, int 
                                                    const int2 *__restrict__ ent,
                                                    const int *__restrict__ col_ptr, int ncol,
                                                    int n_lines, cplx<T> *__restrict__ T1,
-                                                   const cplx<T> *__restrict__ tw, int lc, int ps) {
+                                                   const cplx<T> *__restrict__ tw, int ps) {
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
     constexpr int n = N;
-    const int C = 1 << lc;
+    constexpr int C = FftTile<T, N>::C;
+    constexpr int lc = FftTile<T, N>::lc;
     C2 *sb = sa + n * C;
     C2 *stw = sb + n * C;
-    load_twiddles<T>(stw, tw, n);
     const int L0 = blockIdx.x * C;
-    for (int i = threadIdx.x; i < n * C; i += blockDim.x) sa[i] = cmake<C2>(0, 0);
+    FFT_FOR(i, n * C) sa[i] = cmake<C2>(0, 0);
+    load_twiddles<T>(stw, tw, n);
     __syncthreads();
     const T isq2 = (T)0.70710678118654752440;
-    const int nwave = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nwave = FFT_NT >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int c = wave; c < C; c += nwave) {
         const int L = L0 + c;
         if (L >= n_lines) break;
@@ -200,8 +244,8 @@ __global__ void __launch_bounds__(256) k_sph_inv_z(const T *__restrict__ X, int 
         }
     }
     __syncthreads();
-    C2 *res = lds_fft<T, N>(sa, sb, stw, lc, (T)1);
-    for (int i = threadIdx.x; i < n * C; i += blockDim.x) {
+    C2 *res = lds_fft<T, N>(sa, sb, stw, (T)1);
+    FFT_FOR(i, n * C) {
         const int c = i / n, z = i - c * n;
         const int L = L0 + c;
         if (L < n_lines) T1[(size_t)L * n + z] = res[z * C + c];
@@ -214,15 +258,15 @@ __global__ void __launch_bounds__(256) k_sph_inv_y(const cplx<T> *__restrict__ T
                                                    const int *__restrict__ colmap,
                                                    const int *__restrict__ xlist, int nxp, int ncol,
                                                    cplx<T> *__restrict__ T2,
-                                                   const cplx<T> *__restrict__ tw, int lc, int nzt) {
+                                                   const cplx<T> *__restrict__ tw, int nzt) {
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
     constexpr int n = N;
-    const int C = 1 << lc;
+    constexpr int C = FftTile<T, N>::C;
+    constexpr int lc = FftTile<T, N>::lc;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
     C2 *sb = sa + n * C;
     C2 *stw = sb + n * C;
-    load_twiddles<T>(stw, tw, n);
     int bid = blockIdx.x;
     const int zt = bid % nzt;
     bid /= nzt;
@@ -231,17 +275,20 @@ __global__ void __launch_bounds__(256) k_sph_inv_y(const cplx<T> *__restrict__ T
     const int x = xlist[ix];
     const int z0 = zt * C;
     const C2 *t1 = T1 + (size_t)q * ncol * n;
-    for (int i = threadIdx.x; i < n * C; i += blockDim.x) {
-        const int y = i / C, c = i - y * C;
+    FFT_FOR(i, n * C) {
+        const int y = i >> lc, c = i & (C - 1);
         const int col = colmap[x * n + y];
         const int z = z0 + c;
-        sa[i] = (col >= 0 && z < n) ? t1[(size_t)col * n + z] : cmake<C2>(0, 0);
+        // unconditional load at a clamped address, then select: no branch
+        const C2 v = t1[(size_t)max(col, 0) * n + min(z, n - 1)];
+        sa[i] = keep_if(v, col >= 0 && z < n);
     }
+    load_twiddles<T>(stw, tw, n);  // after the data loads: they overlap
     __syncthreads();
-    C2 *res = lds_fft<T, N>(sa, sb, stw, lc, (T)1);
+    C2 *res = lds_fft<T, N>(sa, sb, stw, (T)1);
     C2 *t2 = T2 + ((size_t)q * nxp + ix) * n * n;
-    for (int i = threadIdx.x; i < n * C; i += blockDim.x) {
-        const int y = i / C, c = i - y * C;
+    FFT_FOR(i, n * C) {
+        const int y = i >> lc, c = i & (C - 1);
         const int z = z0 + c;
         if (z < n) t2[(size_t)y * n + z] = res[i];
     }
@@ -252,37 +299,39 @@ template <typename T, int N>
 __global__ void __launch_bounds__(256) k_sph_inv_x(const cplx<T> *__restrict__ T2,
                                                    const int *__restrict__ xinv, int nxp,
                                                    int n_orb, T *__restrict__ out,
-                                                   const cplx<T> *__restrict__ tw, int lc, int nyzt,
+                                                   const cplx<T> *__restrict__ tw, int nyzt,
                                                    int ps) {
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
     constexpr int n = N;
-    const int C = 1 << lc;
+    constexpr int C = FftTile<T, N>::C;
+    constexpr int lc = FftTile<T, N>::lc;
     const int n2 = n * n;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
     C2 *sb = sa + n * C;
     C2 *stw = sb + n * C;
-    load_twiddles<T>(stw, tw, n);
     const int t = blockIdx.x % nyzt;
     const int q = blockIdx.x / nyzt;
     const int yz0 = t * C;
     const C2 *t2 = T2 + (size_t)q * nxp * n2;
-    for (int i = threadIdx.x; i < n * C; i += blockDim.x) {
-        const int x = i / C, c = i - x * C;
+    FFT_FOR(i, n * C) {
+        const int x = i >> lc, c = i & (C - 1);
         const int ix = xinv[x];
         const int yz = yz0 + c;
-        sa[i] = (ix >= 0 && yz < n2) ? t2[(size_t)ix * n2 + yz] : cmake<C2>(0, 0);
+        const C2 v = t2[(size_t)max(ix, 0) * n2 + min(yz, n2 - 1)];
+        sa[i] = keep_if(v, ix >= 0 && yz < n2);
     }
+    load_twiddles<T>(stw, tw, n);  // after the data loads: they overlap
     __syncthreads();
-    C2 *res = lds_fft<T, N>(sa, sb, stw, lc, (T)1);
+    C2 *res = lds_fft<T, N>(sa, sb, stw, (T)1);
     const size_t nr = (size_t)n2 * n;
     int i1, i2;
     pair_of(q, ps, i1, i2);
     T *o1 = out + (size_t)i1 * nr;
     T *o2 = out + (size_t)i2 * nr;
     const bool has2 = i2 < n_orb;
-    for (int i = threadIdx.x; i < n * C; i += blockDim.x) {
-        const int x = i / C, c = i - x * C;
+    FFT_FOR(i, n * C) {
+        const int x = i >> lc, c = i & (C - 1);
         const int yz = yz0 + c;
         if (yz < n2) {
             o1[(size_t)x * n2 + yz] = res[i].x;
@@ -302,18 +351,18 @@ __global__ void __launch_bounds__(256) k_sph_fwd_x(const T *__restrict__ Cr, con
                                                    const cplx<T> *__restrict__ vH, T k1e,
                                                    int n_orb, int n_occ, const int *__restrict__ xlist,
                                                    int nxp, cplx<T> *__restrict__ T2,
-                                                   const cplx<T> *__restrict__ tw, int lc,
+                                                   const cplx<T> *__restrict__ tw,
                                                    int nyzt) {
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
     constexpr int n = N;
-    const int C = 1 << lc;
+    constexpr int C = FftTile<T, N>::C;
+    constexpr int lc = FftTile<T, N>::lc;
     const int n2 = n * n;
     const size_t nr = (size_t)n2 * n;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
     C2 *sb = sa + n * C;
     C2 *stw = sb + n * C;
-    load_twiddles<T>(stw, tw, n);
     // q fastest: the orbital slots sharing one Hartree tile run back to back
     const int nq = gridDim.x / nyzt;
     const int q = blockIdx.x % nq;
@@ -324,27 +373,27 @@ __global__ void __launch_bounds__(256) k_sph_fwd_x(const T *__restrict__ Cr, con
     const bool has2 = o2 < n_orb;
     const int s1 = o1 / n_occ, v = o1 - s1 * n_occ;  // s1 even
     const T *c1 = Cr + (size_t)o1 * nr;
-    const T *c2 = Cr + (size_t)o2 * nr;
+    const T *c2q = Cr + (size_t)(has2 ? o2 : o1) * nr;  // in bounds either way
     const T *uv = u + (size_t)v * nr;
     const C2 *h = vH + (size_t)(s1 >> 1) * nr;
-    for (int i = threadIdx.x; i < n * C; i += blockDim.x) {
-        const int x = i / C, c = i - x * C;
+    FFT_FOR(i, n * C) {
+        const int x = i >> lc, c = i & (C - 1);
         const int yz = yz0 + c;
-        C2 val = cmake<C2>(0, 0);
-        if (yz < n2) {
-            const size_t r = (size_t)x * n2 + yz;
-            const C2 hv = h[r];
-            const T ku = k1e * uv[r];
-            val.x = c1[r] + ku * hv.x;
-            val.y = has2 ? c2[r] + ku * hv.y : (T)0;
-        }
+        const size_t r = (size_t)x * n2 + min(yz, n2 - 1);
+        const C2 hv = h[r];
+        const T ku = k1e * uv[r];
+        const T a = c1[r], b = c2q[r];
+        C2 val;
+        val.x = yz < n2 ? a + ku * hv.x : (T)0;
+        val.y = yz < n2 && has2 ? b + ku * hv.y : (T)0;
         sa[i] = val;
     }
+    load_twiddles<T>(stw, tw, n);  // after the data loads: they overlap
     __syncthreads();
-    C2 *res = lds_fft<T, N>(sa, sb, stw, lc, (T)-1);
+    C2 *res = lds_fft<T, N>(sa, sb, stw, (T)-1);
     C2 *t2 = T2 + (size_t)q * nxp * n2;
-    for (int i = threadIdx.x; i < nxp * C; i += blockDim.x) {
-        const int ix = i / C, c = i - ix * C;
+    for (int i = threadIdx.x; i < nxp * C; i += FFT_NT) {
+        const int ix = i >> lc, c = i & (C - 1);
         const int yz = yz0 + c;
         if (yz < n2) t2[(size_t)ix * n2 + yz] = res[xlist[ix] * C + c];
     }
@@ -356,15 +405,15 @@ __global__ void __launch_bounds__(256) k_sph_fwd_y(const cplx<T> *__restrict__ T
                                                    const int *__restrict__ colmap,
                                                    const int *__restrict__ xlist, int nxp, int ncol,
                                                    cplx<T> *__restrict__ T1,
-                                                   const cplx<T> *__restrict__ tw, int lc, int nzt) {
+                                                   const cplx<T> *__restrict__ tw, int nzt) {
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
     constexpr int n = N;
-    const int C = 1 << lc;
+    constexpr int C = FftTile<T, N>::C;
+    constexpr int lc = FftTile<T, N>::lc;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
     C2 *sb = sa + n * C;
     C2 *stw = sb + n * C;
-    load_twiddles<T>(stw, tw, n);
     int bid = blockIdx.x;
     const int zt = bid % nzt;
     bid /= nzt;
@@ -373,16 +422,18 @@ __global__ void __launch_bounds__(256) k_sph_fwd_y(const cplx<T> *__restrict__ T
     const int x = xlist[ix];
     const int z0 = zt * C;
     const C2 *t2 = T2 + ((size_t)q * nxp + ix) * n * n;
-    for (int i = threadIdx.x; i < n * C; i += blockDim.x) {
-        const int y = i / C, c = i - y * C;
+    FFT_FOR(i, n * C) {
+        const int y = i >> lc, c = i & (C - 1);
         const int z = z0 + c;
-        sa[i] = (z < n) ? t2[(size_t)y * n + z] : cmake<C2>(0, 0);
+        const C2 v = t2[(size_t)y * n + min(z, n - 1)];
+        sa[i] = keep_if(v, z < n);
     }
+    load_twiddles<T>(stw, tw, n);  // after the data loads: they overlap
     __syncthreads();
-    C2 *res = lds_fft<T, N>(sa, sb, stw, lc, (T)-1);
+    C2 *res = lds_fft<T, N>(sa, sb, stw, (T)-1);
     C2 *t1 = T1 + (size_t)q * ncol * n;
-    for (int i = threadIdx.x; i < n * C; i += blockDim.x) {
-        const int y = i / C, c = i - y * C;
+    FFT_FOR(i, n * C) {
+        const int y = i >> lc, c = i & (C - 1);
         const int z = z0 + c;
         const int col = colmap[x * n + y];
         if (col >= 0 && z < n) t1[(size_t)col * n + z] = res[i];
@@ -399,27 +450,28 @@ __global__ void __launch_bounds__(256) k_sph_fwd_z(const cplx<T> *__restrict__ T
                                                    int n_lines, int n_orb, int npw,
                                                    const T *__restrict__ X,
                                                    const double *__restrict__ kin, T kin_scale,
-                                                   T *__restrict__ Y, const cplx<T> *__restrict__ tw,
-                                                   int lc, int ps) {
+                                                   T *__restrict__ Y, const cplx<T> *__restrict__ tw, int ps) {
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
     constexpr int n = N;
-    const int C = 1 << lc;
+    constexpr int C = FftTile<T, N>::C;
+    constexpr int lc = FftTile<T, N>::lc;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
     C2 *sb = sa + n * C;
     C2 *stw = sb + n * C;
-    load_twiddles<T>(stw, tw, n);
     const int L0 = blockIdx.x * C;
-    for (int i = threadIdx.x; i < n * C; i += blockDim.x) {
+    FFT_FOR(i, n * C) {
         const int c = i / n, z = i - c * n;
         const int L = L0 + c;
-        sa[z * C + c] = (L < n_lines) ? T1[(size_t)L * n + z] : cmake<C2>(0, 0);
+        const C2 v = T1[(size_t)min(L, n_lines - 1) * n + z];
+        sa[z * C + c] = keep_if(v, L < n_lines);
     }
+    load_twiddles<T>(stw, tw, n);  // after the data loads: they overlap
     __syncthreads();
-    C2 *res = lds_fft<T, N>(sa, sb, stw, lc, (T)-1);
+    C2 *res = lds_fft<T, N>(sa, sb, stw, (T)-1);
     const T inv_nr = (T)1 / ((T)n * (T)n * (T)n);
     const T sq2 = (T)1.41421356237309504880;
-    const int nwave = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nwave = FFT_NT >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int c = wave; c < C; c += nwave) {
         const int L = L0 + c;
         if (L >= n_lines) break;
@@ -463,25 +515,27 @@ __global__ void __launch_bounds__(256) k_sph_fwd_z(const cplx<T> *__restrict__ T
 // axis 2 (z): contiguous lines; line L = b * n^2 + (x * n + y)
 template <typename T, int N>
 __global__ void __launch_bounds__(256) k_grid_z(cplx<T> *__restrict__ A, int n_lines,
-                                                const cplx<T> *__restrict__ tw, int lc,
+                                                const cplx<T> *__restrict__ tw,
                                                 T sign) {
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
     constexpr int n = N;
-    const int C = 1 << lc;
+    constexpr int C = FftTile<T, N>::C;
+    constexpr int lc = FftTile<T, N>::lc;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
     C2 *sb = sa + n * C;
     C2 *stw = sb + n * C;
-    load_twiddles<T>(stw, tw, n);
     const int L0 = blockIdx.x * C;
-    for (int i = threadIdx.x; i < n * C; i += blockDim.x) {
+    FFT_FOR(i, n * C) {
         const int c = i / n, z = i - c * n;
         const int L = L0 + c;
-        sa[z * C + c] = (L < n_lines) ? A[(size_t)L * n + z] : cmake<C2>(0, 0);
+        const C2 v = A[(size_t)min(L, n_lines - 1) * n + z];
+        sa[z * C + c] = keep_if(v, L < n_lines);
     }
+    load_twiddles<T>(stw, tw, n);  // after the data loads: they overlap
     __syncthreads();
-    C2 *res = lds_fft<T, N>(sa, sb, stw, lc, sign);
-    for (int i = threadIdx.x; i < n * C; i += blockDim.x) {
+    C2 *res = lds_fft<T, N>(sa, sb, stw, sign);
+    FFT_FOR(i, n * C) {
         const int c = i / n, z = i - c * n;
         const int L = L0 + c;
         if (L < n_lines) A[(size_t)L * n + z] = res[z * C + c];
@@ -491,29 +545,31 @@ __global__ void __launch_bounds__(256) k_grid_z(cplx<T> *__restrict__ A, int n_l
 // axis 1 (y): block (b, x, z-tile)
 template <typename T, int N>
 __global__ void __launch_bounds__(256) k_grid_y(cplx<T> *__restrict__ A,
-                                                const cplx<T> *__restrict__ tw, int lc,
+                                                const cplx<T> *__restrict__ tw,
                                                 int nzt, T sign) {
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
     constexpr int n = N;
-    const int C = 1 << lc;
+    constexpr int C = FftTile<T, N>::C;
+    constexpr int lc = FftTile<T, N>::lc;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
     C2 *sb = sa + n * C;
     C2 *stw = sb + n * C;
-    load_twiddles<T>(stw, tw, n);
     const int zt = blockIdx.x % nzt;
     const int bx = blockIdx.x / nzt;  // b * n + x
     const int z0 = zt * C;
     C2 *p = A + (size_t)bx * n * n;
-    for (int i = threadIdx.x; i < n * C; i += blockDim.x) {
-        const int y = i / C, c = i - y * C;
+    FFT_FOR(i, n * C) {
+        const int y = i >> lc, c = i & (C - 1);
         const int z = z0 + c;
-        sa[i] = (z < n) ? p[(size_t)y * n + z] : cmake<C2>(0, 0);
+        const C2 v = p[(size_t)y * n + min(z, n - 1)];
+        sa[i] = keep_if(v, z < n);
     }
+    load_twiddles<T>(stw, tw, n);  // after the data loads: they overlap
     __syncthreads();
-    C2 *res = lds_fft<T, N>(sa, sb, stw, lc, sign);
-    for (int i = threadIdx.x; i < n * C; i += blockDim.x) {
-        const int y = i / C, c = i - y * C;
+    C2 *res = lds_fft<T, N>(sa, sb, stw, sign);
+    FFT_FOR(i, n * C) {
+        const int y = i >> lc, c = i & (C - 1);
         const int z = z0 + c;
         if (z < n) p[(size_t)y * n + z] = res[i];
     }
@@ -522,30 +578,32 @@ __global__ void __launch_bounds__(256) k_grid_y(cplx<T> *__restrict__ A,
 // axis 0 (x): block (b, yz-tile)
 template <typename T, int N>
 __global__ void __launch_bounds__(256) k_grid_x(cplx<T> *__restrict__ A,
-                                                const cplx<T> *__restrict__ tw, int lc,
+                                                const cplx<T> *__restrict__ tw,
                                                 int nyzt, T sign) {
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
     constexpr int n = N;
-    const int C = 1 << lc;
+    constexpr int C = FftTile<T, N>::C;
+    constexpr int lc = FftTile<T, N>::lc;
     const int n2 = n * n;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
     C2 *sb = sa + n * C;
     C2 *stw = sb + n * C;
-    load_twiddles<T>(stw, tw, n);
     const int t = blockIdx.x % nyzt;
     const int b = blockIdx.x / nyzt;
     const int yz0 = t * C;
     C2 *p = A + (size_t)b * n2 * n;
-    for (int i = threadIdx.x; i < n * C; i += blockDim.x) {
-        const int x = i / C, c = i - x * C;
+    FFT_FOR(i, n * C) {
+        const int x = i >> lc, c = i & (C - 1);
         const int yz = yz0 + c;
-        sa[i] = (yz < n2) ? p[(size_t)x * n2 + yz] : cmake<C2>(0, 0);
+        const C2 v = p[(size_t)x * n2 + min(yz, n2 - 1)];
+        sa[i] = keep_if(v, yz < n2);
     }
+    load_twiddles<T>(stw, tw, n);  // after the data loads: they overlap
     __syncthreads();
-    C2 *res = lds_fft<T, N>(sa, sb, stw, lc, sign);
-    for (int i = threadIdx.x; i < n * C; i += blockDim.x) {
-        const int x = i / C, c = i - x * C;
+    C2 *res = lds_fft<T, N>(sa, sb, stw, sign);
+    FFT_FOR(i, n * C) {
+        const int x = i >> lc, c = i & (C - 1);
         const int yz = yz0 + c;
         if (yz < n2) p[(size_t)x * n2 + yz] = res[i];
     }
@@ -573,19 +631,6 @@ FftPlan make_plan(int n) {
     return p;
 }
 
-static size_t lds_bytes(int n, int C, size_t esz) { return (size_t)(2 * n * C + n) * esz; }
-
-// lines per workgroup: a power of two, as many as fit a 64 KB tile, at most cap
-int fft_tile(int n, size_t esz, int cap) {
-    int C = cap;
-    while (C > 2 && lds_bytes(n, C, esz) > 64 * 1024) C /= 2;
-    return C;
-}
-static int ilog2(int c) {
-    int l = 0;
-    while ((1 << l) < c) ++l;
-    return l;
-}
 
 static int n_lines_for(int n_orb, int ps) {
     return (int)div_up((size_t)n_orb, (size_t)2 * ps) * ps;
@@ -597,27 +642,26 @@ static void sph_inverse_n(const SphereMaps &m, const T *X, int n_orb, T *out, cp
     using C2 = cplx<T>;
     constexpr int n = N;
     const int nq = n_lines_for(n_orb, ps);
-    const size_t esz = sizeof(C2);
-    const int C = fft_tile(n, esz, 64);  // even, so a column and its mirror share a tile
-    const int lc = ilog2(C);
+    constexpr int C = FftTile<T, N>::C;  // even, so a column and its mirror share a tile
+    static_assert(C == FftTile<T, N>::C && C % 2 == 0, "tile width");
     {
         const int n_lines = nq * m.ncol;
-        k_sph_inv_z<T, N><<<div_up(n_lines, C), 256, lds_bytes(n, C, esz), st>>>(
-            X, n_orb, m.npw, m.ent, m.col_ptr, m.ncol, n_lines, T1, tw, lc, ps);
+        k_sph_inv_z<T, N><<<div_up(n_lines, C), 256, FftTile<T, N>::lds, st>>>(
+            X, n_orb, m.npw, m.ent, m.col_ptr, m.ncol, n_lines, T1, tw, ps);
         BSE_LAUNCH_CHECK();
         if (ev) BSE_HIP(hipEventRecord(ev[0], st));
     }
     {
         const int nzt = div_up(n, C);
-        k_sph_inv_y<T, N><<<(unsigned)nq * m.nxp * nzt, 256, lds_bytes(n, C, esz), st>>>(
-            T1, m.colmap, m.xlist, m.nxp, m.ncol, T2, tw, lc, nzt);
+        k_sph_inv_y<T, N><<<(unsigned)nq * m.nxp * nzt, 256, FftTile<T, N>::lds, st>>>(
+            T1, m.colmap, m.xlist, m.nxp, m.ncol, T2, tw, nzt);
         BSE_LAUNCH_CHECK();
         if (ev) BSE_HIP(hipEventRecord(ev[1], st));
     }
     {
         const int nyzt = div_up((size_t)n * n, C);
-        k_sph_inv_x<T, N><<<(unsigned)nq * nyzt, 256, lds_bytes(n, C, esz), st>>>(
-            T2, m.xinv, m.nxp, n_orb, out, tw, lc, nyzt, ps);
+        k_sph_inv_x<T, N><<<(unsigned)nq * nyzt, 256, FftTile<T, N>::lds, st>>>(
+            T2, m.xinv, m.nxp, n_orb, out, tw, nyzt, ps);
         BSE_LAUNCH_CHECK();
         if (ev) BSE_HIP(hipEventRecord(ev[2], st));
     }
@@ -630,27 +674,25 @@ static void sph_forward_n(const SphereMaps &m, const T *Cr, const T *u, const cp
     using C2 = cplx<T>;
     constexpr int n = N;
     const int nq = n_lines_for(n_orb, n_occ);
-    const size_t esz = sizeof(C2);
-    const int C = fft_tile(n, esz, 64);
-    const int lc = ilog2(C);
+    constexpr int C = FftTile<T, N>::C;
     {
         const int nyzt = div_up((size_t)n * n, C);
-        k_sph_fwd_x<T, N><<<(unsigned)nq * nyzt, 256, lds_bytes(n, C, esz), st>>>(
-            Cr, u, vH, k1e, n_orb, n_occ, m.xlist, m.nxp, T2, tw, lc, nyzt);
+        k_sph_fwd_x<T, N><<<(unsigned)nq * nyzt, 256, FftTile<T, N>::lds, st>>>(
+            Cr, u, vH, k1e, n_orb, n_occ, m.xlist, m.nxp, T2, tw, nyzt);
         BSE_LAUNCH_CHECK();
         if (ev) BSE_HIP(hipEventRecord(ev[0], st));
     }
     {
         const int nzt = div_up(n, C);
-        k_sph_fwd_y<T, N><<<(unsigned)nq * m.nxp * nzt, 256, lds_bytes(n, C, esz), st>>>(
-            T2, m.colmap, m.xlist, m.nxp, m.ncol, T1, tw, lc, nzt);
+        k_sph_fwd_y<T, N><<<(unsigned)nq * m.nxp * nzt, 256, FftTile<T, N>::lds, st>>>(
+            T2, m.colmap, m.xlist, m.nxp, m.ncol, T1, tw, nzt);
         BSE_LAUNCH_CHECK();
         if (ev) BSE_HIP(hipEventRecord(ev[1], st));
     }
     {
         const int n_lines = nq * m.ncol;
-        k_sph_fwd_z<T, N><<<div_up(n_lines, C), 256, lds_bytes(n, C, esz), st>>>(
-            T1, m.ent, m.col_ptr, m.ncol, n_lines, n_orb, m.npw, X, m.kin, kin_scale, Y, tw, lc,
+        k_sph_fwd_z<T, N><<<div_up(n_lines, C), 256, FftTile<T, N>::lds, st>>>(
+            T1, m.ent, m.col_ptr, m.ncol, n_lines, n_orb, m.npw, X, m.kin, kin_scale, Y, tw,
             n_occ);
         BSE_LAUNCH_CHECK();
         if (ev) BSE_HIP(hipEventRecord(ev[2], st));
@@ -661,17 +703,15 @@ template <typename T, int N>
 static void grid_fft_n(cplx<T> *A, int nb, T sign, const cplx<T> *tw, hipStream_t st) {
     using C2 = cplx<T>;
     constexpr int n = N;
-    const size_t esz = sizeof(C2);
-    const int C = fft_tile(n, esz, 64);
-    const int lc = ilog2(C);
+    constexpr int C = FftTile<T, N>::C;
     const int n_lines = nb * n * n;
-    k_grid_z<T, N><<<div_up(n_lines, C), 256, lds_bytes(n, C, esz), st>>>(A, n_lines, tw, lc, sign);
+    k_grid_z<T, N><<<div_up(n_lines, C), 256, FftTile<T, N>::lds, st>>>(A, n_lines, tw, sign);
     BSE_LAUNCH_CHECK();
     const int nzt = div_up(n, C);
-    k_grid_y<T, N><<<(unsigned)nb * n * nzt, 256, lds_bytes(n, C, esz), st>>>(A, tw, lc, nzt, sign);
+    k_grid_y<T, N><<<(unsigned)nb * n * nzt, 256, FftTile<T, N>::lds, st>>>(A, tw, nzt, sign);
     BSE_LAUNCH_CHECK();
     const int nyzt = div_up((size_t)n * n, C);
-    k_grid_x<T, N><<<(unsigned)nb * nyzt, 256, lds_bytes(n, C, esz), st>>>(A, tw, lc, nyzt, sign);
+    k_grid_x<T, N><<<(unsigned)nb * nyzt, 256, FftTile<T, N>::lds, st>>>(A, tw, nyzt, sign);
     BSE_LAUNCH_CHECK();
 }
 

@@ -30,7 +30,6 @@ struct SphereMaps {
 };
 
 FftPlan make_plan(int n);
-int fft_tile(int n, size_t esz, int cap);
 
 // ev (optional): three events recorded after the three passes.
 // Two real orbitals share a complex transform: o and o + ps (ps = 1 pairs
