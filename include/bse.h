@@ -238,6 +238,57 @@ bse_status bse_davidson_record(bse_ctx *ctx, const bse_davidson_opts *opts, cons
                                float *label, int64_t max_rows, int64_t *n_rows, double *omega,
                                double *X, bse_davidson_stats *stats);
 
+/* ---------------------------------------------------------------- tuning
+ * The K1d kernel (Eq. k1d) is compiled in several shapes: rows per
+ * workgroup, trial vectors per workgroup and tau columns in flight.  Shape 0
+ * of each precision is the default.  Not in the paper: a tuning aid. */
+/* Number of compiled K1d shapes for a precision (0 for an unknown one). */
+int bse_k1d_num_shapes(int precision);
+/* Autotuner: times the K1d stage of every shape on this cell with a block of
+ * n_vec vectors (an internal, deterministic input; n_rep timed applies per
+ * shape), selects the fastest for `precision` and returns it in *shape
+ * (optional); k1d_ms host [bse_k1d_num_shapes(precision)] (optional) gets
+ * each shape's time.  Drops a captured apply graph.  Requires
+ * bse_screen_pairs in that precision (BSE_ERR_STATE).  Synchronises. */
+bse_status bse_autotune(bse_ctx *ctx, int n_vec, int precision, int n_rep, int *shape,
+                        double *k1d_ms);
+/* Select a K1d shape by hand (BSE_ERR_ARG when out of range). */
+bse_status bse_set_k1d_shape(bse_ctx *ctx, int precision, int shape);
+
+/* ---------------------------------------------------------------- batches
+ * Several independent cells (contexts of uneven size) applied in one launch
+ * sequence: the applies of all cells are captured into one hipGraph, each
+ * cell's kernels on a stream forked from the batch stream, and the graph is
+ * replayed while the arguments stay the same.  Not in the paper: a way to
+ * fill the GPU with cells too small to fill it alone.  A batch does not own
+ * its contexts; destroy the batch first.  Contexts keep their own streams
+ * for everything but the batched applies. */
+typedef struct bse_batch bse_batch;
+
+/* ctxs host [n_ctx] distinct contexts on one device; stream: the batch's
+ * launch stream (a hipStream_t, not the default stream). */
+bse_status bse_batch_create(bse_batch **batch, bse_ctx *const *ctxs, int n_ctx, void *stream);
+bse_status bse_batch_destroy(bse_batch *batch);
+/* Capture and replay (1, default) or launch each cell eagerly (0). */
+bse_status bse_batch_set_graph(bse_batch *batch, int enable);
+/* For every cell i: A_out[i] = L_i A_in[i] as bse_apply_liouville.
+ *   n_vec  host [n_ctx];  A_in, A_out host [n_ctx] arrays of dev pointers.
+ * Inputs must be complete before the call; returns after completion. */
+bse_status bse_batch_apply(bse_batch *batch, const int *n_vec, const void *const *A_in,
+                           void *const *A_out, int precision);
+/* bse_davidson for every cell with the same options, iterations in
+ * lockstep: each iteration applies the pending blocks of all unconverged
+ * cells in one replay of the batch graph (re-captured when a cell drops out).
+ *   X0     host [n_ctx] of dev [block][n_occ_i][n_pw_i] FP64 start blocks
+ *   omega  host [n_ctx] of host [n_eig] FP64 out
+ *   X      host [n_ctx] of dev [n_eig][n_occ_i][n_pw_i] FP64 out
+ *   stats  host [n_ctx] (optional)
+ * Each cell's results are those of bse_davidson on it alone.  BSE_ERR_NOCONV
+ * when any cell hits max_iter (all cells' outputs are still written). */
+bse_status bse_batch_davidson(bse_batch *batch, const bse_davidson_opts *opts,
+                              const double *const *X0, double *const *omega, double *const *X,
+                              bse_davidson_stats *stats);
+
 const char *bse_status_str(bse_status s);
 const char *bse_last_error(void);
 

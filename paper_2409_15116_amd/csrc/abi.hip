@@ -252,6 +252,92 @@ bse_status bse_davidson_record(bse_ctx *c, const bse_davidson_opts *opts, const 
     })
 }
 
+int bse_k1d_num_shapes(int precision) {
+    if (precision != BSE_FP64 && precision != BSE_FP32 && precision != BSE_BF16X3) return 0;
+    return bse::k1d_num_shapes(precision == BSE_FP64);
+}
+
+bse_status bse_autotune(bse_ctx *c, int n_vec, int precision, int n_rep, int *shape,
+                        double *k1d_ms) {
+    CHECK_CTX(c);
+    BSE_GUARD({
+        const int s = bse::ctx_autotune(c, n_vec, precision, n_rep, k1d_ms);
+        if (shape) *shape = s;
+    })
+}
+
+bse_status bse_set_k1d_shape(bse_ctx *c, int precision, int shape) {
+    CHECK_CTX(c);
+    if (precision != BSE_FP64 && precision != BSE_FP32 && precision != BSE_BF16X3) {
+        set_error("bse_set_k1d_shape: unknown precision %d", precision);
+        return BSE_ERR_ARG;
+    }
+    BSE_GUARD(bse::ctx_set_k1d_shape(c, precision, shape))
+}
+
+bse_status bse_batch_create(bse_batch **out, bse_ctx *const *ctxs, int n, void *stream) {
+    if (!out || !ctxs) {
+        set_error("bse_batch_create: null argument");
+        return BSE_ERR_ARG;
+    }
+    *out = nullptr;
+    bse_batch *b = nullptr;
+    try {
+        b = new bse_batch;
+        bse::batch_create(b, ctxs, n, (hipStream_t)stream);
+    } catch (const Err &e) {
+        if (b) bse::batch_free(b);
+        delete b;
+        return e.st;
+    } catch (const std::bad_alloc &) {
+        if (b) bse::batch_free(b);
+        delete b;
+        set_error("host allocation failed");
+        return BSE_ERR_OOM;
+    }
+    *out = b;
+    return BSE_OK;
+}
+
+bse_status bse_batch_destroy(bse_batch *b) {
+    if (!b) return BSE_OK;
+    bse::batch_free(b);
+    delete b;
+    return BSE_OK;
+}
+
+bse_status bse_batch_set_graph(bse_batch *b, int enable) {
+    if (!b) {
+        set_error("null batch");
+        return BSE_ERR_ARG;
+    }
+    BSE_GUARD(bse::batch_set_graph(b, enable != 0))
+}
+
+bse_status bse_batch_apply(bse_batch *b, const int *n_vec, const void *const *A_in,
+                           void *const *A_out, int precision) {
+    if (!b || !n_vec || !A_in || !A_out) {
+        set_error("bse_batch_apply: null argument");
+        return BSE_ERR_ARG;
+    }
+    BSE_GUARD(bse::batch_apply(b, n_vec, A_in, A_out, precision, nullptr))
+}
+
+bse_status bse_batch_davidson(bse_batch *b, const bse_davidson_opts *opts,
+                              const double *const *X0, double *const *omega, double *const *X,
+                              bse_davidson_stats *stats) {
+    if (!b || !opts || !X0 || !omega || !X) {
+        set_error("bse_batch_davidson: null argument");
+        return BSE_ERR_ARG;
+    }
+    for (size_t i = 0; i < b->cells.size(); ++i)
+        if (!X0[i] || !omega[i] || !X[i]) {
+            set_error("bse_batch_davidson: null pointer for cell %zu", i);
+            return BSE_ERR_ARG;
+        }
+    BSE_GUARD(bse::batch_davidson(b, opts, X0, omega, X, stats))
+}
+
 const char *bse_status_str(bse_status s) {
     switch (s) {
         case BSE_OK: return "ok";

@@ -1,6 +1,7 @@
 // Context set-up, pair list, screening and the Liouville apply pipeline.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <map>
 #include <vector>
 
@@ -282,8 +283,8 @@ void ctx_build_pairs(bse_ctx *c, int kind, double thr) {
         if (!host.empty())
             BSE_HIP(hipMemcpy(dev.p, host.data(), host.size() * sizeof(host[0]), hipMemcpyHostToDevice));
     };
-    {
-        const int BI = K1D_BI, BJ = K1D_BJ;
+    for (int set = 0; set < 2; ++set) {
+        const int BI = K1D_BI_SIZES[set], BJ = K1D_BJ;
         const int nIb = (no + BI - 1) / BI, nJb = (no + BJ - 1) / BJ;
         const long long P = c->n_pairs;
         BSE_REQUIRE((P + 1) * TAU_TILE < (1LL << 31), BSE_ERR_ARG, "too many pairs (%lld)", P);
@@ -325,14 +326,16 @@ void ctx_build_pairs(bse_ctx *c, int kind, double thr) {
             BSE_REQUIRE(order.size() - start == (size_t)nJb, BSE_ERR_STATE,
                         "column-block order incomplete");
         }
-        up(c->csr_tbl, tbl);
-        up(c->csr_nz, nz);
-        up(c->csr_order, order);
-        c->csr.nchunk = nJb;
-        c->csr.n_rows = P + 1;
-        c->csr.tbl = c->csr_tbl.p;
-        c->csr.blk_nz = c->csr_nz.p;
-        c->csr.order = c->csr_order.p;
+        up(c->csr_tbl[set], tbl);
+        up(c->csr_nz[set], nz);
+        up(c->csr_order[set], order);
+        PairCSR &t = c->csr[set];
+        t.bi = BI;
+        t.nchunk = nJb;
+        t.n_rows = P + 1;
+        t.tbl = c->csr_tbl[set].p;
+        t.blk_nz = c->csr_nz[set].p;
+        t.order = c->csr_order[set].p;
     }
     std::vector<int2> pd(c->n_pairs);
     for (long long p = 0; p < c->n_pairs; ++p) pd[p] = make_int2(pr[2 * p], pr[2 * p + 1]);
@@ -453,7 +456,7 @@ static void ensure_ws(bse_ctx *c, ApplyWs<T> &w, int nvec) {
     w.T1.alloc(nq * c->maps.ncol * n);
     w.T2.alloc(nq * c->maps.nxp * n * n);
     w.Hc.alloc((size_t)((nvec + 1) / 2) * nr);
-    w.Dp.alloc((size_t)((no + K1D_BI - 1) / K1D_BI) * nvec * nr);
+    w.Dp.alloc((size_t)((no + K1D_BI_MIN - 1) / K1D_BI_MIN) * nvec * nr);
     w.cap = nvec;
     ++w.gen;
 }
@@ -504,7 +507,8 @@ static void apply_impl(bse_ctx *c, int nvec, const T *X, T *Y, bool bf, hipEvent
     // a1: sphere -> grid for every (s, v)
     sph_inverse<T>(c->maps, X, norb, w.Ar.p, w.T1.p, w.T2.p, tw, st, ev ? ev + 1 : nullptr, no);
     // a4 (+ V a of a2, + the K1e density of a3)
-    k1d_apply<T>(w.Ar.p, tau, V, u, c->csr, no, nvec, nr, (T)c->k1d, (T)(1.0 / c->omega), w.Cr.p,
+    k1d_apply<T>(w.Ar.p, tau, V, u, c->csr, c->k1d_shape[dbl ? 0 : 1], no, nvec, nr, (T)c->k1d,
+                 (T)(1.0 / c->omega), w.Cr.p,
                  w.Hc.p, w.Dp.p, st);
     rec(4);
     // a3: Hartree potential of every trial vector's density
@@ -550,6 +554,70 @@ void ctx_profile_apply(bse_ctx *c, int n_vec, const void *in, void *out, int pre
         throw;
     }
     for (auto &e : ev) (void)hipEventDestroy(e);
+}
+
+// Autotuner: time the K1d stage of every compiled shape on this cell with a
+// block of n_vec vectors (deterministic input, n_rep timed applies each after
+// one untimed one), keep the fastest for this precision and return it.  A
+// captured apply graph is dropped (it holds the previous shape).
+int ctx_autotune(bse_ctx *c, int n_vec, int prec, int n_rep, double *ms_out) {
+    BSE_REQUIRE(prec == BSE_FP64 || prec == BSE_FP32 || prec == BSE_BF16X3, BSE_ERR_ARG,
+                "unknown precision %d", prec);
+    BSE_REQUIRE(n_vec >= 1 && n_rep >= 1, BSE_ERR_ARG, "n_vec and n_rep must be >= 1");
+    const bool dbl = prec == BSE_FP64;
+    BSE_REQUIRE(dbl ? c->have_tau64 : c->have_tau32, BSE_ERR_STATE,
+                "bse_autotune needs bse_screen_pairs in the requested precision");
+    const size_t len = (size_t)n_vec * c->n_occ * c->npw;
+    const size_t esz = dbl ? 8 : 4;
+    Dev<unsigned char> X, Y;
+    X.alloc(len * esz);
+    Y.alloc(len * esz);
+    {
+        // a fixed, finite input: values of a simple congruential sequence in [-1, 1)
+        std::vector<unsigned char> h(len * esz);
+        unsigned long long st = 0x9E3779B97F4A7C15ull;
+        for (size_t i = 0; i < len; ++i) {
+            st = st * 6364136223846793005ull + 1442695040888963407ull;
+            const double v = (double)(st >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+            if (dbl) {
+                std::memcpy(&h[i * 8], &v, 8);
+            } else {
+                const float f = (float)v;
+                std::memcpy(&h[i * 4], &f, 4);
+            }
+        }
+        BSE_HIP(hipMemcpy(X.p, h.data(), h.size(), hipMemcpyHostToDevice));
+    }
+    drop_graph(c);
+    int &slot = c->k1d_shape[dbl ? 0 : 1];
+    const int keep = slot;
+    const int ns = k1d_num_shapes(dbl);
+    int best = 0;
+    double best_ms = INFINITY;
+    try {
+        for (int v = 0; v < ns; ++v) {
+            slot = v;
+            double ms[10];
+            ctx_profile_apply(c, n_vec, X.p, Y.p, prec, n_rep, ms);
+            if (ms_out) ms_out[v] = ms[3];
+            if (ms[3] < best_ms) {
+                best_ms = ms[3];
+                best = v;
+            }
+        }
+    } catch (...) {
+        slot = keep;
+        throw;
+    }
+    slot = best;
+    return best;
+}
+
+void ctx_set_k1d_shape(bse_ctx *c, int prec, int shape) {
+    const bool dbl = prec == BSE_FP64;
+    (void)k1d_shape(dbl, shape);  // validates
+    drop_graph(c);
+    c->k1d_shape[dbl ? 0 : 1] = shape;
 }
 
 void ctx_project_c64(bse_ctx *c, int n_vec, double *Y) {

@@ -96,10 +96,12 @@ struct bse_ctx {
     // pairs and tau
     std::vector<int> pairs_h;  // [P][2]
     bse::Dev<int2> pairs_d;
-    bse::Dev<int> csr_tbl;
-    bse::Dev<unsigned char> csr_nz;
-    bse::Dev<int> csr_order;
-    bse::PairCSR csr;
+    // K1d tables, one set per row-block size of K1D_BI_SIZES
+    bse::Dev<int> csr_tbl[2];
+    bse::Dev<unsigned char> csr_nz[2];
+    bse::Dev<int> csr_order[2];
+    bse::PairCSR csr[2];
+    int k1d_shape[2] = {0, 0};  // chosen K1d shape for FP64 / FP32 (bse_autotune)
     long long n_pairs = 0;
     bool have_tau64 = false, have_tau32 = false;
     bse::Dev<double> tau64;
@@ -120,6 +122,23 @@ struct bse_ctx {
     bse::LearnedPre lp;
 };
 
+// several contexts applied in one captured launch sequence
+struct bse_batch {
+    std::vector<bse_ctx *> cells;
+    hipStream_t stream = nullptr;
+    std::vector<hipStream_t> side;  // one forked capture stream per cell
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> join;
+    bool use_graph = true;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int g_prec = -1;
+    std::vector<char> g_active;
+    std::vector<int> g_nvec, g_gen;
+    std::vector<const void *> g_in;
+    std::vector<void *> g_out;
+};
+
 namespace bse {
 void ctx_setup(bse_ctx *c, const bse_cell *cell, const double *psi, const double *eps,
                const double *V);
@@ -128,6 +147,8 @@ void ctx_set_terms(bse_ctx *c, double k1e, double k1d, double scissor);
 void ctx_measure(bse_ctx *c, int kind, double *m_host);
 void ctx_build_pairs(bse_ctx *c, int kind, double thr);
 void ctx_screen(bse_ctx *c, const double *phi, const double *lam, int n_pdep, int prec);
+int ctx_autotune(bse_ctx *c, int n_vec, int prec, int n_rep, double *ms_out);
+void ctx_set_k1d_shape(bse_ctx *c, int prec, int shape);
 void ctx_apply(bse_ctx *c, int n_vec, const void *in, void *out, int prec);
 void ctx_apply_entry(bse_ctx *c, int n_vec, const void *in, void *out, int prec);
 void ctx_profile_apply(bse_ctx *c, int n_vec, const void *in, void *out, int prec, int n_rep,
@@ -135,6 +156,13 @@ void ctx_profile_apply(bse_ctx *c, int n_vec, const void *in, void *out, int pre
 void ctx_project_c64(bse_ctx *c, int n_vec, double *Y);
 void ctx_davidson(bse_ctx *c, const bse_davidson_opts *o, const double *X0, double *omega,
                   double *X, bse_davidson_stats *stats, RecordSpec *rec = nullptr);
+void batch_create(bse_batch *b, bse_ctx *const *ctxs, int n, hipStream_t stream);
+void batch_free(bse_batch *b);
+void batch_apply(bse_batch *b, const int *n_vec, const void *const *in, void *const *out, int prec,
+                 const char *active);
+void batch_set_graph(bse_batch *b, bool on);
+void batch_davidson(bse_batch *b, const bse_davidson_opts *o, const double *const *X0,
+                    double *const *omega, double *const *Xout, bse_davidson_stats *stats);
 void learned_setup(bse_ctx *c, int nwg);
 void learned_record(bse_ctx *c, const double *X, const double *R, const double *theta,
                     const double *Tn, int n_rec, int n_ritz, const double *Xref, int n_ref,

@@ -174,41 +174,59 @@ static int orthonormalize(DavState &s, int k, double drop2) {
     return kk;
 }
 
-static void apply_block(DavState &s, int k, const double *in, double *out, int prec) {
-    bse_ctx *c = s.c;
-    const long long len = (long long)k * s.n;
-    const int B = s.B;
-    // fixed buffers keep a captured apply valid across iterations
-    if (prec == BSE_FP64) {
-        BSE_HIP(hipMemcpyAsync(s.in64.p, in, len * 8, hipMemcpyDeviceToDevice, c->stream));
-        if (k < B) zero<double>(s.in64.p + len, (long long)(B - k) * s.n, c->stream);
-        ctx_apply_entry(c, B, s.in64.p, s.out64.p, prec);
-        BSE_HIP(hipMemcpyAsync(out, s.out64.p, len * 8, hipMemcpyDeviceToDevice, c->stream));
-    } else {
-        convert<double, float>(in, s.in32.p, len, c->stream);
-        if (k < B) zero<float>(s.in32.p + len, (long long)(B - k) * s.n, c->stream);
-        ctx_apply_entry(c, B, s.in32.p, s.out32.p, prec);
-        convert<float, double>(s.out32.p, out, len, c->stream);
-    }
-}
+// One Davidson solve as a resumable state machine: begin() leaves a block of
+// basis rows waiting to be applied; after the caller has applied it (alone,
+// or together with other cells' blocks in one launch sequence), advance()
+// runs the rest of the iteration and leaves the next block, or sets done.
+struct DavRun {
+    bse_ctx *c = nullptr;
+    bse_davidson_opts o{};
+    RecordSpec *rec = nullptr;
+    DavState s;
+    int B = 0, ne = 0, maxb = 0, rst = 0, prec = 0;
+    double delta = 0.05;
+    const double drop2 = 1e-20;
+    int n_apply = 0, used = 0, rejected = 0;
+    int nb = 0, it = 0, kr = 0;
+    std::vector<double> theta, Y, rn;
+    bool learned_on = false, learned_last = false;
+    double res_prev = INFINITY;
+    bse_status result = BSE_ERR_NOCONV;
+    bool done = false;
+    int pa_k = 0;  // rows V[nb, nb + pa_k) wait for W = L V
+    std::chrono::steady_clock::time_point t0;
 
-void ctx_davidson(bse_ctx *c, const bse_davidson_opts *o, const double *X0, double *omega,
-                  double *Xout, bse_davidson_stats *stats, RecordSpec *rec) {
-    const auto t0 = std::chrono::steady_clock::now();
-    const int B = o->block, ne = o->n_eig;
+    void begin(bse_ctx *ctx, const bse_davidson_opts *opts, const double *X0, RecordSpec *r);
+    // fixed apply buffers of B rows (graph-stable addresses)
+    const void *apply_in() const {
+        return prec == BSE_FP64 ? (const void *)s.in64.p : (const void *)s.in32.p;
+    }
+    void *apply_out() { return prec == BSE_FP64 ? (void *)s.out64.p : (void *)s.out32.p; }
+    void stage_in();
+    void stage_out();
+    void advance();
+    void finish(double *omega, double *Xout, bse_davidson_stats *stats);
+};
+
+void DavRun::begin(bse_ctx *ctx, const bse_davidson_opts *opts, const double *X0, RecordSpec *r) {
+    t0 = std::chrono::steady_clock::now();
+    c = ctx;
+    o = *opts;
+    rec = r;
+    B = o.block;
+    ne = o.n_eig;
     BSE_REQUIRE(ne >= 1 && ne <= B && B <= 64, BSE_ERR_ARG, "need 1 <= n_eig <= block <= 64");
-    const int maxb = o->max_basis > 0 ? o->max_basis : 4 * B;
-    const int rst = o->restart > 0 ? o->restart : 2 * B;
+    maxb = o.max_basis > 0 ? o.max_basis : 4 * B;
+    rst = o.restart > 0 ? o.restart : 2 * B;
     BSE_REQUIRE(maxb >= 2 * B && rst >= ne && rst <= maxb - B, BSE_ERR_ARG,
                 "need max_basis >= 2 block and n_eig <= restart <= max_basis - block");
-    BSE_REQUIRE(o->tol > 0, BSE_ERR_ARG, "tol must be > 0");
-    const int prec = o->precision;
+    BSE_REQUIRE(o.tol > 0, BSE_ERR_ARG, "tol must be > 0");
+    prec = o.precision;
     BSE_REQUIRE(prec == BSE_FP64 || prec == BSE_FP32 || prec == BSE_BF16X3, BSE_ERR_ARG,
                 "unknown precision");
     BSE_REQUIRE(prec == BSE_FP64 ? c->have_tau64 : c->have_tau32, BSE_ERR_STATE,
                 "Davidson needs bse_screen_pairs in the requested precision");
-    const double delta = o->delta > 0 ? o->delta : 0.05;
-    DavState s;
+    delta = o.delta > 0 ? o.delta : 0.05;
     s.c = c;
     s.n = (long long)c->n_occ * c->npw;
     const size_t n = s.n;
@@ -230,8 +248,8 @@ void ctx_davidson(bse_ctx *c, const bse_davidson_opts *o, const double *X0, doub
         s.out32.alloc((size_t)B * n);
     }
     s.B = B;
-    int n_apply = 0, used = 0, rejected = 0;
-    const double drop2 = 1e-20;
+    rn.assign(B, 0.0);
+    learned_on = o.precond == 1 && c->lp.net != nullptr;
     // start block
     BSE_HIP(hipMemcpyAsync(s.Tn.p, X0, (size_t)B * n * 8, hipMemcpyDeviceToDevice, c->stream));
     ctx_project_c64(c, B, s.Tn.p);
@@ -239,93 +257,121 @@ void ctx_davidson(bse_ctx *c, const bse_davidson_opts *o, const double *X0, doub
     k = orthonormalize(s, k, drop2);
     BSE_REQUIRE(k > 0, BSE_ERR_ARG, "start block has no component in the P_c space");
     BSE_HIP(hipMemcpyAsync(s.V.p, s.Tn.p, (size_t)k * n * 8, hipMemcpyDeviceToDevice, c->stream));
-    apply_block(s, k, s.V.p, s.W.p, prec);
-    n_apply += k;
-    int nb = k;
-    std::vector<double> theta, Y, rn(B);
-    int it = 0;
-    bse_status result = BSE_ERR_NOCONV;
-    int kr = 0;
-    bool learned_on = o->precond == 1 && c->lp.net != nullptr;
-    bool learned_last = false;
-    double res_prev = INFINITY;
-    for (it = 1; it <= o->max_iter; ++it) {
-        std::vector<double> T = gram(s, nb, s.V.p, nb, s.W.p);
-        for (int i = 0; i < nb; ++i)
-            for (int j = i + 1; j < nb; ++j) {
-                const double a = 0.5 * (T[(size_t)i * nb + j] + T[(size_t)j * nb + i]);
-                T[(size_t)i * nb + j] = T[(size_t)j * nb + i] = a;
-            }
-        jacobi_eigh(nb, T, theta, Y);
-        kr = std::min(B, nb);
-        std::vector<double> Yk((size_t)kr * nb);
-        for (int r = 0; r < kr; ++r)
-            for (int j = 0; j < nb; ++j) Yk[(size_t)r * nb + j] = Y[(size_t)j * nb + r];
-        small_times(s, kr, nb, Yk, s.V.p, s.X.p);
-        small_times(s, kr, nb, Yk, s.W.p, s.LX.p);
-        std::vector<double> th(theta.begin(), theta.begin() + kr);
-        upload(c, s.theta, th);
-        residual(s.LX.p, s.X.p, s.theta.p, n, kr, s.R.p, c->stream);
-        row_norm2(s.R.p, n, kr, s.part.p, s.norms.p, c->stream);
-        BSE_HIP(hipMemcpyAsync(rn.data(), s.norms.p, kr * 8, hipMemcpyDeviceToHost, c->stream));
-        BSE_HIP(hipStreamSynchronize(c->stream));
-        bool conv = true;
-        for (int i = 0; i < kr; ++i) rn[i] = std::sqrt(rn[i]);
-        for (int i = 0; i < ne; ++i) conv = conv && (i < kr) && rn[i] <= o->tol;
-        if (o->verbose)
-            fprintf(stderr, "[bse_davidson] it %d nb %d theta0 %.10f res0 %.3e res_max %.3e\n", it,
-                    nb, theta[0], rn[0], *std::max_element(rn.begin(), rn.begin() + ne));
-        if (conv) {
-            result = BSE_OK;
-            break;
-        }
-        // preconditioned residuals
-        precond_diag(s.R.p, s.theta.p, c->kin.p, c->epsd.p, c->vbar, delta, c->n_occ, c->npw, kr,
-                     s.Tn.p, c->stream);
-        if (rec)
-            learned_record(c, s.X.p, s.R.p, s.theta.p, s.Tn.p, std::min(ne, kr), kr, rec->Xref,
-                           rec->n_ref, c->gws, rec->feat, rec->lab, rec->max_rows, &rec->n_rows);
-        // learned correction; the diagonal preconditioner takes over for good
-        // once a corrected step fails to lower the largest wanted residual
-        const double res_max = *std::max_element(rn.begin(), rn.begin() + ne);
-        if (learned_last && !(res_max < res_prev)) learned_on = false;
-        res_prev = res_max;
-        learned_last = false;
-        if (learned_on) {
-            learned_correction(c, s.R.p, s.theta.p, kr, s.Tn.p, &used, &rejected);
-            learned_last = true;
-        }
-        ctx_project_c64(c, kr, s.Tn.p);
-        if (nb + kr > maxb) {
-            const int m = std::min(rst, nb);
-            std::vector<double> Ym((size_t)m * nb);
-            for (int r = 0; r < m; ++r)
-                for (int j = 0; j < nb; ++j) Ym[(size_t)r * nb + j] = Y[(size_t)j * nb + r];
-            small_times(s, m, nb, Ym, s.V.p, s.tmp.p);
-            BSE_HIP(hipMemcpyAsync(s.V.p, s.tmp.p, (size_t)m * n * 8, hipMemcpyDeviceToDevice,
-                                   c->stream));
-            small_times(s, m, nb, Ym, s.W.p, s.tmp.p);
-            BSE_HIP(hipMemcpyAsync(s.W.p, s.tmp.p, (size_t)m * n * 8, hipMemcpyDeviceToDevice,
-                                   c->stream));
-            nb = m;
-        }
-        orth_against(s, nb, kr);
-        int kk = orthonormalize(s, kr, drop2);
-        orth_against(s, nb, kk);
-        kk = orthonormalize(s, kk, drop2);
-        BSE_REQUIRE(kk > 0, BSE_ERR_NOCONV, "Davidson: no new directions");
-        BSE_HIP(hipMemcpyAsync(s.V.p + (size_t)nb * n, s.Tn.p, (size_t)kk * n * 8,
-                               hipMemcpyDeviceToDevice, c->stream));
-        apply_block(s, kk, s.V.p + (size_t)nb * n, s.W.p + (size_t)nb * n, prec);
-        n_apply += kk;
-        nb += kk;
+    nb = 0;
+    pa_k = k;
+}
+
+// V[nb, nb + pa_k) -> the fixed input buffer (zero rows up to B)
+void DavRun::stage_in() {
+    const long long len = (long long)pa_k * s.n;
+    const double *in = s.V.p + (size_t)nb * s.n;
+    if (prec == BSE_FP64) {
+        BSE_HIP(hipMemcpyAsync(s.in64.p, in, len * 8, hipMemcpyDeviceToDevice, c->stream));
+        if (pa_k < B) zero<double>(s.in64.p + len, (long long)(B - pa_k) * s.n, c->stream);
+    } else {
+        convert<double, float>(in, s.in32.p, len, c->stream);
+        if (pa_k < B) zero<float>(s.in32.p + len, (long long)(B - pa_k) * s.n, c->stream);
     }
+}
+
+// the fixed output buffer -> W[nb, nb + pa_k)
+void DavRun::stage_out() {
+    const long long len = (long long)pa_k * s.n;
+    double *out = s.W.p + (size_t)nb * s.n;
+    if (prec == BSE_FP64)
+        BSE_HIP(hipMemcpyAsync(out, s.out64.p, len * 8, hipMemcpyDeviceToDevice, c->stream));
+    else
+        convert<float, double>(s.out32.p, out, len, c->stream);
+}
+
+void DavRun::advance() {
+    const size_t n = s.n;
+    n_apply += pa_k;
+    nb += pa_k;
+    pa_k = 0;
+    ++it;
+    if (it > o.max_iter) {
+        done = true;
+        return;
+    }
+    std::vector<double> T = gram(s, nb, s.V.p, nb, s.W.p);
+    for (int i = 0; i < nb; ++i)
+        for (int j = i + 1; j < nb; ++j) {
+            const double a = 0.5 * (T[(size_t)i * nb + j] + T[(size_t)j * nb + i]);
+            T[(size_t)i * nb + j] = T[(size_t)j * nb + i] = a;
+        }
+    jacobi_eigh(nb, T, theta, Y);
+    kr = std::min(B, nb);
+    std::vector<double> Yk((size_t)kr * nb);
+    for (int r = 0; r < kr; ++r)
+        for (int j = 0; j < nb; ++j) Yk[(size_t)r * nb + j] = Y[(size_t)j * nb + r];
+    small_times(s, kr, nb, Yk, s.V.p, s.X.p);
+    small_times(s, kr, nb, Yk, s.W.p, s.LX.p);
+    std::vector<double> th(theta.begin(), theta.begin() + kr);
+    upload(c, s.theta, th);
+    residual(s.LX.p, s.X.p, s.theta.p, n, kr, s.R.p, c->stream);
+    row_norm2(s.R.p, n, kr, s.part.p, s.norms.p, c->stream);
+    BSE_HIP(hipMemcpyAsync(rn.data(), s.norms.p, kr * 8, hipMemcpyDeviceToHost, c->stream));
+    BSE_HIP(hipStreamSynchronize(c->stream));
+    bool conv = true;
+    for (int i = 0; i < kr; ++i) rn[i] = std::sqrt(rn[i]);
+    for (int i = 0; i < ne; ++i) conv = conv && (i < kr) && rn[i] <= o.tol;
+    if (o.verbose)
+        fprintf(stderr, "[bse_davidson] it %d nb %d theta0 %.10f res0 %.3e res_max %.3e\n", it, nb,
+                theta[0], rn[0], *std::max_element(rn.begin(), rn.begin() + ne));
+    if (conv) {
+        result = BSE_OK;
+        done = true;
+        return;
+    }
+    // preconditioned residuals
+    precond_diag(s.R.p, s.theta.p, c->kin.p, c->epsd.p, c->vbar, delta, c->n_occ, c->npw, kr,
+                 s.Tn.p, c->stream);
+    if (rec)
+        learned_record(c, s.X.p, s.R.p, s.theta.p, s.Tn.p, std::min(ne, kr), kr, rec->Xref,
+                       rec->n_ref, c->gws, rec->feat, rec->lab, rec->max_rows, &rec->n_rows);
+    // learned correction; the diagonal preconditioner takes over for good
+    // once a corrected step fails to lower the largest wanted residual
+    const double res_max = *std::max_element(rn.begin(), rn.begin() + ne);
+    if (learned_last && !(res_max < res_prev)) learned_on = false;
+    res_prev = res_max;
+    learned_last = false;
+    if (learned_on) {
+        learned_correction(c, s.R.p, s.theta.p, kr, s.Tn.p, &used, &rejected);
+        learned_last = true;
+    }
+    ctx_project_c64(c, kr, s.Tn.p);
+    if (nb + kr > maxb) {
+        const int m = std::min(rst, nb);
+        std::vector<double> Ym((size_t)m * nb);
+        for (int r = 0; r < m; ++r)
+            for (int j = 0; j < nb; ++j) Ym[(size_t)r * nb + j] = Y[(size_t)j * nb + r];
+        small_times(s, m, nb, Ym, s.V.p, s.tmp.p);
+        BSE_HIP(hipMemcpyAsync(s.V.p, s.tmp.p, (size_t)m * n * 8, hipMemcpyDeviceToDevice,
+                               c->stream));
+        small_times(s, m, nb, Ym, s.W.p, s.tmp.p);
+        BSE_HIP(hipMemcpyAsync(s.W.p, s.tmp.p, (size_t)m * n * 8, hipMemcpyDeviceToDevice,
+                               c->stream));
+        nb = m;
+    }
+    orth_against(s, nb, kr);
+    int kk = orthonormalize(s, kr, drop2);
+    orth_against(s, nb, kk);
+    kk = orthonormalize(s, kk, drop2);
+    BSE_REQUIRE(kk > 0, BSE_ERR_NOCONV, "Davidson: no new directions");
+    BSE_HIP(hipMemcpyAsync(s.V.p + (size_t)nb * n, s.Tn.p, (size_t)kk * n * 8,
+                           hipMemcpyDeviceToDevice, c->stream));
+    pa_k = kk;
+}
+
+void DavRun::finish(double *omega, double *Xout, bse_davidson_stats *stats) {
+    const size_t n = s.n;
     const int nout = std::min(ne, kr);
     for (int i = 0; i < nout; ++i) omega[i] = theta[i];
     BSE_HIP(hipMemcpyAsync(Xout, s.X.p, (size_t)nout * n * 8, hipMemcpyDeviceToDevice, c->stream));
     BSE_HIP(hipStreamSynchronize(c->stream));
     if (stats) {
-        stats->iterations = std::min(it, o->max_iter);
+        stats->iterations = std::min(it, o.max_iter);
         stats->n_apply = n_apply;
         stats->learned_used = used;
         stats->learned_rejected = rejected;
@@ -334,9 +380,66 @@ void ctx_davidson(bse_ctx *c, const bse_davidson_opts *o, const double *X0, doub
         for (int i = 0; i < 64; ++i) stats->resid[i] = i < nout ? rn[i] : 0.0;
     }
     if (result != BSE_OK) {
-        set_error("bse_davidson: not converged in %d iterations", o->max_iter);
+        set_error("bse_davidson: not converged in %d iterations", o.max_iter);
         throw Err{BSE_ERR_NOCONV};
     }
+}
+
+void ctx_davidson(bse_ctx *c, const bse_davidson_opts *o, const double *X0, double *omega,
+                  double *Xout, bse_davidson_stats *stats, RecordSpec *rec) {
+    DavRun r;
+    r.begin(c, o, X0, rec);
+    while (!r.done) {
+        r.stage_in();
+        ctx_apply_entry(c, r.B, r.apply_in(), r.apply_out(), r.prec);
+        r.stage_out();
+        r.advance();
+    }
+    r.finish(omega, Xout, stats);
+}
+
+// ---------------------------------------------------------------------------
+// several cells in lockstep: every iteration applies the pending blocks of all
+// unconverged cells in one launch sequence (bse_batch_apply's graph)
+// ---------------------------------------------------------------------------
+void batch_davidson(bse_batch *b, const bse_davidson_opts *o, const double *const *X0,
+                    double *const *omega, double *const *Xout, bse_davidson_stats *stats) {
+    const int nc = (int)b->cells.size();
+    std::vector<DavRun> runs(nc);
+    for (int i = 0; i < nc; ++i) runs[i].begin(b->cells[i], o, X0[i], nullptr);
+    std::vector<int> nvec(nc);
+    std::vector<const void *> in(nc);
+    std::vector<void *> out(nc);
+    for (;;) {
+        std::vector<char> active(nc, 0);
+        bool any = false;
+        for (int i = 0; i < nc; ++i)
+            if (!runs[i].done) {
+                active[i] = 1;
+                any = true;
+                runs[i].stage_in();
+                BSE_HIP(hipStreamSynchronize(b->cells[i]->stream));
+                nvec[i] = runs[i].B;
+                in[i] = runs[i].apply_in();
+                out[i] = runs[i].apply_out();
+            }
+        if (!any) break;
+        batch_apply(b, nvec.data(), in.data(), out.data(), runs[0].prec, active.data());
+        for (int i = 0; i < nc; ++i)
+            if (active[i]) {
+                runs[i].stage_out();
+                runs[i].advance();
+            }
+    }
+    bse_status first_err = BSE_OK;
+    for (int i = 0; i < nc; ++i) {
+        try {
+            runs[i].finish(omega[i], Xout[i], stats ? &stats[i] : nullptr);
+        } catch (const Err &e) {
+            if (first_err == BSE_OK) first_err = e.st;
+        }
+    }
+    if (first_err != BSE_OK) throw Err{first_err};
 }
 
 }  // namespace bse

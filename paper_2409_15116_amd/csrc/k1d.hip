@@ -219,37 +219,74 @@ __global__ void k_sum_density(const T *__restrict__ Dp, int nIb, int B, long lon
     Hc[(size_t)q * nr + i] = cmake<cplx<T>>(a, b);
 }
 
-template <typename T>
-void k1d_apply(const T *A, const T *tau, const T *V, const T *u, const PairCSR &csr, int n_occ,
-               int B, long long nr, T k1d, T inv_omega, T *Cr, cplx<T> *Hc, T *Dp,
-               hipStream_t st) {
-    constexpr bool dbl = sizeof(T) == 8;
-    constexpr int BI = K1D_BI, BJ = K1D_BJ;
-    constexpr int S = dbl ? K1D_S64 : K1D_S32;
-    constexpr int NBUF = dbl ? K1D_NBUF64 : K1D_NBUF32;
+template <typename T, int BI, int S, int NBUF>
+static void launch_k1d(const T *A, const T *tau, const T *V, const T *u, const PairCSR &csr,
+                       int n_occ, int B, long long nr, T k1d, T inv_omega, T *Cr, T *Dp,
+                       hipStream_t st) {
     const int nJb = csr.nchunk;
     const int nIb = (n_occ + BI - 1) / BI;
     const int nSc = (B + S - 1) / S;
     const long long nrt = (nr + K1D_R - 1) / K1D_R;
     const long long nhi = (nrt + 7) / 8;
     const long long nblk = nhi * 8 * nIb * nSc;
+    BSE_REQUIRE(csr.bi == BI, BSE_ERR_STATE, "K1d table set of the wrong row-block size");
     BSE_REQUIRE(nblk < (1LL << 31), BSE_ERR_ARG, "grid too large for the K1d kernel");
     BSE_REQUIRE(csr.n_rows * TAU_TILE * (long long)sizeof(T) < (1LL << 31), BSE_ERR_ARG,
                 "too many pairs for the K1d tables");
-    k_k1d<T, BI, BJ, S, NBUF><<<(unsigned)nblk, 256, 0, st>>>(
-        A, tau, V, u, csr.tbl, csr.blk_nz, csr.order, n_occ, B, nr, csr.n_rows, nIb, nJb, nSc, k1d,
-        inv_omega, Cr, Dp);
+    k_k1d<T, BI, K1D_BJ, S, NBUF><<<(unsigned)nblk, 256, 0, st>>>(
+        A, tau, V, u, csr.tbl, csr.blk_nz, csr.order, n_occ, B, nr, csr.n_rows, nIb, nJb, nSc,
+        k1d, inv_omega, Cr, Dp);
     BSE_LAUNCH_CHECK();
+}
+
+// the compiled shapes; variant 0 is the default of each type
+static constexpr K1dShape K1D_SHAPES32[] = {
+    {32, 16, 2}, {32, 16, 1}, {16, 16, 2}, {32, 8, 2}, {16, 8, 2}};
+static constexpr K1dShape K1D_SHAPES64[] = {{32, 8, 1}, {16, 8, 1}, {32, 4, 1}, {16, 4, 1}};
+
+int k1d_num_shapes(bool dbl) {
+    return dbl ? (int)(sizeof(K1D_SHAPES64) / sizeof(K1dShape))
+               : (int)(sizeof(K1D_SHAPES32) / sizeof(K1dShape));
+}
+K1dShape k1d_shape(bool dbl, int v) {
+    BSE_REQUIRE(v >= 0 && v < k1d_num_shapes(dbl), BSE_ERR_ARG, "unknown K1d shape %d", v);
+    return dbl ? K1D_SHAPES64[v] : K1D_SHAPES32[v];
+}
+
+template <typename T>
+void k1d_apply(const T *A, const T *tau, const T *V, const T *u, const PairCSR *csrs, int shape,
+               int n_occ, int B, long long nr, T k1d, T inv_omega, T *Cr, cplx<T> *Hc, T *Dp,
+               hipStream_t st) {
+    constexpr bool dbl = sizeof(T) == 8;
+    const K1dShape sh = k1d_shape(dbl, shape);
+    const PairCSR &csr = csrs[sh.bi == K1D_BI_SIZES[0] ? 0 : 1];
+#define BSE_K1D_CASE(BI_, S_, NB_)                                                           \
+    if (sh.bi == BI_ && sh.s == S_ && sh.nbuf == NB_)                                          \
+        launch_k1d<T, BI_, S_, NB_>(A, tau, V, u, csr, n_occ, B, nr, k1d, inv_omega, Cr, Dp, st);
+    if constexpr (dbl) {
+        BSE_K1D_CASE(32, 8, 1)
+        BSE_K1D_CASE(16, 8, 1)
+        BSE_K1D_CASE(32, 4, 1)
+        BSE_K1D_CASE(16, 4, 1)
+    } else {
+        BSE_K1D_CASE(32, 16, 2)
+        BSE_K1D_CASE(32, 16, 1)
+        BSE_K1D_CASE(16, 16, 2)
+        BSE_K1D_CASE(32, 8, 2)
+        BSE_K1D_CASE(16, 8, 2)
+    }
+#undef BSE_K1D_CASE
+    const int nIb = (n_occ + sh.bi - 1) / sh.bi;
     dim3 g2(div_up(nr, 256), (B + 1) / 2);
     k_sum_density<T><<<g2, 256, 0, st>>>(Dp, nIb, B, nr, Hc);
     BSE_LAUNCH_CHECK();
 }
 
 template void k1d_apply<float>(const float *, const float *, const float *, const float *,
-                               const PairCSR &, int, int, long long, float, float, float *,
+                               const PairCSR *, int, int, int, long long, float, float, float *,
                                cplx<float> *, float *, hipStream_t);
 template void k1d_apply<double>(const double *, const double *, const double *, const double *,
-                                const PairCSR &, int, int, long long, double, double, double *,
-                                cplx<double> *, double *, hipStream_t);
+                                const PairCSR *, int, int, int, long long, double, double,
+                                double *, cplx<double> *, double *, hipStream_t);
 
 }  // namespace bse

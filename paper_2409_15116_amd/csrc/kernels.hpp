@@ -49,35 +49,38 @@ inline long long tau_elems(long long n_rows, long long nr) {
     return (nr + TAU_TILE - 1) / TAU_TILE * TAU_TILE * n_rows;
 }
 
-// Pair list for the K1d kernel: rows in blocks of K1D_BI, columns in blocks
-// of K1D_BJ; tbl[(ib * nchunk + jb) * BI * BJ + w * BI + i] is the offset
+// Pair list for the K1d kernel: rows in blocks of BI, columns in blocks of
+// K1D_BJ; tbl[(ib * nchunk + jb) * BI * BJ + w * BI + i] is the offset
 // (p * 64) inside a tau tile of pair p = (ib*BI + i, jb*BJ + w), or of the
 // zero row P when the pair is not kept; blk_nz[ib * nchunk + jb] marks blocks
-// holding any kept pair.  n_rows = P + 1.
-// Block shape of the K1d kernel (compile-time tunables): BI rows x BJ columns
-// per table block, S trial vectors per workgroup, NBUF columns of tau in flight.
-#ifndef BSE_K1D_BI
-#define BSE_K1D_BI 32
-#endif
-#ifndef BSE_K1D_NBUF32
-#define BSE_K1D_NBUF32 2
-#endif
-constexpr int K1D_BI = BSE_K1D_BI;
+// holding any kept pair; order[ib * nchunk + k] is the k-th column block that
+// row block ib visits.  n_rows = P + 1.  One table set per row-block size.
 constexpr int K1D_BJ = 8;
-constexpr int K1D_S32 = 16, K1D_S64 = 8;
-constexpr int K1D_NBUF32 = BSE_K1D_NBUF32, K1D_NBUF64 = 1;
-// order[ib * nchunk + k] is the k-th column block that row block ib visits.
 struct PairCSR {
+    int bi = 0;
     int nchunk = 0;
     long long n_rows = 0;
     int *tbl = nullptr;
     unsigned char *blk_nz = nullptr;
     int *order = nullptr;
 };
+constexpr int K1D_BI_SIZES[2] = {32, 16};  // table sets held by a context
+constexpr int K1D_BI_MIN = 16;
 
-// Dp: [ceil(n_occ / K1D_BI)][B][nr] partial K1e densities
+// Compiled shapes of the K1d kernel (the autotuner's choices): BI rows per
+// workgroup, S trial vectors per workgroup, NBUF columns of tau in flight.
+// Variant 0 of each type is the default.
+struct K1dShape {
+    int bi, s, nbuf;
+};
+int k1d_num_shapes(bool dbl);
+K1dShape k1d_shape(bool dbl, int v);
+
+// Dp: [ceil(n_occ / BI)][B][nr] partial K1e densities; csrs[] holds the
+// table set of every size in K1D_BI_SIZES; shape indexes k1d_shape().
 template <typename T>
-void k1d_apply(const T *A, const T *tau, const T *V, const T *u, const PairCSR &csr, int n_occ,
+void k1d_apply(const T *A, const T *tau, const T *V, const T *u, const PairCSR *csrs, int shape,
+               int n_occ,
                int B, long long nr, T k1d, T inv_omega, T *Cr, cplx<T> *Hc, T *Dp,
                hipStream_t st);
 template <typename T>

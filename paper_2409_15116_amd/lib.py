@@ -86,6 +86,15 @@ def load():
         "bse_learned_centers": (i32, [vp, vp]),
         "bse_davidson_record": (i32, [vp, C.POINTER(DavidsonOpts), vp, vp, i32, i32, vp, vp, i64,
                                       C.POINTER(i64), vp, vp, C.POINTER(DavidsonStats)]),
+        "bse_k1d_num_shapes": (i32, [i32]),
+        "bse_autotune": (i32, [vp, i32, i32, i32, C.POINTER(i32), vp]),
+        "bse_set_k1d_shape": (i32, [vp, i32, i32]),
+        "bse_batch_create": (i32, [C.POINTER(vp), vp, i32, vp]),
+        "bse_batch_destroy": (i32, [vp]),
+        "bse_batch_set_graph": (i32, [vp, i32]),
+        "bse_batch_apply": (i32, [vp, vp, vp, vp, i32]),
+        "bse_batch_davidson": (i32, [vp, C.POINTER(DavidsonOpts), vp, vp, vp,
+                                     C.POINTER(DavidsonStats)]),
         "bse_status_str": (C.c_char_p, [i32]),
         "bse_last_error": (C.c_char_p, []),
     }
@@ -104,7 +113,9 @@ def exported_symbols():
             "bse_last_error", "bse_debug_to_grid", "bse_debug_gemm", "bse_profile_apply",
             "bse_mlp_create", "bse_mlp_destroy", "bse_mlp_num_params", "bse_mlp_get_weights",
             "bse_mlp_set_weights", "bse_mlp_forward", "bse_mlp_gradients", "bse_mlp_train",
-            "bse_set_learned", "bse_learned_centers", "bse_davidson_record"]
+            "bse_set_learned", "bse_learned_centers", "bse_davidson_record",
+            "bse_k1d_num_shapes", "bse_autotune", "bse_set_k1d_shape", "bse_batch_create",
+            "bse_batch_destroy", "bse_batch_set_graph", "bse_batch_apply", "bse_batch_davidson"]
 
 
 def _check(st):
@@ -257,6 +268,19 @@ class BseContext:
         n = int(nr.value)
         return feat[:n], lab[:n], om, {"iterations": st.iterations, "n_apply": st.n_apply}
 
+    def autotune(self, n_vec, precision=FP32, n_rep=2):
+        """Time every compiled K1d shape on this cell; select and return the
+        fastest (shape index, list of per-shape K1d milliseconds)."""
+        ns = k1d_num_shapes(precision)
+        ms = np.zeros(ns)
+        shape = C.c_int(0)
+        _check(load().bse_autotune(self.h, int(n_vec), int(precision), int(n_rep),
+                                   C.byref(shape), ms.ctypes.data))
+        return shape.value, ms.tolist()
+
+    def set_k1d_shape(self, precision, shape):
+        _check(load().bse_set_k1d_shape(self.h, int(precision), int(shape)))
+
     def davidson(self, X0, n_eig, *, block=None, max_basis=0, restart=0, max_iter=200,
                  precision=FP64, tol=1e-6, delta=0.05, precond=0, verbose=0):
         torch = self.torch
@@ -274,6 +298,75 @@ class BseContext:
                  "resid": np.array(st.resid[:n_eig]), "status": status}
         _check(status)
         return om, X, stats
+
+
+def k1d_num_shapes(precision):
+    return int(load().bse_k1d_num_shapes(int(precision)))
+
+
+def _stats_dict(st, n_eig, status):
+    return {"iterations": st.iterations, "n_apply": st.n_apply, "seconds": st.seconds,
+            "learned_used": st.learned_used, "learned_rejected": st.learned_rejected,
+            "resid": np.array(st.resid[:n_eig]), "status": status}
+
+
+class BseBatch:
+    """Several contexts whose applies run in one captured launch sequence."""
+
+    def __init__(self, ctxs, stream):
+        import torch
+        self.torch = torch
+        self.ctxs = list(ctxs)
+        self._handles = (C.c_void_p * len(self.ctxs))(*[c.h for c in self.ctxs])
+        h = C.c_void_p()
+        _check(load().bse_batch_create(C.byref(h), self._handles, len(self.ctxs),
+                                       C.c_void_p(stream.cuda_stream)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().bse_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_graph(self, enable=True):
+        _check(load().bse_batch_set_graph(self.h, 1 if enable else 0))
+
+    def apply(self, A_in, A_out, precision=FP64):
+        torch = self.torch
+        dt = torch.float64 if precision == FP64 else torch.float32
+        n = len(self.ctxs)
+        nv = (C.c_int * n)(*[int(a.shape[0]) for a in A_in])
+        pi = (C.c_void_p * n)(*[_dptr(a, dt, (a.shape[0], c.n_occ, c.npw)).value
+                                for a, c in zip(A_in, self.ctxs)])
+        po = (C.c_void_p * n)(*[_dptr(a, dt, (a.shape[0], c.n_occ, c.npw)).value
+                                for a, c in zip(A_out, self.ctxs)])
+        _check(load().bse_batch_apply(self.h, nv, pi, po, int(precision)))
+
+    def davidson(self, X0, n_eig, *, block=None, max_basis=0, restart=0, max_iter=200,
+                 precision=FP64, tol=1e-6, delta=0.05, verbose=0):
+        torch = self.torch
+        n = len(self.ctxs)
+        B = block or X0[0].shape[0]
+        o = DavidsonOpts(n_eig, B, max_basis, restart, max_iter, precision, tol, delta, 0,
+                         verbose)
+        oms = [np.zeros(n_eig) for _ in range(n)]
+        Xs = [torch.empty((n_eig, c.n_occ, c.npw), dtype=torch.float64, device="cuda")
+              for c in self.ctxs]
+        px0 = (C.c_void_p * n)(*[_dptr(x, torch.float64, (B, c.n_occ, c.npw)).value
+                                 for x, c in zip(X0, self.ctxs)])
+        pom = (C.c_void_p * n)(*[om.ctypes.data for om in oms])
+        px = (C.c_void_p * n)(*[x.data_ptr() for x in Xs])
+        sts = (DavidsonStats * n)()
+        status = load().bse_batch_davidson(self.h, C.byref(o), px0, pom, px, sts)
+        stats = [_stats_dict(sts[i], n_eig, status) for i in range(n)]
+        _check(status)
+        return oms, Xs, stats
 
 
 class Mlp:
