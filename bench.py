@@ -195,6 +195,70 @@ def time_to_solution(args, torch, pkg):
     return out
 
 
+def uneven_batch(args, torch, pkg):
+    """Twelve seeded cells of uneven size (grids 48/60/72, N_occ 32..136),
+    4 lowest excitations each, block 8: sequential plain FP64 solves,
+    sequential FP32 solves with the autotuned K1d shape, and all cells in
+    one batch (one graph replay per lockstep iteration) in FP32.  Reports
+    aggregate excitations per second of each and the largest deviation of
+    the batched eigenvalues from the plain ones."""
+    from synth import make_cell, trial_block
+    from synth.cell import uneven_batch_specs
+    specs = uneven_batch_specs(args.uneven_batch)
+    n_eig, B, tol = 4, 8, 1e-5
+    st = torch.cuda.Stream()           # the batch's launch stream
+    cells, ctxs, X0, streams = [], [], [], []
+    out = {"cells": [], "n_eig": n_eig, "block": B, "tol_ha": tol}
+    with torch.cuda.stream(st):
+        for sp in specs:
+            t = time.time()
+            c = make_cell(sp)
+            streams.append(torch.cuda.Stream())   # each cell's own work runs on its stream
+            ctx = pkg.context_for(c, stream=streams[-1])
+            pkg.setup_pairs_and_screen(ctx, c, fraction=args.fraction, precision=pkg.FP64)
+            shape, ms = ctx.autotune(B, pkg.FP32, n_rep=2)
+            ctx.set_graph(True)
+            cells.append(c)
+            ctxs.append(ctx)
+            X0.append(torch.from_numpy(trial_block(c, B, seed=4321)).to("cuda"))
+            out["cells"].append({"name": sp.name, "grid": c.n, "n_occ": c.n_occ, "npw": c.npw,
+                                 "n_pdep": c.n_pdep, "pairs": ctx.n_pairs, "k1d_shape": shape,
+                                 "k1d_ms_by_shape": [round(x, 3) for x in ms]})
+            log(f"uneven cell {sp.name}: grid {c.n} n_occ {c.n_occ} pairs {ctx.n_pairs} "
+                f"shape {shape} ({time.time() - t:.1f} s)")
+        runs = {}
+        for name, prec in (("sequential_fp64", pkg.FP64), ("sequential_fp32_tuned", pkg.FP32)):
+            torch.cuda.synchronize()
+            t = time.time()
+            oms = []
+            for ctx, x0 in zip(ctxs, X0):
+                om, _, _ = ctx.davidson(x0, n_eig, block=B, precision=prec, tol=tol,
+                                        max_iter=400)
+                oms.append(om)
+            torch.cuda.synchronize()
+            runs[name] = (time.time() - t, oms)
+            log("uneven", name, f"{runs[name][0]:.2f} s")
+        b = pkg.BseBatch(ctxs, st)
+        torch.cuda.synchronize()
+        t = time.time()
+        oms, _, sts = b.davidson(X0, n_eig, block=B, precision=pkg.FP32, tol=tol, max_iter=400)
+        torch.cuda.synchronize()
+        runs["batch_fp32_tuned"] = (time.time() - t, oms)
+        log("uneven batch", f"{runs['batch_fp32_tuned'][0]:.2f} s")
+        b.close()
+        for ctx in ctxs:
+            ctx.close()
+    n_exc = n_eig * len(cells)
+    ref = runs["sequential_fp64"][1]
+    for name, (sec, oms) in runs.items():
+        dev = max(float(np.abs(a - r).max()) for a, r in zip(oms, ref))
+        out[name] = {"seconds": sec, "excitations_per_s": n_exc / sec,
+                     "max_dev_vs_fp64_mev": dev / MEV}
+    out["batch_speedup_vs_sequential_fp64"] = (runs["sequential_fp64"][0]
+                                               / runs["batch_fp32_tuned"][0])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,6 +271,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tts", action="store_true")
+    ap.add_argument("--uneven-batch", type=int, default=0, metavar="N",
+                    help="also run the batch of N uneven cells (reported under uneven_batch)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB read + 1 GiB write elementwise kernel first "
                          "(scale reference for HBM byte counters)")
@@ -312,6 +378,9 @@ def main():
     if not args.no_tts:
         log("time to solution")
         res["time_to_solution"] = time_to_solution(args, torch, pkg)
+    if args.uneven_batch > 0:
+        log("uneven batch")
+        res["uneven_batch"] = uneven_batch(args, torch, pkg)
     ctx.close()
     print(json.dumps(res), flush=True)
 

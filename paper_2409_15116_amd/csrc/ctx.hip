@@ -621,8 +621,7 @@ void ctx_set_k1d_shape(bse_ctx *c, int prec, int shape) {
 }
 
 void ctx_project_c64(bse_ctx *c, int n_vec, double *Y) {
-    Dev<double> S;
-    // reuse the FP64 S buffer when large enough
+    Dev<double> &S = c->pc64;  // grows only: no device-wide free per call
     S.alloc((size_t)n_vec * c->n_occ * c->n_occ);
     project_c<double>(c, false, n_vec * c->n_occ, Y, S.p, c->psi64.p, c->gws);
     BSE_HIP(hipStreamSynchronize(c->stream));

@@ -111,6 +111,7 @@ struct bse_ctx {
     bse::ApplyWs<float> ws32;
     bse::Workspace gws;       // GEMM split-K partials of everything but the apply
     bse::Workspace aws;       // GEMM split-K partials of the apply (captured in graphs)
+    bse::Dev<double> pc64;    // P_c products of FP64 blocks (Davidson)
     // graph
     bool use_graph = false;
     hipGraphExec_t gexec = nullptr;

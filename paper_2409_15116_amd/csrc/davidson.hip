@@ -8,6 +8,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "ctx.hpp"
@@ -69,7 +71,7 @@ static void jacobi_eigh(int n, std::vector<double> A, std::vector<double> &w,
 struct DavState {
     bse_ctx *c;
     long long n;  // n_occ * npw
-    Dev<double> V, W, X, LX, R, Tn, tmp, small, part, norms, theta;
+    Dev<double> V, W, X, LX, R, Tn, tmp, small, sm, part, norms, theta;
     Dev<double> in64, out64;
     Dev<float> in32, out32;
     int B = 0;  // rows of the fixed apply buffers
@@ -105,7 +107,7 @@ static std::vector<double> gram(DavState &s, int m, const double *A, int k, cons
 // Tn (k rows) -= (Tn V^T) V over the nb basis rows
 static void orth_against(DavState &s, int nb, int k) {
     if (nb == 0 || k == 0) return;
-    Dev<double> sm;
+    Dev<double> &sm = s.sm;  // grows only: no device-wide free per iteration
     sm.alloc((size_t)k * nb);
     gemm<double>(true, k, nb, (int)s.n, 1.0, s.Tn.p, s.n, 0, s.V.p, s.n, 0, 0.0, sm.p, nb, 0, 1,
                  s.c->gws, s.c->stream);
@@ -406,7 +408,46 @@ void batch_davidson(bse_batch *b, const bse_davidson_opts *o, const double *cons
                     double *const *omega, double *const *Xout, bse_davidson_stats *stats) {
     const int nc = (int)b->cells.size();
     std::vector<DavRun> runs(nc);
-    for (int i = 0; i < nc; ++i) runs[i].begin(b->cells[i], o, X0[i], nullptr);
+    // per-cell host work (small GEMMs, syncs, the small eigenproblem) runs on
+    // one host thread per cell, each on its cell's own stream, so that the
+    // cells' bookkeeping overlaps; errors are carried back to this thread
+    std::vector<bse_status> st(nc, BSE_OK);
+    std::vector<std::string> msg(nc);
+    auto in_parallel = [&](auto &&fn) {
+        std::vector<std::thread> th;
+        th.reserve(nc);
+        for (int i = 0; i < nc; ++i)
+            th.emplace_back([&, i]() {
+                try {
+                    BSE_HIP(hipSetDevice(b->cells[i]->device));
+                    fn(i);
+                } catch (const Err &e) {
+                    st[i] = e.st;
+                    msg[i] = last_error();
+                } catch (const std::bad_alloc &) {
+                    st[i] = BSE_ERR_OOM;
+                    msg[i] = "host allocation failed";
+                } catch (...) {
+                    st[i] = BSE_ERR_HIP;
+                    msg[i] = "unexpected C++ exception";
+                }
+            });
+        for (auto &t : th) t.join();
+        for (int i = 0; i < nc; ++i)
+            if (st[i] != BSE_OK) {
+                set_error("cell %d: %s", i, msg[i].c_str());
+                throw Err{st[i]};
+            }
+    };
+    auto stage = [&](int i) {
+        if (runs[i].done) return;
+        runs[i].stage_in();
+        BSE_HIP(hipStreamSynchronize(b->cells[i]->stream));
+    };
+    in_parallel([&](int i) {
+        runs[i].begin(b->cells[i], o, X0[i], nullptr);
+        stage(i);
+    });
     std::vector<int> nvec(nc);
     std::vector<const void *> in(nc);
     std::vector<void *> out(nc);
@@ -417,29 +458,35 @@ void batch_davidson(bse_batch *b, const bse_davidson_opts *o, const double *cons
             if (!runs[i].done) {
                 active[i] = 1;
                 any = true;
-                runs[i].stage_in();
-                BSE_HIP(hipStreamSynchronize(b->cells[i]->stream));
                 nvec[i] = runs[i].B;
                 in[i] = runs[i].apply_in();
                 out[i] = runs[i].apply_out();
             }
         if (!any) break;
         batch_apply(b, nvec.data(), in.data(), out.data(), runs[0].prec, active.data());
-        for (int i = 0; i < nc; ++i)
-            if (active[i]) {
-                runs[i].stage_out();
-                runs[i].advance();
-            }
+        in_parallel([&](int i) {
+            if (!active[i]) return;
+            runs[i].stage_out();
+            runs[i].advance();
+            stage(i);
+        });
     }
     bse_status first_err = BSE_OK;
+    std::string first_msg;
     for (int i = 0; i < nc; ++i) {
         try {
             runs[i].finish(omega[i], Xout[i], stats ? &stats[i] : nullptr);
         } catch (const Err &e) {
-            if (first_err == BSE_OK) first_err = e.st;
+            if (first_err == BSE_OK) {
+                first_err = e.st;
+                first_msg = last_error();
+            }
         }
     }
-    if (first_err != BSE_OK) throw Err{first_err};
+    if (first_err != BSE_OK) {
+        set_error("%s", first_msg.c_str());
+        throw Err{first_err};
+    }
 }
 
 }  // namespace bse
