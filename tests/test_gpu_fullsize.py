@@ -89,3 +89,29 @@ def test_apply_sampled_graph(setup, prec, tol):
     # any size: the output lies in the P_c space
     ov = np.einsum("svg,wg->svw", got, c.psi)
     assert np.abs(ov).max() < (1e-10 if prec == 0 else 2e-4) * np.abs(got).max()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_davidson_c2_against_stored_oracle(prec):
+    """The gapped 64-well cell (N_occ = 64, ~44 % of the pairs), the 8 lowest
+    excitations with a block of 16 from the stored oracle's seeded start:
+    every precision within 1 meV of the FP64 oracle (written by
+    tests/golden/make_goldens.py, 133 oracle iterations at tol 1e-7)."""
+    import paper_2409_15116_amd as pkg
+    from tests.gpu_common import MEV, golden
+    g = golden("c2")
+    say("fullsize davidson c2", prec)
+    c = cell("c2")
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        ctx = pkg.context_for(c, stream=st)
+        pkg.setup_pairs_and_screen(ctx, c, fraction=g["fraction"], precision=prec)
+        assert ctx.n_pairs == g["n_pairs"]
+        X0 = torch.from_numpy(trial_block(c, g["block"], seed=g["start_seed"])).to("cuda")
+        ctx.set_graph(True)
+        om, X, s = ctx.davidson(X0, g["n_eig"], block=g["block"], precision=prec, tol=1e-5,
+                                max_iter=400)
+        ctx.close()
+    err = np.abs(om - np.array(g["omega_ha"])).max()
+    say("  iterations", s["iterations"], "max |omega - oracle| (meV)", err / MEV)
+    assert err < MEV
