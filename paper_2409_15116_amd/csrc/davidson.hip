@@ -196,6 +196,9 @@ struct DavRun {
     bse_status result = BSE_ERR_NOCONV;
     bool done = false;
     int pa_k = 0;  // rows V[nb, nb + pa_k) wait for W = L V
+    // Rayleigh-Ritz matrix T = V W^T of the current basis (maxb x maxb,
+    // row-major), updated with the columns of each new block only
+    std::vector<double> Tm;
     std::chrono::steady_clock::time_point t0;
 
     void begin(bse_ctx *ctx, const bse_davidson_opts *opts, const double *X0, RecordSpec *r);
@@ -251,6 +254,7 @@ void DavRun::begin(bse_ctx *ctx, const bse_davidson_opts *opts, const double *X0
     }
     s.B = B;
     rn.assign(B, 0.0);
+    Tm.assign((size_t)maxb * maxb, 0.0);
     learned_on = o.precond == 1 && c->lp.net != nullptr;
     // start block
     BSE_HIP(hipMemcpyAsync(s.Tn.p, X0, (size_t)B * n * 8, hipMemcpyDeviceToDevice, c->stream));
@@ -288,6 +292,7 @@ void DavRun::stage_out() {
 
 void DavRun::advance() {
     const size_t n = s.n;
+    const int nb_old = nb, kn = pa_k;
     n_apply += pa_k;
     nb += pa_k;
     pa_k = 0;
@@ -296,12 +301,23 @@ void DavRun::advance() {
         done = true;
         return;
     }
-    std::vector<double> T = gram(s, nb, s.V.p, nb, s.W.p);
+    // new columns of T: V_i . W_j for every basis row i and each new row j
+    // (T is symmetric up to the apply's rounding; the new diagonal block is
+    // symmetrised, the rest mirrored)
+    {
+        const std::vector<double> Cn = gram(s, nb, s.V.p, kn, s.W.p + (size_t)nb_old * n);
+        for (int i = 0; i < nb_old; ++i)
+            for (int j = 0; j < kn; ++j)
+                Tm[(size_t)i * maxb + nb_old + j] = Tm[(size_t)(nb_old + j) * maxb + i] =
+                    Cn[(size_t)i * kn + j];
+        for (int a = 0; a < kn; ++a)
+            for (int j = 0; j < kn; ++j)
+                Tm[(size_t)(nb_old + a) * maxb + nb_old + j] =
+                    0.5 * (Cn[(size_t)(nb_old + a) * kn + j] + Cn[(size_t)(nb_old + j) * kn + a]);
+    }
+    std::vector<double> T((size_t)nb * nb);
     for (int i = 0; i < nb; ++i)
-        for (int j = i + 1; j < nb; ++j) {
-            const double a = 0.5 * (T[(size_t)i * nb + j] + T[(size_t)j * nb + i]);
-            T[(size_t)i * nb + j] = T[(size_t)j * nb + i] = a;
-        }
+        for (int j = 0; j < nb; ++j) T[(size_t)i * nb + j] = Tm[(size_t)i * maxb + j];
     jacobi_eigh(nb, T, theta, Y);
     kr = std::min(B, nb);
     std::vector<double> Yk((size_t)kr * nb);
@@ -354,6 +370,25 @@ void DavRun::advance() {
         small_times(s, m, nb, Ym, s.W.p, s.tmp.p);
         BSE_HIP(hipMemcpyAsync(s.W.p, s.tmp.p, (size_t)m * n * 8, hipMemcpyDeviceToDevice,
                                c->stream));
+        // T of the rotated basis: Ym T Ym^T (the Ritz values up to rounding)
+        std::vector<double> TY((size_t)nb * m, 0.0);
+        for (int i = 0; i < nb; ++i)
+            for (int q = 0; q < m; ++q) {
+                double acc = 0;
+                for (int l = 0; l < nb; ++l) acc += T[(size_t)i * nb + l] * Ym[(size_t)q * nb + l];
+                TY[(size_t)i * m + q] = acc;
+            }
+        for (int r = 0; r < m; ++r)
+            for (int q = 0; q < m; ++q) {
+                double acc = 0;
+                for (int i = 0; i < nb; ++i) acc += Ym[(size_t)r * nb + i] * TY[(size_t)i * m + q];
+                Tm[(size_t)r * maxb + q] = acc;
+            }
+        for (int r = 0; r < m; ++r)
+            for (int q = r + 1; q < m; ++q) {
+                const double a = 0.5 * (Tm[(size_t)r * maxb + q] + Tm[(size_t)q * maxb + r]);
+                Tm[(size_t)r * maxb + q] = Tm[(size_t)q * maxb + r] = a;
+            }
         nb = m;
     }
     orth_against(s, nb, kr);

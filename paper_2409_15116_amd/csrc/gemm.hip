@@ -92,6 +92,35 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, T alpha, cons
     }
 }
 
+// Split-K partial sums [batch][split][M][N] are reduced in two fixed-order
+// passes: groups of SPLIT_GROUP consecutive splits first (many threads, the
+// loads of a group independent), then the group sums with alpha / beta.
+constexpr int SPLIT_GROUP = 32;
+
+template <typename T>
+__global__ void k_splitk_group(const T *__restrict__ part, int nsplit, long long mn, int ngroup,
+                               int nbatch, T *__restrict__ gsum) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = blockIdx.y;
+    const int b = blockIdx.z;
+    if (i >= mn || b >= nbatch) return;
+    const int k0 = g * SPLIT_GROUP;
+    const int k1 = min(nsplit, k0 + SPLIT_GROUP);
+    const T *p = part + ((size_t)b * nsplit + k0) * mn + i;
+    T s[4] = {0, 0, 0, 0};
+    int k = k0;
+#pragma unroll 4
+    for (; k + 4 <= k1; k += 4) {
+        s[0] += p[0];
+        s[1] += p[mn];
+        s[2] += p[2 * mn];
+        s[3] += p[3 * mn];
+        p += 4 * mn;
+    }
+    for (; k < k1; ++k, p += mn) s[0] += *p;
+    gsum[((size_t)b * ngroup + g) * mn + i] = (s[0] + s[1]) + (s[2] + s[3]);
+}
+
 template <typename T>
 __global__ void k_splitk_reduce(const T *__restrict__ part, int nsplit, int M, int N, T alpha,
                                 T beta, T *__restrict__ C, long long ldc, long long sC,
@@ -133,7 +162,9 @@ void gemm(bool nt, int M, int N, int K, T alpha, const T *A, long long lda, long
         return;
     }
     const size_t mn = (size_t)M * N;
-    T *part = (T *)ws.get(mn * nsplit * batch * sizeof(T));
+    const int ngroup = nsplit > SPLIT_GROUP ? (int)div_up(nsplit, SPLIT_GROUP) : 0;
+    T *part = (T *)ws.get(mn * (size_t)(nsplit + ngroup) * batch * sizeof(T));
+    T *gsum = part + mn * (size_t)nsplit * batch;
     if (nt)
         k_gemm<T, true><<<grid, 256, 0, st>>>(M, N, K, (T)1, A, lda, sA, B, ldb, sB, (T)0, part, N,
                                               0, kchunk, nsplit);
@@ -142,8 +173,16 @@ void gemm(bool nt, int M, int N, int K, T alpha, const T *A, long long lda, long
                                                N, 0, kchunk, nsplit);
     BSE_LAUNCH_CHECK();
     const long long tot = (long long)mn * batch;
-    k_splitk_reduce<T><<<div_up(tot, 256), 256, 0, st>>>(part, nsplit, M, N, alpha, beta, C, ldc,
-                                                         sC, batch);
+    if (ngroup > 0) {
+        dim3 g1(div_up(mn, 256), ngroup, batch);
+        k_splitk_group<T><<<g1, 256, 0, st>>>(part, nsplit, (long long)mn, ngroup, batch, gsum);
+        BSE_LAUNCH_CHECK();
+        k_splitk_reduce<T><<<div_up(tot, 256), 256, 0, st>>>(gsum, ngroup, M, N, alpha, beta, C,
+                                                             ldc, sC, batch);
+    } else {
+        k_splitk_reduce<T><<<div_up(tot, 256), 256, 0, st>>>(part, nsplit, M, N, alpha, beta, C,
+                                                             ldc, sC, batch);
+    }
     BSE_LAUNCH_CHECK();
 }
 
