@@ -54,10 +54,11 @@ def sources_sha256(paths):
     return h.hexdigest()
 
 
-def measured_traffic(kernel, workload_key):
-    """Bytes per launch from the counter summary: FETCH_SIZE and WRITE_SIZE
-    (KiB per dispatch) times the factors that the same counters give for a
-    plain copy of known size; None if the summary does not apply."""
+def measured_traffic(kernel, workload_key, shape):
+    """Bytes per launch of K1d shape `shape` from the counter summary:
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) times the factors that the
+    same counters give for a plain copy of known size; None if the summary
+    does not apply."""
     if not os.path.exists(TRAFFIC_SUMMARY):
         return None
     kv = {}
@@ -71,8 +72,8 @@ def measured_traffic(kernel, workload_key):
             return None
         if kv.get("sources_sha256") != sources_sha256(K1D_SOURCES):
             return None
-        fetch = float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_bytes_per_kib"])
-        write = float(kv["write_kib_per_dispatch"]) * float(kv["write_bytes_per_kib"])
+        fetch = float(kv[f"shape_{shape}_fetch_kib"]) * float(kv["fetch_bytes_per_kib"])
+        write = float(kv[f"shape_{shape}_write_kib"]) * float(kv["write_bytes_per_kib"])
     except (KeyError, ValueError):
         return None
     return fetch + write
@@ -313,6 +314,11 @@ def main():
         t_setup = time.time() - t
         P = ctx.n_pairs
         log(f"pairs {P} (threshold {thr:.4g}), setup {t_setup:.2f} s")
+        # the autotuner picks the K1d shape for this cell and block (untimed set-up)
+        t = time.time()
+        shape, shape_ms = ctx.autotune(B, prec, n_rep=2)
+        t_tune = time.time() - t
+        log(f"autotuned K1d shape {shape}: {[round(x, 3) for x in shape_ms]} ms ({t_tune:.1f} s)")
         Xh = trial_block(cell, B, seed=1234)
         X = torch.from_numpy(Xh).to("cuda", dtype=dt)
         Y = torch.empty_like(X)
@@ -348,7 +354,7 @@ def main():
     else:
         ach = nbytes[dom] / (stages[dom] * 1e-3) / 1e9
         wkey = f"{args.cell} {args.precision} block {B} fraction {args.fraction}"
-        traffic = measured_traffic(dom, wkey)
+        traffic = measured_traffic(dom, wkey, shape)
         roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
                 "algorithmic_bytes": nbytes[dom]}
@@ -367,7 +373,8 @@ def main():
                                 f"(fraction {args.fraction}), block {B}, "
                                 f"{'hipGraph replay' if not args.no_graph else 'eager'}"),
                    "block": B, "n_occ": cell.n_occ, "grid": cell.n, "n_pairs": P,
-                   "precision": args.precision},
+                   "precision": args.precision, "k1d_shape": shape,
+                   "k1d_ms_by_shape": [round(x, 3) for x in shape_ms]},
         "roofline": roof,
         "whole_apply_gbs": whole_bytes / (ms_per_step * 1e-3) / 1e9,
         "setup_seconds": t_setup,

@@ -283,7 +283,7 @@ void ctx_build_pairs(bse_ctx *c, int kind, double thr) {
         if (!host.empty())
             BSE_HIP(hipMemcpy(dev.p, host.data(), host.size() * sizeof(host[0]), hipMemcpyHostToDevice));
     };
-    for (int set = 0; set < 2; ++set) {
+    for (int set = 0; set < K1D_NSETS; ++set) {
         const int BI = K1D_BI_SIZES[set], BJ = K1D_BJ;
         const int nIb = (no + BI - 1) / BI, nJb = (no + BJ - 1) / BJ;
         const long long P = c->n_pairs;

@@ -97,10 +97,10 @@ struct bse_ctx {
     std::vector<int> pairs_h;  // [P][2]
     bse::Dev<int2> pairs_d;
     // K1d tables, one set per row-block size of K1D_BI_SIZES
-    bse::Dev<int> csr_tbl[2];
-    bse::Dev<unsigned char> csr_nz[2];
-    bse::Dev<int> csr_order[2];
-    bse::PairCSR csr[2];
+    bse::Dev<int> csr_tbl[bse::K1D_NSETS];
+    bse::Dev<unsigned char> csr_nz[bse::K1D_NSETS];
+    bse::Dev<int> csr_order[bse::K1D_NSETS];
+    bse::PairCSR csr[bse::K1D_NSETS];
     int k1d_shape[2] = {0, 0};  // chosen K1d shape for FP64 / FP32 (bse_autotune)
     long long n_pairs = 0;
     bool have_tau64 = false, have_tau32 = false;

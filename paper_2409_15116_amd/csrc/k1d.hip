@@ -58,8 +58,8 @@ __device__ inline void k1d_request(T (&t)[BW], __amdgpu_buffer_rsrc_t trs, int v
     for (int i = 0; i < BW; ++i) t[i] = tau_load<T>(trs, voff, tb[i] * (int)sizeof(T));
 }
 
-template <typename T, int BI, int BJ, int S, int NBUF>
-__global__ void __launch_bounds__(256) k_k1d(const T *__restrict__ A, const T *__restrict__ tau,
+template <typename T, int BI, int BJ, int S, int NBUF, int NW>
+__global__ void __launch_bounds__(64 * NW) k_k1d(const T *__restrict__ A, const T *__restrict__ tau,
                                              const T *__restrict__ V, const T *__restrict__ u,
                                              const int *__restrict__ tbl,
                                              const unsigned char *__restrict__ blk_nz,
@@ -68,11 +68,12 @@ __global__ void __launch_bounds__(256) k_k1d(const T *__restrict__ A, const T *_
                                              int nJb, int nSc, T k1d, T inv_omega,
                                              T *__restrict__ Cr, T *__restrict__ Dp) {
     static_assert(NBUF == 1 || (NBUF == 2 && BJ % 2 == 0), "NBUF 1, or 2 with an even BJ");
-    static_assert(BI % 4 == 0, "four waves share the rows");
-    constexpr int BW = BI / 4;  // rows per wave
+    static_assert(BI % NW == 0, "the waves share the rows");
+    constexpr int NT = 64 * NW;
+    constexpr int BW = BI / NW;  // rows per wave
     constexpr int TILE = BJ * S * K1D_R;
-    constexpr int PER_T = TILE / 256;  // a values staged per thread
-    static_assert(TILE % 256 == 0 && 4 * S * K1D_R <= 2 * TILE, "tile shapes");
+    constexpr int PER_T = TILE / NT;  // a values staged per thread
+    static_assert(TILE % NT == 0 && NW * S * K1D_R <= 2 * TILE, "tile shapes");
     __shared__ T tile[2][TILE];
     // decode: id = 8 * (hi8 * nIb * nSc + ib * nSc + sc) + lo8, r-tile = hi8 * 8 + lo8
     const int id = blockIdx.x;
@@ -103,13 +104,13 @@ __global__ void __launch_bounds__(256) k_k1d(const T *__restrict__ A, const T *_
     const int *ordr = order + (size_t)ib * nJb;
 
     // a values of column block jb into tile[b]: row (w * S + s) of the tile is
-    // staged by wave (w * S + s) % 4, one point per lane; rows past n_occ,
+    // staged by wave (w * S + s) % NW, one point per lane; rows past n_occ,
     // vectors past B and points past nr read a clamped valid element (their
     // products either meet a zero tau or are never stored)
     auto stage_a = [&](int jb, int b) {
 #pragma unroll
         for (int l = 0; l < PER_T; ++l) {
-            const int row = wv + 4 * l;
+            const int row = wv + NW * l;
             const int s = row % S, w = row / S;
             const int vv = min(jb * BJ + w, n_occ - 1);
             const int ss = min(s0 + s, B - 1);
@@ -176,10 +177,10 @@ __global__ void __launch_bounds__(256) k_k1d(const T *__restrict__ A, const T *_
         }
     }
     // epilogue: Cr for this wave's rows, and the K1e density of the row block
-    // summed over the four waves through LDS (the tiles are free after the
+    // summed over the NW waves through LDS (the tiles are free after the
     // loop's last barrier)
     const T vr = V[rr];
-    T *red = &tile[0][0];  // [4][S][64]
+    T *red = &tile[0][0];  // [NW][S][64]
 #pragma unroll
     for (int j = 0; j < S; ++j) {
         const int s = min(s0 + j, B - 1);
@@ -197,9 +198,10 @@ __global__ void __launch_bounds__(256) k_k1d(const T *__restrict__ A, const T *_
         red[(wv * S + j) * K1D_R + lane] = dn;
     }
     __syncthreads();
-    for (int j = wv; j < S; j += 4) {
-        const T d = red[(0 * S + j) * K1D_R + lane] + red[(1 * S + j) * K1D_R + lane] +
-                    red[(2 * S + j) * K1D_R + lane] + red[(3 * S + j) * K1D_R + lane];
+    for (int j = wv; j < S; j += NW) {
+        T d = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) d += red[(w * S + j) * K1D_R + lane];
         if (rok && s0 + j < B) Dp[((size_t)ib * B + s0 + j) * nr + rr] = d * inv_omega;
     }
 }
@@ -219,7 +221,7 @@ __global__ void k_sum_density(const T *__restrict__ Dp, int nIb, int B, long lon
     Hc[(size_t)q * nr + i] = cmake<cplx<T>>(a, b);
 }
 
-template <typename T, int BI, int S, int NBUF>
+template <typename T, int BI, int S, int NBUF, int NW>
 static void launch_k1d(const T *A, const T *tau, const T *V, const T *u, const PairCSR &csr,
                        int n_occ, int B, long long nr, T k1d, T inv_omega, T *Cr, T *Dp,
                        hipStream_t st) {
@@ -233,16 +235,18 @@ static void launch_k1d(const T *A, const T *tau, const T *V, const T *u, const P
     BSE_REQUIRE(nblk < (1LL << 31), BSE_ERR_ARG, "grid too large for the K1d kernel");
     BSE_REQUIRE(csr.n_rows * TAU_TILE * (long long)sizeof(T) < (1LL << 31), BSE_ERR_ARG,
                 "too many pairs for the K1d tables");
-    k_k1d<T, BI, K1D_BJ, S, NBUF><<<(unsigned)nblk, 256, 0, st>>>(
+    k_k1d<T, BI, K1D_BJ, S, NBUF, NW><<<(unsigned)nblk, 64 * NW, 0, st>>>(
         A, tau, V, u, csr.tbl, csr.blk_nz, csr.order, n_occ, B, nr, csr.n_rows, nIb, nJb, nSc,
         k1d, inv_omega, Cr, Dp);
     BSE_LAUNCH_CHECK();
 }
 
 // the compiled shapes; variant 0 is the default of each type
-static constexpr K1dShape K1D_SHAPES32[] = {
-    {32, 16, 2}, {32, 16, 1}, {16, 16, 2}, {32, 8, 2}, {16, 8, 2}};
-static constexpr K1dShape K1D_SHAPES64[] = {{32, 8, 1}, {16, 8, 1}, {32, 4, 1}, {16, 4, 1}};
+static constexpr K1dShape K1D_SHAPES32[] = {{32, 16, 2, 4}, {32, 16, 1, 4}, {16, 16, 2, 4},
+                                            {32, 8, 2, 4},  {16, 8, 2, 4},  {64, 16, 2, 8},
+                                            {64, 8, 2, 8},  {32, 8, 2, 8}};
+static constexpr K1dShape K1D_SHAPES64[] = {{32, 8, 1, 4}, {16, 8, 1, 4}, {32, 4, 1, 4},
+                                            {16, 4, 1, 4}, {64, 8, 1, 8}, {64, 4, 1, 8}};
 
 int k1d_num_shapes(bool dbl) {
     return dbl ? (int)(sizeof(K1D_SHAPES64) / sizeof(K1dShape))
@@ -259,21 +263,31 @@ void k1d_apply(const T *A, const T *tau, const T *V, const T *u, const PairCSR *
                hipStream_t st) {
     constexpr bool dbl = sizeof(T) == 8;
     const K1dShape sh = k1d_shape(dbl, shape);
-    const PairCSR &csr = csrs[sh.bi == K1D_BI_SIZES[0] ? 0 : 1];
-#define BSE_K1D_CASE(BI_, S_, NB_)                                                           \
-    if (sh.bi == BI_ && sh.s == S_ && sh.nbuf == NB_)                                          \
-        launch_k1d<T, BI_, S_, NB_>(A, tau, V, u, csr, n_occ, B, nr, k1d, inv_omega, Cr, Dp, st);
+    int set = -1;
+    for (int i = 0; i < K1D_NSETS; ++i)
+        if (K1D_BI_SIZES[i] == sh.bi) set = i;
+    BSE_REQUIRE(set >= 0, BSE_ERR_STATE, "no K1d table set for %d-row blocks", sh.bi);
+    const PairCSR &csr = csrs[set];
+#define BSE_K1D_CASE(BI_, S_, NB_, NW_)                                                      \
+    if (sh.bi == BI_ && sh.s == S_ && sh.nbuf == NB_ && sh.nw == NW_)                         \
+        launch_k1d<T, BI_, S_, NB_, NW_>(A, tau, V, u, csr, n_occ, B, nr, k1d, inv_omega, Cr, Dp, \
+                                         st);
     if constexpr (dbl) {
-        BSE_K1D_CASE(32, 8, 1)
-        BSE_K1D_CASE(16, 8, 1)
-        BSE_K1D_CASE(32, 4, 1)
-        BSE_K1D_CASE(16, 4, 1)
+        BSE_K1D_CASE(32, 8, 1, 4)
+        BSE_K1D_CASE(16, 8, 1, 4)
+        BSE_K1D_CASE(32, 4, 1, 4)
+        BSE_K1D_CASE(16, 4, 1, 4)
+        BSE_K1D_CASE(64, 8, 1, 8)
+        BSE_K1D_CASE(64, 4, 1, 8)
     } else {
-        BSE_K1D_CASE(32, 16, 2)
-        BSE_K1D_CASE(32, 16, 1)
-        BSE_K1D_CASE(16, 16, 2)
-        BSE_K1D_CASE(32, 8, 2)
-        BSE_K1D_CASE(16, 8, 2)
+        BSE_K1D_CASE(32, 16, 2, 4)
+        BSE_K1D_CASE(32, 16, 1, 4)
+        BSE_K1D_CASE(16, 16, 2, 4)
+        BSE_K1D_CASE(32, 8, 2, 4)
+        BSE_K1D_CASE(16, 8, 2, 4)
+        BSE_K1D_CASE(64, 16, 2, 8)
+        BSE_K1D_CASE(64, 8, 2, 8)
+        BSE_K1D_CASE(32, 8, 2, 8)
     }
 #undef BSE_K1D_CASE
     const int nIb = (n_occ + sh.bi - 1) / sh.bi;

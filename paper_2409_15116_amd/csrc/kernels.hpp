@@ -64,14 +64,16 @@ struct PairCSR {
     unsigned char *blk_nz = nullptr;
     int *order = nullptr;
 };
-constexpr int K1D_BI_SIZES[2] = {32, 16};  // table sets held by a context
+constexpr int K1D_NSETS = 3;
+constexpr int K1D_BI_SIZES[K1D_NSETS] = {32, 16, 64};  // table sets held by a context
 constexpr int K1D_BI_MIN = 16;
 
 // Compiled shapes of the K1d kernel (the autotuner's choices): BI rows per
-// workgroup, S trial vectors per workgroup, NBUF columns of tau in flight.
-// Variant 0 of each type is the default.
+// workgroup, S trial vectors per workgroup, NBUF columns of tau in flight,
+// NW waves per workgroup (BI / NW rows each).  Variant 0 of each type is the
+// default.
 struct K1dShape {
-    int bi, s, nbuf;
+    int bi, s, nbuf, nw;
 };
 int k1d_num_shapes(bool dbl);
 K1dShape k1d_shape(bool dbl, int v);
