@@ -289,19 +289,26 @@ def _ground_state(basis: _RealBasis, V: np.ndarray, k: int, seed: int):
         return prec.reshape(-1, 1) * X.reshape(npw, -1)
 
     import warnings
-    with warnings.catch_warnings():
-        warnings.simplefilter("ignore")
-        w, X = lobpcg(A, start, M=M, largest=False, tol=1e-7, maxiter=80)
-    o = np.argsort(w)
-    w, X = w[o], X[:, o]
-    # final Rayleigh-Ritz and accuracy check
-    HX = A(X)
-    T = X.T @ HX
-    S = X.T @ X
     from scipy.linalg import eigh as geigh
-    ww, Y = geigh(0.5 * (T + T.T), 0.5 * (S + S.T))
-    X = X @ Y
-    res = np.linalg.norm(A(X[:, :k]) - X[:, :k] * ww[:k], axis=0).max()
+    X = start
+    for rnd in range(4):
+        # rounds of at most 80 iterations, each restarted from the previous
+        # round's Rayleigh-Ritz vectors, until the k lowest are converged
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore")
+            w, X = lobpcg(A, X, M=M, largest=False, tol=1e-7, maxiter=80)
+        o = np.argsort(w)
+        w, X = w[o], X[:, o]
+        # Rayleigh-Ritz in the block and accuracy check
+        HX = A(X)
+        T = X.T @ HX
+        S = X.T @ X
+        ww, Y = geigh(0.5 * (T + T.T), 0.5 * (S + S.T))
+        X = X @ Y
+        res = np.linalg.norm(A(X[:, :k]) - X[:, :k] * ww[:k], axis=0).max()
+        if res <= 1e-6:
+            break
+        _progress(f"LOBPCG round {rnd + 1}: residual {res:.2e}, continuing")
     if res > 1e-6:
         raise RuntimeError(f"ground state not converged (residual {res:.2e})")
     return ww[:k], np.ascontiguousarray(X[:, :k].T)
