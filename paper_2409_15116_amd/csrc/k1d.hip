@@ -244,9 +244,10 @@ static void launch_k1d(const T *A, const T *tau, const T *V, const T *u, const P
 // the compiled shapes; variant 0 is the default of each type
 static constexpr K1dShape K1D_SHAPES32[] = {{32, 16, 2, 4}, {32, 16, 1, 4}, {16, 16, 2, 4},
                                             {32, 8, 2, 4},  {16, 8, 2, 4},  {64, 16, 2, 8},
-                                            {64, 8, 2, 8},  {32, 8, 2, 8}};
+                                            {64, 8, 2, 8},  {32, 8, 2, 8},  {128, 8, 2, 16}};
 static constexpr K1dShape K1D_SHAPES64[] = {{32, 8, 1, 4}, {16, 8, 1, 4}, {32, 4, 1, 4},
-                                            {16, 4, 1, 4}, {64, 8, 1, 8}, {64, 4, 1, 8}};
+                                            {16, 4, 1, 4}, {64, 8, 1, 8}, {64, 4, 1, 8},
+                                            {128, 4, 1, 16}};
 
 int k1d_num_shapes(bool dbl) {
     return dbl ? (int)(sizeof(K1D_SHAPES64) / sizeof(K1dShape))
@@ -279,6 +280,7 @@ void k1d_apply(const T *A, const T *tau, const T *V, const T *u, const PairCSR *
         BSE_K1D_CASE(16, 4, 1, 4)
         BSE_K1D_CASE(64, 8, 1, 8)
         BSE_K1D_CASE(64, 4, 1, 8)
+        BSE_K1D_CASE(128, 4, 1, 16)
     } else {
         BSE_K1D_CASE(32, 16, 2, 4)
         BSE_K1D_CASE(32, 16, 1, 4)
@@ -288,6 +290,7 @@ void k1d_apply(const T *A, const T *tau, const T *V, const T *u, const PairCSR *
         BSE_K1D_CASE(64, 16, 2, 8)
         BSE_K1D_CASE(64, 8, 2, 8)
         BSE_K1D_CASE(32, 8, 2, 8)
+        BSE_K1D_CASE(128, 8, 2, 16)
     }
 #undef BSE_K1D_CASE
     const int nIb = (n_occ + sh.bi - 1) / sh.bi;

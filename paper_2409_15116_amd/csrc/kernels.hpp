@@ -64,8 +64,8 @@ struct PairCSR {
     unsigned char *blk_nz = nullptr;
     int *order = nullptr;
 };
-constexpr int K1D_NSETS = 3;
-constexpr int K1D_BI_SIZES[K1D_NSETS] = {32, 16, 64};  // table sets held by a context
+constexpr int K1D_NSETS = 4;
+constexpr int K1D_BI_SIZES[K1D_NSETS] = {32, 16, 64, 128};  // table sets held by a context
 constexpr int K1D_BI_MIN = 16;
 
 // Compiled shapes of the K1d kernel (the autotuner's choices): BI rows per
