@@ -399,9 +399,9 @@ bse_status bse_debug_gemm(bse_ctx *c, int nt, int M, int N, int K, double alpha,
                               (const double *)B, ldb, 0, beta, (double *)Cm, ldc, 0, 1, c->gws,
                               c->stream);
         else if (precision == BSE_FP32)
-            bse::gemm<float>(nt != 0, M, N, K, (float)alpha, (const float *)A, lda, 0,
-                             (const float *)B, ldb, 0, (float)beta, (float *)Cm, ldc, 0, 1, c->gws,
-                             c->stream);
+            bse::gemm_f32m(nt != 0, M, N, K, (float)alpha, (const float *)A, lda, 0,
+                           (const float *)B, ldb, 0, (float)beta, (float *)Cm, ldc, 0, 1, c->gws,
+                           c->stream);
         else
             bse::gemm_bf16x3(nt != 0, M, N, K, (float)alpha, (const float *)A, lda, 0,
                              (const float *)B, ldb, 0, (float)beta, (float *)Cm, ldc, 0, 1, c->gws,

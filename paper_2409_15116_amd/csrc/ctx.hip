@@ -346,6 +346,21 @@ void ctx_build_pairs(bse_ctx *c, int kind, double thr) {
 // screened integrals (Eqs. tau, tau_from_tau_u, pdep)
 // ---------------------------------------------------------------------------
 template <typename T>
+static void gemm_p(bse_ctx *c, bool bf, bool nt, int M, int N, int K, T alpha, const T *A,
+                   long long lda, long long sA, const T *B, long long ldb, long long sB, T beta,
+                   T *C, long long ldc, long long sC, int batch, Workspace &ws) {
+    if (bf)
+        gemm_bf16x3(nt, M, N, K, (float)alpha, (const float *)A, lda, sA, (const float *)B, ldb, sB,
+                    (float)beta, (float *)C, ldc, sC, batch, ws, c->stream);
+    else if constexpr (std::is_same<T, float>::value)
+        gemm_f32m(nt, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, ws,
+                  c->stream);
+    else
+        gemm<T>(nt, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, ws,
+                c->stream);
+}
+
+template <typename T>
 static void screen_impl(bse_ctx *c, const T *phi, const T *phif, int n_pdep, bool bf16x3,
                         T *tau_out, float *tau32_copy) {
     const long long nr = c->nr;
@@ -380,10 +395,10 @@ static void screen_impl(bse_ctx *c, const T *phi, const T *phif, int n_pdep, boo
                         (const float *)phif, npw1, 0, 0.0f, (float *)D.p, npw1, 0, 1, c->gws,
                         c->stream);
         } else {
-            gemm<T>(true, cnt, n_pdep, npw1, (T)1, Rb.p, npw1, 0, phi, npw1, 0, (T)0, Cm.p, n_pdep,
-                    0, 1, c->gws, c->stream);
-            gemm<T>(false, cnt, npw1, n_pdep, (T)1, Cm.p, n_pdep, 0, phif, npw1, 0, (T)0, D.p, npw1,
-                    0, 1, c->gws, c->stream);
+            gemm_p<T>(c, false, true, cnt, n_pdep, npw1, (T)1, Rb.p, npw1, 0, phi, npw1, 0, (T)0,
+                      Cm.p, n_pdep, 0, 1, c->gws);
+            gemm_p<T>(c, false, false, cnt, npw1, n_pdep, (T)1, Cm.p, n_pdep, 0, phif, npw1, 0,
+                      (T)0, D.p, npw1, 0, 1, c->gws);
         }
         scale_grid<T>(Hc.p, vc, nr, nq, c->stream);
         pdep_scatter<T>(Hc.p, cnt, nr, c->idx_p.p, c->idx_m.p, sqv, nh, D.p, c->stream);
@@ -461,17 +476,6 @@ static void ensure_ws(bse_ctx *c, ApplyWs<T> &w, int nvec) {
     ++w.gen;
 }
 
-template <typename T>
-static void gemm_p(bse_ctx *c, bool bf, bool nt, int M, int N, int K, T alpha, const T *A,
-                   long long lda, long long sA, const T *B, long long ldb, long long sB, T beta,
-                   T *C, long long ldc, long long sC, int batch, Workspace &ws) {
-    if (bf)
-        gemm_bf16x3(nt, M, N, K, (float)alpha, (const float *)A, lda, sA, (const float *)B, ldb, sB,
-                    (float)beta, (float *)C, ldc, sC, batch, ws, c->stream);
-    else
-        gemm<T>(nt, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, ws,
-                c->stream);
-}
 
 // P_c on a block in place: Y -= (Y Psi^T) Psi
 template <typename T>

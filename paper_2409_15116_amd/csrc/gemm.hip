@@ -1,7 +1,8 @@
 // Dense GEMMs: C = alpha * A * op(B) + beta * C, row-major, strided batches.
 //   NN: B is [K][N];  NT: B is [N][K].
-// The vector-FMA kernel serves FP64 and FP32; the FP32 path can instead run
-// on MFMA as split-BF16x3 (gemm_bf16x3 in mfma.hip).
+// The vector-FMA kernel serves FP64 (and FP32 where asked for); the apply's
+// FP32 GEMMs run on the matrix cores (gemm_f32m, or split-BF16x3 gemm_bf16x3,
+// in mfma.hip).
 #include "kernels.hpp"
 
 namespace bse {

@@ -121,6 +121,10 @@ void gemm(bool nt, int M, int N, int K, T alpha, const T *A, long long lda, long
           int batch, Workspace &ws, hipStream_t st);
 
 // split-BF16x3 MFMA GEMM with FP32 accumulate (same conventions as gemm<float>)
+// FP32 GEMM on the matrix cores (exact FP32 products, FP32 accumulate)
+void gemm_f32m(bool nt, int M, int N, int K, float alpha, const float *A, long long lda,
+               long long sA, const float *B, long long ldb, long long sB, float beta, float *C,
+               long long ldc, long long sC, int batch, Workspace &ws, hipStream_t st);
 void gemm_bf16x3(bool nt, int M, int N, int K, float alpha, const float *A, long long lda,
                  long long sA, const float *B, long long ldb, long long sB, float beta, float *C,
                  long long ldc, long long sC, int batch, Workspace &ws, hipStream_t st);

@@ -145,6 +145,97 @@ __global__ void __launch_bounds__(256) k_gemm_bf16x3(int M, int N, int K, float 
             }
 }
 
+// FP32 on the matrix cores: v_mfma_f32_16x16x4f32, exact FP32 products with
+// FP32 accumulation (the FP32 path's GEMMs; twice the rate of non-packed
+// vector FMA).  Lane layout (64 lanes): A element of lane l is A[l % 16][l / 16],
+// B element is B[l / 16][l % 16], accumulator element i is D[4 (l / 16) + i][l % 16].
+// Same 64 x 64 tile and LDS staging as above, FP32 in LDS ([m][k], [n][k],
+// rows padded so that the 64 lanes of a read hit 64 different banks).
+template <bool NT>
+__global__ void __launch_bounds__(256) k_gemm_f32m(int M, int N, int K, float alpha,
+                                                   const float *__restrict__ A, long long lda,
+                                                   long long sA, const float *__restrict__ Bm,
+                                                   long long ldb, long long sB, float beta,
+                                                   float *__restrict__ C, long long ldc,
+                                                   long long sC, int kchunk, int nsplit) {
+    __shared__ float As[TB][TK + PADK], Bs[TB][TK + PADK];
+    const int bz = blockIdx.z;
+    const int batch = bz / nsplit;
+    const int split = bz - batch * nsplit;
+    A += batch * sA;
+    Bm += batch * sB;
+    C += nsplit > 1 ? ((size_t)batch * nsplit + split) * (size_t)M * N : (size_t)(batch * sC);
+    const int m0 = blockIdx.y * TB, n0 = blockIdx.x * TB;
+    const int kbeg = split * kchunk;
+    const int kend = min(K, kbeg + kchunk);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    f32x4_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4_t){0.f, 0.f, 0.f, 0.f};
+    for (int k0 = kbeg; k0 < kend; k0 += TK) {
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            const int idx = tid + l * 256;
+            const int mm = idx >> 4, kk = idx & 15;
+            const int gm = m0 + mm, gk = k0 + kk;
+            As[mm][kk] = (gm < M && gk < kend) ? A[(size_t)gm * lda + gk] : 0.f;
+        }
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            const int idx = tid + l * 256;
+            int nn, kk;
+            float x;
+            if (NT) {
+                nn = idx >> 4;
+                kk = idx & 15;
+                const int gn = n0 + nn, gk = k0 + kk;
+                x = (gn < N && gk < kend) ? Bm[(size_t)gn * ldb + gk] : 0.f;
+            } else {
+                kk = idx >> 6;
+                nn = idx & 63;
+                const int gn = n0 + nn, gk = k0 + kk;
+                x = (gn < N && gk < kend) ? Bm[(size_t)gk * ldb + gn] : 0.f;
+            }
+            Bs[nn][kk] = x;
+        }
+        __syncthreads();
+        const int r16 = lane & 15, kq = lane >> 4;
+#pragma unroll
+        for (int sub = 0; sub < TK / 4; ++sub) {
+            float a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) a[i] = As[wm + i * 16 + r16][4 * sub + kq];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) b[j] = Bs[wn + j * 16 + r16][4 * sub + kq];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    const int c16 = lane & 15, rq = (lane >> 4) * 4;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int gm = m0 + wm + i * 16 + rq + e;
+                const int gn = n0 + wn + j * 16 + c16;
+                if (gm < M && gn < N) {
+                    float *c = C + (size_t)gm * ldc + gn;
+                    const float v = acc[i][j][e];
+                    if (nsplit > 1) *c = v;
+                    else *c = beta == 0.f ? alpha * v : alpha * v + beta * *c;
+                }
+            }
+}
+
 __global__ void k_splitk_reduce_f(const float *__restrict__ part, int nsplit, int M, int N,
                                   float alpha, float beta, float *__restrict__ C, long long ldc,
                                   long long sC, int nbatch) {
@@ -169,7 +260,8 @@ static void launch_bf16(dim3 grid, hipStream_t st, int M, int N, int K, float al
     BSE_LAUNCH_CHECK();
 }
 
-static void gemm_bf16_any(bool ta, bool nt, bool split, int M, int N, int K, float alpha,
+// mode: 0 bf16, 1 split-BF16x3, 2 FP32 (ta only with mode 0)
+static void gemm_mfma_any(bool ta, bool nt, int mode, int M, int N, int K, float alpha,
                           const float *A, long long lda, long long sA, const float *B,
                           long long ldb, long long sB, float beta, float *C, long long ldc,
                           long long sC, int batch, Workspace &ws, hipStream_t st) {
@@ -190,8 +282,19 @@ static void gemm_bf16_any(bool ta, bool nt, bool split, int M, int N, int K, flo
         ldw = N;
         sw = 0;
     }
+    const bool split = mode == 1;
+    if (mode == 2) {
+        BSE_REQUIRE(!ta, BSE_ERR_ARG, "FP32 MFMA GEMM: transposed A not compiled");
+        if (nt)
+            k_gemm_f32m<true><<<grid, 256, 0, st>>>(M, N, K, a, A, lda, sA, B, ldb, sB, b, Cw, ldw,
+                                                   sw, kchunk, nsplit);
+        else
+            k_gemm_f32m<false><<<grid, 256, 0, st>>>(M, N, K, a, A, lda, sA, B, ldb, sB, b, Cw, ldw,
+                                                    sw, kchunk, nsplit);
+        BSE_LAUNCH_CHECK();
+    }
 #define BSE_BF16_CASE(TA_, NT_, SP_)                                                          \
-    if (ta == TA_ && nt == NT_ && split == SP_)                                               \
+    if (mode != 2 && ta == TA_ && nt == NT_ && split == SP_)                                  \
         launch_bf16<TA_, NT_, SP_>(grid, st, M, N, K, a, A, lda, sA, B, ldb, sB, b, Cw, ldw, sw, \
                                    kchunk, nsplit);
     BSE_BF16_CASE(false, false, true)
@@ -212,14 +315,21 @@ static void gemm_bf16_any(bool ta, bool nt, bool split, int M, int N, int K, flo
 void gemm_bf16x3(bool nt, int M, int N, int K, float alpha, const float *A, long long lda,
                  long long sA, const float *B, long long ldb, long long sB, float beta, float *C,
                  long long ldc, long long sC, int batch, Workspace &ws, hipStream_t st) {
-    gemm_bf16_any(false, nt, true, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch,
+    gemm_mfma_any(false, nt, 1, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch,
                   ws, st);
 }
 
 void gemm_bf16(bool ta, bool nt, int M, int N, int K, float alpha, const float *A, long long lda,
                const float *B, long long ldb, float beta, float *C, long long ldc, Workspace &ws,
                hipStream_t st) {
-    gemm_bf16_any(ta, nt, false, M, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1, ws, st);
+    gemm_mfma_any(ta, nt, 0, M, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1, ws, st);
+}
+
+void gemm_f32m(bool nt, int M, int N, int K, float alpha, const float *A, long long lda,
+               long long sA, const float *B, long long ldb, long long sB, float beta, float *C,
+               long long ldc, long long sC, int batch, Workspace &ws, hipStream_t st) {
+    gemm_mfma_any(false, nt, 2, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch,
+                  ws, st);
 }
 
 }  // namespace bse
