@@ -260,6 +260,85 @@ def uneven_batch(args, torch, pkg):
     return out
 
 
+def learned_c5(args, torch, pkg):
+    """Learned preconditioner on jittered 64-well snapshots (N_occ = 64, 72^3,
+    25 Ry, 256 PDEP, 40 % of the pairs): plain FP32 solves of the first
+    n_train snapshots record (features, label) rows, the network is trained
+    on the GPU, and the remaining snapshots are solved with the diagonal
+    preconditioner and with the learned correction.  8 lowest, block 16,
+    tol 1e-5 Ha; eigenvalues compared with the plain FP64 GPU solve."""
+    from synth import make_cell, trial_block
+    n_all = args.learned
+    n_train = max(1, (4 * n_all) // 5)
+    nwg = 127
+    kw = 1 + 2 * nwg
+    n_eig, B, tol = 8, 16, 1e-5
+    st = torch.cuda.Stream()
+    out = {"snapshots": n_all, "train": n_train, "test": n_all - n_train, "n_eig": n_eig,
+           "block": B, "tol_ha": tol, "window_pw": nwg}
+    feats, labs = [], []
+    with torch.cuda.stream(st):
+        def prepare(i):
+            c = make_cell(f"c5_{i:02d}")
+            ctx = pkg.context_for(c, stream=st)
+            pkg.setup_pairs_and_screen(ctx, c, fraction=args.fraction, precision=pkg.FP64)
+            ctx.autotune(B, pkg.FP32, n_rep=2)
+            ctx.set_graph(True)
+            X0 = torch.from_numpy(trial_block(c, B, seed=4321)).to("cuda")
+            return c, ctx, X0
+        t_rec = time.time()
+        for i in range(n_train):
+            c, ctx, X0 = prepare(i)
+            om, X, s = ctx.davidson(X0, n_eig, block=B, precision=pkg.FP32, tol=tol, max_iter=400)
+            f, lab, _, s2 = ctx.davidson_record(X0, X.contiguous(), n_eig, nwg, 60000, block=B,
+                                                precision=pkg.FP32, tol=tol, max_iter=400)
+            feats.append(f.clone())
+            labs.append(lab.clone())
+            log(f"learned: snapshot {i} recorded {f.shape[0]} rows ({s['iterations']} iterations)")
+            ctx.close()
+        t_rec = time.time() - t_rec
+        F = torch.cat(feats).contiguous()
+        L = torch.cat(labs).contiguous()
+        del feats, labs
+        net = pkg.Mlp(kw + 3, 256, kw, pkg.mlp_init_weights(kw + 3, 256, kw, seed=9))
+        torch.cuda.synchronize()
+        t = time.time()
+        losses = net.train(F, L, epochs=30, batch=512, lr=1e-3, seed=2)
+        torch.cuda.synchronize()
+        t_train = time.time() - t
+        out.update({"rows": int(F.shape[0]), "record_seconds": t_rec, "train_seconds": t_train,
+                    "loss_first": float(losses[0]), "loss_last": float(losses[-1])})
+        log(f"learned: trained on {F.shape[0]} rows in {t_train:.1f} s, loss "
+            f"{losses[0]:.4g} -> {losses[-1]:.4g}")
+        del F, L
+        tests = []
+        for i in range(n_train, n_all):
+            c, ctx, X0 = prepare(i)
+            r = {"snapshot": f"c5_{i:02d}"}
+            om64, _, s64 = ctx.davidson(X0, n_eig, block=B, precision=pkg.FP64, tol=tol,
+                                        max_iter=400)
+            for name, pc in (("diagonal", 0), ("learned", 1)):
+                ctx.set_learned(net if pc else None, nwg)
+                torch.cuda.synchronize()
+                t = time.time()
+                om, _, s = ctx.davidson(X0, n_eig, block=B, precision=pkg.FP32, tol=tol,
+                                        max_iter=400, precond=pc)
+                torch.cuda.synchronize()
+                r[name] = {"iterations": s["iterations"], "seconds": time.time() - t,
+                           "learned_used": s["learned_used"],
+                           "learned_rejected": s["learned_rejected"],
+                           "max_dev_vs_fp64_mev": float(np.abs(om - om64).max() / MEV)}
+            ctx.set_learned(None, nwg)
+            log("learned test", r)
+            tests.append(r)
+            ctx.close()
+        net.close()
+    out["tests"] = tests
+    out["mean_iterations_diagonal"] = float(np.mean([r["diagonal"]["iterations"] for r in tests]))
+    out["mean_iterations_learned"] = float(np.mean([r["learned"]["iterations"] for r in tests]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -274,6 +353,9 @@ def main():
     ap.add_argument("--no-tts", action="store_true")
     ap.add_argument("--uneven-batch", type=int, default=0, metavar="N",
                     help="also run the batch of N uneven cells (reported under uneven_batch)")
+    ap.add_argument("--learned", type=int, default=0, metavar="N",
+                    help="also run the learned preconditioner on N jittered 64-well snapshots "
+                         "(4/5 train, 1/5 test; reported under learned)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB read + 1 GiB write elementwise kernel first "
                          "(scale reference for HBM byte counters)")
@@ -388,6 +470,9 @@ def main():
     if args.uneven_batch > 0:
         log("uneven batch")
         res["uneven_batch"] = uneven_batch(args, torch, pkg)
+    if args.learned > 0:
+        log("learned preconditioner")
+        res["learned"] = learned_c5(args, torch, pkg)
     ctx.close()
     print(json.dumps(res), flush=True)
 

@@ -427,6 +427,16 @@ class Mlp:
         return losses
 
 
+def mlp_init_weights(f_in, hidden, k_out, seed=0):
+    """Seeded initial weights for Mlp (flat FP32, the layout of pack_params):
+    He-normal hidden layers, output layer scaled by 0.1, zero biases."""
+    rng = np.random.default_rng(seed)
+    parts = [rng.standard_normal((f_in, hidden)) * np.sqrt(2.0 / f_in), np.zeros(hidden),
+             rng.standard_normal((hidden, hidden)) * np.sqrt(2.0 / hidden), np.zeros(hidden),
+             rng.standard_normal((hidden, k_out)) * np.sqrt(2.0 / hidden) * 0.1, np.zeros(k_out)]
+    return np.concatenate([np.asarray(x, dtype=np.float32).ravel() for x in parts])
+
+
 def pack_params(p):
     """Flat weight vector of a dict of W1, b1, W2, b2, W3, b3."""
     return np.concatenate([np.asarray(p[k], dtype=np.float32).ravel()
