@@ -217,31 +217,72 @@ __global__ void __launch_bounds__(256) k_sph_inv_z(const T *__restrict__ X, int 
     load_twiddles<T>(stw, tw, n);
     __syncthreads();
     const T isq2 = (T)0.70710678118654752440;
-    const int nwave = FFT_NT >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int c = wave; c < C; c += nwave) {
+    constexpr int NWAVE = FFT_NT >> 6;
+    constexpr int CPW = (C + NWAVE - 1) / NWAVE;  // columns per wave
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // one sphere entry -> F = c1 + i c2 in the LDS tile
+    auto put = [&](int c, int2 en, const T *x1, const T *x2, bool has2) {
+        const int z = en.x & 0xffff, kind = en.x >> 16, k = en.y;
+        C2 c1, c2;
+        if (kind == 0) {
+            c1 = cmake<C2>(x1[0], 0);
+            c2 = cmake<C2>(has2 ? x2[0] : (T)0, 0);
+        } else {
+            const T sg = kind == 1 ? (T)1 : (T)-1;
+            c1 = cmake<C2>(x1[k] * isq2, sg * x1[k + 1] * isq2);
+            c2 = has2 ? cmake<C2>(x2[k] * isq2, sg * x2[k + 1] * isq2) : cmake<C2>(0, 0);
+        }
+        sa[z * C + c] = cmake<C2>(c1.x - c2.y, c1.y + c2.x);
+    };
+    // the first 64 entries of each of the wave's columns, in three batched
+    // levels (column ranges, entries, coefficients) so that each level's
+    // loads are in flight together; loads use clamped in-bounds indices
+    int beg[CPW], cnt[CPW], o1s[CPW], o2s[CPW];
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+        const int c = wave + j * NWAVE;
         const int L = L0 + c;
-        if (L >= n_lines) break;
-        const int q = L / ncol, col = L - q * ncol;
-        int o1, o2;
-        pair_of(q, ps, o1, o2);
-        const T *x1 = X + (size_t)o1 * npw;
-        const T *x2 = X + (size_t)o2 * npw;
-        const bool has2 = o2 < n_orb;
-        for (int e = col_ptr[col] + lane; e < col_ptr[col + 1]; e += 64) {
-            const int2 en = ent[e];
-            const int z = en.x & 0xffff, kind = en.x >> 16, k = en.y;
+        const bool act = c < C && L < n_lines;
+        const int Lc = act ? L : 0;
+        const int q = Lc / ncol, col = Lc - q * ncol;
+        pair_of(q, ps, o1s[j], o2s[j]);
+        beg[j] = col_ptr[col];
+        cnt[j] = act ? col_ptr[col + 1] - beg[j] : 0;
+    }
+    int2 en[CPW];
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) en[j] = ent[lane < cnt[j] ? beg[j] + lane : 0];
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+        const bool has2 = o2s[j] < n_orb;
+        const T *x1 = X + (size_t)o1s[j] * npw;
+        const T *x2 = X + (size_t)(has2 ? o2s[j] : o1s[j]) * npw;  // in bounds either way
+        const int k = (en[j].x >> 16) == 0 ? 0 : en[j].y;
+        const T a0 = x1[k], a1 = x1[k + 1], b0 = x2[k], b1 = x2[k + 1];
+        if (lane < cnt[j]) {
+            const int z = en[j].x & 0xffff, kind = en[j].x >> 16;
             C2 c1, c2;
             if (kind == 0) {
-                c1 = cmake<C2>(x1[0], 0);
-                c2 = cmake<C2>(has2 ? x2[0] : (T)0, 0);
+                c1 = cmake<C2>(a0, 0);
+                c2 = cmake<C2>(has2 ? b0 : (T)0, 0);
             } else {
                 const T sg = kind == 1 ? (T)1 : (T)-1;
-                c1 = cmake<C2>(x1[k] * isq2, sg * x1[k + 1] * isq2);
-                c2 = has2 ? cmake<C2>(x2[k] * isq2, sg * x2[k + 1] * isq2) : cmake<C2>(0, 0);
+                c1 = cmake<C2>(a0 * isq2, sg * a1 * isq2);
+                c2 = has2 ? cmake<C2>(b0 * isq2, sg * b1 * isq2) : cmake<C2>(0, 0);
             }
-            // F = c1 + i c2
-            sa[z * C + c] = cmake<C2>(c1.x - c2.y, c1.y + c2.x);
+            sa[z * C + wave + j * NWAVE] = cmake<C2>(c1.x - c2.y, c1.y + c2.x);
         }
+    }
+    // columns longer than 64 entries (none at the compiled grid sizes and
+    // cut-offs used here, kept for generality)
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+        if (cnt[j] <= 64) continue;
+        const bool has2 = o2s[j] < n_orb;
+        const T *x1 = X + (size_t)o1s[j] * npw;
+        const T *x2 = X + (size_t)o2s[j] * npw;
+        for (int e = 64 + lane; e < cnt[j]; e += 64)
+            put(wave + j * NWAVE, ent[beg[j] + e], x1, x2, has2);
     }
     __syncthreads();
     C2 *res = lds_fft<T, N>(sa, sb, stw, (T)1);
@@ -471,42 +512,74 @@ __global__ void __launch_bounds__(256) k_sph_fwd_z(const cplx<T> *__restrict__ T
     C2 *res = lds_fft<T, N>(sa, sb, stw, (T)-1);
     const T inv_nr = (T)1 / ((T)n * (T)n * (T)n);
     const T sq2 = (T)1.41421356237309504880;
-    const int nwave = FFT_NT >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int c = wave; c < C; c += nwave) {
+    constexpr int NWAVE = FFT_NT >> 6;
+    constexpr int CPW = (C + NWAVE - 1) / NWAVE;  // columns per wave
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // one sphere entry of column c (mirror column cm) -> the two orbitals
+    auto take = [&](int c, int cm, int2 en, T kk, T a0, T a1, T b0, T b1, T *y1, T *y2,
+                    bool has2) {
+        const int z = en.x & 0xffff, kind = en.x >> 16, k = en.y;
+        if (kind == 2) return;
+        const C2 F = res[z * C + c];
+        if (kind == 0) {
+            y1[0] = F.x * inv_nr;
+            if (has2) y2[0] = F.y * inv_nr;
+            return;
+        }
+        const int zm = (n - z) % n;
+        const C2 Fm = res[zm * C + cm];
+        // a(G) = (F(G) + conj F(-G)) / 2,  b(G) = -i (F(G) - conj F(-G)) / 2
+        const T ar = (F.x + Fm.x) * (T)0.5, ai = (F.y - Fm.y) * (T)0.5;
+        const T br = (F.y + Fm.y) * (T)0.5, bi = -(F.x - Fm.x) * (T)0.5;
+        y1[k] = sq2 * ar * inv_nr + kk * a0;
+        y1[k + 1] = sq2 * ai * inv_nr + kk * a1;
+        if (has2) {
+            y2[k] = sq2 * br * inv_nr + kk * b0;
+            y2[k + 1] = sq2 * bi * inv_nr + kk * b1;
+        }
+    };
+    // the first 64 entries of each of the wave's columns in three batched
+    // levels (column ranges, entries, kinetic and input coefficients), loads
+    // at clamped in-bounds indices
+    int beg[CPW], cnt[CPW], o1s[CPW], o2s[CPW], cms[CPW];
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+        const int c = wave + j * NWAVE;
         const int L = L0 + c;
-        if (L >= n_lines) break;
-        const int q = L / ncol, col = L - q * ncol;
+        const bool act = c < C && L < n_lines;
+        const int Lc = act ? L : 0;
+        const int q = Lc / ncol, col = Lc - q * ncol;
         const int mcol = col < 2 ? col : (col ^ 1);
-        const int cm = c + (mcol - col);
-        int o1, o2;
-        pair_of(q, ps, o1, o2);
-        const bool has2 = o2 < n_orb;
-        T *y1 = Y + (size_t)o1 * npw;
-        T *y2 = Y + (size_t)o2 * npw;
-        const T *x1 = X + (size_t)o1 * npw;
-        const T *x2 = X + (size_t)o2 * npw;
-        for (int e = col_ptr[col] + lane; e < col_ptr[col + 1]; e += 64) {
-            const int2 en = ent[e];
-            const int z = en.x & 0xffff, kind = en.x >> 16, k = en.y;
-            if (kind == 2) continue;
-            const C2 F = res[z * C + c];
-            if (kind == 0) {
-                y1[0] = F.x * inv_nr;
-                if (has2) y2[0] = F.y * inv_nr;
-                continue;
-            }
-            const int zm = (n - z) % n;
-            const C2 Fm = res[zm * C + cm];
-            // a(G) = (F(G) + conj F(-G)) / 2,  b(G) = -i (F(G) - conj F(-G)) / 2
-            const T ar = (F.x + Fm.x) * (T)0.5, ai = (F.y - Fm.y) * (T)0.5;
-            const T br = (F.y + Fm.y) * (T)0.5, bi = -(F.x - Fm.x) * (T)0.5;
-            const T kk = (T)kin[k] * kin_scale;
-            y1[k] = sq2 * ar * inv_nr + kk * x1[k];
-            y1[k + 1] = sq2 * ai * inv_nr + kk * x1[k + 1];
-            if (has2) {
-                y2[k] = sq2 * br * inv_nr + kk * x2[k];
-                y2[k + 1] = sq2 * bi * inv_nr + kk * x2[k + 1];
-            }
+        cms[j] = c + (mcol - col);
+        pair_of(q, ps, o1s[j], o2s[j]);
+        beg[j] = col_ptr[col];
+        cnt[j] = act ? col_ptr[col + 1] - beg[j] : 0;
+    }
+    int2 en[CPW];
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) en[j] = ent[lane < cnt[j] ? beg[j] + lane : 0];
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+        const bool has2 = o2s[j] < n_orb;
+        const size_t r1 = (size_t)o1s[j] * npw, r2 = (size_t)(has2 ? o2s[j] : o1s[j]) * npw;
+        const int k = (en[j].x >> 16) == 1 ? en[j].y : 0;
+        const T kk = (T)kin[k] * kin_scale;
+        const T a0 = X[r1 + k], a1 = X[r1 + k + 1], b0 = X[r2 + k], b1 = X[r2 + k + 1];
+        if (lane < cnt[j])
+            take(wave + j * NWAVE, cms[j], en[j], kk, a0, a1, b0, b1, Y + r1, Y + r2, has2);
+    }
+    // columns longer than 64 entries (none at the compiled grid sizes and
+    // cut-offs used here, kept for generality)
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+        if (cnt[j] <= 64) continue;
+        const bool has2 = o2s[j] < n_orb;
+        const size_t r1 = (size_t)o1s[j] * npw, r2 = (size_t)(has2 ? o2s[j] : o1s[j]) * npw;
+        for (int e = 64 + lane; e < cnt[j]; e += 64) {
+            const int2 ee = ent[beg[j] + e];
+            const int k = (ee.x >> 16) == 1 ? ee.y : 0;
+            take(wave + j * NWAVE, cms[j], ee, (T)kin[k] * kin_scale, X[r1 + k], X[r1 + k + 1],
+                 X[r2 + k], X[r2 + k + 1], Y + r1, Y + r2, has2);
         }
     }
 }
