@@ -177,3 +177,39 @@ def test_autotune_picks_a_valid_shape():
     with pytest.raises(pkg.BseError):
         ctx.set_k1d_shape(pkg.FP32, pkg.k1d_num_shapes(pkg.FP32))
     ctx.close()
+
+
+@pytest.mark.parametrize("name,rows", [("c4_03", None), ("c4_09", [0, 46, 92])])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 2e-5), (2, 1e-4)])
+def test_uneven_cell_apply_matches_oracle(name, rows, prec, tol):
+    """Two cells of the uneven twelve-cell set (48^3 / 41 orbitals / 232 PDEP
+    and 60^3 / 93 orbitals / 161 PDEP, jittered wells, 40 % of the pairs):
+    the grid lengths 48 and 60 against the oracle (the larger cell on sampled
+    output orbitals, each computed with the pairs that touch it)."""
+    from oracle.liouville import Basis, LiouvilleOracle
+    from oracle.pairs import MEASURE_ABS_L1, build_pairs, pair_measure
+    from oracle.screening import screened_integrals
+    say("uneven cell apply", name, prec)
+    pkg = _pkg()
+    from synth.cell import uneven_batch_specs
+    spec = {s.name: s for s in uneven_batch_specs()}[name]
+    c = make_cell(spec)
+    ctx = pkg.context_for(c)
+    thr = pkg.setup_pairs_and_screen(ctx, c, fraction=0.4, precision=prec)
+    b = Basis(c.L, c.n, c.miller)
+    u = b.to_grid(c.psi)
+    pairs = build_pairs(pair_measure(u, MEASURE_ABS_L1), thr)
+    assert [tuple(p) for p in ctx.get_pairs()] == pairs
+    sub = pairs if rows is None else [p for p in pairs if p[0] in rows or p[1] in rows]
+    op = LiouvilleOracle(b, c.psi, c.eps_mat, c.V, sub, screened_integrals(b, u, sub, c.phi,
+                                                                         c.lam))
+    X = trial_block(c, 3, seed=23)
+    dt = torch.float64 if prec == 0 else torch.float32
+    Y = torch.empty((3, c.n_occ, c.npw), dtype=dt, device="cuda")
+    ctx.apply(_dev(X, dt), Y, prec)
+    got = Y.double().cpu().numpy()
+    if rows is None:
+        assert rel_err(got, op.apply(X)) < tol
+    else:
+        assert rel_err(got[:, rows], op.apply(X, rows=rows)[:, rows]) < tol
+    ctx.close()
