@@ -225,7 +225,7 @@ def uneven_batch(args, torch, pkg):
             X0.append(torch.from_numpy(trial_block(c, B, seed=4321)).to("cuda"))
             out["cells"].append({"name": sp.name, "grid": c.n, "n_occ": c.n_occ, "npw": c.npw,
                                  "n_pdep": c.n_pdep, "pairs": ctx.n_pairs, "k1d_shape": shape,
-                                 "k1d_ms_by_shape": [round(x, 3) for x in ms]})
+                                 "k1d_ms_by_shape": [None if x is None else round(x, 3) for x in ms]})
             log(f"uneven cell {sp.name}: grid {c.n} n_occ {c.n_occ} pairs {ctx.n_pairs} "
                 f"shape {shape} ({time.time() - t:.1f} s)")
         runs = {}
@@ -401,7 +401,7 @@ def main():
         t = time.time()
         shape, shape_ms = ctx.autotune(B, prec, n_rep=2)
         t_tune = time.time() - t
-        log(f"autotuned K1d shape {shape}: {[round(x, 3) for x in shape_ms]} ms ({t_tune:.1f} s)")
+        log(f"autotuned K1d shape {shape}: {[None if x is None else round(x, 3) for x in shape_ms]} ms ({t_tune:.1f} s)")
         Xh = trial_block(cell, B, seed=1234)
         X = torch.from_numpy(Xh).to("cuda", dtype=dt)
         Y = torch.empty_like(X)
@@ -457,7 +457,7 @@ def main():
                                 f"{'hipGraph replay' if not args.no_graph else 'eager'}"),
                    "block": B, "n_occ": cell.n_occ, "grid": cell.n, "n_pairs": P,
                    "precision": args.precision, "k1d_shape": shape,
-                   "k1d_ms_by_shape": [round(x, 3) for x in shape_ms]},
+                   "k1d_ms_by_shape": [None if x is None else round(x, 3) for x in shape_ms]},
         "roofline": roof,
         "whole_apply_gbs": whole_bytes / (ms_per_step * 1e-3) / 1e9,
         "setup_seconds": t_setup,

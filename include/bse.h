@@ -241,18 +241,28 @@ bse_status bse_davidson_record(bse_ctx *ctx, const bse_davidson_opts *opts, cons
 /* ---------------------------------------------------------------- tuning
  * The K1d kernel (Eq. k1d) is compiled in several shapes: rows per
  * workgroup, trial vectors per workgroup and tau columns in flight.  Shape 0
- * of each precision is the default.  Not in the paper: a tuning aid. */
+ * of each precision is the default.  The resident shapes hold every orbital
+ * of a grid tile in one workgroup and apply only to cells of at most 64 or
+ * 128 orbitals.  Not in the paper: a tuning aid. */
 /* Number of compiled K1d shapes for a precision (0 for an unknown one). */
 int bse_k1d_num_shapes(int precision);
+/* Parameters of K1d shape `shape` (BSE_ERR_ARG when out of range): info host
+ * [6] gets the rows one workgroup holds (the cell's orbital limit for a
+ * resident shape), the trial vectors per workgroup, the tau columns in
+ * flight per wave, the waves per workgroup, 1 for a resident shape (0 for a
+ * row-block one) and the grid points per workgroup.  Needs no GPU. */
+bse_status bse_k1d_shape_info(int precision, int shape, int *info);
 /* Autotuner: times the K1d stage of every shape on this cell with a block of
  * n_vec vectors (an internal, deterministic input; n_rep timed applies per
  * shape), selects the fastest for `precision` and returns it in *shape
  * (optional); k1d_ms host [bse_k1d_num_shapes(precision)] (optional) gets
- * each shape's time.  Drops a captured apply graph.  Requires
+ * each shape's time in ms, -1 for a shape that cannot hold this cell's
+ * orbitals (not timed).  Drops a captured apply graph.  Requires
  * bse_screen_pairs in that precision (BSE_ERR_STATE).  Synchronises. */
 bse_status bse_autotune(bse_ctx *ctx, int n_vec, int precision, int n_rep, int *shape,
                         double *k1d_ms);
-/* Select a K1d shape by hand (BSE_ERR_ARG when out of range). */
+/* Select a K1d shape by hand (BSE_ERR_ARG when out of range or when the
+ * shape cannot hold this cell's orbitals). */
 bse_status bse_set_k1d_shape(bse_ctx *ctx, int precision, int shape);
 
 /* ---------------------------------------------------------------- batches

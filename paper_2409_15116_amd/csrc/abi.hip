@@ -257,6 +257,26 @@ int bse_k1d_num_shapes(int precision) {
     return bse::k1d_num_shapes(precision == BSE_FP64);
 }
 
+bse_status bse_k1d_shape_info(int precision, int shape, int *info) {
+    if (precision != BSE_FP64 && precision != BSE_FP32 && precision != BSE_BF16X3) {
+        set_error("bse_k1d_shape_info: unknown precision %d", precision);
+        return BSE_ERR_ARG;
+    }
+    if (!info) {
+        set_error("bse_k1d_shape_info: null info");
+        return BSE_ERR_ARG;
+    }
+    BSE_GUARD({
+        const bse::K1dShape s = bse::k1d_shape(precision == BSE_FP64, shape);
+        info[0] = s.bi;
+        info[1] = s.s;
+        info[2] = s.nbuf;
+        info[3] = s.nw;
+        info[4] = s.res;
+        info[5] = s.pt;
+    })
+}
+
 bse_status bse_autotune(bse_ctx *c, int n_vec, int precision, int n_rep, int *shape,
                         double *k1d_ms) {
     CHECK_CTX(c);

@@ -1,6 +1,7 @@
 // Context set-up, pair list, screening and the Liouville apply pipeline.
 #include <algorithm>
 #include <cmath>
+#include <climits>
 #include <cstring>
 #include <map>
 #include <vector>
@@ -259,6 +260,271 @@ void ctx_measure(bse_ctx *c, int kind, double *m_host) {
         }
 }
 
+// Tables of the resident K1d kernel, one set per LDS capacity (orbitals
+// whose a values fit in LDS at once).  When the cell has more orbitals than
+// that, the columns are split into phases (parts of at most cap orbitals)
+// with few kept pairs between parts: a pair inside a part has both of its
+// uses in the same phase, close in time.  Inside each part the orbitals are
+// split into row groups of K1D_RES_BW so that the groups touch few columns:
+// a wave visits every column that pairs with any orbital of its group, so
+// the sum over groups of the number of such columns is the work.  Both steps
+// start greedy and improve by swaps that do not make them worse (a fixed
+// pseudo-random sequence: the tables are deterministic).
+namespace {
+struct Bits {
+    int nwd;
+    std::vector<unsigned long long> w;  // [n][nwd]
+    const unsigned long long *row(int v) const { return &w[(size_t)v * nwd]; }
+};
+int pop_and(const unsigned long long *a, const unsigned long long *b, int n) {
+    int s = 0;
+    for (int k = 0; k < n; ++k) s += __builtin_popcountll(a[k] & b[k]);
+    return s;
+}
+struct Lcg {
+    unsigned long long st = 0x2545F4914F6CDD1Dull;
+    int operator()(int n) {
+        st = st * 6364136223846793005ull + 1442695040888963407ull;
+        return (int)((st >> 33) % (unsigned long long)n);
+    }
+};
+}  // namespace
+
+static void build_event_set(bse_ctx *c, int set, int cap, const Bits &nb,
+                            const std::vector<int> &pidx) {
+    const int no = c->n_occ, BW = K1D_RES_BW, nwd = nb.nwd;
+    const long long P = c->n_pairs;
+    const int nph = (no + cap - 1) / cap;
+    Lcg rnd;
+    // parts: part_of[v]
+    std::vector<int> part_of(no, 0);
+    if (nph == 2) {
+        const int s0 = (no + 1) / 2;
+        std::vector<unsigned long long> m0(nwd, 0);
+        std::vector<char> in0(no, 0);
+        in0[0] = 1;
+        m0[0] |= 1ull;
+        for (int k = 1; k < s0; ++k) {
+            int best = -1, best_s = -1;
+            for (int v = 0; v < no; ++v) {
+                if (in0[v]) continue;
+                const int s = pop_and(nb.row(v), m0.data(), nwd);
+                if (s > best_s) {
+                    best = v;
+                    best_s = s;
+                }
+            }
+            in0[best] = 1;
+            m0[best / 64] |= 1ull << (best % 64);
+        }
+        for (int v = 0; v < no; ++v) part_of[v] = in0[v] ? 0 : 1;
+        auto cut = [&]() {
+            std::vector<unsigned long long> m1(nwd, 0);
+            for (int v = 0; v < no; ++v)
+                if (part_of[v]) m1[v / 64] |= 1ull << (v % 64);
+            int s = 0;
+            for (int v = 0; v < no; ++v)
+                if (!part_of[v]) s += pop_and(nb.row(v), m1.data(), nwd);
+            return s;
+        };
+        int cc = cut();
+        std::vector<int> p0, p1;
+        for (int v = 0; v < no; ++v) (part_of[v] ? p1 : p0).push_back(v);
+        for (int it = 0; it < 4000 && !p1.empty(); ++it) {
+            const int i = rnd((int)p0.size()), j = rnd((int)p1.size());
+            std::swap(part_of[p0[i]], part_of[p1[j]]);
+            const int nc = cut();
+            if (nc <= cc) {
+                cc = nc;
+                std::swap(p0[i], p1[j]);
+            } else {
+                std::swap(part_of[p0[i]], part_of[p1[j]]);
+            }
+        }
+    }
+    std::vector<std::vector<int>> parts(nph);
+    for (int v = 0; v < no; ++v) parts[part_of[v]].push_back(v);
+    std::vector<int> slot(no);
+    std::vector<int> part_tbl((size_t)nph * cap, -1);
+    for (int h = 0; h < nph; ++h)
+        for (size_t k = 0; k < parts[h].size(); ++k) {
+            slot[parts[h][k]] = (int)k;
+            part_tbl[(size_t)h * cap + k] = parts[h][k];
+        }
+    // row groups inside each part
+    std::vector<int> gpart;  // part of each group
+    std::vector<int> grp;    // [ng][BW]
+    for (int h = 0; h < nph; ++h) {
+        const std::vector<int> &mem = parts[h];
+        const int g0 = (int)gpart.size();
+        const int ngh = ((int)mem.size() + BW - 1) / BW;
+        std::vector<char> used(mem.size(), 0);
+        for (int g = 0; g < ngh; ++g) {
+            gpart.push_back(h);
+            const int size = std::min(BW, (int)mem.size() - g * BW);
+            std::vector<unsigned long long> cv(nwd, 0);
+            for (int i = 0; i < BW; ++i) {
+                if (i >= size) {
+                    grp.push_back(-1);
+                    continue;
+                }
+                int best = -1, best_s = 0;
+                for (size_t k = 0; k < mem.size(); ++k) {
+                    if (used[k]) continue;
+                    const unsigned long long *m = nb.row(mem[k]);
+                    int s = 0;
+                    for (int q = 0; q < nwd; ++q)
+                        s += __builtin_popcountll(m[q] & cv[q]) - __builtin_popcountll(m[q] & ~cv[q]);
+                    if (best < 0 || (i > 0 && s > best_s)) {
+                        best = (int)k;
+                        best_s = s;
+                    }
+                    if (i == 0) break;  // the seed: first free orbital of the part
+                }
+                used[best] = 1;
+                grp.push_back(mem[best]);
+                const unsigned long long *m = nb.row(mem[best]);
+                for (int q = 0; q < nwd; ++q) cv[q] |= m[q];
+            }
+        }
+        // swaps between groups of this part
+        if (ngh > 1) {
+            auto cost = [&](int g) {
+                std::vector<unsigned long long> cv(nwd, 0);
+                for (int i = 0; i < BW; ++i) {
+                    const int v = grp[(size_t)g * BW + i];
+                    if (v >= 0)
+                        for (int q = 0; q < nwd; ++q) cv[q] |= nb.row(v)[q];
+                }
+                int n = 0;
+                for (int q = 0; q < nwd; ++q) n += __builtin_popcountll(cv[q]);
+                return n;
+            };
+            std::vector<int> gc(ngh);
+            for (int g = 0; g < ngh; ++g) gc[g] = cost(g0 + g);
+            for (int it = 0; it < 10000; ++it) {
+                const int a = rnd(ngh);
+                int b = rnd(ngh - 1);
+                if (b >= a) ++b;
+                const int i = rnd(BW), j = rnd(BW);
+                int &x = grp[(size_t)(g0 + a) * BW + i], &y = grp[(size_t)(g0 + b) * BW + j];
+                if (x < 0 && y < 0) continue;
+                std::swap(x, y);
+                const int ca = cost(g0 + a), cb = cost(g0 + b);
+                if (ca + cb <= gc[a] + gc[b]) {
+                    gc[a] = ca;
+                    gc[b] = cb;
+                } else {
+                    std::swap(x, y);
+                }
+            }
+        }
+    }
+    const int ng = (int)gpart.size();
+    BSE_REQUIRE(ng <= K1D_RES_MAXROWS / BW, BSE_ERR_STATE, "too many row groups (%d)", ng);
+    for (int g = 0; g < ng; ++g)
+        std::sort(grp.begin() + (size_t)g * BW, grp.begin() + (size_t)(g + 1) * BW,
+                  [](int a, int b) { return (a < 0 ? INT_MAX : a) < (b < 0 ? INT_MAX : b); });
+    // events: phase by phase; in the phase of its own part a group follows a
+    // round-robin tournament over that part's groups (circle method, an odd
+    // count gets a bye; in round r it visits its partner's columns and its
+    // own come last), in another phase it visits that part's groups in order
+    const int EV = BW + 1;
+    const int zero = (int)(P * TAU_TILE);
+    std::vector<int> ev, start(ng), phc((size_t)ng * nph);
+    auto push = [&](int g, int w) {
+        for (int i = 0; i < BW; ++i) {
+            const int v = grp[(size_t)g * BW + i];
+            const int p = v >= 0 ? pidx[(size_t)v * no + w] : -1;
+            ev.push_back(p >= 0 ? p * TAU_TILE : zero);
+        }
+        ev.push_back(slot[w]);
+    };
+    auto push_zero = [&]() {
+        for (int i = 0; i < BW; ++i) ev.push_back(zero);
+        ev.push_back(0);
+    };
+    for (int g = 0; g < ng; ++g) {
+        start[g] = (int)(ev.size() / EV);
+        std::vector<unsigned long long> cv(nwd, 0);
+        for (int i = 0; i < BW; ++i) {
+            const int v = grp[(size_t)g * BW + i];
+            if (v >= 0)
+                for (int q = 0; q < nwd; ++q) cv[q] |= nb.row(v)[q];
+        }
+        auto visit = [&](int m) {
+            for (int i = 0; i < BW; ++i) {
+                const int w = grp[(size_t)m * BW + i];
+                if (w >= 0 && (cv[w / 64] >> (w % 64) & 1)) push(g, w);
+            }
+        };
+        for (int h = 0; h < nph; ++h) {
+            const size_t before = ev.size() / EV;
+            std::vector<int> gh;
+            for (int m = 0; m < ng; ++m)
+                if (gpart[m] == h) gh.push_back(m);
+            if (gpart[g] == h) {
+                const int n = (int)gh.size(), nt = n + (n & 1);
+                const int me = (int)(std::find(gh.begin(), gh.end(), g) - gh.begin());
+                for (int r = 0; r < nt - 1; ++r) {
+                    int q;
+                    if (me == nt - 1) q = r;
+                    else if (me == r) q = nt - 1;
+                    else q = ((2 * r - me) % (nt - 1) + (nt - 1)) % (nt - 1);
+                    if (q < n && q != me) visit(gh[q]);
+                }
+                visit(g);
+            } else {
+                for (int m : gh) visit(m);
+            }
+            int n = (int)(ev.size() / EV - before);
+            while (n % 4) {
+                push_zero();
+                ++n;
+            }
+            phc[(size_t)g * nph + h] = n;
+        }
+        for (int k = 0; k < 4; ++k) push_zero();  // read ahead past the end
+    }
+    auto up = [&](auto &dev, const auto &host) {
+        dev.alloc(std::max<size_t>(1, host.size()));
+        BSE_HIP(hipMemcpy(dev.p, host.data(), host.size() * sizeof(host[0]), hipMemcpyHostToDevice));
+    };
+    up(c->res_grp[set], grp);
+    up(c->res_part[set], part_tbl);
+    up(c->res_ev[set], ev);
+    up(c->res_start[set], start);
+    up(c->res_cnt[set], phc);
+    PairEvents &e = c->res[set];
+    e.ng = ng;
+    e.nph = nph;
+    e.cap = cap;
+    e.n_rows = P + 1;
+    e.grp = c->res_grp[set].p;
+    e.part = c->res_part[set].p;
+    e.ev = c->res_ev[set].p;
+    e.ev_start = c->res_start[set].p;
+    e.ph_cnt = c->res_cnt[set].p;
+}
+
+static void build_events(bse_ctx *c, const std::vector<int> &pr) {
+    const int no = c->n_occ;
+    for (auto &e : c->res) e = PairEvents{};
+    if (no > K1D_RES_MAXROWS) return;
+    Bits nb;
+    nb.nwd = (no + 63) / 64;
+    nb.w.assign((size_t)no * nb.nwd, 0);
+    std::vector<int> pidx((size_t)no * no, -1);
+    for (long long p = 0; p < c->n_pairs; ++p) {
+        const int v = pr[2 * p], w = pr[2 * p + 1];
+        pidx[(size_t)v * no + w] = pidx[(size_t)w * no + v] = (int)p;
+        nb.w[(size_t)v * nb.nwd + w / 64] |= 1ull << (w % 64);
+        nb.w[(size_t)w * nb.nwd + v / 64] |= 1ull << (v % 64);
+    }
+    for (int set = 0; set < K1D_RES_NSETS; ++set)
+        build_event_set(c, set, K1D_RES_CAPS[set], nb, pidx);
+}
+
 void ctx_build_pairs(bse_ctx *c, int kind, double thr) {
     const int no = c->n_occ;
     std::vector<double> m((size_t)no * no);
@@ -337,6 +603,7 @@ void ctx_build_pairs(bse_ctx *c, int kind, double thr) {
         t.blk_nz = c->csr_nz[set].p;
         t.order = c->csr_order[set].p;
     }
+    build_events(c, pr);
     std::vector<int2> pd(c->n_pairs);
     for (long long p = 0; p < c->n_pairs; ++p) pd[p] = make_int2(pr[2 * p], pr[2 * p + 1]);
     up(c->pairs_d, pd);
@@ -511,7 +778,8 @@ static void apply_impl(bse_ctx *c, int nvec, const T *X, T *Y, bool bf, hipEvent
     // a1: sphere -> grid for every (s, v)
     sph_inverse<T>(c->maps, X, norb, w.Ar.p, w.T1.p, w.T2.p, tw, st, ev ? ev + 1 : nullptr, no);
     // a4 (+ V a of a2, + the K1e density of a3)
-    k1d_apply<T>(w.Ar.p, tau, V, u, c->csr, c->k1d_shape[dbl ? 0 : 1], no, nvec, nr, (T)c->k1d,
+    k1d_apply<T>(w.Ar.p, tau, V, u, c->csr, c->res, c->k1d_shape[dbl ? 0 : 1], no, nvec, nr,
+                 (T)c->k1d,
                  (T)(1.0 / c->omega), w.Cr.p,
                  w.Hc.p, w.Dp.p, st);
     rec(4);
@@ -560,6 +828,12 @@ void ctx_profile_apply(bse_ctx *c, int n_vec, const void *in, void *out, int pre
     for (auto &e : ev) (void)hipEventDestroy(e);
 }
 
+// A resident shape needs every orbital of the cell in one workgroup.
+static bool k1d_shape_fits(const bse_ctx *c, bool dbl, int v) {
+    const K1dShape s = k1d_shape(dbl, v);
+    return !s.res || c->n_occ <= s.bi;
+}
+
 // Autotuner: time the K1d stage of every compiled shape on this cell with a
 // block of n_vec vectors (deterministic input, n_rep timed applies each after
 // one untimed one), keep the fastest for this precision and return it.  A
@@ -600,6 +874,10 @@ int ctx_autotune(bse_ctx *c, int n_vec, int prec, int n_rep, double *ms_out) {
     double best_ms = INFINITY;
     try {
         for (int v = 0; v < ns; ++v) {
+            if (!k1d_shape_fits(c, dbl, v)) {
+                if (ms_out) ms_out[v] = -1.0;  // not applicable to this cell
+                continue;
+            }
             slot = v;
             double ms[10];
             ctx_profile_apply(c, n_vec, X.p, Y.p, prec, n_rep, ms);
@@ -620,6 +898,9 @@ int ctx_autotune(bse_ctx *c, int n_vec, int prec, int n_rep, double *ms_out) {
 void ctx_set_k1d_shape(bse_ctx *c, int prec, int shape) {
     const bool dbl = prec == BSE_FP64;
     (void)k1d_shape(dbl, shape);  // validates
+    BSE_REQUIRE(k1d_shape_fits(c, dbl, shape), BSE_ERR_ARG,
+                "K1d shape %d holds at most %d orbitals (the cell has %d)", shape,
+                k1d_shape(dbl, shape).bi, c->n_occ);
     drop_graph(c);
     c->k1d_shape[dbl ? 0 : 1] = shape;
 }

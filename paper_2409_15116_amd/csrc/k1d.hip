@@ -206,6 +206,172 @@ __global__ void __launch_bounds__(64 * NW) k_k1d(const T *__restrict__ A, const 
     }
 }
 
+// The resident kernel: one workgroup holds every row of a PT-point piece of
+// the grid for SW = VPL * 64 / PT trial vectors; lane l works on point
+// l % PT and vectors (l / PT) * VPL + j, j < VPL, so with PT < 64 the lanes
+// that share a point load the same tau value.  A tau value loaded into a
+// register serves VPL products per row, and the load instructions, not the
+// bytes, bound this kernel: VPL is as large as LDS allows.  The a values of
+// up to CAP orbitals stay in LDS ([slot][lane], VPL values per lane, one
+// 16- or 32-byte read per column); with more orbitals the columns are taken
+// in phases, one part of the orbitals resident per phase.  Inside a phase
+// the column loop has no barrier and every wave walks its own event list:
+// wave g owns the K1D_RES_BW orbitals of group g and visits only the columns
+// that pair with one of them.  The lists follow a round-robin schedule over
+// the groups of a part, in which groups g and h visit each other's columns
+// in the same round: the two uses of a kept pair's tau, (v, w) by one wave
+// and (w, v) by the other, are loaded close in time in one CU, and tau comes
+// from HBM about once.  The tau loads of the next phase's first events are
+// issued before its barrier.  The workgroup covers every row, so it
+// finishes the K1e density and writes the Hartree input Hc directly.
+template <typename T, int VPL, int PT, int NW, int NBUF, int CAP>
+__global__ void __launch_bounds__(64 * NW) k_k1d_res(
+    const T *__restrict__ A, const T *__restrict__ tau, const T *__restrict__ V,
+    const T *__restrict__ u, const int *__restrict__ grp, const int *__restrict__ part,
+    const int *__restrict__ ev, const int *__restrict__ ev_start, const int *__restrict__ ph_cnt,
+    int ng, int nph, int n_occ, int B, long long nr, long long n_rows, int nSc, T k1d,
+    T inv_omega, T *__restrict__ Cr, cplx<T> *__restrict__ Hc) {
+    constexpr int BW = K1D_RES_BW;
+    constexpr int EV = BW + 1;  // ints per event
+    constexpr int NQ = K1D_R / PT;  // pieces of a 64-point tau tile
+    constexpr int SW = VPL * NQ;    // vectors per workgroup
+    static_assert(VPL % 2 == 0 && VPL * sizeof(T) % 16 == 0, "VPL values fill 16-byte LDS words");
+    static_assert(PT == 16 || PT == 32 || PT == 64, "PT divides the tau tile");
+    static_assert(NBUF == 1 || NBUF == 2 || NBUF == 4, "events are padded to multiples of 4");
+    static_assert(CAP % NW == 0, "the waves share the staging");
+    using VecS = T __attribute__((ext_vector_type(VPL)));
+    __shared__ VecS a_s[CAP * K1D_R];   // [slot][lane]
+    __shared__ T red[NW * VPL * K1D_R];  // [wave][value][lane]
+    // decode: id = 8 * ((hi8 * NQ + q) * nSc + sc) + lo8; tau tile hi8 * 8 + lo8,
+    // piece q of it: the pieces and vector groups of one tile share an XCD
+    const int id = blockIdx.x;
+    const int lo8 = id & 7;
+    int rest = id >> 3;
+    const int sc = rest % nSc;
+    rest /= nSc;
+    const int q = rest % NQ;
+    const long long rt = (long long)(rest / NQ) * 8 + lo8;
+    const long long r0 = rt * K1D_R + q * PT;
+    if (r0 >= nr) return;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int pt = lane % PT, vg = lane / PT;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const long long rr = r0 + pt < nr ? r0 + pt : nr - 1;
+    const bool rok = r0 + pt < nr;
+    const int s0 = sc * SW + vg * VPL;  // this lane's first vector
+    const size_t sstride = (size_t)n_occ * nr;
+    const __amdgpu_buffer_rsrc_t trs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(tau + rt * n_rows * TAU_TILE), (short)0, (int)(n_rows * TAU_TILE * sizeof(T)),
+        0x00020000);
+    const int voff = (q * PT + pt) * (int)sizeof(T);
+    // a of this lane's vector j (clamped to a valid one) and orbital o; the
+    // empty asm hides B from loop-invariant hoisting, which would keep VPL
+    // 64-bit offsets live through the column loop
+    auto a_at = [&](int j, size_t vo) {
+        int bl = B;
+        asm volatile("" : "+s"(bl));
+        return A[(size_t)min(s0 + j, bl - 1) * sstride + vo + rr];
+    };
+
+    T acc[BW][VPL];
+#pragma unroll
+    for (int i = 0; i < BW; ++i)
+#pragma unroll
+        for (int j = 0; j < VPL; ++j) acc[i][j] = 0;
+    const bool act = wv < ng;
+    const int *evg = ev + (size_t)(act ? ev_start[wv] : 0) * EV;
+    T t[NBUF][BW];
+    if (act) {
+        // issued in buffer order, the order the loop waits for them in
+#pragma unroll
+        for (int b = 0; b < NBUF; ++b) {
+            k1d_request<T, BW>(t[b], trs, voff, evg + b * EV);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    int e = 0;
+    for (int h = 0; h < nph; ++h) {
+        if (h > 0) __syncthreads();  // every wave is done with the previous part
+        // stage part h: wave wv loads slots wv, wv + NW, ... (an empty slot
+        // stages a valid orbital; it is never read)
+#pragma unroll
+        for (int l = 0; l < CAP / NW; ++l) {
+            const int k = wv + NW * l;
+            const int o = part[h * CAP + k];
+            const size_t vo = (size_t)(o >= 0 ? o : 0) * nr;
+            VecS x;
+#pragma unroll
+            for (int j = 0; j < VPL; ++j) x[j] = a_at(j, vo);
+            a_s[k * K1D_R + lane] = x;
+        }
+        __syncthreads();
+        if (act) {
+            const int end = e + ph_cnt[wv * nph + h];
+#pragma unroll 1
+            for (; e < end; e += NBUF) {
+#pragma unroll
+                for (int b = 0; b < NBUF; ++b) {
+                    const int *cur = evg + (e + b) * EV;
+                    const VecS aw = a_s[cur[BW] * K1D_R + lane];
+#pragma unroll
+                    for (int i = 0; i < BW; ++i)
+#pragma unroll
+                        for (int j = 0; j < VPL; ++j) acc[i][j] += t[b][i] * aw[j];
+                    __builtin_amdgcn_sched_barrier(0);
+                    k1d_request<T, BW>(t[b], trs, voff, cur + NBUF * EV);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+        }
+    }
+    // epilogue: Cr of this wave's orbitals and their share of the density
+    // (a from LDS when every orbital is resident: slot = orbital)
+    const T vr = V[rr];
+    T dn[VPL];
+#pragma unroll
+    for (int j = 0; j < VPL; ++j) dn[j] = 0;
+    if (act) {
+#pragma unroll
+        for (int i = 0; i < BW; ++i) {
+            const int v = grp[wv * BW + i];
+            if (v >= 0) {
+                VecS av;
+                if (nph == 1) {
+                    av = a_s[v * K1D_R + lane];
+                } else {
+#pragma unroll
+                    for (int j = 0; j < VPL; ++j) av[j] = a_at(j, (size_t)v * nr);
+                }
+                const T uv = u[(size_t)v * nr + rr];
+#pragma unroll
+                for (int j = 0; j < VPL; ++j) {
+                    if (rok && s0 + j < B)
+                        Cr[(size_t)(s0 + j) * sstride + (size_t)v * nr + rr] =
+                            vr * av[j] - k1d * acc[i][j];
+                    dn[j] += uv * av[j];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < VPL; ++j) red[(wv * VPL + j) * K1D_R + lane] = dn[j];
+    __syncthreads();
+    // Hc[s / 2] = (D[s], D[s + 1]) / Omega for even s, summed over the waves
+    // in fixed order
+    if (wv < VPL / 2) {
+        const int j = 2 * wv;
+        T re = 0, im = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            re += red[(w * VPL + j) * K1D_R + lane];
+            im += red[(w * VPL + j + 1) * K1D_R + lane];
+        }
+        if (rok && s0 + j < B)
+            Hc[(size_t)((s0 + j) / 2) * nr + rr] =
+                cmake<cplx<T>>(re * inv_omega, s0 + j + 1 < B ? im * inv_omega : (T)0);
+    }
+}
+
 // Hc[s/2](r).{x|y} = sum_ib Dp[ib][s](r)  (fixed order: deterministic)
 template <typename T>
 __global__ void k_sum_density(const T *__restrict__ Dp, int nIb, int B, long long nr,
@@ -241,13 +407,46 @@ static void launch_k1d(const T *A, const T *tau, const T *V, const T *u, const P
     BSE_LAUNCH_CHECK();
 }
 
+template <typename T, int VPL, int PT, int NW, int NBUF>
+static void launch_k1d_res(const T *A, const T *tau, const T *V, const T *u,
+                           const PairEvents *pes, int n_occ, int B, long long nr, T k1d,
+                           T inv_omega, T *Cr, cplx<T> *Hc, hipStream_t st) {
+    constexpr int SW = VPL * (K1D_R / PT);
+    // LDS capacity in orbitals: 128 KB of a values
+    constexpr int CAP = std::min(K1D_RES_MAXROWS, 2048 / (VPL * (int)sizeof(T)));
+    int set = -1;
+    for (int i = 0; i < K1D_RES_NSETS; ++i)
+        if (K1D_RES_CAPS[i] == CAP) set = i;
+    BSE_REQUIRE(set >= 0, BSE_ERR_STATE, "no resident K1d tables for %d orbitals", CAP);
+    const PairEvents &pe = pes[set];
+    const int nSc = (B + SW - 1) / SW;
+    const long long nrt = (nr + K1D_R - 1) / K1D_R;
+    const long long nblk = (nrt + 7) / 8 * 8 * (K1D_R / PT) * nSc;
+    BSE_REQUIRE(pe.ng >= 1 && pe.ng <= NW && pe.cap == CAP && n_occ <= NW * K1D_RES_BW,
+                BSE_ERR_ARG, "the resident K1d shape holds %d orbitals, the cell has %d",
+                NW * K1D_RES_BW, n_occ);
+    BSE_REQUIRE(nblk < (1LL << 31), BSE_ERR_ARG, "grid too large for the K1d kernel");
+    BSE_REQUIRE(pe.n_rows * TAU_TILE * (long long)sizeof(T) < (1LL << 31), BSE_ERR_ARG,
+                "too many pairs for the K1d tables");
+    k_k1d_res<T, VPL, PT, NW, NBUF, CAP><<<(unsigned)nblk, 64 * NW, 0, st>>>(
+        A, tau, V, u, pe.grp, pe.part, pe.ev, pe.ev_start, pe.ph_cnt, pe.ng, pe.nph, n_occ, B, nr,
+        pe.n_rows, nSc, k1d, inv_omega, Cr, Hc);
+    BSE_LAUNCH_CHECK();
+}
+
 // the compiled shapes; variant 0 is the default of each type
-static constexpr K1dShape K1D_SHAPES32[] = {{32, 16, 2, 4}, {32, 16, 1, 4}, {16, 16, 2, 4},
-                                            {32, 8, 2, 4},  {16, 8, 2, 4},  {64, 16, 2, 8},
-                                            {64, 8, 2, 8},  {32, 8, 2, 8},  {128, 8, 2, 16}};
-static constexpr K1dShape K1D_SHAPES64[] = {{32, 8, 1, 4}, {16, 8, 1, 4}, {32, 4, 1, 4},
-                                            {16, 4, 1, 4}, {64, 8, 1, 8}, {64, 4, 1, 8},
-                                            {128, 4, 1, 16}};
+static constexpr K1dShape K1D_SHAPES32[] = {
+    {32, 16, 2, 4},           {32, 16, 1, 4},           {16, 16, 2, 4},
+    {32, 8, 2, 4},            {16, 8, 2, 4},            {64, 16, 2, 8},
+    {64, 8, 2, 8},            {32, 8, 2, 8},            {128, 8, 2, 16},
+    {128, 4, 2, 16, 1, 64},   {128, 8, 2, 16, 1, 32},   {128, 8, 2, 16, 1, 64},
+    {128, 16, 2, 16, 1, 32},  {64, 8, 2, 8, 1, 64},     {64, 16, 2, 8, 1, 32}};
+static constexpr K1dShape K1D_SHAPES64[] = {
+    {32, 8, 1, 4},            {16, 8, 1, 4},            {32, 4, 1, 4},
+    {16, 4, 1, 4},            {64, 8, 1, 8},            {64, 4, 1, 8},
+    {128, 4, 1, 16},          {128, 2, 2, 16, 1, 64},   {128, 4, 2, 16, 1, 32},
+    {128, 4, 2, 16, 1, 64},   {128, 8, 2, 16, 1, 32},   {64, 4, 2, 8, 1, 64},
+    {64, 8, 2, 8, 1, 32}};
 
 int k1d_num_shapes(bool dbl) {
     return dbl ? (int)(sizeof(K1D_SHAPES64) / sizeof(K1dShape))
@@ -259,11 +458,34 @@ K1dShape k1d_shape(bool dbl, int v) {
 }
 
 template <typename T>
-void k1d_apply(const T *A, const T *tau, const T *V, const T *u, const PairCSR *csrs, int shape,
-               int n_occ, int B, long long nr, T k1d, T inv_omega, T *Cr, cplx<T> *Hc, T *Dp,
-               hipStream_t st) {
+void k1d_apply(const T *A, const T *tau, const T *V, const T *u, const PairCSR *csrs,
+               const PairEvents *pes, int shape, int n_occ, int B, long long nr, T k1d,
+               T inv_omega, T *Cr, cplx<T> *Hc, T *Dp, hipStream_t st) {
     constexpr bool dbl = sizeof(T) == 8;
     const K1dShape sh = k1d_shape(dbl, shape);
+    if (sh.res) {
+#define BSE_K1D_RES_CASE(S_, NW_, NB_, PT_)                                                  \
+    if (sh.s == S_ && sh.nw == NW_ && sh.nbuf == NB_ && sh.pt == PT_)                         \
+        launch_k1d_res<T, S_ * PT_ / K1D_R, PT_, NW_, NB_>(A, tau, V, u, pes, n_occ, B, nr, k1d,  \
+                                                          inv_omega, Cr, Hc, st);
+        if constexpr (dbl) {
+            BSE_K1D_RES_CASE(2, 16, 2, 64)
+            BSE_K1D_RES_CASE(4, 16, 2, 32)
+            BSE_K1D_RES_CASE(4, 16, 2, 64)
+            BSE_K1D_RES_CASE(8, 16, 2, 32)
+            BSE_K1D_RES_CASE(4, 8, 2, 64)
+            BSE_K1D_RES_CASE(8, 8, 2, 32)
+        } else {
+            BSE_K1D_RES_CASE(4, 16, 2, 64)
+            BSE_K1D_RES_CASE(8, 16, 2, 32)
+            BSE_K1D_RES_CASE(8, 16, 2, 64)
+            BSE_K1D_RES_CASE(16, 16, 2, 32)
+            BSE_K1D_RES_CASE(8, 8, 2, 64)
+            BSE_K1D_RES_CASE(16, 8, 2, 32)
+        }
+#undef BSE_K1D_RES_CASE
+        return;
+    }
     int set = -1;
     for (int i = 0; i < K1D_NSETS; ++i)
         if (K1D_BI_SIZES[i] == sh.bi) set = i;
@@ -300,10 +522,10 @@ void k1d_apply(const T *A, const T *tau, const T *V, const T *u, const PairCSR *
 }
 
 template void k1d_apply<float>(const float *, const float *, const float *, const float *,
-                               const PairCSR *, int, int, int, long long, float, float, float *,
-                               cplx<float> *, float *, hipStream_t);
+                               const PairCSR *, const PairEvents *, int, int, int, long long,
+                               float, float, float *, cplx<float> *, float *, hipStream_t);
 template void k1d_apply<double>(const double *, const double *, const double *, const double *,
-                                const PairCSR *, int, int, int, long long, double, double,
-                                double *, cplx<double> *, double *, hipStream_t);
+                                const PairCSR *, const PairEvents *, int, int, int, long long,
+                                double, double, double *, cplx<double> *, double *, hipStream_t);
 
 }  // namespace bse

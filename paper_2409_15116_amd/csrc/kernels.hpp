@@ -68,21 +68,53 @@ constexpr int K1D_NSETS = 4;
 constexpr int K1D_BI_SIZES[K1D_NSETS] = {32, 16, 64, 128};  // table sets held by a context
 constexpr int K1D_BI_MIN = 16;
 
+// Pair events of the resident K1d kernel, which holds every row of a grid
+// piece in one workgroup and the a values of up to cap orbitals in LDS.  The
+// orbitals are split into nph parts of at most cap (the column phases;
+// part[h * cap + k] is the orbital in LDS slot k during phase h, -1 past the
+// part's end) and into ng row groups of K1D_RES_BW inside the parts
+// (grp[g * BW + i], -1 for an empty slot).  Group g's events are
+// ev[(ev_start[g] + e) * (BW + 1) + k], phase after phase, ph_cnt[g * nph + h]
+// of them in phase h (a multiple of 4), followed by 4 padding events: k < BW
+// holds the tau offset (p * 64) of pair (grp[g * BW + k], column), or that of
+// the zero row P when the pair is not kept, and k = BW the column's LDS slot.
+// Only columns with a kept pair in the group have an event.
+constexpr int K1D_RES_BW = 8;
+constexpr int K1D_RES_MAXROWS = 128;
+constexpr int K1D_RES_NSETS = 2;
+constexpr int K1D_RES_CAPS[K1D_RES_NSETS] = {128, 64};
+struct PairEvents {
+    int ng = 0, nph = 0, cap = 0;
+    long long n_rows = 0;
+    const int *grp = nullptr;
+    const int *part = nullptr;
+    const int *ev = nullptr;
+    const int *ev_start = nullptr;
+    const int *ph_cnt = nullptr;
+};
+
 // Compiled shapes of the K1d kernel (the autotuner's choices): BI rows per
 // workgroup, S trial vectors per workgroup, NBUF columns of tau in flight,
-// NW waves per workgroup (BI / NW rows each).  Variant 0 of each type is the
-// default.
+// NW waves per workgroup; res = 0: the row-block kernel (BI / NW rows per
+// wave, PairCSR tables), res = 1: the resident kernel (K1D_RES_BW rows per
+// wave, PairEvents tables, at most BI = NW * K1D_RES_BW orbitals, PT grid
+// points per workgroup and S * PT / 64 vectors per lane).  Variant 0 of each
+// type is the default.
 struct K1dShape {
     int bi, s, nbuf, nw;
+    int res = 0;
+    int pt = 64;
 };
 int k1d_num_shapes(bool dbl);
 K1dShape k1d_shape(bool dbl, int v);
 
 // Dp: [ceil(n_occ / BI)][B][nr] partial K1e densities; csrs[] holds the
-// table set of every size in K1D_BI_SIZES; shape indexes k1d_shape().
+// table set of every size in K1D_BI_SIZES, pes[] the resident kernel's
+// event set of every capacity in K1D_RES_CAPS (ng = 0 when the cell has too
+// many orbitals for it); shape indexes k1d_shape().
 template <typename T>
-void k1d_apply(const T *A, const T *tau, const T *V, const T *u, const PairCSR *csrs, int shape,
-               int n_occ,
+void k1d_apply(const T *A, const T *tau, const T *V, const T *u, const PairCSR *csrs,
+               const PairEvents *pes, int shape, int n_occ,
                int B, long long nr, T k1d, T inv_omega, T *Cr, cplx<T> *Hc, T *Dp,
                hipStream_t st);
 template <typename T>

@@ -87,6 +87,7 @@ def load():
         "bse_davidson_record": (i32, [vp, C.POINTER(DavidsonOpts), vp, vp, i32, i32, vp, vp, i64,
                                       C.POINTER(i64), vp, vp, C.POINTER(DavidsonStats)]),
         "bse_k1d_num_shapes": (i32, [i32]),
+        "bse_k1d_shape_info": (i32, [i32, i32, vp]),
         "bse_autotune": (i32, [vp, i32, i32, i32, C.POINTER(i32), vp]),
         "bse_set_k1d_shape": (i32, [vp, i32, i32]),
         "bse_batch_create": (i32, [C.POINTER(vp), vp, i32, vp]),
@@ -114,7 +115,8 @@ def exported_symbols():
             "bse_mlp_create", "bse_mlp_destroy", "bse_mlp_num_params", "bse_mlp_get_weights",
             "bse_mlp_set_weights", "bse_mlp_forward", "bse_mlp_gradients", "bse_mlp_train",
             "bse_set_learned", "bse_learned_centers", "bse_davidson_record",
-            "bse_k1d_num_shapes", "bse_autotune", "bse_set_k1d_shape", "bse_batch_create",
+            "bse_k1d_num_shapes", "bse_k1d_shape_info", "bse_autotune", "bse_set_k1d_shape",
+            "bse_batch_create",
             "bse_batch_destroy", "bse_batch_set_graph", "bse_batch_apply", "bse_batch_davidson"]
 
 
@@ -270,13 +272,14 @@ class BseContext:
 
     def autotune(self, n_vec, precision=FP32, n_rep=2):
         """Time every compiled K1d shape on this cell; select and return the
-        fastest (shape index, list of per-shape K1d milliseconds)."""
+        fastest (shape index, list of per-shape K1d milliseconds, None for a
+        shape that cannot hold this cell's orbitals)."""
         ns = k1d_num_shapes(precision)
         ms = np.zeros(ns)
         shape = C.c_int(0)
         _check(load().bse_autotune(self.h, int(n_vec), int(precision), int(n_rep),
                                    C.byref(shape), ms.ctypes.data))
-        return shape.value, ms.tolist()
+        return shape.value, [float(x) if x >= 0 else None for x in ms]
 
     def set_k1d_shape(self, precision, shape):
         _check(load().bse_set_k1d_shape(self.h, int(precision), int(shape)))
@@ -302,6 +305,16 @@ class BseContext:
 
 def k1d_num_shapes(precision):
     return int(load().bse_k1d_num_shapes(int(precision)))
+
+
+def k1d_shape_info(precision, shape):
+    """Parameters of a compiled K1d shape: rows per workgroup (the orbital
+    limit of a resident shape), vectors per workgroup, tau columns in flight,
+    waves, resident (bool) and grid points per workgroup."""
+    info = np.zeros(6, dtype=np.int32)
+    _check(load().bse_k1d_shape_info(int(precision), int(shape), info.ctypes.data))
+    return {"rows": int(info[0]), "vectors": int(info[1]), "nbuf": int(info[2]),
+            "waves": int(info[3]), "resident": bool(info[4]), "points": int(info[5])}
 
 
 def _stats_dict(st, n_eig, status):

@@ -82,3 +82,29 @@ def test_build_compiles_every_source():
     import paper_2409_15116_amd.build as b
     srcs = sorted(f for f in os.listdir(b.CSRC) if f.endswith(".hip"))
     assert sorted(b.SOURCES) == srcs
+
+
+def test_k1d_shape_info():
+    """Every compiled K1d shape describes itself; resident shapes hold at
+    most 128 orbitals and store 16 or 32 bytes of a per lane and column."""
+    import paper_2409_15116_amd as pkg
+    for prec, esz in ((pkg.FP64, 8), (pkg.FP32, 4), (pkg.BF16X3, 4)):
+        n = pkg.k1d_num_shapes(prec)
+        assert n >= 1
+        assert pkg.k1d_shape_info(prec, 0)["resident"] is False   # shape 0: any cell
+        n_res = 0
+        for s in range(n):
+            i = pkg.k1d_shape_info(prec, s)
+            assert i["rows"] % i["waves"] == 0 and i["nbuf"] in (1, 2, 4)
+            if i["resident"]:
+                n_res += 1
+                assert i["rows"] == 8 * i["waves"] <= 128
+                vpl = i["vectors"] * i["points"] // 64
+                assert vpl % 2 == 0 and vpl * esz in (16, 32)
+            else:
+                assert i["points"] == 64
+        assert n_res >= 2
+        with pytest.raises(pkg.BseError):
+            pkg.k1d_shape_info(prec, n)
+    with pytest.raises(pkg.BseError):
+        pkg.k1d_shape_info(7, 0)
