@@ -240,7 +240,11 @@ __global__ void __launch_bounds__(64 * NW) k_k1d_res(
     static_assert(NBUF == 1 || NBUF == 2 || NBUF == 4, "events are padded to multiples of 4");
     static_assert(CAP % NW == 0, "the waves share the staging");
     using VecS = T __attribute__((ext_vector_type(VPL)));
-    __shared__ VecS a_s[CAP * K1D_R];   // [slot][lane]
+    constexpr int NH = VPL * (int)sizeof(T) / 16;  // 16-byte words per lane and column
+    using Vec16 = T __attribute__((ext_vector_type(16 / sizeof(T))));
+    constexpr int V16 = 16 / (int)sizeof(T);
+    // [slot][word][lane]: a wave's 16-byte reads of one word are contiguous
+    __shared__ Vec16 a_s[CAP * NH * K1D_R];
     __shared__ T red[NW * VPL * K1D_R];  // [wave][value][lane]
     // decode: id = 8 * ((hi8 * NQ + q) * nSc + sc) + lo8; tau tile hi8 * 8 + lo8,
     // piece q of it: the pieces and vector groups of one tile share an XCD
@@ -264,13 +268,33 @@ __global__ void __launch_bounds__(64 * NW) k_k1d_res(
         (void *)(tau + rt * n_rows * TAU_TILE), (short)0, (int)(n_rows * TAU_TILE * sizeof(T)),
         0x00020000);
     const int voff = (q * PT + pt) * (int)sizeof(T);
-    // a of this lane's vector j (clamped to a valid one) and orbital o; the
-    // empty asm hides B from loop-invariant hoisting, which would keep VPL
-    // 64-bit offsets live through the column loop
-    auto a_at = [&](int j, size_t vo) {
+    // offsets of this lane's vectors (clamped to valid ones); the empty asm
+    // hides B from loop-invariant hoisting, which would keep VPL 64-bit
+    // offsets live through the column loop
+    auto vec_offsets = [&](size_t (&so)[VPL]) {
         int bl = B;
         asm volatile("" : "+s"(bl));
-        return A[(size_t)min(s0 + j, bl - 1) * sstride + vo + rr];
+#pragma unroll
+        for (int j = 0; j < VPL; ++j) so[j] = (size_t)min(s0 + j, bl - 1) * sstride + rr;
+    };
+    auto lds_put = [&](int k, const VecS &x) {
+#pragma unroll
+        for (int hh = 0; hh < NH; ++hh) {
+            Vec16 y;
+#pragma unroll
+            for (int m = 0; m < V16; ++m) y[m] = x[hh * V16 + m];
+            a_s[(k * NH + hh) * K1D_R + lane] = y;
+        }
+    };
+    auto lds_get = [&](int k) {
+        VecS x;
+#pragma unroll
+        for (int hh = 0; hh < NH; ++hh) {
+            const Vec16 y = a_s[(k * NH + hh) * K1D_R + lane];
+#pragma unroll
+            for (int m = 0; m < V16; ++m) x[hh * V16 + m] = y[m];
+        }
+        return x;
     };
 
     T acc[BW][VPL];
@@ -294,15 +318,19 @@ __global__ void __launch_bounds__(64 * NW) k_k1d_res(
         if (h > 0) __syncthreads();  // every wave is done with the previous part
         // stage part h: wave wv loads slots wv, wv + NW, ... (an empty slot
         // stages a valid orbital; it is never read)
+        {
+            size_t so[VPL];
+            vec_offsets(so);
 #pragma unroll
-        for (int l = 0; l < CAP / NW; ++l) {
-            const int k = wv + NW * l;
-            const int o = part[h * CAP + k];
-            const size_t vo = (size_t)(o >= 0 ? o : 0) * nr;
-            VecS x;
+            for (int l = 0; l < CAP / NW; ++l) {
+                const int k = wv + NW * l;
+                const int o = part[h * CAP + k];
+                const T *ao = A + (size_t)(o >= 0 ? o : 0) * nr;
+                VecS x;
 #pragma unroll
-            for (int j = 0; j < VPL; ++j) x[j] = a_at(j, vo);
-            a_s[k * K1D_R + lane] = x;
+                for (int j = 0; j < VPL; ++j) x[j] = ao[so[j]];
+                lds_put(k, x);
+            }
         }
         __syncthreads();
         if (act) {
@@ -312,7 +340,7 @@ __global__ void __launch_bounds__(64 * NW) k_k1d_res(
 #pragma unroll
                 for (int b = 0; b < NBUF; ++b) {
                     const int *cur = evg + (e + b) * EV;
-                    const VecS aw = a_s[cur[BW] * K1D_R + lane];
+                    const VecS aw = lds_get(cur[BW]);
 #pragma unroll
                     for (int i = 0; i < BW; ++i)
 #pragma unroll
@@ -331,23 +359,25 @@ __global__ void __launch_bounds__(64 * NW) k_k1d_res(
 #pragma unroll
     for (int j = 0; j < VPL; ++j) dn[j] = 0;
     if (act) {
+        size_t so[VPL];
+        vec_offsets(so);
 #pragma unroll
         for (int i = 0; i < BW; ++i) {
             const int v = grp[wv * BW + i];
             if (v >= 0) {
                 VecS av;
                 if (nph == 1) {
-                    av = a_s[v * K1D_R + lane];
+                    av = lds_get(v);
                 } else {
+                    const T *ao = A + (size_t)v * nr;
 #pragma unroll
-                    for (int j = 0; j < VPL; ++j) av[j] = a_at(j, (size_t)v * nr);
+                    for (int j = 0; j < VPL; ++j) av[j] = ao[so[j]];
                 }
                 const T uv = u[(size_t)v * nr + rr];
 #pragma unroll
                 for (int j = 0; j < VPL; ++j) {
-                    if (rok && s0 + j < B)
-                        Cr[(size_t)(s0 + j) * sstride + (size_t)v * nr + rr] =
-                            vr * av[j] - k1d * acc[i][j];
+                    if (rok && s0 + j < B)  // so[j] is not clamped here
+                        Cr[so[j] + (size_t)v * nr] = vr * av[j] - k1d * acc[i][j];
                     dn[j] += uv * av[j];
                 }
             }
