@@ -490,7 +490,12 @@ static void build_event_set(bse_ctx *c, int set, int cap, const Bits &nb,
         dev.alloc(std::max<size_t>(1, host.size()));
         BSE_HIP(hipMemcpy(dev.p, host.data(), host.size() * sizeof(host[0]), hipMemcpyHostToDevice));
     };
+    std::vector<int> gslot(grp.size(), 0);
+    for (size_t k = 0; k < grp.size(); ++k)
+        if (grp[k] >= 0) gslot[k] = slot[grp[k]];
     up(c->res_grp[set], grp);
+    up(c->res_gpart[set], gpart);
+    up(c->res_gslot[set], gslot);
     up(c->res_part[set], part_tbl);
     up(c->res_ev[set], ev);
     up(c->res_start[set], start);
@@ -501,6 +506,8 @@ static void build_event_set(bse_ctx *c, int set, int cap, const Bits &nb,
     e.cap = cap;
     e.n_rows = P + 1;
     e.grp = c->res_grp[set].p;
+    e.gpart = c->res_gpart[set].p;
+    e.gslot = c->res_gslot[set].p;
     e.part = c->res_part[set].p;
     e.ev = c->res_ev[set].p;
     e.ev_start = c->res_start[set].p;

@@ -103,7 +103,8 @@ struct bse_ctx {
     bse::PairCSR csr[bse::K1D_NSETS];
     // events of the resident K1d kernel, one set per LDS capacity in
     // K1D_RES_CAPS (ng = 0 past K1D_RES_MAXROWS orbitals)
-    bse::Dev<int> res_grp[bse::K1D_RES_NSETS], res_part[bse::K1D_RES_NSETS],
+    bse::Dev<int> res_grp[bse::K1D_RES_NSETS], res_gpart[bse::K1D_RES_NSETS],
+        res_gslot[bse::K1D_RES_NSETS], res_part[bse::K1D_RES_NSETS],
         res_ev[bse::K1D_RES_NSETS], res_start[bse::K1D_RES_NSETS], res_cnt[bse::K1D_RES_NSETS];
     bse::PairEvents res[bse::K1D_RES_NSETS];
     int k1d_shape[2] = {0, 0};  // chosen K1d shape for FP64 / FP32 (bse_autotune)

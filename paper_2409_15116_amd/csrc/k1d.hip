@@ -227,7 +227,8 @@ __global__ void __launch_bounds__(64 * NW) k_k1d(const T *__restrict__ A, const 
 template <typename T, int VPL, int PT, int NW, int NBUF, int CAP>
 __global__ void __launch_bounds__(64 * NW) k_k1d_res(
     const T *__restrict__ A, const T *__restrict__ tau, const T *__restrict__ V,
-    const T *__restrict__ u, const int *__restrict__ grp, const int *__restrict__ part,
+    const T *__restrict__ u, const int *__restrict__ grp, const int *__restrict__ gpart,
+    const int *__restrict__ gslot, const int *__restrict__ part,
     const int *__restrict__ ev, const int *__restrict__ ev_start, const int *__restrict__ ph_cnt,
     int ng, int nph, int n_occ, int B, long long nr, long long n_rows, int nSc, T k1d,
     T inv_omega, T *__restrict__ Cr, cplx<T> *__restrict__ Hc) {
@@ -353,7 +354,7 @@ __global__ void __launch_bounds__(64 * NW) k_k1d_res(
         }
     }
     // epilogue: Cr of this wave's orbitals and their share of the density
-    // (a from LDS when every orbital is resident: slot = orbital)
+    // (a from LDS when the orbitals' part is the one resident last)
     const T vr = V[rr];
     T dn[VPL];
 #pragma unroll
@@ -361,13 +362,14 @@ __global__ void __launch_bounds__(64 * NW) k_k1d_res(
     if (act) {
         size_t so[VPL];
         vec_offsets(so);
+        const bool last = gpart[wv] == nph - 1;
 #pragma unroll
         for (int i = 0; i < BW; ++i) {
             const int v = grp[wv * BW + i];
             if (v >= 0) {
                 VecS av;
-                if (nph == 1) {
-                    av = lds_get(v);
+                if (last) {
+                    av = lds_get(gslot[wv * BW + i]);
                 } else {
                     const T *ao = A + (size_t)v * nr;
 #pragma unroll
@@ -459,7 +461,8 @@ static void launch_k1d_res(const T *A, const T *tau, const T *V, const T *u,
     BSE_REQUIRE(pe.n_rows * TAU_TILE * (long long)sizeof(T) < (1LL << 31), BSE_ERR_ARG,
                 "too many pairs for the K1d tables");
     k_k1d_res<T, VPL, PT, NW, NBUF, CAP><<<(unsigned)nblk, 64 * NW, 0, st>>>(
-        A, tau, V, u, pe.grp, pe.part, pe.ev, pe.ev_start, pe.ph_cnt, pe.ng, pe.nph, n_occ, B, nr,
+        A, tau, V, u, pe.grp, pe.gpart, pe.gslot, pe.part, pe.ev, pe.ev_start, pe.ph_cnt, pe.ng,
+        pe.nph, n_occ, B, nr,
         pe.n_rows, nSc, k1d, inv_omega, Cr, Hc);
     BSE_LAUNCH_CHECK();
 }

@@ -78,7 +78,9 @@ constexpr int K1D_BI_MIN = 16;
 // of them in phase h (a multiple of 4), followed by 4 padding events: k < BW
 // holds the tau offset (p * 64) of pair (grp[g * BW + k], column), or that of
 // the zero row P when the pair is not kept, and k = BW the column's LDS slot.
-// Only columns with a kept pair in the group have an event.
+// Only columns with a kept pair in the group have an event.  gpart[g] is the
+// part of group g's orbitals and gslot[g * BW + i] the LDS slot of orbital
+// grp[g * BW + i] in it.
 constexpr int K1D_RES_BW = 8;
 constexpr int K1D_RES_MAXROWS = 128;
 constexpr int K1D_RES_NSETS = 2;
@@ -87,6 +89,8 @@ struct PairEvents {
     int ng = 0, nph = 0, cap = 0;
     long long n_rows = 0;
     const int *grp = nullptr;
+    const int *gpart = nullptr;
+    const int *gslot = nullptr;
     const int *part = nullptr;
     const int *ev = nullptr;
     const int *ev_start = nullptr;
