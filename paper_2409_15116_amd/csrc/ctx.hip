@@ -425,6 +425,87 @@ static void build_event_set(bse_ctx *c, int set, int cap, const Bits &nb,
     for (int g = 0; g < ng; ++g)
         std::sort(grp.begin() + (size_t)g * BW, grp.begin() + (size_t)(g + 1) * BW,
                   [](int a, int b) { return (a < 0 ? INT_MAX : a) < (b < 0 ? INT_MAX : b); });
+    // wave order: a workgroup's waves are spread over the CU's four SIMDs
+    // in turn (wave w on SIMD w % 4), and every phase ends at a barrier, so
+    // the groups are ordered to even out each SIMD's events in each phase
+    // (greedy by total, then swaps that do not raise the sum over phases of
+    // the busiest SIMD's events)
+    if (ng > 4) {
+        std::vector<std::vector<int>> E(ng, std::vector<int>(nph, 0));
+        for (int g = 0; g < ng; ++g) {
+            std::vector<unsigned long long> cv(nwd, 0);
+            for (int i = 0; i < BW; ++i) {
+                const int v = grp[(size_t)g * BW + i];
+                if (v >= 0)
+                    for (int q = 0; q < nwd; ++q) cv[q] |= nb.row(v)[q];
+            }
+            for (int w = 0; w < no; ++w)
+                if (cv[w / 64] >> (w % 64) & 1) ++E[g][part_of[w]];
+            for (int h = 0; h < nph; ++h) E[g][h] = (E[g][h] + 3) / 4 * 4;
+        }
+        std::vector<int> perm(ng);  // wave -> group
+        for (int g = 0; g < ng; ++g) perm[g] = g;
+        auto tot = [&](int g) {
+            int s = 0;
+            for (int h = 0; h < nph; ++h) s += E[g][h];
+            return s;
+        };
+        std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return tot(a) > tot(b); });
+        {  // greedy: largest first onto the least loaded SIMD with a free wave
+            std::vector<int> load(4, 0);
+            const int per = (ng + 3) / 4;
+            std::vector<int> order = perm;
+            std::vector<std::vector<int>> bins(4);
+            for (int g : order) {
+                int best = -1;
+                for (int s = 0; s < 4; ++s)
+                    if ((int)bins[s].size() < per && (best < 0 || load[s] < load[best])) best = s;
+                bins[best].push_back(g);
+                load[best] += tot(g);
+            }
+            std::vector<int> used(4, 0);
+            for (int w = 0; w < ng; ++w) {
+                auto &b = bins[w % 4];
+                perm[w] = used[w % 4] < (int)b.size() ? b[used[w % 4]++] : -1;
+            }
+            // a SIMD short of groups leaves -1 slots: fill them with the rest
+            std::vector<int> rest;
+            for (int s = 0; s < 4; ++s)
+                for (int k = used[s]; k < (int)bins[s].size(); ++k) rest.push_back(bins[s][k]);
+            for (int w = 0, k = 0; w < ng; ++w)
+                if (perm[w] < 0) perm[w] = rest[k++];
+        }
+        auto span = [&]() {
+            int s = 0;
+            for (int h = 0; h < nph; ++h) {
+                int mx = 0;
+                for (int q = 0; q < 4; ++q) {
+                    int l = 0;
+                    for (int w = q; w < ng; w += 4) l += E[perm[w]][h];
+                    mx = std::max(mx, l);
+                }
+                s += mx;
+            }
+            return s;
+        };
+        int cur = span();
+        for (int it = 0; it < 4000; ++it) {
+            const int a = rnd(ng), b = rnd(ng);
+            if (a % 4 == b % 4) continue;
+            std::swap(perm[a], perm[b]);
+            const int s = span();
+            if (s <= cur) cur = s;
+            else std::swap(perm[a], perm[b]);
+        }
+        std::vector<int> grp2(grp.size()), gpart2(ng);
+        for (int w = 0; w < ng; ++w) {
+            std::copy(grp.begin() + (size_t)perm[w] * BW, grp.begin() + (size_t)(perm[w] + 1) * BW,
+                      grp2.begin() + (size_t)w * BW);
+            gpart2[w] = gpart[perm[w]];
+        }
+        grp.swap(grp2);
+        gpart.swap(gpart2);
+    }
     // events: phase by phase; in the phase of its own part a group follows a
     // round-robin tournament over that part's groups (circle method, an odd
     // count gets a bye; in round r it visits its partner's columns and its
