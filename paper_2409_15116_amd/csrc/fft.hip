@@ -20,19 +20,25 @@ namespace bse {
 constexpr int FFT_NT = 256;
 
 // Lines per workgroup: a power of two, as many as fit a 64 KB LDS tile (two
-// buffers of n * C elements plus n twiddles), at most 64.  Compile-time, so
-// that every staging loop has a constant trip count and unrolls.
+// buffers of n * (C + 1) elements plus n twiddles), at most 64.
+// Compile-time, so that every staging loop has a constant trip count and
+// unrolls.  Element e of line c sits at e * C + c; the z passes, whose
+// global side runs along the lines, use e * (C + 1) + c for the data they
+// stage in and out, so that the 64 lanes of a wave, which walk e there,
+// fall on different LDS banks.
 template <typename T, int N>
 struct FftTile {
     static constexpr size_t esz = 2 * sizeof(T);
     static constexpr int pick() {
         int c = 64;
-        while (c > 2 && (size_t)(2 * N * c + N) * esz > 64 * 1024) c /= 2;
+        while (c > 2 && (size_t)(2 * N * (c + 1) + N) * esz > 64 * 1024) c /= 2;
         return c;
     }
     static constexpr int C = pick();
+    static constexpr int CP = C + 1;  // padded line stride
     static constexpr int lc = C == 64 ? 6 : C == 32 ? 5 : C == 16 ? 4 : C == 8 ? 3 : C == 4 ? 2 : 1;
-    static constexpr size_t lds = (size_t)(2 * N * C + N) * esz;
+    static constexpr int buf = N * CP;  // elements per buffer
+    static constexpr size_t lds = (size_t)(2 * buf + N) * esz;
     static_assert((1 << lc) == C, "tile width");
 };
 
@@ -124,8 +130,8 @@ constexpr int fft_factor(int n, int at) {
 
 // One Stockham stage of radix R for lines of compile-time length N after
 // stages whose radices multiply to NS; C (a power of two, 1 << lc) lines in
-// LDS at addr = e * C + c.
-template <int R, int N, int NS, int LC, typename T>
+// LDS at addr = e * SI + c in src and e * SO + c in dst.
+template <int R, int N, int NS, int LC, int SI, int SO, typename T>
 __device__ __forceinline__ void stage(const cplx<T> *__restrict__ src, cplx<T> *__restrict__ dst,
                              const cplx<T> *__restrict__ tw, T sign) {
     using C2 = cplx<T>;
@@ -143,7 +149,7 @@ __device__ __forceinline__ void stage(const cplx<T> *__restrict__ src, cplx<T> *
         const int k = j % NS;
         C2 v[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = src[((j + r * nR) << lc) + c];
+        for (int r = 0; r < R; ++r) v[r] = src[(j + r * nR) * SI + c];
         const int base = k * twstep;  // r * base < N
 #pragma unroll
         for (int r = 1; r < R; ++r) {
@@ -157,29 +163,32 @@ __device__ __forceinline__ void stage(const cplx<T> *__restrict__ src, cplx<T> *
         if (R == 5) bfly5<C2, T>(v, sign);
         const int idxD = (j / NS) * NS * R + k;
 #pragma unroll
-        for (int r = 0; r < R; ++r) dst[((idxD + r * NS) << lc) + c] = v[r];
+        for (int r = 0; r < R; ++r) dst[(idxD + r * NS) * SO + c] = v[r];
     }
 }
 
-template <typename T, int N, int ST, int NS, int LC>
+template <typename T, int N, int ST, int NS, int LC, int SP>
 __device__ __forceinline__ cplx<T> *fft_stages(cplx<T> *a, cplx<T> *b, const cplx<T> *tw, T sign) {
-    if constexpr (ST < fft_nfactors(N)) {
+    constexpr int NF = fft_nfactors(N);
+    if constexpr (ST < NF) {
         constexpr int R = fft_factor(N, ST);
-        stage<R, N, NS, LC, T>(a, b, tw, sign);
+        constexpr int C = 1 << LC;
+        stage<R, N, NS, LC, ST == 0 ? SP : C, ST == NF - 1 ? SP : C, T>(a, b, tw, sign);
         __syncthreads();
-        return fft_stages<T, N, ST + 1, NS * R, LC>(b, a, tw, sign);
+        return fft_stages<T, N, ST + 1, NS * R, LC, SP>(b, a, tw, sign);
     } else {
         return a;
     }
 }
 
-// FFT of the C = FftTile<T, N>::C lines of length N held in LDS buffer a
-// (layout e*C + c); b is scratch of the same size.  sign = -1 forward, +1
-// inverse (unnormalised).  Returns the buffer holding the result.  Ends with a
-// barrier.
-template <typename T, int N>
+// FFT of the C = FftTile<T, N>::C lines of length N held in LDS buffer a;
+// b is scratch of the same size.  Input and result at e * C + c, or at
+// e * (C + 1) + c with PAD.  sign = -1 forward, +1 inverse (unnormalised).
+// Returns the buffer holding the result.  Ends with a barrier.
+template <typename T, int N, bool PAD = false>
 __device__ __forceinline__ cplx<T> *lds_fft(cplx<T> *a, cplx<T> *b, const cplx<T> *tw, T sign) {
-    return fft_stages<T, N, 0, 1, FftTile<T, N>::lc>(a, b, tw, sign);
+    using F = FftTile<T, N>;
+    return fft_stages<T, N, 0, 1, F::lc, PAD ? F::CP : F::C>(a, b, tw, sign);
 }
 
 template <typename T>
@@ -210,10 +219,11 @@ __global__ void __launch_bounds__(256) k_sph_inv_z(const T *__restrict__ X, int 
     constexpr int n = N;
     constexpr int C = FftTile<T, N>::C;
     constexpr int lc = FftTile<T, N>::lc;
-    C2 *sb = sa + n * C;
-    C2 *stw = sb + n * C;
+    C2 *sb = sa + FftTile<T, N>::buf;
+    C2 *stw = sb + FftTile<T, N>::buf;
+    constexpr int CP = FftTile<T, N>::CP;
     const int L0 = blockIdx.x * C;
-    FFT_FOR(i, n * C) sa[i] = cmake<C2>(0, 0);
+    FFT_FOR(i, n * CP) sa[i] = cmake<C2>(0, 0);
     load_twiddles<T>(stw, tw, n);
     __syncthreads();
     const T isq2 = (T)0.70710678118654752440;
@@ -232,7 +242,7 @@ __global__ void __launch_bounds__(256) k_sph_inv_z(const T *__restrict__ X, int 
             c1 = cmake<C2>(x1[k] * isq2, sg * x1[k + 1] * isq2);
             c2 = has2 ? cmake<C2>(x2[k] * isq2, sg * x2[k + 1] * isq2) : cmake<C2>(0, 0);
         }
-        sa[z * C + c] = cmake<C2>(c1.x - c2.y, c1.y + c2.x);
+        sa[z * CP + c] = cmake<C2>(c1.x - c2.y, c1.y + c2.x);
     };
     // the first 64 entries of each of the wave's columns, in three batched
     // levels (column ranges, entries, coefficients) so that each level's
@@ -270,7 +280,7 @@ __global__ void __launch_bounds__(256) k_sph_inv_z(const T *__restrict__ X, int 
                 c1 = cmake<C2>(a0 * isq2, sg * a1 * isq2);
                 c2 = has2 ? cmake<C2>(b0 * isq2, sg * b1 * isq2) : cmake<C2>(0, 0);
             }
-            sa[z * C + wave + j * NWAVE] = cmake<C2>(c1.x - c2.y, c1.y + c2.x);
+            sa[z * CP + wave + j * NWAVE] = cmake<C2>(c1.x - c2.y, c1.y + c2.x);
         }
     }
     // columns longer than 64 entries (none at the compiled grid sizes and
@@ -285,11 +295,11 @@ __global__ void __launch_bounds__(256) k_sph_inv_z(const T *__restrict__ X, int 
             put(wave + j * NWAVE, ent[beg[j] + e], x1, x2, has2);
     }
     __syncthreads();
-    C2 *res = lds_fft<T, N>(sa, sb, stw, (T)1);
+    C2 *res = lds_fft<T, N, true>(sa, sb, stw, (T)1);
     FFT_FOR(i, n * C) {
         const int c = i / n, z = i - c * n;
         const int L = L0 + c;
-        if (L < n_lines) T1[(size_t)L * n + z] = res[z * C + c];
+        if (L < n_lines) T1[(size_t)L * n + z] = res[z * CP + c];
     }
 }
 
@@ -306,8 +316,8 @@ __global__ void __launch_bounds__(256) k_sph_inv_y(const cplx<T> *__restrict__ T
     constexpr int C = FftTile<T, N>::C;
     constexpr int lc = FftTile<T, N>::lc;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
-    C2 *sb = sa + n * C;
-    C2 *stw = sb + n * C;
+    C2 *sb = sa + FftTile<T, N>::buf;
+    C2 *stw = sb + FftTile<T, N>::buf;
     int bid = blockIdx.x;
     const int zt = bid % nzt;
     bid /= nzt;
@@ -349,8 +359,8 @@ __global__ void __launch_bounds__(256) k_sph_inv_x(const cplx<T> *__restrict__ T
     constexpr int lc = FftTile<T, N>::lc;
     const int n2 = n * n;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
-    C2 *sb = sa + n * C;
-    C2 *stw = sb + n * C;
+    C2 *sb = sa + FftTile<T, N>::buf;
+    C2 *stw = sb + FftTile<T, N>::buf;
     const int t = blockIdx.x % nyzt;
     const int q = blockIdx.x / nyzt;
     const int yz0 = t * C;
@@ -402,8 +412,8 @@ __global__ void __launch_bounds__(256) k_sph_fwd_x(const T *__restrict__ Cr, con
     const int n2 = n * n;
     const size_t nr = (size_t)n2 * n;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
-    C2 *sb = sa + n * C;
-    C2 *stw = sb + n * C;
+    C2 *sb = sa + FftTile<T, N>::buf;
+    C2 *stw = sb + FftTile<T, N>::buf;
     // q fastest: the orbital slots sharing one Hartree tile run back to back
     const int nq = gridDim.x / nyzt;
     const int q = blockIdx.x % nq;
@@ -453,8 +463,8 @@ __global__ void __launch_bounds__(256) k_sph_fwd_y(const cplx<T> *__restrict__ T
     constexpr int C = FftTile<T, N>::C;
     constexpr int lc = FftTile<T, N>::lc;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
-    C2 *sb = sa + n * C;
-    C2 *stw = sb + n * C;
+    C2 *sb = sa + FftTile<T, N>::buf;
+    C2 *stw = sb + FftTile<T, N>::buf;
     int bid = blockIdx.x;
     const int zt = bid % nzt;
     bid /= nzt;
@@ -498,18 +508,19 @@ __global__ void __launch_bounds__(256) k_sph_fwd_z(const cplx<T> *__restrict__ T
     constexpr int C = FftTile<T, N>::C;
     constexpr int lc = FftTile<T, N>::lc;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
-    C2 *sb = sa + n * C;
-    C2 *stw = sb + n * C;
+    C2 *sb = sa + FftTile<T, N>::buf;
+    C2 *stw = sb + FftTile<T, N>::buf;
+    constexpr int CP = FftTile<T, N>::CP;
     const int L0 = blockIdx.x * C;
     FFT_FOR(i, n * C) {
         const int c = i / n, z = i - c * n;
         const int L = L0 + c;
         const C2 v = T1[(size_t)min(L, n_lines - 1) * n + z];
-        sa[z * C + c] = keep_if(v, L < n_lines);
+        sa[z * CP + c] = keep_if(v, L < n_lines);
     }
     load_twiddles<T>(stw, tw, n);  // after the data loads: they overlap
     __syncthreads();
-    C2 *res = lds_fft<T, N>(sa, sb, stw, (T)-1);
+    C2 *res = lds_fft<T, N, true>(sa, sb, stw, (T)-1);
     const T inv_nr = (T)1 / ((T)n * (T)n * (T)n);
     const T sq2 = (T)1.41421356237309504880;
     constexpr int NWAVE = FFT_NT >> 6;
@@ -520,14 +531,14 @@ __global__ void __launch_bounds__(256) k_sph_fwd_z(const cplx<T> *__restrict__ T
                     bool has2) {
         const int z = en.x & 0xffff, kind = en.x >> 16, k = en.y;
         if (kind == 2) return;
-        const C2 F = res[z * C + c];
+        const C2 F = res[z * CP + c];
         if (kind == 0) {
             y1[0] = F.x * inv_nr;
             if (has2) y2[0] = F.y * inv_nr;
             return;
         }
         const int zm = (n - z) % n;
-        const C2 Fm = res[zm * C + cm];
+        const C2 Fm = res[zm * CP + cm];
         // a(G) = (F(G) + conj F(-G)) / 2,  b(G) = -i (F(G) - conj F(-G)) / 2
         const T ar = (F.x + Fm.x) * (T)0.5, ai = (F.y - Fm.y) * (T)0.5;
         const T br = (F.y + Fm.y) * (T)0.5, bi = -(F.x - Fm.x) * (T)0.5;
@@ -596,22 +607,23 @@ __global__ void __launch_bounds__(256) k_grid_z(cplx<T> *__restrict__ A, int n_l
     constexpr int C = FftTile<T, N>::C;
     constexpr int lc = FftTile<T, N>::lc;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
-    C2 *sb = sa + n * C;
-    C2 *stw = sb + n * C;
+    C2 *sb = sa + FftTile<T, N>::buf;
+    C2 *stw = sb + FftTile<T, N>::buf;
+    constexpr int CP = FftTile<T, N>::CP;
     const int L0 = blockIdx.x * C;
     FFT_FOR(i, n * C) {
         const int c = i / n, z = i - c * n;
         const int L = L0 + c;
         const C2 v = A[(size_t)min(L, n_lines - 1) * n + z];
-        sa[z * C + c] = keep_if(v, L < n_lines);
+        sa[z * CP + c] = keep_if(v, L < n_lines);
     }
     load_twiddles<T>(stw, tw, n);  // after the data loads: they overlap
     __syncthreads();
-    C2 *res = lds_fft<T, N>(sa, sb, stw, sign);
+    C2 *res = lds_fft<T, N, true>(sa, sb, stw, sign);
     FFT_FOR(i, n * C) {
         const int c = i / n, z = i - c * n;
         const int L = L0 + c;
-        if (L < n_lines) A[(size_t)L * n + z] = res[z * C + c];
+        if (L < n_lines) A[(size_t)L * n + z] = res[z * CP + c];
     }
 }
 
@@ -626,8 +638,8 @@ __global__ void __launch_bounds__(256) k_grid_y(cplx<T> *__restrict__ A,
     constexpr int C = FftTile<T, N>::C;
     constexpr int lc = FftTile<T, N>::lc;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
-    C2 *sb = sa + n * C;
-    C2 *stw = sb + n * C;
+    C2 *sb = sa + FftTile<T, N>::buf;
+    C2 *stw = sb + FftTile<T, N>::buf;
     const int zt = blockIdx.x % nzt;
     const int bx = blockIdx.x / nzt;  // b * n + x
     const int z0 = zt * C;
@@ -660,8 +672,8 @@ __global__ void __launch_bounds__(256) k_grid_x(cplx<T> *__restrict__ A,
     constexpr int lc = FftTile<T, N>::lc;
     const int n2 = n * n;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
-    C2 *sb = sa + n * C;
-    C2 *stw = sb + n * C;
+    C2 *sb = sa + FftTile<T, N>::buf;
+    C2 *stw = sb + FftTile<T, N>::buf;
     const int t = blockIdx.x % nyzt;
     const int b = blockIdx.x / nyzt;
     const int yz0 = t * C;
