@@ -26,11 +26,11 @@ constexpr int FFT_NT = 256;
 // global side runs along the lines, use e * (C + 1) + c for the data they
 // stage in and out, so that the 64 lanes of a wave, which walk e there,
 // fall on different LDS banks.
-template <typename T, int N>
+template <typename T, int N, int CMAX = 64>
 struct FftTile {
     static constexpr size_t esz = 2 * sizeof(T);
     static constexpr int pick() {
-        int c = 64;
+        int c = CMAX;
         while (c > 2 && (size_t)(2 * N * (c + 1) + N) * esz > 64 * 1024) c /= 2;
         return c;
     }
@@ -41,6 +41,13 @@ struct FftTile {
     static constexpr size_t lds = (size_t)(2 * buf + N) * esz;
     static_assert((1 << lc) == C, "tile width");
 };
+
+// Lines per workgroup of the z passes (even: a sphere column and its mirror
+// share a tile): their global side is whole lines, so
+// the tile width does not shape their memory access; narrower tiles leave
+// room for more workgroups per CU to hide the latency of the sphere gathers.
+constexpr int FFT_ZC = 16;
+static_assert(FFT_ZC % 2 == 0, "z tiles hold column pairs");
 
 // Element loop of a staging pass: i = k * FFT_NT + threadIdx.x for every
 // i < TOTAL, with a compile-time trip count so that it unrolls and all of a
@@ -181,13 +188,13 @@ __device__ __forceinline__ cplx<T> *fft_stages(cplx<T> *a, cplx<T> *b, const cpl
     }
 }
 
-// FFT of the C = FftTile<T, N>::C lines of length N held in LDS buffer a;
+// FFT of the C = FftTile<T, N, CMAX>::C lines of length N held in LDS buffer a;
 // b is scratch of the same size.  Input and result at e * C + c, or at
 // e * (C + 1) + c with PAD.  sign = -1 forward, +1 inverse (unnormalised).
 // Returns the buffer holding the result.  Ends with a barrier.
-template <typename T, int N, bool PAD = false>
+template <typename T, int N, bool PAD = false, int CMAX = 64>
 __device__ __forceinline__ cplx<T> *lds_fft(cplx<T> *a, cplx<T> *b, const cplx<T> *tw, T sign) {
-    using F = FftTile<T, N>;
+    using F = FftTile<T, N, CMAX>;
     return fft_stages<T, N, 0, 1, F::lc, PAD ? F::CP : F::C>(a, b, tw, sign);
 }
 
@@ -217,11 +224,11 @@ __global__ void __launch_bounds__(256) k_sph_inv_z(const T *__restrict__ X, int 
     extern __shared__ unsigned char smem_raw[];
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
     constexpr int n = N;
-    constexpr int C = FftTile<T, N>::C;
-    constexpr int lc = FftTile<T, N>::lc;
-    C2 *sb = sa + FftTile<T, N>::buf;
-    C2 *stw = sb + FftTile<T, N>::buf;
-    constexpr int CP = FftTile<T, N>::CP;
+    constexpr int C = FftTile<T, N, FFT_ZC>::C;
+    constexpr int lc = FftTile<T, N, FFT_ZC>::lc;
+    C2 *sb = sa + FftTile<T, N, FFT_ZC>::buf;
+    C2 *stw = sb + FftTile<T, N, FFT_ZC>::buf;
+    constexpr int CP = FftTile<T, N, FFT_ZC>::CP;
     const int L0 = blockIdx.x * C;
     FFT_FOR(i, n * CP) sa[i] = cmake<C2>(0, 0);
     load_twiddles<T>(stw, tw, n);
@@ -295,7 +302,7 @@ __global__ void __launch_bounds__(256) k_sph_inv_z(const T *__restrict__ X, int 
             put(wave + j * NWAVE, ent[beg[j] + e], x1, x2, has2);
     }
     __syncthreads();
-    C2 *res = lds_fft<T, N, true>(sa, sb, stw, (T)1);
+    C2 *res = lds_fft<T, N, true, FFT_ZC>(sa, sb, stw, (T)1);
     FFT_FOR(i, n * C) {
         const int c = i / n, z = i - c * n;
         const int L = L0 + c;
@@ -505,12 +512,12 @@ __global__ void __launch_bounds__(256) k_sph_fwd_z(const cplx<T> *__restrict__ T
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
     constexpr int n = N;
-    constexpr int C = FftTile<T, N>::C;
-    constexpr int lc = FftTile<T, N>::lc;
+    constexpr int C = FftTile<T, N, FFT_ZC>::C;
+    constexpr int lc = FftTile<T, N, FFT_ZC>::lc;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
-    C2 *sb = sa + FftTile<T, N>::buf;
-    C2 *stw = sb + FftTile<T, N>::buf;
-    constexpr int CP = FftTile<T, N>::CP;
+    C2 *sb = sa + FftTile<T, N, FFT_ZC>::buf;
+    C2 *stw = sb + FftTile<T, N, FFT_ZC>::buf;
+    constexpr int CP = FftTile<T, N, FFT_ZC>::CP;
     const int L0 = blockIdx.x * C;
     FFT_FOR(i, n * C) {
         const int c = i / n, z = i - c * n;
@@ -520,7 +527,7 @@ __global__ void __launch_bounds__(256) k_sph_fwd_z(const cplx<T> *__restrict__ T
     }
     load_twiddles<T>(stw, tw, n);  // after the data loads: they overlap
     __syncthreads();
-    C2 *res = lds_fft<T, N, true>(sa, sb, stw, (T)-1);
+    C2 *res = lds_fft<T, N, true, FFT_ZC>(sa, sb, stw, (T)-1);
     const T inv_nr = (T)1 / ((T)n * (T)n * (T)n);
     const T sq2 = (T)1.41421356237309504880;
     constexpr int NWAVE = FFT_NT >> 6;
@@ -604,12 +611,12 @@ __global__ void __launch_bounds__(256) k_grid_z(cplx<T> *__restrict__ A, int n_l
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
     constexpr int n = N;
-    constexpr int C = FftTile<T, N>::C;
-    constexpr int lc = FftTile<T, N>::lc;
+    constexpr int C = FftTile<T, N, FFT_ZC>::C;
+    constexpr int lc = FftTile<T, N, FFT_ZC>::lc;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
-    C2 *sb = sa + FftTile<T, N>::buf;
-    C2 *stw = sb + FftTile<T, N>::buf;
-    constexpr int CP = FftTile<T, N>::CP;
+    C2 *sb = sa + FftTile<T, N, FFT_ZC>::buf;
+    C2 *stw = sb + FftTile<T, N, FFT_ZC>::buf;
+    constexpr int CP = FftTile<T, N, FFT_ZC>::CP;
     const int L0 = blockIdx.x * C;
     FFT_FOR(i, n * C) {
         const int c = i / n, z = i - c * n;
@@ -619,7 +626,7 @@ __global__ void __launch_bounds__(256) k_grid_z(cplx<T> *__restrict__ A, int n_l
     }
     load_twiddles<T>(stw, tw, n);  // after the data loads: they overlap
     __syncthreads();
-    C2 *res = lds_fft<T, N, true>(sa, sb, stw, sign);
+    C2 *res = lds_fft<T, N, true, FFT_ZC>(sa, sb, stw, sign);
     FFT_FOR(i, n * C) {
         const int c = i / n, z = i - c * n;
         const int L = L0 + c;
@@ -731,7 +738,8 @@ static void sph_inverse_n(const SphereMaps &m, const T *X, int n_orb, T *out, cp
     static_assert(C == FftTile<T, N>::C && C % 2 == 0, "tile width");
     {
         const int n_lines = nq * m.ncol;
-        k_sph_inv_z<T, N><<<div_up(n_lines, C), 256, FftTile<T, N>::lds, st>>>(
+        k_sph_inv_z<T, N><<<div_up(n_lines, FftTile<T, N, FFT_ZC>::C), 256,
+                            FftTile<T, N, FFT_ZC>::lds, st>>>(
             X, n_orb, m.npw, m.ent, m.col_ptr, m.ncol, n_lines, T1, tw, ps);
         BSE_LAUNCH_CHECK();
         if (ev) BSE_HIP(hipEventRecord(ev[0], st));
@@ -776,7 +784,8 @@ static void sph_forward_n(const SphereMaps &m, const T *Cr, const T *u, const cp
     }
     {
         const int n_lines = nq * m.ncol;
-        k_sph_fwd_z<T, N><<<div_up(n_lines, C), 256, FftTile<T, N>::lds, st>>>(
+        k_sph_fwd_z<T, N><<<div_up(n_lines, FftTile<T, N, FFT_ZC>::C), 256,
+                            FftTile<T, N, FFT_ZC>::lds, st>>>(
             T1, m.ent, m.col_ptr, m.ncol, n_lines, n_orb, m.npw, X, m.kin, kin_scale, Y, tw,
             n_occ);
         BSE_LAUNCH_CHECK();
@@ -790,7 +799,8 @@ static void grid_fft_n(cplx<T> *A, int nb, T sign, const cplx<T> *tw, hipStream_
     constexpr int n = N;
     constexpr int C = FftTile<T, N>::C;
     const int n_lines = nb * n * n;
-    k_grid_z<T, N><<<div_up(n_lines, C), 256, FftTile<T, N>::lds, st>>>(A, n_lines, tw, sign);
+    k_grid_z<T, N><<<div_up(n_lines, FftTile<T, N, FFT_ZC>::C), 256, FftTile<T, N, FFT_ZC>::lds,
+                     st>>>(A, n_lines, tw, sign);
     BSE_LAUNCH_CHECK();
     const int nzt = div_up(n, C);
     k_grid_y<T, N><<<(unsigned)nb * n * nzt, 256, FftTile<T, N>::lds, st>>>(A, tw, nzt, sign);
