@@ -48,6 +48,10 @@ struct FftTile {
 // room for more workgroups per CU to hide the latency of the sphere gathers.
 constexpr int FFT_ZC = 16;
 static_assert(FFT_ZC % 2 == 0, "z tiles hold column pairs");
+// Upper bounds on the lines per workgroup of the y and x passes, whose tile
+// width is the length of the contiguous runs they read and write.
+constexpr int FFT_YC = 64;
+constexpr int FFT_XC = 64;
 
 // Element loop of a staging pass: i = k * FFT_NT + threadIdx.x for every
 // i < TOTAL, with a compile-time trip count so that it unrolls and all of a
@@ -320,11 +324,11 @@ __global__ void __launch_bounds__(256) k_sph_inv_y(const cplx<T> *__restrict__ T
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
     constexpr int n = N;
-    constexpr int C = FftTile<T, N>::C;
-    constexpr int lc = FftTile<T, N>::lc;
+    constexpr int C = FftTile<T, N, FFT_YC>::C;
+    constexpr int lc = FftTile<T, N, FFT_YC>::lc;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
-    C2 *sb = sa + FftTile<T, N>::buf;
-    C2 *stw = sb + FftTile<T, N>::buf;
+    C2 *sb = sa + FftTile<T, N, FFT_YC>::buf;
+    C2 *stw = sb + FftTile<T, N, FFT_YC>::buf;
     int bid = blockIdx.x;
     const int zt = bid % nzt;
     bid /= nzt;
@@ -343,7 +347,7 @@ __global__ void __launch_bounds__(256) k_sph_inv_y(const cplx<T> *__restrict__ T
     }
     load_twiddles<T>(stw, tw, n);  // after the data loads: they overlap
     __syncthreads();
-    C2 *res = lds_fft<T, N>(sa, sb, stw, (T)1);
+    C2 *res = lds_fft<T, N, false, FFT_YC>(sa, sb, stw, (T)1);
     C2 *t2 = T2 + ((size_t)q * nxp + ix) * n * n;
     FFT_FOR(i, n * C) {
         const int y = i >> lc, c = i & (C - 1);
@@ -362,12 +366,12 @@ __global__ void __launch_bounds__(256) k_sph_inv_x(const cplx<T> *__restrict__ T
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
     constexpr int n = N;
-    constexpr int C = FftTile<T, N>::C;
-    constexpr int lc = FftTile<T, N>::lc;
+    constexpr int C = FftTile<T, N, FFT_XC>::C;
+    constexpr int lc = FftTile<T, N, FFT_XC>::lc;
     const int n2 = n * n;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
-    C2 *sb = sa + FftTile<T, N>::buf;
-    C2 *stw = sb + FftTile<T, N>::buf;
+    C2 *sb = sa + FftTile<T, N, FFT_XC>::buf;
+    C2 *stw = sb + FftTile<T, N, FFT_XC>::buf;
     const int t = blockIdx.x % nyzt;
     const int q = blockIdx.x / nyzt;
     const int yz0 = t * C;
@@ -381,7 +385,7 @@ __global__ void __launch_bounds__(256) k_sph_inv_x(const cplx<T> *__restrict__ T
     }
     load_twiddles<T>(stw, tw, n);  // after the data loads: they overlap
     __syncthreads();
-    C2 *res = lds_fft<T, N>(sa, sb, stw, (T)1);
+    C2 *res = lds_fft<T, N, false, FFT_XC>(sa, sb, stw, (T)1);
     const size_t nr = (size_t)n2 * n;
     int i1, i2;
     pair_of(q, ps, i1, i2);
@@ -414,13 +418,13 @@ __global__ void __launch_bounds__(256) k_sph_fwd_x(const T *__restrict__ Cr, con
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
     constexpr int n = N;
-    constexpr int C = FftTile<T, N>::C;
-    constexpr int lc = FftTile<T, N>::lc;
+    constexpr int C = FftTile<T, N, FFT_XC>::C;
+    constexpr int lc = FftTile<T, N, FFT_XC>::lc;
     const int n2 = n * n;
     const size_t nr = (size_t)n2 * n;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
-    C2 *sb = sa + FftTile<T, N>::buf;
-    C2 *stw = sb + FftTile<T, N>::buf;
+    C2 *sb = sa + FftTile<T, N, FFT_XC>::buf;
+    C2 *stw = sb + FftTile<T, N, FFT_XC>::buf;
     // q fastest: the orbital slots sharing one Hartree tile run back to back
     const int nq = gridDim.x / nyzt;
     const int q = blockIdx.x % nq;
@@ -448,7 +452,7 @@ __global__ void __launch_bounds__(256) k_sph_fwd_x(const T *__restrict__ Cr, con
     }
     load_twiddles<T>(stw, tw, n);  // after the data loads: they overlap
     __syncthreads();
-    C2 *res = lds_fft<T, N>(sa, sb, stw, (T)-1);
+    C2 *res = lds_fft<T, N, false, FFT_XC>(sa, sb, stw, (T)-1);
     C2 *t2 = T2 + (size_t)q * nxp * n2;
     for (int i = threadIdx.x; i < nxp * C; i += FFT_NT) {
         const int ix = i >> lc, c = i & (C - 1);
@@ -467,11 +471,11 @@ __global__ void __launch_bounds__(256) k_sph_fwd_y(const cplx<T> *__restrict__ T
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
     constexpr int n = N;
-    constexpr int C = FftTile<T, N>::C;
-    constexpr int lc = FftTile<T, N>::lc;
+    constexpr int C = FftTile<T, N, FFT_YC>::C;
+    constexpr int lc = FftTile<T, N, FFT_YC>::lc;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
-    C2 *sb = sa + FftTile<T, N>::buf;
-    C2 *stw = sb + FftTile<T, N>::buf;
+    C2 *sb = sa + FftTile<T, N, FFT_YC>::buf;
+    C2 *stw = sb + FftTile<T, N, FFT_YC>::buf;
     int bid = blockIdx.x;
     const int zt = bid % nzt;
     bid /= nzt;
@@ -488,7 +492,7 @@ __global__ void __launch_bounds__(256) k_sph_fwd_y(const cplx<T> *__restrict__ T
     }
     load_twiddles<T>(stw, tw, n);  // after the data loads: they overlap
     __syncthreads();
-    C2 *res = lds_fft<T, N>(sa, sb, stw, (T)-1);
+    C2 *res = lds_fft<T, N, false, FFT_YC>(sa, sb, stw, (T)-1);
     C2 *t1 = T1 + (size_t)q * ncol * n;
     FFT_FOR(i, n * C) {
         const int y = i >> lc, c = i & (C - 1);
@@ -642,11 +646,11 @@ __global__ void __launch_bounds__(256) k_grid_y(cplx<T> *__restrict__ A,
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
     constexpr int n = N;
-    constexpr int C = FftTile<T, N>::C;
-    constexpr int lc = FftTile<T, N>::lc;
+    constexpr int C = FftTile<T, N, FFT_YC>::C;
+    constexpr int lc = FftTile<T, N, FFT_YC>::lc;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
-    C2 *sb = sa + FftTile<T, N>::buf;
-    C2 *stw = sb + FftTile<T, N>::buf;
+    C2 *sb = sa + FftTile<T, N, FFT_YC>::buf;
+    C2 *stw = sb + FftTile<T, N, FFT_YC>::buf;
     const int zt = blockIdx.x % nzt;
     const int bx = blockIdx.x / nzt;  // b * n + x
     const int z0 = zt * C;
@@ -659,7 +663,7 @@ __global__ void __launch_bounds__(256) k_grid_y(cplx<T> *__restrict__ A,
     }
     load_twiddles<T>(stw, tw, n);  // after the data loads: they overlap
     __syncthreads();
-    C2 *res = lds_fft<T, N>(sa, sb, stw, sign);
+    C2 *res = lds_fft<T, N, false, FFT_YC>(sa, sb, stw, sign);
     FFT_FOR(i, n * C) {
         const int y = i >> lc, c = i & (C - 1);
         const int z = z0 + c;
@@ -675,12 +679,12 @@ __global__ void __launch_bounds__(256) k_grid_x(cplx<T> *__restrict__ A,
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
     constexpr int n = N;
-    constexpr int C = FftTile<T, N>::C;
-    constexpr int lc = FftTile<T, N>::lc;
+    constexpr int C = FftTile<T, N, FFT_XC>::C;
+    constexpr int lc = FftTile<T, N, FFT_XC>::lc;
     const int n2 = n * n;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
-    C2 *sb = sa + FftTile<T, N>::buf;
-    C2 *stw = sb + FftTile<T, N>::buf;
+    C2 *sb = sa + FftTile<T, N, FFT_XC>::buf;
+    C2 *stw = sb + FftTile<T, N, FFT_XC>::buf;
     const int t = blockIdx.x % nyzt;
     const int b = blockIdx.x / nyzt;
     const int yz0 = t * C;
@@ -693,7 +697,7 @@ __global__ void __launch_bounds__(256) k_grid_x(cplx<T> *__restrict__ A,
     }
     load_twiddles<T>(stw, tw, n);  // after the data loads: they overlap
     __syncthreads();
-    C2 *res = lds_fft<T, N>(sa, sb, stw, sign);
+    C2 *res = lds_fft<T, N, false, FFT_XC>(sa, sb, stw, sign);
     FFT_FOR(i, n * C) {
         const int x = i >> lc, c = i & (C - 1);
         const int yz = yz0 + c;
@@ -734,8 +738,6 @@ static void sph_inverse_n(const SphereMaps &m, const T *X, int n_orb, T *out, cp
     using C2 = cplx<T>;
     constexpr int n = N;
     const int nq = n_lines_for(n_orb, ps);
-    constexpr int C = FftTile<T, N>::C;  // even, so a column and its mirror share a tile
-    static_assert(C == FftTile<T, N>::C && C % 2 == 0, "tile width");
     {
         const int n_lines = nq * m.ncol;
         k_sph_inv_z<T, N><<<div_up(n_lines, FftTile<T, N, FFT_ZC>::C), 256,
@@ -745,15 +747,17 @@ static void sph_inverse_n(const SphereMaps &m, const T *X, int n_orb, T *out, cp
         if (ev) BSE_HIP(hipEventRecord(ev[0], st));
     }
     {
-        const int nzt = div_up(n, C);
-        k_sph_inv_y<T, N><<<(unsigned)nq * m.nxp * nzt, 256, FftTile<T, N>::lds, st>>>(
+        using F = FftTile<T, N, FFT_YC>;
+        const int nzt = div_up(n, F::C);
+        k_sph_inv_y<T, N><<<(unsigned)nq * m.nxp * nzt, 256, F::lds, st>>>(
             T1, m.colmap, m.xlist, m.nxp, m.ncol, T2, tw, nzt);
         BSE_LAUNCH_CHECK();
         if (ev) BSE_HIP(hipEventRecord(ev[1], st));
     }
     {
-        const int nyzt = div_up((size_t)n * n, C);
-        k_sph_inv_x<T, N><<<(unsigned)nq * nyzt, 256, FftTile<T, N>::lds, st>>>(
+        using F = FftTile<T, N, FFT_XC>;
+        const int nyzt = div_up((size_t)n * n, F::C);
+        k_sph_inv_x<T, N><<<(unsigned)nq * nyzt, 256, F::lds, st>>>(
             T2, m.xinv, m.nxp, n_orb, out, tw, nyzt, ps);
         BSE_LAUNCH_CHECK();
         if (ev) BSE_HIP(hipEventRecord(ev[2], st));
@@ -767,17 +771,18 @@ static void sph_forward_n(const SphereMaps &m, const T *Cr, const T *u, const cp
     using C2 = cplx<T>;
     constexpr int n = N;
     const int nq = n_lines_for(n_orb, n_occ);
-    constexpr int C = FftTile<T, N>::C;
     {
-        const int nyzt = div_up((size_t)n * n, C);
-        k_sph_fwd_x<T, N><<<(unsigned)nq * nyzt, 256, FftTile<T, N>::lds, st>>>(
+        using F = FftTile<T, N, FFT_XC>;
+        const int nyzt = div_up((size_t)n * n, F::C);
+        k_sph_fwd_x<T, N><<<(unsigned)nq * nyzt, 256, F::lds, st>>>(
             Cr, u, vH, k1e, n_orb, n_occ, m.xlist, m.nxp, T2, tw, nyzt);
         BSE_LAUNCH_CHECK();
         if (ev) BSE_HIP(hipEventRecord(ev[0], st));
     }
     {
-        const int nzt = div_up(n, C);
-        k_sph_fwd_y<T, N><<<(unsigned)nq * m.nxp * nzt, 256, FftTile<T, N>::lds, st>>>(
+        using F = FftTile<T, N, FFT_YC>;
+        const int nzt = div_up(n, F::C);
+        k_sph_fwd_y<T, N><<<(unsigned)nq * m.nxp * nzt, 256, F::lds, st>>>(
             T2, m.colmap, m.xlist, m.nxp, m.ncol, T1, tw, nzt);
         BSE_LAUNCH_CHECK();
         if (ev) BSE_HIP(hipEventRecord(ev[1], st));
@@ -797,16 +802,17 @@ template <typename T, int N>
 static void grid_fft_n(cplx<T> *A, int nb, T sign, const cplx<T> *tw, hipStream_t st) {
     using C2 = cplx<T>;
     constexpr int n = N;
-    constexpr int C = FftTile<T, N>::C;
     const int n_lines = nb * n * n;
     k_grid_z<T, N><<<div_up(n_lines, FftTile<T, N, FFT_ZC>::C), 256, FftTile<T, N, FFT_ZC>::lds,
                      st>>>(A, n_lines, tw, sign);
     BSE_LAUNCH_CHECK();
-    const int nzt = div_up(n, C);
-    k_grid_y<T, N><<<(unsigned)nb * n * nzt, 256, FftTile<T, N>::lds, st>>>(A, tw, nzt, sign);
+    using FY = FftTile<T, N, FFT_YC>;
+    const int nzt = div_up(n, FY::C);
+    k_grid_y<T, N><<<(unsigned)nb * n * nzt, 256, FY::lds, st>>>(A, tw, nzt, sign);
     BSE_LAUNCH_CHECK();
-    const int nyzt = div_up((size_t)n * n, C);
-    k_grid_x<T, N><<<(unsigned)nb * nyzt, 256, FftTile<T, N>::lds, st>>>(A, tw, nyzt, sign);
+    using FX = FftTile<T, N, FFT_XC>;
+    const int nyzt = div_up((size_t)n * n, FX::C);
+    k_grid_x<T, N><<<(unsigned)nb * nyzt, 256, FX::lds, st>>>(A, tw, nyzt, sign);
     BSE_LAUNCH_CHECK();
 }
 
