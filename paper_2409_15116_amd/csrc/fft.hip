@@ -26,12 +26,12 @@ constexpr int FFT_NT = 256;
 // global side runs along the lines, use e * (C + 1) + c for the data they
 // stage in and out, so that the 64 lanes of a wave, which walk e there,
 // fall on different LDS banks.
-template <typename T, int N, int CMAX = 64>
+template <typename T, int N, int CMAX = 64, int LDS_KB = 64>
 struct FftTile {
     static constexpr size_t esz = 2 * sizeof(T);
     static constexpr int pick() {
         int c = CMAX;
-        while (c > 2 && (size_t)(2 * N * (c + 1) + N) * esz > 64 * 1024) c /= 2;
+        while (c > 2 && (size_t)(2 * N * (c + 1) + N) * esz > (size_t)LDS_KB * 1024) c /= 2;
         return c;
     }
     static constexpr int C = pick();
@@ -52,6 +52,9 @@ static_assert(FFT_ZC % 2 == 0, "z tiles hold column pairs");
 // width is the length of the contiguous runs they read and write.
 constexpr int FFT_YC = 64;
 constexpr int FFT_XC = 64;
+// LDS budget (KB) of the y and x tiles
+constexpr int FFT_YKB = 64;
+constexpr int FFT_XKB = 64;
 
 // Element loop of a staging pass: i = k * FFT_NT + threadIdx.x for every
 // i < TOTAL, with a compile-time trip count so that it unrolls and all of a
@@ -196,9 +199,9 @@ __device__ __forceinline__ cplx<T> *fft_stages(cplx<T> *a, cplx<T> *b, const cpl
 // b is scratch of the same size.  Input and result at e * C + c, or at
 // e * (C + 1) + c with PAD.  sign = -1 forward, +1 inverse (unnormalised).
 // Returns the buffer holding the result.  Ends with a barrier.
-template <typename T, int N, bool PAD = false, int CMAX = 64>
+template <typename T, int N, bool PAD = false, int CMAX = 64, int LDS_KB = 64>
 __device__ __forceinline__ cplx<T> *lds_fft(cplx<T> *a, cplx<T> *b, const cplx<T> *tw, T sign) {
-    using F = FftTile<T, N, CMAX>;
+    using F = FftTile<T, N, CMAX, LDS_KB>;
     return fft_stages<T, N, 0, 1, F::lc, PAD ? F::CP : F::C>(a, b, tw, sign);
 }
 
@@ -324,11 +327,11 @@ __global__ void __launch_bounds__(256) k_sph_inv_y(const cplx<T> *__restrict__ T
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
     constexpr int n = N;
-    constexpr int C = FftTile<T, N, FFT_YC>::C;
-    constexpr int lc = FftTile<T, N, FFT_YC>::lc;
+    constexpr int C = FftTile<T, N, FFT_YC, FFT_YKB>::C;
+    constexpr int lc = FftTile<T, N, FFT_YC, FFT_YKB>::lc;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
-    C2 *sb = sa + FftTile<T, N, FFT_YC>::buf;
-    C2 *stw = sb + FftTile<T, N, FFT_YC>::buf;
+    C2 *sb = sa + FftTile<T, N, FFT_YC, FFT_YKB>::buf;
+    C2 *stw = sb + FftTile<T, N, FFT_YC, FFT_YKB>::buf;
     int bid = blockIdx.x;
     const int zt = bid % nzt;
     bid /= nzt;
@@ -347,7 +350,7 @@ __global__ void __launch_bounds__(256) k_sph_inv_y(const cplx<T> *__restrict__ T
     }
     load_twiddles<T>(stw, tw, n);  // after the data loads: they overlap
     __syncthreads();
-    C2 *res = lds_fft<T, N, false, FFT_YC>(sa, sb, stw, (T)1);
+    C2 *res = lds_fft<T, N, false, FFT_YC, FFT_YKB>(sa, sb, stw, (T)1);
     C2 *t2 = T2 + ((size_t)q * nxp + ix) * n * n;
     FFT_FOR(i, n * C) {
         const int y = i >> lc, c = i & (C - 1);
@@ -366,12 +369,12 @@ __global__ void __launch_bounds__(256) k_sph_inv_x(const cplx<T> *__restrict__ T
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
     constexpr int n = N;
-    constexpr int C = FftTile<T, N, FFT_XC>::C;
-    constexpr int lc = FftTile<T, N, FFT_XC>::lc;
+    constexpr int C = FftTile<T, N, FFT_XC, FFT_XKB>::C;
+    constexpr int lc = FftTile<T, N, FFT_XC, FFT_XKB>::lc;
     const int n2 = n * n;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
-    C2 *sb = sa + FftTile<T, N, FFT_XC>::buf;
-    C2 *stw = sb + FftTile<T, N, FFT_XC>::buf;
+    C2 *sb = sa + FftTile<T, N, FFT_XC, FFT_XKB>::buf;
+    C2 *stw = sb + FftTile<T, N, FFT_XC, FFT_XKB>::buf;
     const int t = blockIdx.x % nyzt;
     const int q = blockIdx.x / nyzt;
     const int yz0 = t * C;
@@ -385,7 +388,7 @@ __global__ void __launch_bounds__(256) k_sph_inv_x(const cplx<T> *__restrict__ T
     }
     load_twiddles<T>(stw, tw, n);  // after the data loads: they overlap
     __syncthreads();
-    C2 *res = lds_fft<T, N, false, FFT_XC>(sa, sb, stw, (T)1);
+    C2 *res = lds_fft<T, N, false, FFT_XC, FFT_XKB>(sa, sb, stw, (T)1);
     const size_t nr = (size_t)n2 * n;
     int i1, i2;
     pair_of(q, ps, i1, i2);
@@ -418,13 +421,13 @@ __global__ void __launch_bounds__(256) k_sph_fwd_x(const T *__restrict__ Cr, con
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
     constexpr int n = N;
-    constexpr int C = FftTile<T, N, FFT_XC>::C;
-    constexpr int lc = FftTile<T, N, FFT_XC>::lc;
+    constexpr int C = FftTile<T, N, FFT_XC, FFT_XKB>::C;
+    constexpr int lc = FftTile<T, N, FFT_XC, FFT_XKB>::lc;
     const int n2 = n * n;
     const size_t nr = (size_t)n2 * n;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
-    C2 *sb = sa + FftTile<T, N, FFT_XC>::buf;
-    C2 *stw = sb + FftTile<T, N, FFT_XC>::buf;
+    C2 *sb = sa + FftTile<T, N, FFT_XC, FFT_XKB>::buf;
+    C2 *stw = sb + FftTile<T, N, FFT_XC, FFT_XKB>::buf;
     // q fastest: the orbital slots sharing one Hartree tile run back to back
     const int nq = gridDim.x / nyzt;
     const int q = blockIdx.x % nq;
@@ -452,7 +455,7 @@ __global__ void __launch_bounds__(256) k_sph_fwd_x(const T *__restrict__ Cr, con
     }
     load_twiddles<T>(stw, tw, n);  // after the data loads: they overlap
     __syncthreads();
-    C2 *res = lds_fft<T, N, false, FFT_XC>(sa, sb, stw, (T)-1);
+    C2 *res = lds_fft<T, N, false, FFT_XC, FFT_XKB>(sa, sb, stw, (T)-1);
     C2 *t2 = T2 + (size_t)q * nxp * n2;
     for (int i = threadIdx.x; i < nxp * C; i += FFT_NT) {
         const int ix = i >> lc, c = i & (C - 1);
@@ -471,11 +474,11 @@ __global__ void __launch_bounds__(256) k_sph_fwd_y(const cplx<T> *__restrict__ T
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
     constexpr int n = N;
-    constexpr int C = FftTile<T, N, FFT_YC>::C;
-    constexpr int lc = FftTile<T, N, FFT_YC>::lc;
+    constexpr int C = FftTile<T, N, FFT_YC, FFT_YKB>::C;
+    constexpr int lc = FftTile<T, N, FFT_YC, FFT_YKB>::lc;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
-    C2 *sb = sa + FftTile<T, N, FFT_YC>::buf;
-    C2 *stw = sb + FftTile<T, N, FFT_YC>::buf;
+    C2 *sb = sa + FftTile<T, N, FFT_YC, FFT_YKB>::buf;
+    C2 *stw = sb + FftTile<T, N, FFT_YC, FFT_YKB>::buf;
     int bid = blockIdx.x;
     const int zt = bid % nzt;
     bid /= nzt;
@@ -492,7 +495,7 @@ __global__ void __launch_bounds__(256) k_sph_fwd_y(const cplx<T> *__restrict__ T
     }
     load_twiddles<T>(stw, tw, n);  // after the data loads: they overlap
     __syncthreads();
-    C2 *res = lds_fft<T, N, false, FFT_YC>(sa, sb, stw, (T)-1);
+    C2 *res = lds_fft<T, N, false, FFT_YC, FFT_YKB>(sa, sb, stw, (T)-1);
     C2 *t1 = T1 + (size_t)q * ncol * n;
     FFT_FOR(i, n * C) {
         const int y = i >> lc, c = i & (C - 1);
@@ -646,11 +649,11 @@ __global__ void __launch_bounds__(256) k_grid_y(cplx<T> *__restrict__ A,
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
     constexpr int n = N;
-    constexpr int C = FftTile<T, N, FFT_YC>::C;
-    constexpr int lc = FftTile<T, N, FFT_YC>::lc;
+    constexpr int C = FftTile<T, N, FFT_YC, FFT_YKB>::C;
+    constexpr int lc = FftTile<T, N, FFT_YC, FFT_YKB>::lc;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
-    C2 *sb = sa + FftTile<T, N, FFT_YC>::buf;
-    C2 *stw = sb + FftTile<T, N, FFT_YC>::buf;
+    C2 *sb = sa + FftTile<T, N, FFT_YC, FFT_YKB>::buf;
+    C2 *stw = sb + FftTile<T, N, FFT_YC, FFT_YKB>::buf;
     const int zt = blockIdx.x % nzt;
     const int bx = blockIdx.x / nzt;  // b * n + x
     const int z0 = zt * C;
@@ -663,7 +666,7 @@ __global__ void __launch_bounds__(256) k_grid_y(cplx<T> *__restrict__ A,
     }
     load_twiddles<T>(stw, tw, n);  // after the data loads: they overlap
     __syncthreads();
-    C2 *res = lds_fft<T, N, false, FFT_YC>(sa, sb, stw, sign);
+    C2 *res = lds_fft<T, N, false, FFT_YC, FFT_YKB>(sa, sb, stw, sign);
     FFT_FOR(i, n * C) {
         const int y = i >> lc, c = i & (C - 1);
         const int z = z0 + c;
@@ -679,12 +682,12 @@ __global__ void __launch_bounds__(256) k_grid_x(cplx<T> *__restrict__ A,
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
     constexpr int n = N;
-    constexpr int C = FftTile<T, N, FFT_XC>::C;
-    constexpr int lc = FftTile<T, N, FFT_XC>::lc;
+    constexpr int C = FftTile<T, N, FFT_XC, FFT_XKB>::C;
+    constexpr int lc = FftTile<T, N, FFT_XC, FFT_XKB>::lc;
     const int n2 = n * n;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
-    C2 *sb = sa + FftTile<T, N, FFT_XC>::buf;
-    C2 *stw = sb + FftTile<T, N, FFT_XC>::buf;
+    C2 *sb = sa + FftTile<T, N, FFT_XC, FFT_XKB>::buf;
+    C2 *stw = sb + FftTile<T, N, FFT_XC, FFT_XKB>::buf;
     const int t = blockIdx.x % nyzt;
     const int b = blockIdx.x / nyzt;
     const int yz0 = t * C;
@@ -697,7 +700,7 @@ __global__ void __launch_bounds__(256) k_grid_x(cplx<T> *__restrict__ A,
     }
     load_twiddles<T>(stw, tw, n);  // after the data loads: they overlap
     __syncthreads();
-    C2 *res = lds_fft<T, N, false, FFT_XC>(sa, sb, stw, sign);
+    C2 *res = lds_fft<T, N, false, FFT_XC, FFT_XKB>(sa, sb, stw, sign);
     FFT_FOR(i, n * C) {
         const int x = i >> lc, c = i & (C - 1);
         const int yz = yz0 + c;
@@ -747,7 +750,7 @@ static void sph_inverse_n(const SphereMaps &m, const T *X, int n_orb, T *out, cp
         if (ev) BSE_HIP(hipEventRecord(ev[0], st));
     }
     {
-        using F = FftTile<T, N, FFT_YC>;
+        using F = FftTile<T, N, FFT_YC, FFT_YKB>;
         const int nzt = div_up(n, F::C);
         k_sph_inv_y<T, N><<<(unsigned)nq * m.nxp * nzt, 256, F::lds, st>>>(
             T1, m.colmap, m.xlist, m.nxp, m.ncol, T2, tw, nzt);
@@ -755,7 +758,7 @@ static void sph_inverse_n(const SphereMaps &m, const T *X, int n_orb, T *out, cp
         if (ev) BSE_HIP(hipEventRecord(ev[1], st));
     }
     {
-        using F = FftTile<T, N, FFT_XC>;
+        using F = FftTile<T, N, FFT_XC, FFT_XKB>;
         const int nyzt = div_up((size_t)n * n, F::C);
         k_sph_inv_x<T, N><<<(unsigned)nq * nyzt, 256, F::lds, st>>>(
             T2, m.xinv, m.nxp, n_orb, out, tw, nyzt, ps);
@@ -772,7 +775,7 @@ static void sph_forward_n(const SphereMaps &m, const T *Cr, const T *u, const cp
     constexpr int n = N;
     const int nq = n_lines_for(n_orb, n_occ);
     {
-        using F = FftTile<T, N, FFT_XC>;
+        using F = FftTile<T, N, FFT_XC, FFT_XKB>;
         const int nyzt = div_up((size_t)n * n, F::C);
         k_sph_fwd_x<T, N><<<(unsigned)nq * nyzt, 256, F::lds, st>>>(
             Cr, u, vH, k1e, n_orb, n_occ, m.xlist, m.nxp, T2, tw, nyzt);
@@ -780,7 +783,7 @@ static void sph_forward_n(const SphereMaps &m, const T *Cr, const T *u, const cp
         if (ev) BSE_HIP(hipEventRecord(ev[0], st));
     }
     {
-        using F = FftTile<T, N, FFT_YC>;
+        using F = FftTile<T, N, FFT_YC, FFT_YKB>;
         const int nzt = div_up(n, F::C);
         k_sph_fwd_y<T, N><<<(unsigned)nq * m.nxp * nzt, 256, F::lds, st>>>(
             T2, m.colmap, m.xlist, m.nxp, m.ncol, T1, tw, nzt);
@@ -806,11 +809,11 @@ static void grid_fft_n(cplx<T> *A, int nb, T sign, const cplx<T> *tw, hipStream_
     k_grid_z<T, N><<<div_up(n_lines, FftTile<T, N, FFT_ZC>::C), 256, FftTile<T, N, FFT_ZC>::lds,
                      st>>>(A, n_lines, tw, sign);
     BSE_LAUNCH_CHECK();
-    using FY = FftTile<T, N, FFT_YC>;
+    using FY = FftTile<T, N, FFT_YC, FFT_YKB>;
     const int nzt = div_up(n, FY::C);
     k_grid_y<T, N><<<(unsigned)nb * n * nzt, 256, FY::lds, st>>>(A, tw, nzt, sign);
     BSE_LAUNCH_CHECK();
-    using FX = FftTile<T, N, FFT_XC>;
+    using FX = FftTile<T, N, FFT_XC, FFT_XKB>;
     const int nyzt = div_up((size_t)n * n, FX::C);
     k_grid_x<T, N><<<(unsigned)nb * nyzt, 256, FX::lds, st>>>(A, tw, nyzt, sign);
     BSE_LAUNCH_CHECK();
