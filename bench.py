@@ -42,7 +42,8 @@ def log(*a):
 # kept as a text summary; it is reported only for the workload it was taken
 # on and while the kernel's sources are the ones that were measured.
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k1d_c2_lit_fp32_b16_hbm.md")
-K1D_SOURCES = ["paper_2409_15116_amd/csrc/k1d.hip", "paper_2409_15116_amd/csrc/kernels.hpp"]
+K1D_SOURCES = ["paper_2409_15116_amd/csrc/k1d.hip", "paper_2409_15116_amd/csrc/kernels.hpp",
+               "paper_2409_15116_amd/csrc/ctx.hip"]
 
 
 def sources_sha256(paths):
