@@ -7,14 +7,18 @@
 
 namespace bse {
 
-constexpr int BM = 64, BN = 64, BK = 16;
+// Tiles of BM x BN outputs (16, 32 or 64 each, chosen per call from M and N
+// so that skinny products do not compute padding), BK = 16 deep; 256
+// threads, thread (tm, tn) owns outputs (tm + 16 i, tn + 16 j).
+constexpr int BK = 16;
 
-template <typename T, bool NT>
+template <typename T, bool NT, int BM, int BN>
 __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, T alpha, const T *__restrict__ A,
                                               long long lda, long long sA, const T *__restrict__ Bm,
                                               long long ldb, long long sB, T beta, T *__restrict__ C,
                                               long long ldc, long long sC, int kchunk,
                                               int nsplit) {
+    constexpr int TM = BM / 16, TN = BN / 16;
     __shared__ T As[BK][BM + 1];
     __shared__ T Bs[BK][BN + 1];
     const int bz = blockIdx.z;
@@ -29,15 +33,15 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, T alpha, cons
     const int kend = min(K, kbeg + kchunk);
     const int tid = threadIdx.x;
     const int tm = tid >> 4, tn = tid & 15;
-    T acc[4][4];
+    T acc[TM][TN];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0;
+        for (int j = 0; j < TN; ++j) acc[i][j] = 0;
     for (int k0 = kbeg; k0 < kend; k0 += BK) {
-        // A tile: 64 x 16, k fastest
+        // A tile: BM x 16, k fastest
 #pragma unroll
-        for (int l = 0; l < 4; ++l) {
+        for (int l = 0; l < TM; ++l) {
             const int idx = tid + l * 256;
             const int mm = idx >> 4, kk = idx & 15;
             const int gm = m0 + mm, gk = k0 + kk;
@@ -45,7 +49,7 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, T alpha, cons
         }
         if (NT) {
 #pragma unroll
-            for (int l = 0; l < 4; ++l) {
+            for (int l = 0; l < TN; ++l) {
                 const int idx = tid + l * 256;
                 const int nn = idx >> 4, kk = idx & 15;
                 const int gn = n0 + nn, gk = k0 + kk;
@@ -53,9 +57,9 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, T alpha, cons
             }
         } else {
 #pragma unroll
-            for (int l = 0; l < 4; ++l) {
+            for (int l = 0; l < TN; ++l) {
                 const int idx = tid + l * 256;
-                const int kk = idx >> 6, nn = idx & 63;
+                const int kk = idx / BN, nn = idx % BN;
                 const int gn = n0 + nn, gk = k0 + kk;
                 Bs[kk][nn] = (gn < N && gk < kend) ? Bm[(size_t)gk * ldb + gn] : (T)0;
             }
@@ -63,24 +67,24 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, T alpha, cons
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < BK; ++kk) {
-            T a[4], b[4];
+            T a[TM], b[TN];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[kk][tm + 16 * i];
+            for (int i = 0; i < TM; ++i) a[i] = As[kk][tm + 16 * i];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tn + 16 * j];
+            for (int j = 0; j < TN; ++j) b[j] = Bs[kk][tn + 16 * j];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < TM; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+                for (int j = 0; j < TN; ++j) acc[i][j] += a[i] * b[j];
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < TM; ++i) {
         const int gm = m0 + tm + 16 * i;
         if (gm >= M) continue;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < TN; ++j) {
             const int gn = n0 + tn + 16 * j;
             if (gn >= N) continue;
             T *c = C + (size_t)gm * ldc + gn;
@@ -138,11 +142,12 @@ __global__ void k_splitk_reduce(const T *__restrict__ part, int nsplit, int M, i
     *c = beta == (T)0 ? alpha * s : alpha * s + beta * *c;
 }
 
-template <typename T>
-void gemm(bool nt, int M, int N, int K, T alpha, const T *A, long long lda, long long sA,
-          const T *B, long long ldb, long long sB, T beta, T *C, long long ldc, long long sC,
-          int batch, Workspace &ws, hipStream_t st) {
-    if (M <= 0 || N <= 0 || batch <= 0) return;
+static int tile_for(int n) { return n <= 16 ? 16 : n <= 32 ? 32 : 64; }
+
+template <typename T, int BM, int BN>
+static void gemm_t(bool nt, int M, int N, int K, T alpha, const T *A, long long lda, long long sA,
+                   const T *B, long long ldb, long long sB, T beta, T *C, long long ldc,
+                   long long sC, int batch, Workspace &ws, hipStream_t st) {
     const int tiles = div_up(M, BM) * div_up(N, BN) * batch;
     int nsplit = 1;
     if (K > 4 * BK && tiles < 512) {
@@ -154,11 +159,11 @@ void gemm(bool nt, int M, int N, int K, T alpha, const T *A, long long lda, long
     dim3 grid(div_up(N, BN), div_up(M, BM), batch * nsplit);
     if (nsplit == 1) {
         if (nt)
-            k_gemm<T, true><<<grid, 256, 0, st>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C,
-                                                  ldc, sC, kchunk, 1);
+            k_gemm<T, true, BM, BN><<<grid, 256, 0, st>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB,
+                                                          beta, C, ldc, sC, kchunk, 1);
         else
-            k_gemm<T, false><<<grid, 256, 0, st>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C,
-                                                   ldc, sC, kchunk, 1);
+            k_gemm<T, false, BM, BN><<<grid, 256, 0, st>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB,
+                                                           beta, C, ldc, sC, kchunk, 1);
         BSE_LAUNCH_CHECK();
         return;
     }
@@ -167,11 +172,11 @@ void gemm(bool nt, int M, int N, int K, T alpha, const T *A, long long lda, long
     T *part = (T *)ws.get(mn * (size_t)(nsplit + ngroup) * batch * sizeof(T));
     T *gsum = part + mn * (size_t)nsplit * batch;
     if (nt)
-        k_gemm<T, true><<<grid, 256, 0, st>>>(M, N, K, (T)1, A, lda, sA, B, ldb, sB, (T)0, part, N,
-                                              0, kchunk, nsplit);
+        k_gemm<T, true, BM, BN><<<grid, 256, 0, st>>>(M, N, K, (T)1, A, lda, sA, B, ldb, sB, (T)0,
+                                                      part, N, 0, kchunk, nsplit);
     else
-        k_gemm<T, false><<<grid, 256, 0, st>>>(M, N, K, (T)1, A, lda, sA, B, ldb, sB, (T)0, part,
-                                               N, 0, kchunk, nsplit);
+        k_gemm<T, false, BM, BN><<<grid, 256, 0, st>>>(M, N, K, (T)1, A, lda, sA, B, ldb, sB,
+                                                       (T)0, part, N, 0, kchunk, nsplit);
     BSE_LAUNCH_CHECK();
     const long long tot = (long long)mn * batch;
     if (ngroup > 0) {
@@ -185,6 +190,27 @@ void gemm(bool nt, int M, int N, int K, T alpha, const T *A, long long lda, long
                                                              ldc, sC, batch);
     }
     BSE_LAUNCH_CHECK();
+}
+
+template <typename T>
+void gemm(bool nt, int M, int N, int K, T alpha, const T *A, long long lda, long long sA,
+          const T *B, long long ldb, long long sB, T beta, T *C, long long ldc, long long sC,
+          int batch, Workspace &ws, hipStream_t st) {
+    if (M <= 0 || N <= 0 || batch <= 0) return;
+#define BSE_GEMM_TILE(BM_, BN_)                                                               \
+    if (tile_for(M) == BM_ && tile_for(N) == BN_)                                            \
+        return gemm_t<T, BM_, BN_>(nt, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, \
+                                   batch, ws, st);
+    BSE_GEMM_TILE(16, 16)
+    BSE_GEMM_TILE(16, 32)
+    BSE_GEMM_TILE(16, 64)
+    BSE_GEMM_TILE(32, 16)
+    BSE_GEMM_TILE(32, 32)
+    BSE_GEMM_TILE(32, 64)
+    BSE_GEMM_TILE(64, 16)
+    BSE_GEMM_TILE(64, 32)
+    BSE_GEMM_TILE(64, 64)
+#undef BSE_GEMM_TILE
 }
 
 template void gemm<float>(bool, int, int, int, float, const float *, long long, long long,

@@ -108,18 +108,26 @@ def test_batch_eager_matches_graph(batch_cells):
         b.close()
 
 
+# Residual tolerance a Davidson run can reach: an FP32 apply adds about
+# 6e-8 relative noise times the operator norm (several Ha at these cut-offs)
+# to every applied vector, so FP32 runs stop at 1e-6 (eigenvalues still far
+# inside 1 meV), FP64 runs at 1e-7.
+DAV_TOL = {0: 1e-7, 1: 1e-6}
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_batch_davidson_matches_single(batch_cells, prec):
     say("batch davidson", prec)
     pkg = _pkg()
     st, cells, ctxs = batch_cells
     n_eig, B = 2, 4
+    tol = DAV_TOL[prec]
     with torch.cuda.stream(st):
         b = pkg.BseBatch(ctxs, st)
         X0 = [_dev(trial_block(c, B, seed=4321)) for c in cells]
-        oms, Xs, sts = b.davidson(X0, n_eig, block=B, tol=1e-7, max_iter=300, precision=prec)
+        oms, Xs, sts = b.davidson(X0, n_eig, block=B, tol=tol, max_iter=300, precision=prec)
         for c, ctx, x0, om, s in zip(cells, ctxs, X0, oms, sts):
-            om1, X1, s1 = ctx.davidson(x0, n_eig, block=B, tol=1e-7, max_iter=300,
+            om1, X1, s1 = ctx.davidson(x0, n_eig, block=B, tol=tol, max_iter=300,
                                        precision=prec)
             say(c.spec.name, "iterations batch", s["iterations"], "alone", s1["iterations"])
             assert s["iterations"] == s1["iterations"]
@@ -136,7 +144,7 @@ def test_batch_davidson_against_oracle(batch_cells):
     with torch.cuda.stream(st):
         b = pkg.BseBatch(ctxs, st)
         X0 = [_dev(trial_block(c, g["block"], seed=g["start_seed"])) for c in cells]
-        oms, _, _ = b.davidson(X0, g["n_eig"], block=g["block"], tol=1e-7, max_iter=400,
+        oms, _, _ = b.davidson(X0, g["n_eig"], block=g["block"], tol=DAV_TOL[1], max_iter=400,
                                precision=pkg.FP32)
         b.close()
     om = oms[BATCH.index("c1")]

@@ -71,7 +71,9 @@ def test_sphere_to_grid(name, prec):
 
 @pytest.mark.parametrize("nt", [0, 1])
 @pytest.mark.parametrize("prec", [0, 1, 2])
-@pytest.mark.parametrize("shape", [(16, 16, 16), (70, 45, 1000), (200, 130, 33)])
+# tile shapes 16/32/64 on each side, split-K (long K) and plain
+@pytest.mark.parametrize("shape", [(16, 16, 16), (70, 45, 1000), (200, 130, 33), (20, 40, 3000),
+                                   (64, 16, 50000), (16, 300, 64), (33, 17, 500)])
 def test_gemm(nt, prec, shape):
     say("gemm", nt, prec, shape)
     pkg = _pkg()
