@@ -38,33 +38,46 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, T alpha, cons
     for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = 0;
-    for (int k0 = kbeg; k0 < kend; k0 += BK) {
-        // A tile: BM x 16, k fastest
+    // the next k-step's tiles are loaded into registers while the current
+    // one is multiplied from LDS
+    T ra[TM], rb[TN];
+    auto fetch = [&](int k0) {
 #pragma unroll
-        for (int l = 0; l < TM; ++l) {
+        for (int l = 0; l < TM; ++l) {  // A tile: BM x 16, k fastest
             const int idx = tid + l * 256;
             const int mm = idx >> 4, kk = idx & 15;
             const int gm = m0 + mm, gk = k0 + kk;
-            As[kk][mm] = (gm < M && gk < kend) ? A[(size_t)gm * lda + gk] : (T)0;
+            ra[l] = (gm < M && gk < kend) ? A[(size_t)gm * lda + gk] : (T)0;
         }
-        if (NT) {
 #pragma unroll
-            for (int l = 0; l < TN; ++l) {
-                const int idx = tid + l * 256;
+        for (int l = 0; l < TN; ++l) {
+            const int idx = tid + l * 256;
+            if (NT) {
                 const int nn = idx >> 4, kk = idx & 15;
                 const int gn = n0 + nn, gk = k0 + kk;
-                Bs[kk][nn] = (gn < N && gk < kend) ? Bm[(size_t)gn * ldb + gk] : (T)0;
-            }
-        } else {
-#pragma unroll
-            for (int l = 0; l < TN; ++l) {
-                const int idx = tid + l * 256;
+                rb[l] = (gn < N && gk < kend) ? Bm[(size_t)gn * ldb + gk] : (T)0;
+            } else {
                 const int kk = idx / BN, nn = idx % BN;
                 const int gn = n0 + nn, gk = k0 + kk;
-                Bs[kk][nn] = (gn < N && gk < kend) ? Bm[(size_t)gk * ldb + gn] : (T)0;
+                rb[l] = (gn < N && gk < kend) ? Bm[(size_t)gk * ldb + gn] : (T)0;
             }
         }
+    };
+    if (kbeg < kend) fetch(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+#pragma unroll
+        for (int l = 0; l < TM; ++l) {
+            const int idx = tid + l * 256;
+            As[idx & 15][idx >> 4] = ra[l];
+        }
+#pragma unroll
+        for (int l = 0; l < TN; ++l) {
+            const int idx = tid + l * 256;
+            if (NT) Bs[idx & 15][idx >> 4] = rb[l];
+            else Bs[idx / BN][idx % BN] = rb[l];
+        }
         __syncthreads();
+        if (k0 + BK < kend) fetch(k0 + BK);
 #pragma unroll
         for (int kk = 0; kk < BK; ++kk) {
             T a[TM], b[TN];
@@ -150,8 +163,8 @@ static void gemm_t(bool nt, int M, int N, int K, T alpha, const T *A, long long 
                    long long sC, int batch, Workspace &ws, hipStream_t st) {
     const int tiles = div_up(M, BM) * div_up(N, BN) * batch;
     int nsplit = 1;
-    if (K > 4 * BK && tiles < 512) {
-        nsplit = std::min(div_up(1024, tiles), div_up(K, 256));
+    if (K > 4 * BK && tiles < 1024) {
+        nsplit = std::min(div_up(2048, tiles), div_up(K, 256));
         nsplit = std::max(1, nsplit);
     }
     int kchunk = div_up(div_up(K, nsplit), BK) * BK;
