@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <numeric>
 #include <string>
 #include <thread>
 #include <vector>
@@ -16,54 +17,105 @@
 
 namespace bse {
 
-// cyclic Jacobi eigen-decomposition of a small symmetric matrix (row-major),
-// eigenvalues ascending, eigenvectors in the columns of Z
-static void jacobi_eigh(int n, std::vector<double> A, std::vector<double> &w,
-                        std::vector<double> &Z) {
-    Z.assign((size_t)n * n, 0.0);
-    for (int i = 0; i < n; ++i) Z[(size_t)i * n + i] = 1.0;
+// Symmetric eigen-decomposition: Householder reduction to tridiagonal form
+// (accumulating the reflections), then implicit-shift QR on the tridiagonal
+// with Wilkinson shifts (Golub and Van Loan, Matrix Computations, Alg. 8.3.1
+// and 8.3.3).  A is n x n row-major symmetric; w ascending, Z[i * n + j] =
+// component i of eigenvector j.
+static void sym_eig(int n, std::vector<double> A, std::vector<double> &w, std::vector<double> &Z) {
     auto at = [&](int i, int j) -> double & { return A[(size_t)i * n + j]; };
-    for (int sweep = 0; sweep < 100; ++sweep) {
-        double off = 0, tot = 0;
-        for (int i = 0; i < n; ++i)
-            for (int j = 0; j < n; ++j) {
-                tot += at(i, j) * at(i, j);
-                if (i != j) off += at(i, j) * at(i, j);
+    auto z = [&](int i, int j) -> double & { return Z[(size_t)j * n + i]; };  // stored transposed
+    Z.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) z(i, i) = 1.0;
+    std::vector<double> v(n), p(n), q(n);
+    for (int k = 0; k + 2 < n; ++k) {
+        double xn2 = 0;
+        for (int i = k + 1; i < n; ++i) xn2 += at(i, k) * at(i, k);
+        const double x0 = at(k + 1, k);
+        if (xn2 <= x0 * x0) continue;  // already tridiagonal in this column
+        const double alpha = x0 >= 0 ? -std::sqrt(xn2) : std::sqrt(xn2);
+        for (int i = k + 1; i < n; ++i) v[i] = at(i, k);
+        v[k + 1] -= alpha;
+        const double vn2 = xn2 - x0 * x0 + v[k + 1] * v[k + 1];
+        const double beta = 2.0 / vn2;
+        double vp = 0;
+        for (int i = k + 1; i < n; ++i) {
+            double s = 0;
+            for (int j = k + 1; j < n; ++j) s += at(i, j) * v[j];
+            p[i] = beta * s;
+            vp += v[i] * p[i];
+        }
+        const double K = 0.5 * beta * vp;
+        for (int i = k + 1; i < n; ++i) q[i] = p[i] - K * v[i];
+        for (int i = k + 1; i < n; ++i)
+            for (int j = k + 1; j < n; ++j) at(i, j) -= v[i] * q[j] + q[i] * v[j];
+        at(k + 1, k) = at(k, k + 1) = alpha;
+        for (int i = k + 2; i < n; ++i) at(i, k) = at(k, i) = 0.0;
+        // Z <- Z H, with Z held transposed: rows k+1.. of Z^T get -beta v (v^T Z^T)
+        std::vector<double> sr(n, 0.0);
+        for (int j = k + 1; j < n; ++j) {
+            const double *zr = &Z[(size_t)j * n];
+            const double vj = v[j];
+            for (int r = 0; r < n; ++r) sr[r] += vj * zr[r];
+        }
+        for (int j = k + 1; j < n; ++j) {
+            double *zr = &Z[(size_t)j * n];
+            const double f = beta * v[j];
+            for (int r = 0; r < n; ++r) zr[r] -= f * sr[r];
+        }
+    }
+    // implicit QR sweeps on the unreduced blocks, bottom up
+    const double eps = 4.0 * 2.220446049250313e-16;
+    int hi = n - 1, guard = 0;
+    while (hi > 0 && guard < 60 * n) {
+        int lo = hi;
+        while (lo > 0 && std::fabs(at(lo, lo - 1)) >
+                             eps * (std::fabs(at(lo, lo)) + std::fabs(at(lo - 1, lo - 1))))
+            --lo;
+        if (lo > 0) at(lo, lo - 1) = at(lo - 1, lo) = 0.0;
+        if (lo == hi) {
+            --hi;
+            continue;
+        }
+        ++guard;
+        const double a = at(hi - 1, hi - 1), b = at(hi, hi - 1), c = at(hi, hi);
+        const double dd = 0.5 * (a - c);
+        const double mu = c - b * b / (dd + std::copysign(std::hypot(dd, b), dd == 0 ? 1.0 : dd));
+        double x = at(lo, lo) - mu, y = at(lo + 1, lo);
+        for (int k = lo; k < hi; ++k) {
+            const double r = std::hypot(x, y);
+            const double cs = r == 0 ? 1.0 : x / r, sn = r == 0 ? 0.0 : y / r;
+            const int j0 = std::max(lo, k - 1), j1 = std::min(hi, k + 2);
+            for (int j = j0; j <= j1; ++j) {
+                const double t1 = at(k, j), t2 = at(k + 1, j);
+                at(k, j) = cs * t1 + sn * t2;
+                at(k + 1, j) = -sn * t1 + cs * t2;
             }
-        if (off <= 1e-30 * tot || off == 0) break;
-        for (int p = 0; p < n - 1; ++p)
-            for (int q = p + 1; q < n; ++q) {
-                const double apq = at(p, q);
-                if (std::fabs(apq) < 1e-300) continue;
-                const double theta = (at(q, q) - at(p, p)) / (2.0 * apq);
-                const double t = (theta >= 0 ? 1.0 : -1.0) /
-                                 (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-                const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
-                for (int k = 0; k < n; ++k) {
-                    const double akp = at(k, p), akq = at(k, q);
-                    at(k, p) = cs * akp - sn * akq;
-                    at(k, q) = sn * akp + cs * akq;
-                }
-                for (int k = 0; k < n; ++k) {
-                    const double apk = at(p, k), aqk = at(q, k);
-                    at(p, k) = cs * apk - sn * aqk;
-                    at(q, k) = sn * apk + cs * aqk;
-                }
-                for (int k = 0; k < n; ++k) {
-                    const double zkp = Z[(size_t)k * n + p], zkq = Z[(size_t)k * n + q];
-                    Z[(size_t)k * n + p] = cs * zkp - sn * zkq;
-                    Z[(size_t)k * n + q] = sn * zkp + cs * zkq;
-                }
+            for (int i = j0; i <= j1; ++i) {
+                const double t1 = at(i, k), t2 = at(i, k + 1);
+                at(i, k) = cs * t1 + sn * t2;
+                at(i, k + 1) = -sn * t1 + cs * t2;
             }
+            double *z1 = &Z[(size_t)k * n], *z2 = &Z[(size_t)(k + 1) * n];
+            for (int i = 0; i < n; ++i) {
+                const double t1 = z1[i], t2 = z2[i];
+                z1[i] = cs * t1 + sn * t2;
+                z2[i] = -sn * t1 + cs * t2;
+            }
+            if (k + 1 < hi) {
+                x = at(k + 1, k);
+                y = at(k + 2, k);
+            }
+        }
     }
     std::vector<int> idx(n);
-    for (int i = 0; i < n; ++i) idx[i] = i;
+    std::iota(idx.begin(), idx.end(), 0);
     std::sort(idx.begin(), idx.end(), [&](int a, int b) { return at(a, a) < at(b, b); });
     w.resize(n);
     std::vector<double> Zs((size_t)n * n);
     for (int j = 0; j < n; ++j) {
         w[j] = at(idx[j], idx[j]);
-        for (int i = 0; i < n; ++i) Zs[(size_t)i * n + j] = Z[(size_t)i * n + idx[j]];
+        for (int i = 0; i < n; ++i) Zs[(size_t)i * n + j] = z(i, idx[j]);
     }
     Z.swap(Zs);
 }
@@ -156,7 +208,7 @@ static int orthonormalize(DavState &s, int k, double drop2) {
         }
     } else {
         std::vector<double> w, Z;
-        jacobi_eigh(k, G, w, Z);
+        sym_eig(k, G, w, Z);
         std::vector<int> keep;
         for (int i = k - 1; i >= 0; --i)
             if (w[i] > drop2 * gmax) keep.push_back(i);
@@ -318,7 +370,7 @@ void DavRun::advance() {
     std::vector<double> T((size_t)nb * nb);
     for (int i = 0; i < nb; ++i)
         for (int j = 0; j < nb; ++j) T[(size_t)i * nb + j] = Tm[(size_t)i * maxb + j];
-    jacobi_eigh(nb, T, theta, Y);
+    sym_eig(nb, T, theta, Y);
     kr = std::min(B, nb);
     std::vector<double> Yk((size_t)kr * nb);
     for (int r = 0; r < kr; ++r)
