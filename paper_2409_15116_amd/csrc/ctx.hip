@@ -506,37 +506,110 @@ static void build_event_set(bse_ctx *c, int set, int cap, const Bits &nb,
         grp.swap(grp2);
         gpart.swap(gpart2);
     }
+    // halves: each group's rows are ordered so that rows 0-3 and rows 4-7
+    // share few columns (the split of the 8 rows into two sets of 4 that
+    // gives the fewest events when a column live in only one half is paired
+    // with another such column of the other half)
+    for (int g = 0; g < ng; ++g) {
+        int *row = &grp[(size_t)g * BW];
+        auto events_of = [&](unsigned mask) {
+            int tot = 0;
+            for (int h = 0; h < nph; ++h) {
+                int full = 0, lo = 0, hi = 0;
+                for (int w : parts[h]) {
+                    bool l = false, u = false;
+                    for (int i = 0; i < BW; ++i)
+                        if (row[i] >= 0 && pidx[(size_t)row[i] * no + w] >= 0)
+                            (mask >> i & 1 ? l : u) = true;
+                    full += l && u;
+                    lo += l && !u;
+                    hi += u && !l;
+                }
+                tot += (full + std::max(lo, hi) + 1) / 2 * 2;
+            }
+            return tot;
+        };
+        unsigned best = 0x0F;
+        int best_n = events_of(best);
+        for (unsigned mask = 1; mask < 256; mask += 2)  // row 0 in the first half
+            if (__builtin_popcount(mask) == BW / 2) {
+                const int e = events_of(mask);
+                if (e < best_n) {
+                    best_n = e;
+                    best = mask;
+                }
+            }
+        std::vector<int> lo, hi;
+        for (int i = 0; i < BW; ++i) (best >> i & 1 ? lo : hi).push_back(row[i]);
+        auto key = [](int a) { return a < 0 ? INT_MAX : a; };
+        std::sort(lo.begin(), lo.end(), [&](int a, int b) { return key(a) < key(b); });
+        std::sort(hi.begin(), hi.end(), [&](int a, int b) { return key(a) < key(b); });
+        for (int i = 0; i < BW / 2; ++i) {
+            row[i] = lo[i];
+            row[BW / 2 + i] = hi[i];
+        }
+    }
     // events: phase by phase; in the phase of its own part a group follows a
     // round-robin tournament over that part's groups (circle method, an odd
     // count gets a bye; in round r it visits its partner's columns and its
     // own come last), in another phase it visits that part's groups in order
-    const int EV = BW + 1;
+    // An event is 8 tau offsets and two column slots: rows 0-3 take column
+    // A, rows 4-7 column B.  A column live in both halves is one event (A =
+    // B); columns live in one half only are paired with the next such column
+    // of the other half, in visiting order; one left over takes an event of
+    // its own with the other half on the zero row.
+    const int EV = BW + 2;
+    const int HB = BW / 2;
     const int zero = (int)(P * TAU_TILE);
     std::vector<int> ev, start(ng), phc((size_t)ng * nph);
-    auto push = [&](int g, int w) {
-        for (int i = 0; i < BW; ++i) {
-            const int v = grp[(size_t)g * BW + i];
-            const int p = v >= 0 ? pidx[(size_t)v * no + w] : -1;
-            ev.push_back(p >= 0 ? p * TAU_TILE : zero);
-        }
-        ev.push_back(slot[w]);
+    auto off = [&](int g, int i, int w) {
+        const int v = grp[(size_t)g * BW + i];
+        const int p = v >= 0 && w >= 0 ? pidx[(size_t)v * no + w] : -1;
+        return p >= 0 ? p * TAU_TILE : zero;
+    };
+    auto push = [&](int g, int wa, int wb) {  // wa / wb < 0: that half idle
+        for (int i = 0; i < BW; ++i) ev.push_back(off(g, i, i < HB ? wa : wb));
+        const int sa = wa >= 0 ? slot[wa] : slot[wb];
+        const int sb = wb >= 0 ? slot[wb] : sa;
+        ev.push_back(sa);
+        ev.push_back(sb);
     };
     auto push_zero = [&]() {
         for (int i = 0; i < BW; ++i) ev.push_back(zero);
         ev.push_back(0);
+        ev.push_back(0);
     };
     for (int g = 0; g < ng; ++g) {
         start[g] = (int)(ev.size() / EV);
-        std::vector<unsigned long long> cv(nwd, 0);
+        std::vector<unsigned long long> cl(nwd, 0), ch(nwd, 0);
         for (int i = 0; i < BW; ++i) {
             const int v = grp[(size_t)g * BW + i];
             if (v >= 0)
-                for (int q = 0; q < nwd; ++q) cv[q] |= nb.row(v)[q];
+                for (int q = 0; q < nwd; ++q) (i < HB ? cl : ch)[q] |= nb.row(v)[q];
         }
+        std::vector<int> qlo, qhi;  // columns waiting for a partner, in order
         auto visit = [&](int m) {
             for (int i = 0; i < BW; ++i) {
                 const int w = grp[(size_t)m * BW + i];
-                if (w >= 0 && (cv[w / 64] >> (w % 64) & 1)) push(g, w);
+                if (w < 0) continue;
+                const bool l = cl[w / 64] >> (w % 64) & 1, u = ch[w / 64] >> (w % 64) & 1;
+                if (l && u) {
+                    push(g, w, w);
+                } else if (l) {
+                    if (!qhi.empty()) {
+                        push(g, w, qhi.front());
+                        qhi.erase(qhi.begin());
+                    } else {
+                        qlo.push_back(w);
+                    }
+                } else if (u) {
+                    if (!qlo.empty()) {
+                        push(g, qlo.front(), w);
+                        qlo.erase(qlo.begin());
+                    } else {
+                        qhi.push_back(w);
+                    }
+                }
             }
         };
         for (int h = 0; h < nph; ++h) {
@@ -558,8 +631,12 @@ static void build_event_set(bse_ctx *c, int set, int cap, const Bits &nb,
             } else {
                 for (int m : gh) visit(m);
             }
+            for (int w : qlo) push(g, w, -1);
+            for (int w : qhi) push(g, -1, w);
+            qlo.clear();
+            qhi.clear();
             int n = (int)(ev.size() / EV - before);
-            while (n % 4) {
+            while (n % 2) {
                 push_zero();
                 ++n;
             }

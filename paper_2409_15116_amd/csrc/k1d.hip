@@ -217,7 +217,10 @@ __global__ void __launch_bounds__(64 * NW) k_k1d(const T *__restrict__ A, const 
 // in phases, one part of the orbitals resident per phase.  Inside a phase
 // the column loop has no barrier and every wave walks its own event list:
 // wave g owns the K1D_RES_BW orbitals of group g and visits only the columns
-// that pair with one of them.  The lists follow a round-robin schedule over
+// that pair with one of them; an event feeds the first half of the rows from
+// one column and the second half from another (the same column when both
+// halves pair with it), so a column that pairs with one half only does not
+// load the zero tau of the other.  The lists follow a round-robin schedule over
 // the groups of a part, in which groups g and h visit each other's columns
 // in the same round: the two uses of a kept pair's tau, (v, w) by one wave
 // and (w, v) by the other, are loaded close in time in one CU, and tau comes
@@ -233,12 +236,13 @@ __global__ void __launch_bounds__(64 * NW) k_k1d_res(
     int ng, int nph, int n_occ, int B, long long nr, long long n_rows, int nSc, T k1d,
     T inv_omega, T *__restrict__ Cr, cplx<T> *__restrict__ Hc) {
     constexpr int BW = K1D_RES_BW;
-    constexpr int EV = BW + 1;  // ints per event
+    constexpr int EV = BW + 2;  // ints per event: BW tau offsets, two column slots
+    constexpr int HB = BW / 2;
     constexpr int NQ = K1D_R / PT;  // pieces of a 64-point tau tile
     constexpr int SW = VPL * NQ;    // vectors per workgroup
     static_assert(VPL % 2 == 0 && VPL * sizeof(T) % 16 == 0, "VPL values fill 16-byte LDS words");
     static_assert(PT == 16 || PT == 32 || PT == 64, "PT divides the tau tile");
-    static_assert(NBUF == 1 || NBUF == 2 || NBUF == 4, "events are padded to multiples of 4");
+    static_assert(NBUF == 1 || NBUF == 2, "events are padded to multiples of 2");
     static_assert(CAP % NW == 0, "the waves share the staging");
     using VecS = T __attribute__((ext_vector_type(VPL)));
     constexpr int NH = VPL * (int)sizeof(T) / 16;  // 16-byte words per lane and column
@@ -342,10 +346,12 @@ __global__ void __launch_bounds__(64 * NW) k_k1d_res(
                 for (int b = 0; b < NBUF; ++b) {
                     const int *cur = evg + (e + b) * EV;
                     const VecS aw = lds_get(cur[BW]);
+                    const VecS ax = lds_get(cur[BW + 1]);
 #pragma unroll
                     for (int i = 0; i < BW; ++i)
 #pragma unroll
-                        for (int j = 0; j < VPL; ++j) acc[i][j] += t[b][i] * aw[j];
+                        for (int j = 0; j < VPL; ++j)
+                            acc[i][j] += t[b][i] * (i < HB ? aw[j] : ax[j]);
                     __builtin_amdgcn_sched_barrier(0);
                     k1d_request<T, BW>(t[b], trs, voff, cur + NBUF * EV);
                     __builtin_amdgcn_sched_barrier(0);

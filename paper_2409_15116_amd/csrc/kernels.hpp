@@ -74,11 +74,14 @@ constexpr int K1D_BI_MIN = 16;
 // part[h * cap + k] is the orbital in LDS slot k during phase h, -1 past the
 // part's end) and into ng row groups of K1D_RES_BW inside the parts
 // (grp[g * BW + i], -1 for an empty slot).  Group g's events are
-// ev[(ev_start[g] + e) * (BW + 1) + k], phase after phase, ph_cnt[g * nph + h]
-// of them in phase h (a multiple of 4), followed by 4 padding events: k < BW
-// holds the tau offset (p * 64) of pair (grp[g * BW + k], column), or that of
-// the zero row P when the pair is not kept, and k = BW the column's LDS slot.
-// Only columns with a kept pair in the group have an event.  gpart[g] is the
+// ev[(ev_start[g] + e) * (BW + 2) + k], phase after phase, ph_cnt[g * nph + h]
+// of them in phase h (a multiple of 2), followed by 4 padding events.  Rows
+// 0 .. BW/2-1 of an event take column A (LDS slot at k = BW), rows BW/2 ..
+// BW-1 column B (slot at k = BW + 1); k < BW holds the tau offset (p * 64)
+// of pair (grp[g * BW + k], that column), or that of the zero row P when the
+// pair is not kept.  Only columns with a kept pair in the group are visited;
+// a column with kept pairs in one half only shares its event with such a
+// column of the other half.  gpart[g] is the
 // part of group g's orbitals and gslot[g * BW + i] the LDS slot of orbital
 // grp[g * BW + i] in it.
 constexpr int K1D_RES_BW = 8;
