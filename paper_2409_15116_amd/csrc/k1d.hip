@@ -210,8 +210,9 @@ __global__ void __launch_bounds__(64 * NW) k_k1d(const T *__restrict__ A, const 
 // the grid for SW = VPL * 64 / PT trial vectors; lane l works on point
 // l % PT and vectors (l / PT) * VPL + j, j < VPL, so with PT < 64 the lanes
 // that share a point load the same tau value.  A tau value loaded into a
-// register serves VPL products per row, and the load instructions, not the
-// bytes, bound this kernel: VPL is as large as LDS allows.  The a values of
+// register serves VPL products per row, and vector-memory instructions are
+// the scarce resource (a CU issues one dword load every 8 cycles even from
+// L1): VPL is as large as LDS allows.  The a values of
 // up to CAP orbitals stay in LDS ([slot][lane], VPL values per lane, one
 // 16- or 32-byte read per column); with more orbitals the columns are taken
 // in phases, one part of the orbitals resident per phase.  Inside a phase
@@ -384,7 +385,7 @@ __global__ void __launch_bounds__(64 * NW) k_k1d_res(
                 const T uv = u[(size_t)v * nr + rr];
 #pragma unroll
                 for (int j = 0; j < VPL; ++j) {
-                    if (rok && s0 + j < B)  // so[j] is not clamped here
+                    if (rok && s0 + j < B)  // then so[j] is vector s0 + j's own offset
                         Cr[so[j] + (size_t)v * nr] = vr * av[j] - k1d * acc[i][j];
                     dn[j] += uv * av[j];
                 }
@@ -450,8 +451,11 @@ static void launch_k1d_res(const T *A, const T *tau, const T *V, const T *u,
                            const PairEvents *pes, int n_occ, int B, long long nr, T k1d,
                            T inv_omega, T *Cr, cplx<T> *Hc, hipStream_t st) {
     constexpr int SW = VPL * (K1D_R / PT);
-    // LDS capacity in orbitals: 128 KB of a values
-    constexpr int CAP = std::min(K1D_RES_MAXROWS, 2048 / (VPL * (int)sizeof(T)));
+    // LDS capacity in orbitals: 128 KB of a values, and no more slots than
+    // the shape has rows (a shape of 8 waves with 16-byte words keeps 64 KB,
+    // so that two workgroups share a CU)
+    constexpr int CAP = std::min(std::min(K1D_RES_MAXROWS, NW * K1D_RES_BW),
+                                 2048 / (VPL * (int)sizeof(T)));
     int set = -1;
     for (int i = 0; i < K1D_RES_NSETS; ++i)
         if (K1D_RES_CAPS[i] == CAP) set = i;
@@ -479,13 +483,14 @@ static constexpr K1dShape K1D_SHAPES32[] = {
     {32, 8, 2, 4},            {16, 8, 2, 4},            {64, 16, 2, 8},
     {64, 8, 2, 8},            {32, 8, 2, 8},            {128, 8, 2, 16},
     {128, 4, 2, 16, 1, 64},   {128, 8, 2, 16, 1, 32},   {128, 8, 2, 16, 1, 64},
-    {128, 16, 2, 16, 1, 32},  {64, 8, 2, 8, 1, 64},     {64, 16, 2, 8, 1, 32}};
+    {128, 16, 2, 16, 1, 32},  {64, 8, 2, 8, 1, 64},     {64, 16, 2, 8, 1, 32},
+    {64, 4, 2, 8, 1, 64},     {64, 8, 2, 8, 1, 32}};
 static constexpr K1dShape K1D_SHAPES64[] = {
     {32, 8, 1, 4},            {16, 8, 1, 4},            {32, 4, 1, 4},
     {16, 4, 1, 4},            {64, 8, 1, 8},            {64, 4, 1, 8},
     {128, 4, 1, 16},          {128, 2, 2, 16, 1, 64},   {128, 4, 2, 16, 1, 32},
     {128, 4, 2, 16, 1, 64},   {128, 8, 2, 16, 1, 32},   {64, 4, 2, 8, 1, 64},
-    {64, 8, 2, 8, 1, 32}};
+    {64, 8, 2, 8, 1, 32},     {64, 2, 2, 8, 1, 64},     {64, 4, 2, 8, 1, 32}};
 
 int k1d_num_shapes(bool dbl) {
     return dbl ? (int)(sizeof(K1D_SHAPES64) / sizeof(K1dShape))
@@ -514,6 +519,8 @@ void k1d_apply(const T *A, const T *tau, const T *V, const T *u, const PairCSR *
             BSE_K1D_RES_CASE(8, 16, 2, 32)
             BSE_K1D_RES_CASE(4, 8, 2, 64)
             BSE_K1D_RES_CASE(8, 8, 2, 32)
+            BSE_K1D_RES_CASE(2, 8, 2, 64)
+            BSE_K1D_RES_CASE(4, 8, 2, 32)
         } else {
             BSE_K1D_RES_CASE(4, 16, 2, 64)
             BSE_K1D_RES_CASE(8, 16, 2, 32)
@@ -521,6 +528,8 @@ void k1d_apply(const T *A, const T *tau, const T *V, const T *u, const PairCSR *
             BSE_K1D_RES_CASE(16, 16, 2, 32)
             BSE_K1D_RES_CASE(8, 8, 2, 64)
             BSE_K1D_RES_CASE(16, 8, 2, 32)
+            BSE_K1D_RES_CASE(4, 8, 2, 64)
+            BSE_K1D_RES_CASE(8, 8, 2, 32)
         }
 #undef BSE_K1D_RES_CASE
         return;

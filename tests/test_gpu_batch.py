@@ -163,7 +163,7 @@ def test_every_k1d_shape_matches_oracle(spec, prec, tol):
     X = trial_block(c, 3, seed=19)                   # 3 vectors: ragged vs. 8 or 16 per group
     ref = op.apply(X)
     dt = torch.float64 if prec == 0 else torch.float32
-    n_run = 0
+    n_res = 0
     for shape in range(pkg.k1d_num_shapes(prec)):
         info = pkg.k1d_shape_info(prec, shape)
         if info["resident"] and c.n_occ > info["rows"]:
@@ -174,8 +174,8 @@ def test_every_k1d_shape_matches_oracle(spec, prec, tol):
         Y = torch.empty((3, c.n_occ, c.npw), dtype=dt, device="cuda")
         ctx.apply(_dev(X, dt), Y, prec)
         assert rel_err(Y.double().cpu().numpy(), ref) < tol, shape
-        n_run += 1
-    assert n_run >= pkg.k1d_num_shapes(prec) - 2
+        n_res += info["resident"]
+    assert n_res >= 2                                 # resident shapes were exercised
     ctx.close()
 
 
