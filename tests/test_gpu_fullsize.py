@@ -70,25 +70,36 @@ def test_tau_sampled(setup):
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 2e-5), (2, 1e-4)])
 def test_apply_sampled_graph(setup, prec, tol):
+    """Every compiled K1d shape that holds the cell's 128 orbitals (the
+    autotuner's candidates, so whichever the benchmark picks), graph replays."""
     pkg, c, ctx, st, pairs, sub, tau, X, ref = setup
-    say("fullsize apply", prec)
     dt = torch.float64 if prec == 0 else torch.float32
-    with torch.cuda.stream(st):
-        Xd = torch.from_numpy(X).to("cuda", dtype=dt)
-        Y = torch.empty_like(Xd)
-        ctx.set_graph(True)
-        for _ in range(3):                         # capture, then replays
-            Y.fill_(float("nan"))
-            ctx.apply(Xd, Y, prec)
-        ctx.set_graph(False)
-    st.synchronize()
-    got = Y.double().cpu().numpy()
-    assert np.isfinite(got).all()
-    for k, s in enumerate(VECS):
-        assert rel_err(got[s][ROWS], ref[k][ROWS]) < tol, (s, prec)
-    # any size: the output lies in the P_c space
-    ov = np.einsum("svg,wg->svw", got, c.psi)
-    assert np.abs(ov).max() < (1e-10 if prec == 0 else 2e-4) * np.abs(got).max()
+    n_res = 0
+    for shape in range(pkg.k1d_num_shapes(prec)):
+        info = pkg.k1d_shape_info(prec, shape)
+        if info["resident"] and c.n_occ > info["rows"]:
+            continue
+        say("fullsize apply", prec, "shape", shape)
+        with torch.cuda.stream(st):
+            ctx.set_k1d_shape(prec, shape)
+            Xd = torch.from_numpy(X).to("cuda", dtype=dt)
+            Y = torch.empty_like(Xd)
+            ctx.set_graph(True)
+            for _ in range(3):                         # capture, then replays
+                Y.fill_(float("nan"))
+                ctx.apply(Xd, Y, prec)
+            ctx.set_graph(False)
+        st.synchronize()
+        got = Y.double().cpu().numpy()
+        assert np.isfinite(got).all(), shape
+        for k, s in enumerate(VECS):
+            assert rel_err(got[s][ROWS], ref[k][ROWS]) < tol, (s, prec, shape)
+        # any size: the output lies in the P_c space
+        ov = got.reshape(-1, c.npw) @ c.psi.T
+        assert np.abs(ov).max() < (1e-10 if prec == 0 else 2e-4) * np.abs(got).max(), shape
+        n_res += info["resident"]
+    assert n_res >= 2
+    ctx.set_k1d_shape(prec, 0)
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2])
@@ -108,6 +119,8 @@ def test_davidson_c2_against_stored_oracle(prec):
         pkg.setup_pairs_and_screen(ctx, c, fraction=g["fraction"], precision=prec)
         assert ctx.n_pairs == g["n_pairs"]
         X0 = torch.from_numpy(trial_block(c, g["block"], seed=g["start_seed"])).to("cuda")
+        shape, _ = ctx.autotune(g["block"], prec, n_rep=1)   # as the benchmark does
+        say("  autotuned K1d shape", shape)
         ctx.set_graph(True)
         om, X, s = ctx.davidson(X0, g["n_eig"], block=g["block"], precision=prec, tol=1e-5,
                                 max_iter=400)
