@@ -545,6 +545,24 @@ def trial_block(cell: Cell, n_vec: int, seed: int = 1234) -> np.ndarray:
     return z / (1.0 + 0.5 * cell.g2)[None, None, :]
 
 
+def dipole_block(cell: Cell, n_pol: int = 3) -> np.ndarray:
+    """Perturbation of the occupied orbitals along x, y, z: packed
+    coefficients of X_i(r) psi_v(r) with the periodic coordinate
+    X_i(r) = L / (2 pi) sin(2 pi r_i / L) (equal to r_i near the origin, smooth
+    across the cell boundary), shape [n_pol, n_occ, n_pw].  An input of the
+    spectrum: the method applies P_c to it itself."""
+    b = _RealBasis(cell.L, cell.n, cell.miller)
+    u = b.to_grid(cell.psi)                                     # [n_occ, n, n, n]
+    j = np.arange(cell.n) * (cell.L / cell.n)
+    X = (cell.L / (2.0 * np.pi)) * np.sin(2.0 * np.pi * j / cell.L)
+    out = []
+    for i in range(n_pol):
+        shape = [1, 1, 1]
+        shape[i % 3] = cell.n
+        out.append(b.to_packed(u * X.reshape(shape)[None]))
+    return np.stack(out)
+
+
 def random_block(shape, seed: int) -> np.ndarray:
     """Plain N(0,1) block of the given shape."""
     return np.random.default_rng(seed).standard_normal(shape)
