@@ -238,6 +238,35 @@ bse_status bse_davidson_record(bse_ctx *ctx, const bse_davidson_opts *opts, cons
                                float *label, int64_t max_rows, int64_t *n_rows, double *omega,
                                double *X, bse_davidson_stats *stats);
 
+/* ---------------------------------------------------------------- spectrum
+ * Lanczos chains of L for an absorption spectrum (Sec. 4: the spectrum needs
+ * N_Lanczos x N_pol applications of L and no diagonalisation).  For each of
+ * the n_pol perturbations d_p in D (device FP64 [n_pol][n_occ][n_pw],
+ * caller-owned, read only; e.g. the dipole x_i psi_v of polarisation i):
+ * q_1 = P_c d_p / ||P_c d_p||, then the three-term recurrence without
+ * reorthogonalisation, alpha_k = <q_k, L q_k>,
+ * w = L q_k - alpha_k q_k - beta_{k-1} q_{k-1}, beta_k = ||w||,
+ * q_{k+1} = w / beta_k (0 once beta_k = 0).  All chains advance together:
+ * each step is one apply of the n_pol vectors, in `precision`; vectors and
+ * recurrence are FP64 on the device.
+ *   alpha host out [n_pol][n_steps]; beta host out [n_pol][n_steps + 1],
+ *   beta[p][0] = ||P_c d_p||.
+ * Requires bse_screen_pairs in that precision (BSE_ERR_STATE); BSE_ERR_ARG
+ * for n_pol or n_steps < 1.  Uses the context's apply graph setting and
+ * stream; synchronises.  Not in the paper: the recurrence's form (the
+ * paper cites it). */
+bse_status bse_lanczos(bse_ctx *ctx, int n_pol, int n_steps, int precision, const double *D,
+                       double *alpha, double *beta);
+/* S(omega) = <d| (omega + i eta - L)^-1 |d> of one chain (alpha [n_steps],
+ * beta [n_steps + 1] as written by bse_lanczos) at n_omega frequencies
+ * (host arrays, Ha): the continued fraction
+ * beta_0^2 / (z - alpha_1 - beta_1^2 / (z - alpha_2 - ...)), z = omega + i eta,
+ * truncated after alpha_{n_steps}; the absorption line shape is -Im S / pi.
+ * Host code, no GPU; BSE_ERR_ARG for eta <= 0 or n_steps < 1. */
+bse_status bse_lanczos_spectrum(const double *alpha, const double *beta, int n_steps,
+                                const double *omega, int n_omega, double eta, double *s_re,
+                                double *s_im);
+
 /* ---------------------------------------------------------------- tuning
  * The K1d kernel (Eq. k1d) is compiled in several shapes: rows per
  * workgroup, trial vectors per workgroup and tau columns in flight.  Shape 0

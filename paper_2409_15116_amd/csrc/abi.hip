@@ -257,6 +257,27 @@ int bse_k1d_num_shapes(int precision) {
     return bse::k1d_num_shapes(precision == BSE_FP64);
 }
 
+bse_status bse_lanczos(bse_ctx *c, int n_pol, int n_steps, int precision, const double *D,
+                       double *alpha, double *beta) {
+    CHECK_CTX(c);
+    if (!D || !alpha || !beta) {
+        set_error("bse_lanczos: null argument");
+        return BSE_ERR_ARG;
+    }
+    BSE_GUARD(bse::ctx_lanczos(c, n_pol, n_steps, precision, D, alpha, beta))
+}
+
+bse_status bse_lanczos_spectrum(const double *alpha, const double *beta, int n_steps,
+                                const double *omega, int n_omega, double eta, double *s_re,
+                                double *s_im) {
+    if (!alpha || !beta || !omega || !s_re || !s_im || n_steps < 1 || n_omega < 0 ||
+        !(eta > 0)) {
+        set_error("bse_lanczos_spectrum: bad argument");
+        return BSE_ERR_ARG;
+    }
+    BSE_GUARD(bse::lanczos_spectrum(alpha, beta, n_steps, omega, n_omega, eta, s_re, s_im))
+}
+
 bse_status bse_k1d_shape_info(int precision, int shape, int *info) {
     if (precision != BSE_FP64 && precision != BSE_FP32 && precision != BSE_BF16X3) {
         set_error("bse_k1d_shape_info: unknown precision %d", precision);

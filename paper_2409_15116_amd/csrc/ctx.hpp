@@ -170,6 +170,10 @@ void batch_apply(bse_batch *b, const int *n_vec, const void *const *in, void *co
 void batch_set_graph(bse_batch *b, bool on);
 void batch_davidson(bse_batch *b, const bse_davidson_opts *o, const double *const *X0,
                     double *const *omega, double *const *Xout, bse_davidson_stats *stats);
+void ctx_lanczos(bse_ctx *c, int n_pol, int n_steps, int prec, const double *D, double *alpha,
+                 double *beta);
+void lanczos_spectrum(const double *alpha, const double *beta, int n_steps, const double *omega,
+                      int n_omega, double eta, double *s_re, double *s_im);
 void learned_setup(bse_ctx *c, int nwg);
 void learned_record(bse_ctx *c, const double *X, const double *R, const double *theta,
                     const double *Tn, int n_rec, int n_ritz, const double *Xref, int n_ref,

@@ -86,6 +86,8 @@ def load():
         "bse_learned_centers": (i32, [vp, vp]),
         "bse_davidson_record": (i32, [vp, C.POINTER(DavidsonOpts), vp, vp, i32, i32, vp, vp, i64,
                                       C.POINTER(i64), vp, vp, C.POINTER(DavidsonStats)]),
+        "bse_lanczos": (i32, [vp, i32, i32, i32, vp, vp, vp]),
+        "bse_lanczos_spectrum": (i32, [vp, vp, i32, vp, i32, C.c_double, vp, vp]),
         "bse_k1d_num_shapes": (i32, [i32]),
         "bse_k1d_shape_info": (i32, [i32, i32, vp]),
         "bse_autotune": (i32, [vp, i32, i32, i32, C.POINTER(i32), vp]),
@@ -115,6 +117,7 @@ def exported_symbols():
             "bse_mlp_create", "bse_mlp_destroy", "bse_mlp_num_params", "bse_mlp_get_weights",
             "bse_mlp_set_weights", "bse_mlp_forward", "bse_mlp_gradients", "bse_mlp_train",
             "bse_set_learned", "bse_learned_centers", "bse_davidson_record",
+            "bse_lanczos", "bse_lanczos_spectrum",
             "bse_k1d_num_shapes", "bse_k1d_shape_info", "bse_autotune", "bse_set_k1d_shape",
             "bse_batch_create",
             "bse_batch_destroy", "bse_batch_set_graph", "bse_batch_apply", "bse_batch_davidson"]
@@ -281,6 +284,18 @@ class BseContext:
                                    C.byref(shape), ms.ctypes.data))
         return shape.value, [float(x) if x >= 0 else None for x in ms]
 
+    def lanczos(self, D, n_steps, precision=FP64):
+        """Lanczos chains of L started from the perturbations D (device FP64
+        [n_pol, n_occ, n_pw]): (alpha [n_pol, n_steps], beta [n_pol, n_steps + 1])."""
+        torch = self.torch
+        n_pol = D.shape[0]
+        alpha = np.zeros((n_pol, n_steps))
+        beta = np.zeros((n_pol, n_steps + 1))
+        _check(load().bse_lanczos(self.h, int(n_pol), int(n_steps), int(precision),
+                                  _dptr(D, torch.float64, (n_pol, self.n_occ, self.npw)),
+                                  alpha.ctypes.data, beta.ctypes.data))
+        return alpha, beta
+
     def set_k1d_shape(self, precision, shape):
         _check(load().bse_set_k1d_shape(self.h, int(precision), int(shape)))
 
@@ -301,6 +316,21 @@ class BseContext:
                  "resid": np.array(st.resid[:n_eig]), "status": status}
         _check(status)
         return om, X, stats
+
+
+def lanczos_spectrum(alpha, beta, omega, eta):
+    """S(omega) = <d|(omega + i eta - L)^-1|d> of one chain (complex array)."""
+    alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+    beta = np.ascontiguousarray(beta, dtype=np.float64)
+    omega = np.ascontiguousarray(omega, dtype=np.float64)
+    if beta.shape[0] != alpha.shape[0] + 1:
+        raise ValueError("beta must have one more entry than alpha")
+    re = np.zeros(omega.shape[0])
+    im = np.zeros(omega.shape[0])
+    _check(load().bse_lanczos_spectrum(alpha.ctypes.data, beta.ctypes.data, int(alpha.shape[0]),
+                                       omega.ctypes.data, int(omega.shape[0]), float(eta),
+                                       re.ctypes.data, im.ctypes.data))
+    return re + 1j * im
 
 
 def k1d_num_shapes(precision):

@@ -108,3 +108,24 @@ def test_k1d_shape_info():
             pkg.k1d_shape_info(prec, n)
     with pytest.raises(pkg.BseError):
         pkg.k1d_shape_info(7, 0)
+
+
+def test_lanczos_spectrum_host():
+    """The library's continued fraction (host code) against the oracle's on
+    random coefficients, and against a 2-state resolvent in closed form."""
+    import paper_2409_15116_amd as pkg
+    from oracle.lanczos import spectrum
+    rng = np.random.default_rng(3)
+    alpha = rng.uniform(0.1, 1.0, 40)
+    beta = rng.uniform(0.05, 0.5, 41)
+    omega = np.linspace(-0.5, 2.0, 97)
+    got = pkg.lanczos_spectrum(alpha, beta, omega, 0.03)
+    ref = spectrum(alpha, beta, omega, 0.03)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    # two steps: <e1|(z - T)^-1|e1> of T = [[a1, b1], [b1, a2]] by Cramer's rule
+    a, b = np.array([0.3, 0.8]), np.array([1.5, 0.2, 0.0])
+    z = omega + 0.03j
+    closed = b[0] ** 2 * (z - a[1]) / ((z - a[0]) * (z - a[1]) - b[1] ** 2)
+    assert np.abs(pkg.lanczos_spectrum(a, b, omega, 0.03) - closed).max() < 1e-12 * np.abs(closed).max()
+    with pytest.raises(pkg.BseError):
+        pkg.lanczos_spectrum(a, b, omega, 0.0)
