@@ -262,6 +262,32 @@ def uneven_batch(args, torch, pkg):
     return out
 
 
+def lanczos_run(args, torch, pkg, ctx, cell, st, prec):
+    """Absorption-spectrum workload (Sec. 4: N_Lanczos x N_pol applications
+    of L): N Lanczos steps for the three dipole perturbations of the bench
+    cell, one block apply of 3 vectors per step, in the bench precision
+    (graph replay).  Reports the chain's wall time, steps and applies per
+    second, and the brightest peak of the x spectrum (eta = 0.02 Ha)."""
+    from synth import dipole_block
+    n = args.lanczos
+    with torch.cuda.stream(st):
+        D = torch.from_numpy(dipole_block(cell, 3)).to("cuda")
+        ctx.set_graph(True)
+        ctx.lanczos(D, 2, prec)                  # capture the 3-vector apply graph
+        torch.cuda.synchronize()
+        t = time.time()
+        alpha, beta = ctx.lanczos(D, n, prec)
+        torch.cuda.synchronize()
+        sec = time.time() - t
+    omega = np.linspace(0.0, 1.0, 2001)
+    s = pkg.lanczos_spectrum(alpha[0], beta[0], omega, 0.02)
+    peak = float(omega[int(np.argmax(-s.imag))])
+    log(f"lanczos: {n} steps x 3 polarisations in {sec:.2f} s, x peak at {peak:.4f} Ha")
+    return {"steps": n, "n_pol": 3, "seconds": sec, "steps_per_s": n / sec,
+            "applies_per_s": 3 * n / sec, "precision": args.precision,
+            "x_peak_ha": peak, "eta_ha": 0.02}
+
+
 def learned_c5(args, torch, pkg):
     """Learned preconditioner on jittered 64-well snapshots (N_occ = 64, 72^3,
     25 Ry, 256 PDEP, 40 % of the pairs): plain FP32 solves of the first
@@ -358,6 +384,9 @@ def main():
     ap.add_argument("--learned", type=int, default=0, metavar="N",
                     help="also run the learned preconditioner on N jittered 64-well snapshots "
                          "(4/5 train, 1/5 test; reported under learned)")
+    ap.add_argument("--lanczos", type=int, default=0, metavar="N",
+                    help="also run N Lanczos steps for the 3 dipole perturbations of the "
+                         "bench cell (reported under lanczos)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB read + 1 GiB write elementwise kernel first "
                          "(scale reference for HBM byte counters)")
@@ -469,6 +498,9 @@ def main():
     if not args.no_tts:
         log("time to solution")
         res["time_to_solution"] = time_to_solution(args, torch, pkg)
+    if args.lanczos > 0:
+        log("lanczos")
+        res["lanczos"] = lanczos_run(args, torch, pkg, ctx, cell, st, prec)
     if args.uneven_batch > 0:
         log("uneven batch")
         res["uneven_batch"] = uneven_batch(args, torch, pkg)
