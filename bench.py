@@ -272,6 +272,7 @@ def lanczos_run(args, torch, pkg, ctx, cell, st, prec):
     n = args.lanczos
     with torch.cuda.stream(st):
         D = torch.from_numpy(dipole_block(cell, 3)).to("cuda")
+        shape, _ = ctx.autotune(3, prec, n_rep=2)   # K1d shape for 3-vector applies (set-up)
         ctx.set_graph(True)
         ctx.lanczos(D, 2, prec)                  # capture the 3-vector apply graph
         torch.cuda.synchronize()
@@ -282,9 +283,10 @@ def lanczos_run(args, torch, pkg, ctx, cell, st, prec):
     omega = np.linspace(0.0, 1.0, 2001)
     s = pkg.lanczos_spectrum(alpha[0], beta[0], omega, 0.02)
     peak = float(omega[int(np.argmax(-s.imag))])
-    log(f"lanczos: {n} steps x 3 polarisations in {sec:.2f} s, x peak at {peak:.4f} Ha")
+    log(f"lanczos: {n} steps x 3 polarisations in {sec:.2f} s, x peak at {peak:.4f} Ha "
+        f"(K1d shape {shape})")
     return {"steps": n, "n_pol": 3, "seconds": sec, "steps_per_s": n / sec,
-            "applies_per_s": 3 * n / sec, "precision": args.precision,
+            "applies_per_s": 3 * n / sec, "precision": args.precision, "k1d_shape": shape,
             "x_peak_ha": peak, "eta_ha": 0.02}
 
 
