@@ -175,33 +175,40 @@ __global__ void __launch_bounds__(256) k_gemm_f32m(int M, int N, int K, float al
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4_t){0.f, 0.f, 0.f, 0.f};
-    for (int k0 = kbeg; k0 < kend; k0 += TK) {
+    // the next k-step's tiles are loaded into registers while the current
+    // one is multiplied from LDS
+    float ra[4], rb[4];
+    auto fetch = [&](int k0) {
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
             const int idx = tid + l * 256;
             const int mm = idx >> 4, kk = idx & 15;
             const int gm = m0 + mm, gk = k0 + kk;
-            As[mm][kk] = (gm < M && gk < kend) ? A[(size_t)gm * lda + gk] : 0.f;
+            ra[l] = (gm < M && gk < kend) ? A[(size_t)gm * lda + gk] : 0.f;
         }
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
             const int idx = tid + l * 256;
-            int nn, kk;
-            float x;
             if (NT) {
-                nn = idx >> 4;
-                kk = idx & 15;
-                const int gn = n0 + nn, gk = k0 + kk;
-                x = (gn < N && gk < kend) ? Bm[(size_t)gn * ldb + gk] : 0.f;
+                const int gn = n0 + (idx >> 4), gk = k0 + (idx & 15);
+                rb[l] = (gn < N && gk < kend) ? Bm[(size_t)gn * ldb + gk] : 0.f;
             } else {
-                kk = idx >> 6;
-                nn = idx & 63;
-                const int gn = n0 + nn, gk = k0 + kk;
-                x = (gn < N && gk < kend) ? Bm[(size_t)gk * ldb + gn] : 0.f;
+                const int gn = n0 + (idx & 63), gk = k0 + (idx >> 6);
+                rb[l] = (gn < N && gk < kend) ? Bm[(size_t)gk * ldb + gn] : 0.f;
             }
-            Bs[nn][kk] = x;
+        }
+    };
+    if (kbeg < kend) fetch(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += TK) {
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            const int idx = tid + l * 256;
+            As[idx >> 4][idx & 15] = ra[l];
+            if (NT) Bs[idx >> 4][idx & 15] = rb[l];
+            else Bs[idx & 63][idx >> 6] = rb[l];
         }
         __syncthreads();
+        if (k0 + TK < kend) fetch(k0 + TK);
         const int r16 = lane & 15, kq = lane >> 4;
 #pragma unroll
         for (int sub = 0; sub < TK / 4; ++sub) {
