@@ -53,48 +53,45 @@ __global__ void __launch_bounds__(256) k_gemm_bf16x3(int M, int N, int K, float 
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4_t){0.f, 0.f, 0.f, 0.f};
+    // the next k-step's values are loaded into registers while the current
+    // one is multiplied from LDS
+    float ra[4], rb[4];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            const int idx = tid + l * 256;
+            if (TA) {
+                const int gm = m0 + (idx & 63), gk = k0 + (idx >> 6);
+                ra[l] = (gm < M && gk < kend) ? A[(size_t)gk * lda + gm] : 0.f;
+            } else {
+                const int gm = m0 + (idx >> 4), gk = k0 + (idx & 15);
+                ra[l] = (gm < M && gk < kend) ? A[(size_t)gm * lda + gk] : 0.f;
+            }
+            if (NT) {
+                const int gn = n0 + (idx >> 4), gk = k0 + (idx & 15);
+                rb[l] = (gn < N && gk < kend) ? Bm[(size_t)gn * ldb + gk] : 0.f;
+            } else {
+                const int gn = n0 + (idx & 63), gk = k0 + (idx >> 6);
+                rb[l] = (gn < N && gk < kend) ? Bm[(size_t)gk * ldb + gn] : 0.f;
+            }
+        }
+    };
+    if (kbeg < kend) fetch(kbeg);
     for (int k0 = kbeg; k0 < kend; k0 += TK) {
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
             const int idx = tid + l * 256;
-            int mm, kk;
-            float x;
-            if (TA) {
-                kk = idx >> 6;
-                mm = idx & 63;
-                const int gm = m0 + mm, gk = k0 + kk;
-                x = (gm < M && gk < kend) ? A[(size_t)gk * lda + gm] : 0.f;
-            } else {
-                mm = idx >> 4;
-                kk = idx & 15;
-                const int gm = m0 + mm, gk = k0 + kk;
-                x = (gm < M && gk < kend) ? A[(size_t)gm * lda + gk] : 0.f;
-            }
-            const unsigned short h = bf16_rne(x);
-            Ah[mm][kk] = h;
-            if (SPLIT) Al[mm][kk] = bf16_rne(x - bf16_to_f32(h));
-        }
-#pragma unroll
-        for (int l = 0; l < 4; ++l) {
-            const int idx = tid + l * 256;
-            int nn, kk;
-            float x;
-            if (NT) {
-                nn = idx >> 4;
-                kk = idx & 15;
-                const int gn = n0 + nn, gk = k0 + kk;
-                x = (gn < N && gk < kend) ? Bm[(size_t)gn * ldb + gk] : 0.f;
-            } else {
-                kk = idx >> 6;
-                nn = idx & 63;
-                const int gn = n0 + nn, gk = k0 + kk;
-                x = (gn < N && gk < kend) ? Bm[(size_t)gk * ldb + gn] : 0.f;
-            }
-            const unsigned short h = bf16_rne(x);
-            Bh[nn][kk] = h;
-            if (SPLIT) Bl[nn][kk] = bf16_rne(x - bf16_to_f32(h));
+            const int mm = TA ? (idx & 63) : (idx >> 4), ka = TA ? (idx >> 6) : (idx & 15);
+            const unsigned short h = bf16_rne(ra[l]);
+            Ah[mm][ka] = h;
+            if (SPLIT) Al[mm][ka] = bf16_rne(ra[l] - bf16_to_f32(h));
+            const int nn = NT ? (idx >> 4) : (idx & 63), kb = NT ? (idx & 15) : (idx >> 6);
+            const unsigned short g = bf16_rne(rb[l]);
+            Bh[nn][kb] = g;
+            if (SPLIT) Bl[nn][kb] = bf16_rne(rb[l] - bf16_to_f32(g));
         }
         __syncthreads();
+        if (k0 + TK < kend) fetch(k0 + TK);
         const int r16 = lane & 15, kq = (lane >> 4) * 4;
         bf16x4_t ah[2], al[2], bh[2], bl[2];
 #pragma unroll
