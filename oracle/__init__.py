@@ -14,6 +14,8 @@ Modules
   eh          explicit electron-hole Hamiltonian over all empty states
               (the e-h-basis formulation of Sec. 2 / Sec. 5), built with
               its own primitives, used to pin the Liouville form
+  jade        Wannier localisation: the six A^(n) matrices and the JADE
+              sweeps of Sec. 2 (Eq. (wannier), Eq. (spread))
   mlp         reference forward/backward of the learned preconditioner's
               network (parity unpinned against the paper: no such network
               appears there)
