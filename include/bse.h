@@ -92,6 +92,46 @@ bse_status bse_destroy(bse_ctx *ctx);
  * triplet channel.  Drops a captured apply graph. */
 bse_status bse_set_terms(bse_ctx *ctx, double k1e, double k1d, double scissor);
 
+/* Wannier localisation (Sec. 2, Eq. wannier, Eq. spread).  The usual order is
+ * bse_create with canonical orbitals, bse_spread_matrices, bse_jade,
+ * bse_localize, then bse_build_pairs.
+ *
+ * bse_spread_matrices: A^(n)_vw = <psi_v|M^(n)|psi_w> of the context's
+ * orbitals for the six operators M^(1..6) = cos, sin of 2 pi x / L, of
+ * 2 pi y / L and of 2 pi z / L (in that order), as FP64 sums over the grid.
+ *   A  dev [6][n_occ][n_occ] FP64 output, row-major, symmetric.
+ * Synchronises the stream.  Errors: BSE_ERR_ARG (null A). */
+bse_status bse_spread_matrices(bse_ctx *ctx, double *A);
+
+/* bse_jade: joint approximate diagonalisation of n_mat real symmetric N x N
+ * matrices (the JADE minimisation of Eq. spread: the sum over n of the squared
+ * off-diagonal entries of Q^T A^(n) Q).  Start: Q as given (start_given = 1)
+ * or the eigenvectors of A^(1) (start_given = 0, the choice of Sec. 2).
+ * Sweeps of rounds of disjoint pairs (circle method; index N rounded up to
+ * even minus one stays fixed); each pair's angle is Cardoso and Souloumiac's
+ * t = atan2(2 g01, g00 - g11) / 4 with G = sum_n h_n h_n^T, h_n = (A_pp -
+ * A_qq, 2 A_pq); rotations with |sin t| < tol are skipped and the sweeps stop
+ * after one that rotates nothing, or after max_sweeps.
+ *   A          dev [n_mat][N][N] FP64, in place: on return Q^T A^(n) Q
+ *   Q          dev [N][N] FP64: the start if start_given, on return the
+ *              accumulated rotation (column v: localised orbital v in terms
+ *              of the input orbitals)
+ *   n_sweeps   host, may be NULL: sweeps run
+ *   offsum     host, may be NULL: off-diagonal sum after the last sweep
+ * The context only lends its stream and workspace (N need not be n_occ).
+ * Synchronises the stream.  Errors: BSE_ERR_ARG (sizes, tol < 0, a
+ * non-finite start). */
+bse_status bse_jade(bse_ctx *ctx, int N, int n_mat, double *A, double *Q, int start_given,
+                    double tol, int max_sweeps, int *n_sweeps, double *offsum);
+
+/* bse_localize: rotate the context's orbitals, psi~_v = sum_w Q[w][v] psi_w
+ * and eps~ = Q^T eps Q (Eq. wannier), and derive their grid and FP32 copies
+ * again.
+ *   Q  dev [n_occ][n_occ] FP64 orthogonal (checked to 1e-8).
+ * Errors: BSE_ERR_STATE after bse_build_pairs (pairs and tau would go
+ * stale); BSE_ERR_ARG for a null, non-finite or non-orthogonal Q. */
+bse_status bse_localize(bse_ctx *ctx, const double *Q);
+
 /* Measure of every orbital pair (Eq. overlap or the abs-L1 measure).
  *   m  host [n_occ][n_occ] FP64 output.  Synchronises the stream. */
 bse_status bse_pair_measure(bse_ctx *ctx, int measure, double *m);

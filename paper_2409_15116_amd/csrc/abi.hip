@@ -104,6 +104,34 @@ bse_status bse_pair_measure(bse_ctx *c, int measure, double *m) {
     BSE_GUARD(bse::ctx_measure(c, measure, m))
 }
 
+bse_status bse_spread_matrices(bse_ctx *c, double *A) {
+    CHECK_CTX(c);
+    if (!A) {
+        set_error("bse_spread_matrices: null output");
+        return BSE_ERR_ARG;
+    }
+    BSE_GUARD(bse::ctx_spread_matrices(c, A))
+}
+
+bse_status bse_jade(bse_ctx *c, int N, int n_mat, double *A, double *Q, int start_given,
+                    double tol, int max_sweeps, int *n_sweeps, double *offsum) {
+    CHECK_CTX(c);
+    if (!A || !Q) {
+        set_error("bse_jade: null matrix");
+        return BSE_ERR_ARG;
+    }
+    BSE_GUARD(bse::ctx_jade(c, N, n_mat, A, Q, start_given, tol, max_sweeps, n_sweeps, offsum))
+}
+
+bse_status bse_localize(bse_ctx *c, const double *Q) {
+    CHECK_CTX(c);
+    if (!Q) {
+        set_error("bse_localize: null Q");
+        return BSE_ERR_ARG;
+    }
+    BSE_GUARD(bse::ctx_localize(c, Q))
+}
+
 bse_status bse_build_pairs(bse_ctx *c, int measure, double threshold, int64_t *n_pairs) {
     CHECK_CTX(c);
     if (!std::isfinite(threshold)) {

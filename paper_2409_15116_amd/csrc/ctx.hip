@@ -207,6 +207,13 @@ void ctx_setup(bse_ctx *c, const bse_cell *cell, const double *psi, const double
             BSE_REQUIRE(std::fabs(eps[i * no + j] - eps[j * no + i]) <= 1e-10 * (1 + std::fabs(eps[i * no + j])),
                         BSE_ERR_ARG, "eps is not symmetric");
         }
+    ctx_derive_orbitals(c);
+}
+
+// Everything derived from psi64 and eps_h: the device energies, the FP32
+// orbitals and the orbitals on the grid (FP64 and FP32).
+void ctx_derive_orbitals(bse_ctx *c) {
+    const size_t no = c->n_occ, npw = c->npw, nr = c->nr;
     ctx_set_terms(c, c->k1e, c->k1d, c->scissor);
     c->psi32.alloc(no * npw);
     convert<double, float>(c->psi64.p, c->psi32.p, no * npw, c->stream);

@@ -150,6 +150,11 @@ namespace bse {
 void ctx_setup(bse_ctx *c, const bse_cell *cell, const double *psi, const double *eps,
                const double *V);
 void ctx_free(bse_ctx *c);
+void ctx_derive_orbitals(bse_ctx *c);
+void ctx_spread_matrices(bse_ctx *c, double *A);
+void ctx_jade(bse_ctx *c, int N, int nm, double *A, double *Q, int start_given, double tol,
+              int max_sweeps, int *n_sweeps, double *offsum);
+void ctx_localize(bse_ctx *c, const double *Q);
 void ctx_set_terms(bse_ctx *c, double k1e, double k1d, double scissor);
 void ctx_measure(bse_ctx *c, int kind, double *m_host);
 void ctx_build_pairs(bse_ctx *c, int kind, double thr);

@@ -22,7 +22,7 @@ namespace bse {
 // with Wilkinson shifts (Golub and Van Loan, Matrix Computations, Alg. 8.3.1
 // and 8.3.3).  A is n x n row-major symmetric; w ascending, Z[i * n + j] =
 // component i of eigenvector j.
-static void sym_eig(int n, std::vector<double> A, std::vector<double> &w, std::vector<double> &Z) {
+void sym_eig(int n, std::vector<double> A, std::vector<double> &w, std::vector<double> &Z) {
     auto at = [&](int i, int j) -> double & { return A[(size_t)i * n + j]; };
     auto z = [&](int i, int j) -> double & { return Z[(size_t)j * n + i]; };  // stored transposed
     Z.assign((size_t)n * n, 0.0);

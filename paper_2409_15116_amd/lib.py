@@ -63,6 +63,9 @@ def load():
         "bse_set_terms": (i32, [vp, dbl, dbl, dbl]),
         "bse_pair_measure": (i32, [vp, i32, vp]),
         "bse_build_pairs": (i32, [vp, i32, dbl, C.POINTER(i64)]),
+        "bse_spread_matrices": (i32, [vp, vp]),
+        "bse_jade": (i32, [vp, i32, i32, vp, vp, i32, dbl, i32, C.POINTER(i32), C.POINTER(dbl)]),
+        "bse_localize": (i32, [vp, vp]),
         "bse_threshold_for_fraction": (dbl, [vp, i32, dbl]),
         "bse_get_pairs": (i32, [vp, vp]),
         "bse_screen_pairs": (i32, [vp, vp, vp, i32, i32]),
@@ -118,6 +121,7 @@ def exported_symbols():
             "bse_mlp_set_weights", "bse_mlp_forward", "bse_mlp_gradients", "bse_mlp_train",
             "bse_set_learned", "bse_learned_centers", "bse_davidson_record",
             "bse_lanczos", "bse_lanczos_spectrum",
+            "bse_spread_matrices", "bse_jade", "bse_localize",
             "bse_k1d_num_shapes", "bse_k1d_shape_info", "bse_autotune", "bse_set_k1d_shape",
             "bse_batch_create",
             "bse_batch_destroy", "bse_batch_set_graph", "bse_batch_apply", "bse_batch_davidson"]
@@ -181,6 +185,33 @@ class BseContext:
         m = np.empty((self.n_occ, self.n_occ))
         _check(load().bse_pair_measure(self.h, kind, m.ctypes.data))
         return m
+
+    def spread_matrices(self):
+        """The six A^(n) of the context's orbitals (device FP64 [6, n_occ, n_occ])."""
+        torch = self.torch
+        A = torch.empty((6, self.n_occ, self.n_occ), dtype=torch.float64, device="cuda")
+        _check(load().bse_spread_matrices(self.h, A.data_ptr()))
+        return A
+
+    def jade(self, A, Q=None, tol=1e-7, max_sweeps=100):
+        """JADE on device FP64 matrices A [n_mat, N, N] (rotated in place).
+        Q: device [N, N] start, or None for the eigenvectors of A[0].  Returns
+        (Q, sweeps, off-diagonal sum)."""
+        torch = self.torch
+        nm, N = int(A.shape[0]), int(A.shape[1])
+        _dptr(A, torch.float64, (nm, N, N))
+        given = Q is not None
+        if not given:
+            Q = torch.empty((N, N), dtype=torch.float64, device="cuda")
+        _dptr(Q, torch.float64, (N, N))
+        sw, off = C.c_int(), C.c_double()
+        _check(load().bse_jade(self.h, N, nm, A.data_ptr(), Q.data_ptr(), int(given), float(tol),
+                               int(max_sweeps), C.byref(sw), C.byref(off)))
+        return Q, int(sw.value), float(off.value)
+
+    def localize(self, Q):
+        """Rotate the context's orbitals by Q (device FP64 [n_occ, n_occ])."""
+        _check(load().bse_localize(self.h, _dptr(Q, self.torch.float64, (self.n_occ, self.n_occ))))
 
     def build_pairs(self, kind=MEASURE_ABS_L1, threshold=-1.0):
         P = C.c_int64()
