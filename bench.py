@@ -290,6 +290,43 @@ def lanczos_run(args, torch, pkg, ctx, cell, st, prec):
             "x_peak_ha": peak, "eta_ha": 0.02}
 
 
+def jade_run(args, torch, pkg):
+    """Wannier localisation (Sec. 2) of the canonical orbitals of each named
+    cell on the GPU: the six spread matrices, the JADE sweeps from the
+    eigenvectors of A^(1) (tol 1e-7 on sin t, at most 60 sweeps) and the
+    rotation of the context's orbitals, each timed after a synchronisation."""
+    from synth import make_cell
+    out = []
+    for name in args.jade.split(","):
+        cell = make_cell(name)
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            ctx = pkg.context_for(cell, localized=False, stream=st)
+            torch.cuda.synchronize()
+            t0 = time.time()
+            A = ctx.spread_matrices()
+            torch.cuda.synchronize()
+            t1 = time.time()
+            Q, sweeps, off = ctx.jade(A, tol=1e-7, max_sweeps=60)
+            torch.cuda.synchronize()
+            t2 = time.time()
+            ctx.localize(Q)
+            torch.cuda.synchronize()
+            t3 = time.time()
+            ctx.close()
+        N = cell.n_occ
+        rounds = sweeps * (N + (N & 1) - 1)
+        ref = cell.jade_history[-1] if len(cell.jade_history) else None
+        log(f"jade {name}: N_occ {N}, spread {t1 - t0:.3f} s, {sweeps} sweeps in {t2 - t1:.3f} s "
+            f"({(t2 - t1) / max(rounds, 1) * 1e6:.1f} us per round), localise {t3 - t2:.3f} s, "
+            f"off-diagonal {off:.6g}")
+        out.append({"cell": name, "n_occ": N, "grid": cell.n, "spread_s": t1 - t0,
+                    "jade_s": t2 - t1, "sweeps": sweeps, "rounds": rounds,
+                    "us_per_round": (t2 - t1) / max(rounds, 1) * 1e6, "localize_s": t3 - t2,
+                    "offdiag": off, "offdiag_input_fixture": ref})
+    return out
+
+
 def learned_c5(args, torch, pkg):
     """Learned preconditioner on jittered 64-well snapshots (N_occ = 64, 72^3,
     25 Ry, 256 PDEP, 40 % of the pairs): plain FP32 solves of the first
@@ -389,6 +426,9 @@ def main():
     ap.add_argument("--lanczos", type=int, default=0, metavar="N",
                     help="also run N Lanczos steps for the 3 dipole perturbations of the "
                          "bench cell (reported under lanczos)")
+    ap.add_argument("--jade", default="", metavar="CELLS",
+                    help="also localise the canonical orbitals of these cells (comma list) "
+                         "on the GPU (reported under jade)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB read + 1 GiB write elementwise kernel first "
                          "(scale reference for HBM byte counters)")
@@ -503,6 +543,9 @@ def main():
     if args.lanczos > 0:
         log("lanczos")
         res["lanczos"] = lanczos_run(args, torch, pkg, ctx, cell, st, prec)
+    if args.jade:
+        log("jade")
+        res["jade"] = jade_run(args, torch, pkg)
     if args.uneven_batch > 0:
         log("uneven batch")
         res["uneven_batch"] = uneven_batch(args, torch, pkg)
