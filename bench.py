@@ -295,9 +295,30 @@ def jade_run(args, torch, pkg):
     cell on the GPU: the six spread matrices, the JADE sweeps from the
     eigenvectors of A^(1) (tol 1e-7 on sin t, at most 60 sweeps) and the
     rotation of the context's orbitals, each timed after a synchronisation."""
-    from synth import make_cell
+    from synth import make_cell, near_commuting_matrices
     out = []
     for name in args.jade.split(","):
+        if name.startswith("N") and name[1:].isdigit():
+            # synthetic: six near-commuting N x N matrices (the paper's largest
+            # case has 2048 orbitals), from Q = I, on the bench cell's context
+            N = int(name[1:])
+            A0, _ = near_commuting_matrices(N, seed=5)
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                A = torch.from_numpy(A0).to("cuda")
+                Q0 = torch.eye(N, dtype=torch.float64, device="cuda")   # start: Q = I
+                torch.cuda.synchronize()
+                t1 = time.time()
+                Q, sweeps, off = args._ctx.jade(A, Q0, tol=1e-7, max_sweeps=60)
+                torch.cuda.synchronize()
+                t2 = time.time()
+            rounds = sweeps * (N + (N & 1) - 1)
+            log(f"jade {name}: {sweeps} sweeps in {t2 - t1:.3f} s "
+                f"({(t2 - t1) / max(rounds, 1) * 1e6:.1f} us per round), off-diagonal {off:.6g}")
+            out.append({"cell": name, "n_occ": N, "jade_s": t2 - t1, "sweeps": sweeps,
+                        "rounds": rounds, "us_per_round": (t2 - t1) / max(rounds, 1) * 1e6,
+                        "offdiag": off})
+            continue
         cell = make_cell(name)
         st = torch.cuda.Stream()
         with torch.cuda.stream(st):
@@ -545,6 +566,7 @@ def main():
         res["lanczos"] = lanczos_run(args, torch, pkg, ctx, cell, st, prec)
     if args.jade:
         log("jade")
+        args._ctx = ctx
         res["jade"] = jade_run(args, torch, pkg)
     if args.uneven_batch > 0:
         log("uneven batch")

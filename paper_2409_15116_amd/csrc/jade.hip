@@ -86,11 +86,39 @@ __global__ void k_jade_angles(const double *__restrict__ A, int nm, int N, int M
     pq[k] = e;
 }
 
-// Rotations of one round.  Threads [0, nm * H * H): block (k, l), k <= l, of
-// matrix m: rows {p_k, q_k}, columns {p_l, q_l}; the mirror block (l, k) is
-// written as its transpose, so every A stays exactly symmetric.  Threads
-// [nm * H * H, + N * H): row i of Q, pair l.  New column p = c a_p + s a_q,
-// new column q = -s a_p + c a_q; rows likewise.
+// A^(n) <- (A^(n) + A^(n)T) / 2, one thread per (n, i < j): the start
+// transform's rounding leaves the products slightly unsymmetric
+__global__ void k_symmetrize(double *__restrict__ A, int nm, int N) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nn = (long long)N * N;
+    if (t >= nm * nn) return;
+    const int i = (int)((t % nn) / N), j = (int)(t % N);
+    if (i >= j) return;
+    double *a = A + (t / nn) * nn;
+    const double s = 0.5 * (a[(size_t)i * N + j] + a[(size_t)j * N + i]);
+    a[(size_t)i * N + j] = s;
+    a[(size_t)j * N + i] = s;
+}
+
+// 2x2 block rotation B <- Jr^T B Jc: columns first (Jc), then rows (Jr).
+// New column p = c b_p + s b_q, new column q = -s b_p + c b_q; rows likewise.
+__device__ __forceinline__ void rot2(double2 jr, double2 jc, double &b00, double &b01, double &b10,
+                                     double &b11) {
+    const double c0 = jc.x * b00 + jc.y * b01, c1 = -jc.y * b00 + jc.x * b01;
+    const double d0 = jc.x * b10 + jc.y * b11, d1 = -jc.y * b10 + jc.x * b11;
+    b00 = jr.x * c0 + jr.y * d0;
+    b01 = jr.x * c1 + jr.y * d1;
+    b10 = -jr.y * c0 + jr.x * d0;
+    b11 = -jr.y * c1 + jr.x * d1;
+}
+
+// Rotations of one round.  Threads [0, nm * H * H): block (k, l) of matrix m,
+// rows {p_k, q_k} and columns {p_l, q_l}, read and written by this thread
+// only (consecutive threads walk l, so both stay close to row-contiguous).
+// Block (k, l) with k > l is the transpose of block (l, k): it is evaluated
+// as that block's product (same operands, same order) and transposed, so
+// every A stays exactly symmetric.  Threads [nm * H * H, + N * H): row i of
+// Q, pair l.
 __global__ void k_jade_rotate(double *__restrict__ A, double *__restrict__ Q, int nm, int N,
                               int H, const double2 *__restrict__ cs, const int2 *__restrict__ pq) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -99,7 +127,6 @@ __global__ void k_jade_rotate(double *__restrict__ A, double *__restrict__ Q, in
         const int m = (int)(t / ((long long)H * H));
         const int k = (int)((t / H) % H);
         const int l = (int)(t % H);
-        if (k > l) return;
         double *a = A + (size_t)m * N * N;
         const int2 rk = pq[k], cl = pq[l];
         const double2 jk = cs[k], jl = cs[l];
@@ -108,38 +135,21 @@ __global__ void k_jade_rotate(double *__restrict__ A, double *__restrict__ Q, in
         double b01 = cq ? a[(size_t)rk.x * N + cl.y] : 0.0;
         double b10 = rq ? a[(size_t)rk.y * N + cl.x] : 0.0;
         double b11 = (rq && cq) ? a[(size_t)rk.y * N + cl.y] : 0.0;
-        // columns: B J_l
-        const double c0 = jl.x * b00 + jl.y * b01, c1 = -jl.y * b00 + jl.x * b01;
-        const double d0 = jl.x * b10 + jl.y * b11, d1 = -jl.y * b10 + jl.x * b11;
-        // rows: J_k^T (B J_l)
-        b00 = jk.x * c0 + jk.y * d0;
-        b01 = jk.x * c1 + jk.y * d1;
-        b10 = -jk.y * c0 + jk.x * d0;
-        b11 = -jk.y * c1 + jk.x * d1;
-        if (k == l) {
-            // one diagonal block: (p, q) and (q, p) hold the same value
-            a[(size_t)rk.x * N + rk.x] = b00;
-            if (rq) {
-                a[(size_t)rk.x * N + rk.y] = b01;
-                a[(size_t)rk.y * N + rk.x] = b01;
-                a[(size_t)rk.y * N + rk.y] = b11;
-            }
-            return;
+        if (k <= l) {
+            rot2(jk, jl, b00, b01, b10, b11);
+        } else {
+            double t00 = b00, t01 = b10, t10 = b01, t11 = b11;  // block (l, k)
+            rot2(jl, jk, t00, t01, t10, t11);
+            b00 = t00;
+            b01 = t10;
+            b10 = t01;
+            b11 = t11;
         }
+        if (k == l) b10 = b01;  // one diagonal block: (p, q) and (q, p) hold the same value
         a[(size_t)rk.x * N + cl.x] = b00;
-        a[(size_t)cl.x * N + rk.x] = b00;
-        if (cq) {
-            a[(size_t)rk.x * N + cl.y] = b01;
-            a[(size_t)cl.y * N + rk.x] = b01;
-        }
-        if (rq) {
-            a[(size_t)rk.y * N + cl.x] = b10;
-            a[(size_t)cl.x * N + rk.y] = b10;
-        }
-        if (rq && cq) {
-            a[(size_t)rk.y * N + cl.y] = b11;
-            a[(size_t)cl.y * N + rk.y] = b11;
-        }
+        if (cq) a[(size_t)rk.x * N + cl.y] = b01;
+        if (rq) a[(size_t)rk.y * N + cl.x] = b10;
+        if (rq && cq) a[(size_t)rk.y * N + cl.y] = b11;
         return;
     }
     const long long u = t - nblk;
@@ -209,6 +219,8 @@ void ctx_jade(bse_ctx *c, int N, int nm, double *A, double *Q, int start_given, 
                  c->gws, st);
     gemm<double>(false, N, N, N, 1.0, dq0t.p, N, 0, T.p, N, (long long)nn, 0.0, A, N,
                  (long long)nn, nm, c->gws, st);
+    k_symmetrize<<<(unsigned)(((long long)nm * nn + 255) / 256), 256, 0, st>>>(A, nm, N);
+    BSE_LAUNCH_CHECK();
     int sweeps = 0;
     {
         const long long nthr = (long long)nm * H * H + (long long)N * H;

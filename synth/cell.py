@@ -566,3 +566,17 @@ def dipole_block(cell: Cell, n_pol: int = 3) -> np.ndarray:
 def random_block(shape, seed: int) -> np.ndarray:
     """Plain N(0,1) block of the given shape."""
     return np.random.default_rng(seed).standard_normal(shape)
+
+
+def near_commuting_matrices(N: int, seed: int, n_mat: int = 6, noise: float = 1e-3):
+    """n_mat symmetric N x N matrices R D_n R^T + noise * (Z + Z^T)/2 with one
+    seeded orthogonal R and diagonal D_n ~ U(-1, 1): the shape of the spread
+    matrices of well-separated localised orbitals, at any N.  Returns (A, R)."""
+    rng = np.random.default_rng(seed)
+    R, Rr = np.linalg.qr(rng.standard_normal((N, N)))
+    R *= np.sign(np.diag(Rr))[None, :]
+    A = np.empty((n_mat, N, N))
+    for k in range(n_mat):
+        Z = rng.standard_normal((N, N))
+        A[k] = (R * rng.uniform(-1.0, 1.0, N)[None, :]) @ R.T + 0.5 * noise * (Z + Z.T)
+    return A, R

@@ -132,3 +132,26 @@ def test_localize_then_apply():
     with pytest.raises(_pkg().BseError):           # pairs exist: the orbitals are fixed
         ctx.localize(Q)
     ctx.close()
+
+
+def test_jade_large_properties():
+    """Six near-commuting 1024 x 1024 matrices from Q = I (the oracle's dense
+    rounds are too slow at this size): Q orthogonal, the returned matrices
+    equal Q^T A Q, the off-diagonal sum falls to the noise level and the
+    common eigenbasis is recovered up to order and sign."""
+    from synth import near_commuting_matrices
+    say("jade_large", 1024)
+    c, ctx, b = _canonical("c1")
+    A, R = near_commuting_matrices(1024, seed=3, noise=1e-6)
+    Ad = _dev(A)
+    Qd, sw, off = ctx.jade(Ad, _dev(np.eye(1024)), tol=1e-7, max_sweeps=30)
+    assert sw < 30
+    I = torch.eye(1024, dtype=torch.float64, device="cuda")
+    assert (Qd.T @ Qd - I).abs().max().item() < 1e-11
+    rot = Qd.T @ _dev(A) @ Qd
+    assert (rot - Ad).abs().max().item() < 1e-10
+    off0 = float(sum((a ** 2).sum() - (np.diag(a) ** 2).sum() for a in A))   # at Q = I
+    assert off < 1e-6 * off0
+    P = np.abs(Qd.cpu().numpy().T @ R)
+    assert P.max(1).min() > 0.999
+    ctx.close()
