@@ -180,6 +180,35 @@ void ctx_spread_matrices(bse_ctx *c, double *A) {
     BSE_HIP(hipStreamSynchronize(c->stream));
 }
 
+// Sweeps until one rotates nothing (or max_sweeps); returns the sweeps run.
+static int run_sweeps(hipStream_t st, double *A, double *Q, int nm, int N, double tol,
+                      int max_sweeps, double2 *cs, int2 *pq, int *flag) {
+    const int M = N + (N & 1), H = M / 2;
+    const long long nthr = (long long)nm * H * H + (long long)N * H;
+    const unsigned ablk = (unsigned)((H + 63) / 64), rblk = (unsigned)((nthr + 255) / 256);
+    int sweeps = 0;
+    while (sweeps < max_sweeps) {
+        ++sweeps;
+        BSE_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
+        for (int r = 0; r < M - 1; ++r) {
+            k_jade_angles<<<ablk, 64, 0, st>>>(A, nm, N, M, r, tol, cs, pq, flag);
+            BSE_LAUNCH_CHECK();
+            k_jade_rotate<<<rblk, 256, 0, st>>>(A, Q, nm, N, H, cs, pq);
+            BSE_LAUNCH_CHECK();
+        }
+        int any = 0;
+        BSE_HIP(hipMemcpyAsync(&any, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+        BSE_HIP(hipStreamSynchronize(st));
+        if (!any) break;
+    }
+    return sweeps;
+}
+
+// Above this order the start's eigenvectors come from the device (the
+// one-matrix form of the sweeps is Jacobi's eigenvalue method) rather than
+// from the host's O(N^3) eigensolver.
+constexpr int JADE_HOST_EIG_MAX = 256;
+
 void ctx_jade(bse_ctx *c, int N, int nm, double *A, double *Q, int start_given, double tol,
               int max_sweeps, int *n_sweeps, double *offsum) {
     BSE_REQUIRE(N >= 1 && N <= 65536 && nm >= 1 && nm <= 64, BSE_ERR_ARG,
@@ -188,30 +217,42 @@ void ctx_jade(bse_ctx *c, int N, int nm, double *A, double *Q, int start_given, 
                 "bse_jade: bad tol or max_sweeps");
     hipStream_t st = c->stream;
     const size_t nn = (size_t)N * N;
+    const int H = (N + (N & 1)) / 2;
+    Dev<double2> cs;
+    Dev<int2> pq;
+    Dev<int> flag;
+    cs.alloc(H);
+    pq.alloc(H);
+    flag.alloc(1);
     std::vector<double> q0(nn), q0t(nn);
     if (start_given) {
         BSE_HIP(hipMemcpyAsync(q0.data(), Q, nn * 8, hipMemcpyDeviceToHost, st));
         BSE_HIP(hipStreamSynchronize(st));
-    } else {
+    } else if (N <= JADE_HOST_EIG_MAX) {
         // start: eigenvectors of A^(1) (Sec. 2)
         std::vector<double> a0(nn), w;
         BSE_HIP(hipMemcpyAsync(a0.data(), A, nn * 8, hipMemcpyDeviceToHost, st));
         BSE_HIP(hipStreamSynchronize(st));
         sym_eig(N, a0, w, q0);  // q0[i * N + j] = component i of eigenvector j
+    } else {
+        // start: eigenvectors of A^(1) by the sweeps on a copy of A^(1) alone
+        Dev<double> a1;
+        a1.alloc(nn);
+        BSE_HIP(hipMemcpyAsync(a1.p, A, nn * 8, hipMemcpyDeviceToDevice, st));
+        k_symmetrize<<<(unsigned)((nn + 255) / 256), 256, 0, st>>>(a1.p, 1, N);
+        BSE_LAUNCH_CHECK();
+        for (int i = 0; i < N; ++i) q0[(size_t)i * N + i] = 1.0;
+        BSE_HIP(hipMemcpyAsync(Q, q0.data(), nn * 8, hipMemcpyHostToDevice, st));
+        run_sweeps(st, a1.p, Q, 1, N, tol, 100, cs.p, pq.p, flag.p);
+        BSE_HIP(hipMemcpyAsync(q0.data(), Q, nn * 8, hipMemcpyDeviceToHost, st));
+        BSE_HIP(hipStreamSynchronize(st));
     }
     for (double x : q0) BSE_REQUIRE(std::isfinite(x), BSE_ERR_ARG, "bse_jade: non-finite start");
     for (int i = 0; i < N; ++i)
         for (int j = 0; j < N; ++j) q0t[(size_t)j * N + i] = q0[(size_t)i * N + j];
     Dev<double> dq0t, T;
-    Dev<double2> cs;
-    Dev<int2> pq;
-    Dev<int> flag;
     dq0t.alloc(nn);
     T.alloc(nn * nm);
-    const int M = N + (N & 1), H = M / 2;
-    cs.alloc(H);
-    pq.alloc(H);
-    flag.alloc(1);
     BSE_HIP(hipMemcpyAsync(Q, q0.data(), nn * 8, hipMemcpyHostToDevice, st));
     BSE_HIP(hipMemcpyAsync(dq0t.p, q0t.data(), nn * 8, hipMemcpyHostToDevice, st));
     // A^(n) <- Q0^T (A^(n) Q0), all matrices as one strided batch
@@ -221,25 +262,7 @@ void ctx_jade(bse_ctx *c, int N, int nm, double *A, double *Q, int start_given, 
                  (long long)nn, nm, c->gws, st);
     k_symmetrize<<<(unsigned)(((long long)nm * nn + 255) / 256), 256, 0, st>>>(A, nm, N);
     BSE_LAUNCH_CHECK();
-    int sweeps = 0;
-    {
-        const long long nthr = (long long)nm * H * H + (long long)N * H;
-        const unsigned ablk = (unsigned)((H + 63) / 64), rblk = (unsigned)((nthr + 255) / 256);
-        for (; sweeps < max_sweeps;) {
-            ++sweeps;
-            BSE_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), st));
-            for (int r = 0; r < M - 1; ++r) {
-                k_jade_angles<<<ablk, 64, 0, st>>>(A, nm, N, M, r, tol, cs.p, pq.p, flag.p);
-                BSE_LAUNCH_CHECK();
-                k_jade_rotate<<<rblk, 256, 0, st>>>(A, Q, nm, N, H, cs.p, pq.p);
-                BSE_LAUNCH_CHECK();
-            }
-            int any = 0;
-            BSE_HIP(hipMemcpyAsync(&any, flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
-            BSE_HIP(hipStreamSynchronize(st));
-            if (!any) break;
-        }
-    }
+    const int sweeps = run_sweeps(st, A, Q, nm, N, tol, max_sweeps, cs.p, pq.p, flag.p);
     if (n_sweeps) *n_sweeps = sweeps;
     if (offsum) {
         std::vector<double> a(nn * nm);
@@ -265,39 +288,35 @@ void ctx_localize(bse_ctx *c, const double *Q) {
     BSE_HIP(hipMemcpyAsync(q.data(), Q, nn * 8, hipMemcpyDeviceToHost, st));
     BSE_HIP(hipStreamSynchronize(st));
     for (double x : q) BSE_REQUIRE(std::isfinite(x), BSE_ERR_ARG, "bse_localize: non-finite Q");
-    double dev = 0;  // Q must be orthogonal: the rotated orbitals stay orthonormal
-    for (int i = 0; i < N; ++i)
-        for (int j = 0; j < N; ++j) {
-            double s = 0;
-            for (int k = 0; k < N; ++k) s += q[(size_t)k * N + i] * q[(size_t)k * N + j];
-            dev = std::max(dev, std::fabs(s - (i == j ? 1.0 : 0.0)));
-        }
-    BSE_REQUIRE(dev <= 1e-8, BSE_ERR_ARG, "bse_localize: Q is not orthogonal (%.3g)", dev);
     for (int i = 0; i < N; ++i)
         for (int j = 0; j < N; ++j) qt[(size_t)j * N + i] = q[(size_t)i * N + j];
-    // eps~ = Q^T eps Q (host, N x N)
-    std::vector<double> t(nn, 0.0), e2(nn, 0.0);
-    const std::vector<double> &e = c->eps_h;
+    // Q^T Q, eps~ = Q^T (eps Q) and psi~ = Q^T psi on the device
+    Dev<double> dqt, de, dt, dg, p2;
+    dqt.alloc(nn);
+    de.alloc(nn);
+    dt.alloc(nn);
+    dg.alloc(2 * nn);
+    p2.alloc((size_t)N * npw);
+    BSE_HIP(hipMemcpyAsync(dqt.p, qt.data(), nn * 8, hipMemcpyHostToDevice, st));
+    BSE_HIP(hipMemcpyAsync(de.p, c->eps_h.data(), nn * 8, hipMemcpyHostToDevice, st));
+    gemm<double>(false, N, N, N, 1.0, dqt.p, N, 0, Q, N, 0, 0.0, dg.p, N, 0, 1, c->gws, st);
+    gemm<double>(false, N, N, N, 1.0, de.p, N, 0, Q, N, 0, 0.0, dt.p, N, 0, 1, c->gws, st);
+    gemm<double>(false, N, N, N, 1.0, dqt.p, N, 0, dt.p, N, 0, 0.0, dg.p + nn, N, 0, 1, c->gws,
+                 st);
+    std::vector<double> g(2 * nn);
+    BSE_HIP(hipMemcpyAsync(g.data(), dg.p, 2 * nn * 8, hipMemcpyDeviceToHost, st));
+    BSE_HIP(hipStreamSynchronize(st));
+    double dev = 0;  // Q must be orthogonal: the rotated orbitals stay orthonormal
     for (int i = 0; i < N; ++i)
-        for (int k = 0; k < N; ++k) {
-            const double a = e[(size_t)i * N + k];
-            for (int j = 0; j < N; ++j) t[(size_t)i * N + j] += a * q[(size_t)k * N + j];
-        }
-    for (int i = 0; i < N; ++i)
-        for (int k = 0; k < N; ++k) {
-            const double a = qt[(size_t)i * N + k];
-            for (int j = 0; j < N; ++j) e2[(size_t)i * N + j] += a * t[(size_t)k * N + j];
-        }
+        for (int j = 0; j < N; ++j)
+            dev = std::max(dev, std::fabs(g[(size_t)i * N + j] - (i == j ? 1.0 : 0.0)));
+    BSE_REQUIRE(dev <= 1e-8, BSE_ERR_ARG, "bse_localize: Q is not orthogonal (%.3g)", dev);
+    std::vector<double> e2(g.begin() + nn, g.end());
     for (int i = 0; i < N; ++i)
         for (int j = 0; j < i; ++j) {
             const double s = 0.5 * (e2[(size_t)i * N + j] + e2[(size_t)j * N + i]);
             e2[(size_t)i * N + j] = e2[(size_t)j * N + i] = s;
         }
-    // psi~ = Q^T psi on the device
-    Dev<double> dqt, p2;
-    dqt.alloc(nn);
-    p2.alloc((size_t)N * npw);
-    BSE_HIP(hipMemcpyAsync(dqt.p, qt.data(), nn * 8, hipMemcpyHostToDevice, st));
     gemm<double>(false, N, npw, N, 1.0, dqt.p, N, 0, c->psi64.p, npw, 0, 0.0, p2.p, npw, 0, 1,
                  c->gws, st);
     BSE_HIP(hipMemcpyAsync(c->psi64.p, p2.p, (size_t)N * npw * 8, hipMemcpyDeviceToDevice, st));

@@ -155,3 +155,21 @@ def test_jade_large_properties():
     P = np.abs(Qd.cpu().numpy().T @ R)
     assert P.max(1).min() > 0.999
     ctx.close()
+
+
+def test_jade_default_start_on_device():
+    """Above 256 orbitals the start's eigenvectors of A^(1) come from the
+    device sweeps on A^(1) alone: the result is orthogonal, consistent with
+    the returned matrices, and diagonalises near-commuting matrices."""
+    from synth import near_commuting_matrices
+    say("jade_device_start", 600)
+    c, ctx, b = _canonical("c1")
+    A, R = near_commuting_matrices(600, seed=4, noise=1e-6)
+    Ad = _dev(A)
+    Q, sw, off = ctx.jade(Ad, tol=1e-7, max_sweeps=30)
+    I = torch.eye(600, dtype=torch.float64, device="cuda")
+    assert (Q.T @ Q - I).abs().max().item() < 1e-11
+    assert (Q.T @ _dev(A) @ Q - Ad).abs().max().item() < 1e-10
+    assert off < 1e-5          # the noise's own off-diagonal part is about 1e-6 here
+    assert np.abs(Q.cpu().numpy().T @ R).max(1).min() > 0.999
+    ctx.close()
