@@ -569,7 +569,7 @@ def random_block(shape, seed: int) -> np.ndarray:
 
 
 def near_commuting_matrices(N: int, seed: int, n_mat: int = 6, noise: float = 1e-3):
-    """n_mat symmetric N x N matrices R D_n R^T + noise * (Z + Z^T)/2 with one
+    """n_mat symmetric N x N matrices sym(R D_n R^T + noise * Z) with one
     seeded orthogonal R and diagonal D_n ~ U(-1, 1): the shape of the spread
     matrices of well-separated localised orbitals, at any N.  Returns (A, R)."""
     rng = np.random.default_rng(seed)
@@ -578,5 +578,6 @@ def near_commuting_matrices(N: int, seed: int, n_mat: int = 6, noise: float = 1e
     A = np.empty((n_mat, N, N))
     for k in range(n_mat):
         Z = rng.standard_normal((N, N))
-        A[k] = (R * rng.uniform(-1.0, 1.0, N)[None, :]) @ R.T + 0.5 * noise * (Z + Z.T)
+        M = (R * rng.uniform(-1.0, 1.0, N)[None, :]) @ R.T + noise * Z
+        A[k] = 0.5 * (M + M.T)
     return A, R

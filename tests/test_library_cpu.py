@@ -62,6 +62,9 @@ def test_status_strings_and_null_context():
     assert lib.bse_set_terms(None, 2.0, 1.0, 0.0) == 1
     assert lib.bse_apply_liouville(None, 1, None, None, 0) == 1
     assert lib.bse_build_pairs(None, 0, 0.1, None) == 1
+    assert lib.bse_spread_matrices(None, None) == 1
+    assert lib.bse_jade(None, 8, 6, None, None, 0, 1e-7, 10, None, None) == 1
+    assert lib.bse_localize(None, None) == 1
     assert b"null" in lib.bse_last_error()
     assert lib.bse_destroy(None) == 0
     # bse_create validates its arguments before any HIP call

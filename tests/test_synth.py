@@ -83,3 +83,17 @@ def test_cache_roundtrip(tmp_path, monkeypatch):
     a = make_cell("tiny")
     b = make_cell("tiny")
     assert np.array_equal(a.psi, b.psi) and np.array_equal(a.V, b.V)
+
+
+def test_near_commuting_matrices():
+    """Seeded input of the large JADE cases: symmetric, R orthogonal, and
+    R^T A R diagonal up to the stated noise."""
+    from synth import near_commuting_matrices
+    A, R = near_commuting_matrices(50, seed=2, noise=1e-4)
+    A2, _ = near_commuting_matrices(50, seed=2, noise=1e-4)
+    assert np.array_equal(A, A2)
+    assert np.abs(A - A.transpose(0, 2, 1)).max() == 0.0
+    assert np.abs(R.T @ R - np.eye(50)).max() < 1e-12
+    off = np.stack([R.T @ a @ R for a in A])
+    off[:, np.arange(50), np.arange(50)] = 0
+    assert np.abs(off).max() < 1e-3
