@@ -100,7 +100,8 @@ bse_status bse_set_terms(bse_ctx *ctx, double k1e, double k1d, double scissor);
  * orbitals for the six operators M^(1..6) = cos, sin of 2 pi x / L, of
  * 2 pi y / L and of 2 pi z / L (in that order), as FP64 sums over the grid.
  *   A  dev [6][n_occ][n_occ] FP64 output, row-major, symmetric.
- * Synchronises the stream.  Errors: BSE_ERR_ARG (null A). */
+ * Allocates a temporary [n_occ][N_r] FP64 buffer for the weighted orbitals.
+ * Synchronises the stream.  Errors: BSE_ERR_ARG (null A), BSE_ERR_OOM. */
 bse_status bse_spread_matrices(bse_ctx *ctx, double *A);
 
 /* bse_jade: joint approximate diagonalisation of n_mat real symmetric N x N
@@ -119,8 +120,11 @@ bse_status bse_spread_matrices(bse_ctx *ctx, double *A);
  *   n_sweeps   host, may be NULL: sweeps run
  *   offsum     host, may be NULL: off-diagonal sum after the last sweep
  * The context only lends its stream and workspace (N need not be n_occ).
+ * Allocates temporaries of n_mat + 2 N x N FP64 matrices; above N = 256 the
+ * default start runs the same sweeps on a copy of A^(1) alone (Jacobi's
+ * eigenvalue method) instead of the host eigensolver.
  * Synchronises the stream.  Errors: BSE_ERR_ARG (sizes, tol < 0, a
- * non-finite start). */
+ * non-finite start), BSE_ERR_OOM. */
 bse_status bse_jade(bse_ctx *ctx, int N, int n_mat, double *A, double *Q, int start_given,
                     double tol, int max_sweeps, int *n_sweeps, double *offsum);
 
