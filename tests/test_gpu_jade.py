@@ -173,3 +173,20 @@ def test_jade_default_start_on_device():
     assert off < 1e-5          # the noise's own off-diagonal part is about 1e-6 here
     assert np.abs(Q.cpu().numpy().T @ R).max(1).min() > 0.999
     ctx.close()
+
+
+def test_full_size_c2():
+    """The 64-well cell at its full grid (72^3, 64 orbitals): spread matrices
+    against the oracle's, and the localisation from the library's own start
+    reaches the oracle's minimum."""
+    say("jade_full_size", "c2")
+    c = make_cell("c2")
+    ctx = _pkg().context_for(c, localized=False)
+    b = Basis(c.L, c.n, c.miller)
+    ref = spread_matrices(b.to_grid(c.psi_canon))
+    A = ctx.spread_matrices()
+    assert np.abs(A.cpu().numpy() - ref).max() < 1e-12
+    _, _, _, hist = jade(ref, tol=1e-7)
+    Q, sw, off = ctx.jade(A, tol=1e-7)
+    assert off == pytest.approx(hist[-1], rel=1e-6)
+    ctx.close()
