@@ -173,7 +173,11 @@ bse_status bse_copy_tau(bse_ctx *ctx, int64_t p0, int64_t count, double *out);
  *   A_in   dev [n_vec][n_occ][n_pw]: double for BSE_FP64, float otherwise
  *   A_out  dev, same shape and type; may not alias A_in
  * A_out is P_c-projected.  Requires bse_screen_pairs with a tau of the
- * requested precision (BSE_ERR_STATE otherwise). */
+ * requested precision (BSE_ERR_STATE otherwise).  The context's workspaces
+ * (real-space block, FFT intermediates) grow to n_vec vectors; when that does
+ * not fit in device memory the block is applied in consecutive chunks of the
+ * largest length that fits (found once by halving, then kept), which gives
+ * the same result; BSE_ERR_OOM only when one vector does not fit. */
 bse_status bse_apply_liouville(bse_ctx *ctx, int n_vec, const void *A_in, void *A_out,
                                int precision);
 
@@ -187,6 +191,11 @@ bse_status bse_apply_liouville(bse_ctx *ctx, int n_vec, const void *A_in, void *
  * Synchronises. */
 bse_status bse_profile_apply(bse_ctx *ctx, int n_vec, const void *A_in, void *A_out,
                              int precision, int n_rep, double *ms);
+
+/* Number of trial vectors the apply processes at once for a block of n_vec
+ * in this precision (sizes the workspaces as bse_apply_liouville does; n_vec
+ * when the whole block fits). */
+bse_status bse_apply_chunk(bse_ctx *ctx, int n_vec, int precision, int *chunk);
 
 /* Capture the apply for (n_vec, A_in, A_out, precision) in a hipGraph and
  * replay it on later calls with the same arguments (1) or launch eagerly (0). */

@@ -234,6 +234,16 @@ bse_status bse_profile_apply(bse_ctx *c, int n_vec, const void *A_in, void *A_ou
     })
 }
 
+bse_status bse_apply_chunk(bse_ctx *c, int n_vec, int precision, int *chunk) {
+    CHECK_CTX(c);
+    if (!chunk || n_vec < 1 ||
+        (precision != BSE_FP64 && precision != BSE_FP32 && precision != BSE_BF16X3)) {
+        set_error("bse_apply_chunk: null output, n_vec < 1 or unknown precision");
+        return BSE_ERR_ARG;
+    }
+    BSE_GUARD({ *chunk = bse::ctx_chunk(c, n_vec, precision); })
+}
+
 bse_status bse_set_graph(bse_ctx *c, int enable) {
     CHECK_CTX(c);
     c->use_graph = enable != 0;

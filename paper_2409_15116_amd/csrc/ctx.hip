@@ -915,6 +915,25 @@ static void ensure_ws(bse_ctx *c, ApplyWs<T> &w, int nvec) {
     ++w.gen;
 }
 
+// Workspaces for a block of nvec vectors, or for the largest chunk of it that
+// fits in device memory (halving on an allocation failure; the result is kept,
+// so later calls go straight to it).  Returns the chunk length.
+template <typename T>
+static int ensure_ws_chunk(bse_ctx *c, ApplyWs<T> &w, int nvec) {
+    int chunk = w.fit > 0 ? std::min(nvec, w.fit) : nvec;
+    for (;;) {
+        try {
+            ensure_ws<T>(c, w, chunk);
+            if (chunk < nvec) w.fit = chunk;
+            return chunk;
+        } catch (const Err &e) {
+            if (e.st != BSE_ERR_OOM || chunk == 1) throw;
+            w.release();
+            (void)hipGetLastError();
+            chunk = (chunk + 1) / 2;
+        }
+    }
+}
 
 // P_c on a block in place: Y -= (Y Psi^T) Psi
 template <typename T>
@@ -928,10 +947,42 @@ static void project_c(bse_ctx *c, bool bf, int norb, T *Y, T *S, const T *psi, W
 // of the ten stages (inv z, inv y, inv x, k1d, hartree, fwd x, fwd y, fwd z,
 // eps gemm, P_c gemms)
 template <typename T>
-static void apply_impl(bse_ctx *c, int nvec, const T *X, T *Y, bool bf, hipEvent_t *ev = nullptr) {
+static void apply_chunk(bse_ctx *c, int nvec, const T *X, T *Y, bool bf, hipEvent_t *ev);
+
+// A block too large for the workspaces runs as consecutive chunks of trial
+// vectors (the operator acts on each vector independently).  With stage
+// events (profiling), each chunk is timed on its own and the stage times are
+// summed into ms[10].
+template <typename T>
+static void apply_impl(bse_ctx *c, int nvec, const T *X, T *Y, bool bf, hipEvent_t *ev = nullptr,
+                       double *ms = nullptr) {
     const bool dbl = std::is_same<T, double>::value;
     ApplyWs<T> &w = *reinterpret_cast<ApplyWs<T> *>(dbl ? (void *)&c->ws64 : (void *)&c->ws32);
-    ensure_ws<T>(c, w, nvec);
+    const int chunk = ensure_ws_chunk<T>(c, w, nvec);
+    const size_t len = (size_t)c->n_occ * c->npw;
+    for (int s0 = 0; s0 < nvec; s0 += chunk) {
+        const int k = std::min(chunk, nvec - s0);
+        apply_chunk<T>(c, k, X + s0 * len, Y + s0 * len, bf, ev);
+        if (ev && ms) {
+            BSE_HIP(hipEventSynchronize(ev[10]));
+            for (int i = 0; i < 10; ++i) {
+                float t = 0;
+                BSE_HIP(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+                ms[i] += t;
+            }
+        }
+    }
+}
+
+int ctx_chunk(bse_ctx *c, int n_vec, int prec) {
+    if (prec == BSE_FP64) return ensure_ws_chunk<double>(c, c->ws64, n_vec);
+    return ensure_ws_chunk<float>(c, c->ws32, n_vec);
+}
+
+template <typename T>
+static void apply_chunk(bse_ctx *c, int nvec, const T *X, T *Y, bool bf, hipEvent_t *ev) {
+    const bool dbl = std::is_same<T, double>::value;
+    ApplyWs<T> &w = *reinterpret_cast<ApplyWs<T> *>(dbl ? (void *)&c->ws64 : (void *)&c->ws32);
     const int no = c->n_occ, npw = c->npw;
     const int norb = nvec * no;
     const long long nr = c->nr;
@@ -983,16 +1034,12 @@ void ctx_profile_apply(bse_ctx *c, int n_vec, const void *in, void *out, int pre
     try {
         for (int r = 0; r < n_rep; ++r) {
             if (prec == BSE_FP64)
-                apply_impl<double>(c, n_vec, (const double *)in, (double *)out, false, ev);
+                apply_impl<double>(c, n_vec, (const double *)in, (double *)out, false, ev, ms);
             else
-                apply_impl<float>(c, n_vec, (const float *)in, (float *)out, prec == BSE_BF16X3, ev);
-            BSE_HIP(hipEventSynchronize(ev[10]));
-            for (int s = 0; s < 10; ++s) {
-                float t = 0;
-                BSE_HIP(hipEventElapsedTime(&t, ev[s], ev[s + 1]));
-                ms[s] += t / n_rep;
-            }
+                apply_impl<float>(c, n_vec, (const float *)in, (float *)out, prec == BSE_BF16X3,
+                                  ev, ms);
         }
+        for (int s = 0; s < 10; ++s) ms[s] /= n_rep;
     } catch (...) {
         for (auto &e : ev) (void)hipEventDestroy(e);
         throw;

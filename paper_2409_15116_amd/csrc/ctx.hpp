@@ -44,8 +44,14 @@ template <typename T>
 struct ApplyWs {
     int cap = 0;              // trial vectors the buffers hold
     int gen = 0;              // bumped when the buffers are reallocated
+    int fit = 0;              // largest block known to fit in memory (0: not probed)
     Dev<T> Ar, Cr, S, Dp;
     Dev<cplx<T>> T1, T2, Hc;
+    void release() {
+        Ar.free(); Cr.free(); S.free(); Dp.free(); T1.free(); T2.free(); Hc.free();
+        cap = 0;
+        ++gen;
+    }
 };
 
 struct LearnedPre {
@@ -162,6 +168,7 @@ void ctx_screen(bse_ctx *c, const double *phi, const double *lam, int n_pdep, in
 int ctx_autotune(bse_ctx *c, int n_vec, int prec, int n_rep, double *ms_out);
 void ctx_set_k1d_shape(bse_ctx *c, int prec, int shape);
 void ctx_apply(bse_ctx *c, int n_vec, const void *in, void *out, int prec);
+int ctx_chunk(bse_ctx *c, int n_vec, int prec);
 void ctx_apply_entry(bse_ctx *c, int n_vec, const void *in, void *out, int prec);
 void ctx_profile_apply(bse_ctx *c, int n_vec, const void *in, void *out, int prec, int n_rep,
                        double *ms);

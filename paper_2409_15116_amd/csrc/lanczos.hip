@@ -113,11 +113,11 @@ void ctx_lanczos(bse_ctx *c, int n_pol, int n_steps, int prec, const double *D, 
     for (int k = 0; k < n_steps; ++k) {
         if (prec == BSE_FP64) {
             BSE_HIP(hipMemcpyAsync(in64.p, Q, len * 8, hipMemcpyDeviceToDevice, st));
-            ctx_apply(c, n_pol, in64.p, out64.p, prec);
+            ctx_apply_entry(c, n_pol, in64.p, out64.p, prec);
             BSE_HIP(hipMemcpyAsync(W, out64.p, len * 8, hipMemcpyDeviceToDevice, st));
         } else {
             convert<double, float>(Q, in32.p, len, st);
-            ctx_apply(c, n_pol, in32.p, out32.p, prec);
+            ctx_apply_entry(c, n_pol, in32.p, out32.p, prec);
             convert<float, double>(out32.p, W, len, st);
         }
         double *ak = a.p + (size_t)k * n_pol;

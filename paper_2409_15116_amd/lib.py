@@ -72,6 +72,7 @@ def load():
         "bse_copy_tau": (i32, [vp, i64, i64, vp]),
         "bse_apply_liouville": (i32, [vp, i32, vp, vp, i32]),
         "bse_set_graph": (i32, [vp, i32]),
+        "bse_apply_chunk": (i32, [vp, i32, i32, C.POINTER(i32)]),
         "bse_profile_apply": (i32, [vp, i32, vp, vp, i32, i32, vp]),
         "bse_davidson": (i32, [vp, C.POINTER(DavidsonOpts), vp, vp, vp,
                                C.POINTER(DavidsonStats)]),
@@ -115,7 +116,7 @@ def load():
 def exported_symbols():
     return ["bse_create", "bse_destroy", "bse_set_terms", "bse_pair_measure", "bse_build_pairs",
             "bse_threshold_for_fraction", "bse_get_pairs", "bse_screen_pairs", "bse_copy_tau",
-            "bse_apply_liouville", "bse_set_graph", "bse_davidson", "bse_status_str",
+            "bse_apply_liouville", "bse_apply_chunk", "bse_set_graph", "bse_davidson", "bse_status_str",
             "bse_last_error", "bse_debug_to_grid", "bse_debug_gemm", "bse_profile_apply",
             "bse_mlp_create", "bse_mlp_destroy", "bse_mlp_num_params", "bse_mlp_get_weights",
             "bse_mlp_set_weights", "bse_mlp_forward", "bse_mlp_gradients", "bse_mlp_train",
@@ -273,6 +274,12 @@ class BseContext:
 
     def set_graph(self, enable=True):
         _check(load().bse_set_graph(self.h, 1 if enable else 0))
+
+    def apply_chunk(self, n_vec, precision=FP64):
+        """Trial vectors the apply processes at once for a block of n_vec."""
+        out = C.c_int(0)
+        _check(load().bse_apply_chunk(self.h, int(n_vec), int(precision), C.byref(out)))
+        return out.value
 
     def set_learned(self, mlp, n_window_pw):
         _check(load().bse_set_learned(self.h, mlp.h if mlp is not None else None, n_window_pw))

@@ -1,7 +1,7 @@
 """Write the stored oracle results used by the GPU parity tests.
 
 Calls only the oracle and the seeded input generator:
-    python tests/golden/make_goldens.py [c1] [c2]
+    python tests/golden/make_goldens.py [c1] [c1_f40] [c2] [c4_03] [c4_07]
 Output: tests/golden/<cell>_oracle.json with the lowest excitation energies
 (Ha) of the plain FP64 oracle Davidson, the pair threshold and count, and the
 oracle's iteration count and wall time.
@@ -27,12 +27,22 @@ CASES = {
     "c1": ("c1", None, 4, 4, 4321),
     "c1_f40": ("c1", 0.4, 4, 4, 4321),
     "c2": ("c2", 0.4, 8, 16, 4321),
+    # two 48^3 cells of the seeded uneven twelve-cell set, 40 % of the pairs
+    "c4_03": ("c4_03", 0.4, 4, 8, 4321),
+    "c4_07": ("c4_07", 0.4, 4, 8, 4321),
 }
+
+
+def _cell(name):
+    if name.startswith("c4_"):
+        from synth.cell import uneven_batch_specs
+        return make_cell({s.name: s for s in uneven_batch_specs()}[name])
+    return make_cell(name)
 
 
 def run(case):
     name, frac, n_eig, B, seed = CASES[case]
-    cell = make_cell(name)
+    cell = _cell(name)
     b = Basis(cell.L, cell.n, cell.miller)
     u = b.to_grid(cell.psi)
     m = pair_measure(u, MEASURE_ABS_L1)

@@ -46,11 +46,13 @@ def test_lanczos_matches_oracle(chain_ref, prec, tol_c, tol_s):
     import paper_2409_15116_amd as pkg
     c, D, alpha, beta = chain_ref
     say("lanczos", prec)
-    ctx = pkg.context_for(c)
-    pkg.setup_pairs_and_screen(ctx, c, fraction=0.4, precision=prec)
-    ctx.set_graph(True)
-    a, b = ctx.lanczos(torch.from_numpy(D).to("cuda"), N_STEPS, prec)
-    ctx.close()
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        ctx = pkg.context_for(c, stream=st)
+        pkg.setup_pairs_and_screen(ctx, c, fraction=0.4, precision=prec)
+        ctx.set_graph(True)                  # every step replays the captured apply
+        a, b = ctx.lanczos(torch.from_numpy(D).to("cuda"), N_STEPS, prec)
+        ctx.close()
     assert np.isfinite(a).all() and np.isfinite(b).all()
     np.testing.assert_allclose(b[:, 0], beta[:, 0], rtol=1e-12 if prec == 0 else 1e-6)
     scale = max(np.abs(alpha[:, :N_EARLY]).max(), np.abs(beta[:, :N_EARLY + 1]).max())
@@ -75,3 +77,23 @@ def test_lanczos_block_equals_single_chains(chain_ref):
     scale = np.abs(b3[1]).max()
     assert np.abs(a3[1] - a1[0]).max() < 1e-11 * scale
     assert np.abs(b3[1] - b1[0]).max() < 1e-11 * scale
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_lanczos_graph_equals_eager(chain_ref, prec):
+    """The steps replay the context's captured apply graph; the chains equal
+    the eagerly launched ones exactly."""
+    import paper_2409_15116_amd as pkg
+    c, D, alpha, beta = chain_ref
+    st = torch.cuda.Stream()
+    out = {}
+    with torch.cuda.stream(st):
+        ctx = pkg.context_for(c, stream=st)
+        pkg.setup_pairs_and_screen(ctx, c, fraction=0.4, precision=prec)
+        Dd = torch.from_numpy(D).to("cuda")
+        for g in (False, True):
+            ctx.set_graph(g)
+            out[g] = ctx.lanczos(Dd, 25, prec)
+        ctx.close()
+    assert np.array_equal(out[False][0], out[True][0])
+    assert np.array_equal(out[False][1], out[True][1])
