@@ -263,6 +263,19 @@ bse_status bse_mlp_get_weights(bse_mlp *mlp, float *w);          /* host out */
 bse_status bse_mlp_set_weights(bse_mlp *mlp, const float *w);    /* host in; resets Adam */
 /* Y dev [n][k_out] = network(X dev [n][f_in]).  Synchronises. */
 bse_status bse_mlp_forward(bse_mlp *mlp, int n, const float *X, float *Y);
+/* The same forward pass for callers that cannot allocate device memory
+ * (code under hipGraph capture, tight inference loops, hosts that forbid
+ * hipMalloc): it calls no hipMalloc, hipFree or allocating routine and does
+ * not synchronise (work is queued on the network's stream).  X and Y are
+ * the caller's (same layout as bse_mlp_forward); the layers' temporaries
+ * (4 n hidden floats) and the GEMMs' split-K partials live in a fixed 32 MiB
+ * device array of the library, one per GPU, held until the process ends;
+ * with hidden = 256 that allows about 7000 rows per call.  BSE_ERR_ARG when
+ * n rows need more than that, when the current device is not the one the
+ * network was created on, or for a null or empty argument.  Every call on a
+ * GPU shares that GPU's array: calls that overlap in time on one GPU race
+ * (their results are undefined); calls queued on one stream do not. */
+bse_status bse_mlp_forward_noalloc(bse_mlp *mlp, int n, const float *X, float *Y);
 /* Gradients (host, flat like the weights) of the mean-squared error of
  * network(X) against T dev [n][k_out]; loss (host) optional.  Synchronises. */
 bse_status bse_mlp_gradients(bse_mlp *mlp, int n, const float *X, const float *T, float *g,

@@ -12,12 +12,22 @@ struct Workspace {
     void *ptr = nullptr;
     size_t bytes = 0;
     int gen = 0;  // bumped on every reallocation
+    bool external = false;  // borrowed memory: never reallocated or freed
     Workspace() = default;
     Workspace(const Workspace &) = delete;
     Workspace &operator=(const Workspace &) = delete;
     ~Workspace() { release(); }
+    // use `b` bytes at `p` (owned by the caller) instead of allocating
+    void borrow(void *p, size_t b) {
+        release();
+        ptr = p;
+        bytes = b;
+        external = true;
+    }
     void *get(size_t need) {
         if (need > bytes) {
+            BSE_REQUIRE(!external, BSE_ERR_ARG,
+                        "scratch of %zu bytes needed, the borrowed buffer holds %zu", need, bytes);
             if (ptr) BSE_HIP(hipFree(ptr));
             ptr = nullptr;
             bytes = 0;
@@ -33,9 +43,10 @@ struct Workspace {
         return ptr;
     }
     void release() {
-        if (ptr) (void)hipFree(ptr);
+        if (ptr && !external) (void)hipFree(ptr);
         ptr = nullptr;
         bytes = 0;
+        external = false;
     }
 };
 
@@ -173,5 +184,8 @@ void gemm_bf16x3(bool nt, int M, int N, int K, float alpha, const float *A, long
 void gemm_bf16(bool ta, bool nt, int M, int N, int K, float alpha, const float *A, long long lda,
                const float *B, long long ldb, float beta, float *C, long long ldc, Workspace &ws,
                hipStream_t st);
+// bytes of split-K partials the matrix-core GEMMs above take from their
+// workspace for an M x N x K product (0 when the inner dimension is not split)
+size_t gemm_mfma_ws_bytes(int M, int N, int K, int batch);
 
 }  // namespace bse

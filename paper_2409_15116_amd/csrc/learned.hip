@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <random>
 #include <vector>
@@ -104,6 +105,7 @@ __global__ void k_gather_rows(const float *__restrict__ src, const int *__restri
 
 struct bse_mlp {
     int F = 0, H = 0, K = 0;
+    int device = 0;            // the GPU holding the weights
     hipStream_t stream = nullptr;
     long long oW1, ob1, oW2, ob2, oW3, ob3, total;
     bse::Dev<float> w, g, m, v;
@@ -145,21 +147,83 @@ static void mlp_ensure(bse_mlp *m, int n) {
     m->cap = n;
 }
 
-void mlp_forward(bse_mlp *m, int n, const float *X, float *Y) {
-    mlp_ensure(m, n);
+// the three layers, with the pre-activations Z1, Z2 and activations H1, H2
+// ([n][H] each) and the GEMMs' split-K partials in the buffers given
+static void mlp_forward_into(bse_mlp *m, int n, const float *X, float *Y, float *Z1, float *H1,
+                             float *Z2, float *H2, Workspace &ws) {
     BSE_REQUIRE(X && Y, BSE_ERR_ARG, "network forward: null buffer");
     hipStream_t st = m->stream;
     const int F = m->F, H = m->H, K = m->K;
     const float *w = m->w.p;
-    gemm_bf16(false, false, n, H, F, 1.f, X, F, w + m->oW1, H, 0.f, m->Z1.p, H, m->ws, st);
-    k_bias_relu<<<div_up((size_t)n * H, 256), 256, 0, st>>>(m->Z1.p, w + m->ob1, m->H1.p, n, H, 1);
+    gemm_bf16(false, false, n, H, F, 1.f, X, F, w + m->oW1, H, 0.f, Z1, H, ws, st);
+    k_bias_relu<<<div_up((size_t)n * H, 256), 256, 0, st>>>(Z1, w + m->ob1, H1, n, H, 1);
     BSE_LAUNCH_CHECK();
-    gemm_bf16(false, false, n, H, H, 1.f, m->H1.p, H, w + m->oW2, H, 0.f, m->Z2.p, H, m->ws, st);
-    k_bias_relu<<<div_up((size_t)n * H, 256), 256, 0, st>>>(m->Z2.p, w + m->ob2, m->H2.p, n, H, 1);
+    gemm_bf16(false, false, n, H, H, 1.f, H1, H, w + m->oW2, H, 0.f, Z2, H, ws, st);
+    k_bias_relu<<<div_up((size_t)n * H, 256), 256, 0, st>>>(Z2, w + m->ob2, H2, n, H, 1);
     BSE_LAUNCH_CHECK();
-    gemm_bf16(false, false, n, K, H, 1.f, m->H2.p, H, w + m->oW3, K, 0.f, Y, K, m->ws, st);
+    gemm_bf16(false, false, n, K, H, 1.f, H2, H, w + m->oW3, K, 0.f, Y, K, ws, st);
     k_bias_relu<<<div_up((size_t)n * K, 256), 256, 0, st>>>(Y, w + m->ob3, nullptr, n, K, 0);
     BSE_LAUNCH_CHECK();
+}
+
+void mlp_forward(bse_mlp *m, int n, const float *X, float *Y) {
+    mlp_ensure(m, n);
+    mlp_forward_into(m, n, X, Y, m->Z1.p, m->H1.p, m->Z2.p, m->H2.p, m->ws);
+}
+
+// ---------------------------------------------------------------------------
+// Forward pass that allocates nothing (bse_mlp_forward_noalloc).  Its
+// temporaries live in one file-scope device array of fixed size: every GPU
+// the library runs on holds its own copy until the process ends, and every
+// such call on that GPU uses it (concurrent calls on one GPU race).  Host
+// code never passes the array's name to a kernel (on the host that name is
+// not a device address): the address comes from hipGetSymbolAddress, taken
+// once per device with that device current.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[64];  // device address of `scratch` on each GPU
+
+static unsigned char *noalloc_scratch(int dev) {
+    BSE_REQUIRE(dev >= 0 && dev < 64, BSE_ERR_ARG, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        BSE_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        BSE_REQUIRE(p != nullptr, BSE_ERR_HIP, "no device address for the scratch array");
+        g_scratch_dev[dev] = p;
+    }
+    return (unsigned char *)g_scratch_dev[dev];
+}
+
+// bytes of scratch a forward pass of n rows takes: Z1, H1, Z2, H2 and the
+// largest split-K partials of the three products
+static size_t noalloc_bytes(const bse_mlp *m, long long n) {
+    const size_t act = (size_t)n * m->H * sizeof(float);
+    const size_t a4 = 4 * ((act + 255) / 256 * 256);
+    size_t part = gemm_mfma_ws_bytes((int)n, m->H, m->F, 1);
+    part = std::max(part, gemm_mfma_ws_bytes((int)n, m->H, m->H, 1));
+    part = std::max(part, gemm_mfma_ws_bytes((int)n, m->K, m->H, 1));
+    return a4 + part;
+}
+
+void mlp_forward_noalloc(bse_mlp *m, int n, const float *X, float *Y) {
+    int dev = -1;
+    BSE_HIP(hipGetDevice(&dev));
+    BSE_REQUIRE(dev == m->device, BSE_ERR_ARG,
+                "the network lives on device %d, the current device is %d", m->device, dev);
+    const size_t need = noalloc_bytes(m, n);
+    BSE_REQUIRE(need <= NOALLOC_SCRATCH_BYTES, BSE_ERR_ARG,
+                "%d rows of width %d need %zu bytes of scratch; at most %zu are available", n,
+                m->H, need, NOALLOC_SCRATCH_BYTES);
+    unsigned char *base = noalloc_scratch(dev);
+    const size_t act = ((size_t)n * m->H * sizeof(float) + 255) / 256 * 256;
+    float *Z1 = (float *)base, *H1 = (float *)(base + act), *Z2 = (float *)(base + 2 * act),
+          *H2 = (float *)(base + 3 * act);
+    Workspace ws;
+    ws.borrow(base + 4 * act, NOALLOC_SCRATCH_BYTES - 4 * act);
+    mlp_forward_into(m, n, X, Y, Z1, H1, Z2, H2, ws);
 }
 
 // gradients of the mean-squared error into m->g; loss into m->loss (device)
@@ -579,6 +643,7 @@ bse_status bse_mlp_create(bse_mlp **out, int f_in, int hidden, int k_out, const 
     m->stream = (hipStream_t)stream;
     bse::mlp_layout(m);
     try {
+        BSE_HIP(hipGetDevice(&m->device));
         m->w.alloc(m->total);
         m->g.alloc(m->total);
         m->m.alloc(m->total);
@@ -640,6 +705,14 @@ bse_status bse_mlp_forward(bse_mlp *m, int n, const float *X, float *Y) {
         bse::mlp_forward(m, n, X, Y);
         BSE_HIP(hipStreamSynchronize(m->stream));
     })
+}
+
+bse_status bse_mlp_forward_noalloc(bse_mlp *m, int n, const float *X, float *Y) {
+    if (!m || !X || !Y || n < 1) {
+        set_error("bse_mlp_forward_noalloc: bad argument");
+        return BSE_ERR_ARG;
+    }
+    MLP_GUARD({ bse::mlp_forward_noalloc(m, n, X, Y); })
 }
 
 bse_status bse_mlp_gradients(bse_mlp *m, int n, const float *X, const float *T, float *g,

@@ -264,17 +264,32 @@ static void launch_bf16(dim3 grid, hipStream_t st, int M, int N, int K, float al
     BSE_LAUNCH_CHECK();
 }
 
+// K split of a matrix-core GEMM: skinny products with few output tiles
+// split their inner dimension so that enough workgroups run (partials are
+// summed by a second kernel in fixed order)
+static int mfma_split(int M, int N, int K, int batch, int *kchunk) {
+    const int tiles = div_up(M, TB) * div_up(N, TB) * batch;
+    int nsplit = 1;
+    if (K > 4 * TK && tiles < 512) nsplit = std::max(1, (int)std::min(div_up(1024, tiles), div_up(K, 256)));
+    *kchunk = div_up(div_up(K, nsplit), TK) * TK;
+    return std::max(1, (int)div_up(K, *kchunk));
+}
+
+size_t gemm_mfma_ws_bytes(int M, int N, int K, int batch) {
+    if (M <= 0 || N <= 0 || batch <= 0) return 0;
+    int kchunk;
+    const int nsplit = mfma_split(M, N, K, batch, &kchunk);
+    return nsplit > 1 ? (size_t)M * N * nsplit * batch * sizeof(float) : 0;
+}
+
 // mode: 0 bf16, 1 split-BF16x3, 2 FP32 (ta only with mode 0)
 static void gemm_mfma_any(bool ta, bool nt, int mode, int M, int N, int K, float alpha,
                           const float *A, long long lda, long long sA, const float *B,
                           long long ldb, long long sB, float beta, float *C, long long ldc,
                           long long sC, int batch, Workspace &ws, hipStream_t st) {
     if (M <= 0 || N <= 0 || batch <= 0) return;
-    const int tiles = div_up(M, TB) * div_up(N, TB) * batch;
-    int nsplit = 1;
-    if (K > 4 * TK && tiles < 512) nsplit = std::max(1, (int)std::min(div_up(1024, tiles), div_up(K, 256)));
-    const int kchunk = div_up(div_up(K, nsplit), TK) * TK;
-    nsplit = std::max(1, (int)div_up(K, kchunk));
+    int kchunk;
+    const int nsplit = mfma_split(M, N, K, batch, &kchunk);
     dim3 grid(div_up(N, TB), div_up(M, TB), batch * nsplit);
     float *Cw = C;
     float a = alpha, b = beta;

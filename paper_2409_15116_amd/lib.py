@@ -84,6 +84,7 @@ def load():
         "bse_mlp_get_weights": (i32, [vp, vp]),
         "bse_mlp_set_weights": (i32, [vp, vp]),
         "bse_mlp_forward": (i32, [vp, i32, vp, vp]),
+        "bse_mlp_forward_noalloc": (i32, [vp, i32, vp, vp]),
         "bse_mlp_gradients": (i32, [vp, i32, vp, vp, vp, vp]),
         "bse_mlp_train": (i32, [vp, i32, vp, vp, i32, i32, C.c_float, C.c_uint64, vp]),
         "bse_set_learned": (i32, [vp, vp, i32]),
@@ -119,7 +120,7 @@ def exported_symbols():
             "bse_apply_liouville", "bse_apply_chunk", "bse_set_graph", "bse_davidson", "bse_status_str",
             "bse_last_error", "bse_debug_to_grid", "bse_debug_gemm", "bse_profile_apply",
             "bse_mlp_create", "bse_mlp_destroy", "bse_mlp_num_params", "bse_mlp_get_weights",
-            "bse_mlp_set_weights", "bse_mlp_forward", "bse_mlp_gradients", "bse_mlp_train",
+            "bse_mlp_set_weights", "bse_mlp_forward", "bse_mlp_forward_noalloc", "bse_mlp_gradients", "bse_mlp_train",
             "bse_set_learned", "bse_learned_centers", "bse_davidson_record",
             "bse_lanczos", "bse_lanczos_spectrum",
             "bse_spread_matrices", "bse_jade", "bse_localize",
@@ -490,6 +491,14 @@ class Mlp:
         Y = t.empty((X.shape[0], self.shape[2]), dtype=t.float32, device="cuda")
         _check(load().bse_mlp_forward(self.h, X.shape[0], _dptr(X, t.float32),
                                       _dptr(Y, t.float32)))
+        return Y
+
+    def forward_noalloc(self, X, Y):
+        """Forward pass into the caller's Y with no device allocation (queued
+        on the network's stream, not synchronised)."""
+        t = self.torch
+        _check(load().bse_mlp_forward_noalloc(self.h, X.shape[0], _dptr(X, t.float32),
+                                              _dptr(Y, t.float32, (X.shape[0], self.shape[2]))))
         return Y
 
     def gradients(self, X, T):
