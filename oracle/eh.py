@@ -120,3 +120,56 @@ def eh_hamiltonian(L, n, miller, V, phi, lam, n_occ, *, k1e=2.0, k1d=1.0, scisso
                 M = (ue * tau[None, :]) @ ue.T / nr
                 Heh[v * ne:(v + 1) * ne, w * ne:(w + 1) * ne] -= k1d * M
     return 0.5 * (Heh + Heh.T), eps, X
+
+
+def eh_hamiltonian_spin(L, n, miller, V, phi, lam, n_up, n_down, *, k1d=1.0):
+    """Explicit spin-conserving TDA e-h Hamiltonian of a spin-polarised cell:
+    both spins see the same discretised H (one local potential); spin sigma
+    occupies its lowest n_sigma states, and its transitions (sigma, v, c) run
+    over its occupied v and all its empty c.
+
+      H^eh = (eps_c - eps_v) delta + int int rho_{sigma cv} v_c rho_{sigma' c'v'}
+                                   - delta_{sigma sigma'} int int rho_{sigma cc'} W rho_{sigma vv'}
+
+    (the exchange-like term couples every pair of spins with factor 1, the
+    direct term acts within a spin).  Returns (Heh, eps, X, dims) with the up
+    transitions first, (v, c) row-major inside each spin, dims = (up, down)."""
+    H, E = dense_hamiltonian(L, n, miller, V)
+    eps, X = np.linalg.eigh(H)
+    u = X.T @ E
+    nr = E.shape[1]
+    omega = L ** 3
+    b = 2.0 * np.pi / L
+    f1 = np.fft.fftfreq(n, d=1.0 / n)
+    G2 = ((b * f1[:, None, None]) ** 2 + (b * f1[None, :, None]) ** 2
+          + (b * f1[None, None, :]) ** 2).reshape(-1)
+    vg = np.zeros_like(G2)
+    vg[G2 > 0] = 4.0 * np.pi / G2[G2 > 0]
+    Wm = dense_w(L, n, miller, phi, lam) if k1d != 0.0 else None
+    chans, F = [], []
+    for no in (n_up, n_down):
+        uo, ue = u[:no], u[no:]
+        ne = ue.shape[0]
+        rho = (uo[:, None, :] * ue[None, :, :]).reshape(no * ne, n, n, n) / omega
+        F.append(np.fft.fftn(rho, axes=(1, 2, 3)).reshape(no * ne, nr) / nr)
+        chans.append((no, ne, uo, ue))
+    dims = tuple(no * ne for no, ne, _, _ in chans)
+    off = (0, dims[0])
+    Heh = np.zeros((sum(dims), sum(dims)))
+    for s, (no, ne, uo, ue) in enumerate(chans):
+        de = (eps[no:][None, :] - eps[:no][:, None]).reshape(-1)
+        i = slice(off[s], off[s] + dims[s])
+        Heh[i, i] += np.diag(de)
+        for t in range(2):
+            j = slice(off[t], off[t] + dims[t])
+            Heh[i, j] += omega * ((np.conj(F[s]) * vg[None, :]) @ F[t].T).real
+        if k1d != 0.0:
+            for v in range(no):
+                for w in range(no):
+                    rho = (uo[v] * uo[w]).reshape(n, n, n) / omega
+                    Fr = np.fft.fftn(rho).reshape(-1) / nr
+                    tau = (np.fft.ifftn((Wm @ Fr).reshape(n, n, n)) * nr).real.reshape(-1)
+                    M = (ue * tau[None, :]) @ ue.T / nr
+                    r0, c0 = off[s] + v * ne, off[s] + w * ne
+                    Heh[r0:r0 + ne, c0:c0 + ne] -= k1d * M
+    return 0.5 * (Heh + Heh.T), eps, X, dims
