@@ -92,6 +92,23 @@ bse_status bse_destroy(bse_ctx *ctx);
  * triplet channel.  Drops a captured apply graph. */
 bse_status bse_set_terms(bse_ctx *ctx, double k1e, double k1d, double scissor);
 
+/* Spin-polarised, spin-conserving excitations (Sec. 2; Sec. 3 keeps the two
+ * spins as separate pools): the context's orbital slots [0, n_up) are the
+ * occupied spin-up orbitals and [n_up, n_occ) the spin-down ones (each
+ * channel orthonormal; eps block-diagonal in the two channels).  The
+ * projector acts per channel, P_c^sigma = 1 - sum_{v in sigma} |psi_v><psi_v|,
+ * kept pairs (and so K1d) stay within a channel, and K1e is the Hartree
+ * potential of the density response summed over both channels: with
+ * bse_set_terms(k1e = 1) the apply is
+ *   (L A)_{sigma v} = P_c^sigma[ (H - eps^sigma) a_{sigma v}
+ *       + psi_{sigma v} v_c[ sum_{sigma' v'} psi_{sigma' v'} a_{sigma' v'} ]
+ *       - sum_{v' in N_sigma(v)} tau_{vv'} a_{sigma v'} ].
+ * One local potential V for both channels.  n_up = n_occ returns to one
+ * channel.  Clears the pair list and tau (call bse_build_pairs and
+ * bse_screen_pairs again) and drops a captured graph.  BSE_ERR_ARG unless
+ * 1 <= n_up <= n_occ. */
+bse_status bse_set_spin(bse_ctx *ctx, int n_up);
+
 /* Wannier localisation (Sec. 2, Eq. wannier, Eq. spread).  The usual order is
  * bse_create with canonical orbitals, bse_spread_matrices, bse_jade,
  * bse_localize, then bse_build_pairs.
@@ -229,7 +246,9 @@ typedef struct {
  *   omega  host [n_eig] FP64 out
  *   X      dev  [n_eig][n_occ][n_pw] FP64 out: orthonormal eigenvectors
  * Synchronises once per iteration.  BSE_ERR_NOCONV when max_iter is hit
- * (omega and X then hold the last Ritz pairs). */
+ * (omega and X then hold the last Ritz pairs: a later call started from X
+ * resumes the solve).  BSE_ERR_ARG when the subspace matrix gets a
+ * non-finite entry (NaN or Inf in X0 or in the operator's output). */
 bse_status bse_davidson(bse_ctx *ctx, const bse_davidson_opts *opts, const double *X0,
                         double *omega, double *X, bse_davidson_stats *stats);
 

@@ -95,6 +95,11 @@ bse_status bse_set_terms(bse_ctx *c, double k1e, double k1d, double scissor) {
     BSE_GUARD(bse::ctx_set_terms(c, k1e, k1d, scissor))
 }
 
+bse_status bse_set_spin(bse_ctx *c, int n_up) {
+    CHECK_CTX(c);
+    BSE_GUARD(bse::ctx_set_spin(c, n_up))
+}
+
 bse_status bse_pair_measure(bse_ctx *c, int measure, double *m) {
     CHECK_CTX(c);
     if (!m) {

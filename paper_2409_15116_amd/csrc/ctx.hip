@@ -168,6 +168,21 @@ void ctx_set_terms(bse_ctx *c, double k1e, double k1d, double scissor) {
     drop_graph(c);  // a captured apply bakes the terms in
 }
 
+// Two spin channels: slots [0, n_up) are spin up, [n_up, n_occ) spin down
+// (n_up = n_occ: one channel).  Pairs are kept within a channel and P_c acts
+// per channel; the pair list and tau must be built again.
+void ctx_set_spin(bse_ctx *c, int n_up) {
+    BSE_REQUIRE(n_up >= 1 && n_up <= c->n_occ, BSE_ERR_ARG,
+                "n_up must be in [1, n_occ = %d], got %d", c->n_occ, n_up);
+    c->n_up = n_up >= c->n_occ ? 0 : n_up;
+    c->pairs_h.clear();
+    c->n_pairs = 0;
+    c->have_tau64 = c->have_tau32 = false;
+    c->tau64.free();
+    c->tau32.free();
+    drop_graph(c);
+}
+
 void ctx_setup(bse_ctx *c, const bse_cell *cell, const double *psi, const double *eps,
                const double *V) {
     c->L = cell->L;
@@ -665,10 +680,435 @@ static void build_event_set(bse_ctx *c, int set, int cap, const Bits &nb,
     up(c->res_ev[set], ev);
     up(c->res_start[set], start);
     up(c->res_cnt[set], phc);
+    const std::vector<int> rbng{ng}, rbnph{nph};
+    up(c->res_rbng[set], rbng);
+    up(c->res_rbnph[set], rbnph);
     PairEvents &e = c->res[set];
     e.ng = ng;
     e.nph = nph;
     e.cap = cap;
+    e.nrb = 1;
+    e.rb_ng = c->res_rbng[set].p;
+    e.rb_nph = c->res_rbnph[set].p;
+    e.n_rows = P + 1;
+    e.grp = c->res_grp[set].p;
+    e.gpart = c->res_gpart[set].p;
+    e.gslot = c->res_gslot[set].p;
+    e.part = c->res_part[set].p;
+    e.ev = c->res_ev[set].p;
+    e.ev_start = c->res_start[set].p;
+    e.ph_cnt = c->res_cnt[set].p;
+}
+
+// Resident K1d tables for more orbitals than one workgroup holds: the rows
+// are split into nrb row blocks of at most K1D_RES_MAXROWS orbitals, each laid
+// out like one workgroup's tables (groups of K1D_RES_BW rows, one per wave;
+// phases of at most cap resident columns).  A block's columns are the
+// orbitals that pair with one of its rows.  The other blocks' orbitals come
+// first, in parts ordered by a round-robin tournament over the blocks (in
+// round r blocks I and J take each other's columns, so the two uses of a
+// pair between them fall close in time in workgroups launched next to each
+// other on one XCD); the block's own rows come last, split into parts with
+// few pairs between them (a pair inside one part has both uses in the same
+// phase, in one CU), and the last part's a values stay in LDS for the
+// epilogue.  Row blocks and own parts grow greedily by kept pairs and are
+// improved by swaps that do not add pairs between them; groups grow greedily
+// by shared columns and are improved by swaps that do not add columns (a
+// fixed pseudo-random sequence: the tables are deterministic).
+static void build_event_blocks(bse_ctx *c, int set, int cap, const Bits &nb,
+                               const std::vector<int> &pidx) {
+    const int no = c->n_occ, BW = K1D_RES_BW, nwd = nb.nwd;
+    const int GW = K1D_RES_MAXROWS / BW;  // groups (waves) of one row block
+    const long long P = c->n_pairs;
+    const int nrb = (no + K1D_RES_MAXROWS - 1) / K1D_RES_MAXROWS;
+    Lcg rnd;
+    auto bit = [&](int v, int w) { return (int)((nb.row(v)[w / 64] >> (w % 64)) & 1); };
+    // pool split into parts of the given sizes with few pairs between parts
+    auto partition = [&](const std::vector<int> &pool, const std::vector<int> &sizes) {
+        const int k = (int)sizes.size();
+        std::vector<int> of(no, -1);
+        std::vector<std::vector<int>> parts(k);
+        std::vector<std::vector<unsigned long long>> pm(k, std::vector<unsigned long long>(nwd, 0));
+        for (int b = 0; b < k; ++b)
+            for (int t = 0; t < sizes[b]; ++t) {
+                int best = -1, best_s = -1;
+                for (int v : pool) {
+                    if (of[v] >= 0) continue;
+                    if (t == 0) {  // seed: the first free member
+                        best = v;
+                        break;
+                    }
+                    const int s = pop_and(nb.row(v), pm[b].data(), nwd);
+                    if (s > best_s) {
+                        best = v;
+                        best_s = s;
+                    }
+                }
+                of[best] = b;
+                parts[b].push_back(best);
+                pm[b][best / 64] |= 1ull << (best % 64);
+            }
+        auto links = [&](int v, int b) { return pop_and(nb.row(v), pm[b].data(), nwd); };
+        for (int it = 0; it < 20000 && k > 1; ++it) {
+            const int a = rnd(k);
+            int b = rnd(k - 1);
+            if (b >= a) ++b;
+            if (parts[a].empty() || parts[b].empty()) continue;
+            const int i = rnd((int)parts[a].size()), j = rnd((int)parts[b].size());
+            const int v = parts[a][i], w = parts[b][j];
+            const int vw = bit(v, w);
+            // change of the pairs between parts when v and w trade places
+            // (links count v's own diagonal pair inside its part)
+            const int d = (links(v, a) - bit(v, v)) - (links(v, b) - vw) +
+                          (links(w, b) - bit(w, w)) - (links(w, a) - vw);
+            if (d > 0) continue;
+            parts[a][i] = w;
+            parts[b][j] = v;
+            of[v] = b;
+            of[w] = a;
+            pm[a][v / 64] &= ~(1ull << (v % 64));
+            pm[b][w / 64] &= ~(1ull << (w % 64));
+            pm[a][w / 64] |= 1ull << (w % 64);
+            pm[b][v / 64] |= 1ull << (v % 64);
+        }
+        for (auto &q : parts) std::sort(q.begin(), q.end());
+        return parts;
+    };
+    auto balanced = [](int n, int k) {
+        std::vector<int> sz(k, n / k);
+        for (int i = 0; i < n % k; ++i) ++sz[i];
+        return sz;
+    };
+    std::vector<int> all(no);
+    for (int v = 0; v < no; ++v) all[v] = v;
+    const std::vector<std::vector<int>> blocks = partition(all, balanced(no, nrb));
+    std::vector<int> blk_of(no);
+    for (int b = 0; b < nrb; ++b)
+        for (int v : blocks[b]) blk_of[v] = b;
+    // columns a group touches (union of its rows' pair masks)
+    auto cover = [&](const int *row) {
+        std::vector<unsigned long long> cv(nwd, 0);
+        for (int i = 0; i < BW; ++i)
+            if (row[i] >= 0)
+                for (int q = 0; q < nwd; ++q) cv[q] |= nb.row(row[i])[q];
+        return cv;
+    };
+    auto popcnt = [&](const std::vector<unsigned long long> &m) {
+        int n = 0;
+        for (unsigned long long x : m) n += __builtin_popcountll(x);
+        return n;
+    };
+    // groups of BW rows inside one part: greedy growth by shared columns,
+    // then swaps between groups that do not add columns
+    auto make_groups = [&](const std::vector<int> &mem) {
+        const int ngh = ((int)mem.size() + BW - 1) / BW;
+        std::vector<int> grp((size_t)ngh * BW, -1);
+        std::vector<char> used(mem.size(), 0);
+        for (int g = 0; g < ngh; ++g) {
+            std::vector<unsigned long long> cv(nwd, 0);
+            const int size = std::min(BW, (int)mem.size() - g * BW);
+            for (int i = 0; i < size; ++i) {
+                int best = -1, best_s = INT_MIN;
+                for (size_t k = 0; k < mem.size(); ++k) {
+                    if (used[k]) continue;
+                    if (i == 0) {
+                        best = (int)k;
+                        break;
+                    }
+                    const unsigned long long *m = nb.row(mem[k]);
+                    int sc = 0;
+                    for (int q = 0; q < nwd; ++q)
+                        sc += __builtin_popcountll(m[q] & cv[q]) - __builtin_popcountll(m[q] & ~cv[q]);
+                    if (sc > best_s) {
+                        best = (int)k;
+                        best_s = sc;
+                    }
+                }
+                used[best] = 1;
+                grp[(size_t)g * BW + i] = mem[best];
+                for (int q = 0; q < nwd; ++q) cv[q] |= nb.row(mem[best])[q];
+            }
+        }
+        if (ngh > 1) {
+            std::vector<int> gc(ngh);
+            for (int g = 0; g < ngh; ++g) gc[g] = popcnt(cover(&grp[(size_t)g * BW]));
+            for (int it = 0; it < 10000; ++it) {
+                const int a = rnd(ngh);
+                int b = rnd(ngh - 1);
+                if (b >= a) ++b;
+                int &x = grp[(size_t)a * BW + rnd(BW)], &y = grp[(size_t)b * BW + rnd(BW)];
+                if (x < 0 && y < 0) continue;
+                std::swap(x, y);
+                const int ca = popcnt(cover(&grp[(size_t)a * BW])),
+                          cb = popcnt(cover(&grp[(size_t)b * BW]));
+                if (ca + cb <= gc[a] + gc[b]) {
+                    gc[a] = ca;
+                    gc[b] = cb;
+                } else {
+                    std::swap(x, y);
+                }
+            }
+        }
+        return grp;
+    };
+    const int EV = BW + 2, HB = BW / 2;
+    const int zero = (int)(P * TAU_TILE);
+    const int nt = nrb + (nrb & 1);
+    auto partner = [&](int I, int r) {
+        if (I == nt - 1) return r;
+        if (I == r) return nt - 1;
+        return ((2 * r - I) % (nt - 1) + (nt - 1)) % (nt - 1);
+    };
+    struct Block {
+        std::vector<std::vector<int>> phases;  // resident columns of each phase
+        int n_ext = 0;                         // phases of other blocks' columns
+        std::vector<int> grp, gpart;           // [GW][BW], [GW] (own phase)
+        int ng = 0;
+    };
+    std::vector<Block> B(nrb);
+    int nph_max = 0;
+    for (int b = 0; b < nrb; ++b) {
+        Block &K = B[b];
+        const std::vector<int> &own = blocks[b];
+        std::vector<char> touch(no, 0);
+        for (int v : own)
+            for (int w = 0; w < no; ++w)
+                if (bit(v, w)) touch[w] = 1;
+        std::vector<int> ext;
+        for (int r = 0; r < nt - 1; ++r) {
+            const int J = partner(b, r);
+            if (J >= nrb) continue;
+            for (int w : blocks[J])
+                if (touch[w]) ext.push_back(w);
+        }
+        for (size_t i = 0; i < ext.size(); i += cap)
+            K.phases.emplace_back(ext.begin() + i,
+                                  ext.begin() + std::min(ext.size(), i + (size_t)cap));
+        K.n_ext = (int)K.phases.size();
+        const int nown = ((int)own.size() + cap - 1) / cap;
+        const auto oparts = partition(own, balanced((int)own.size(), nown));
+        K.grp.assign((size_t)GW * BW, -1);
+        K.gpart.assign(GW, 0);
+        std::vector<std::pair<int, std::vector<int>>> groups;  // (own phase, rows)
+        for (int h = 0; h < nown; ++h) {
+            K.phases.push_back(oparts[h]);
+            const std::vector<int> g = make_groups(oparts[h]);
+            for (size_t q = 0; q < g.size(); q += BW)
+                groups.emplace_back(K.n_ext + h, std::vector<int>(g.begin() + q, g.begin() + q + BW));
+        }
+        K.ng = (int)groups.size();
+        BSE_REQUIRE(K.ng <= GW, BSE_ERR_STATE, "row block %d needs %d groups", b, K.ng);
+        // waves: groups with the most columns first, each onto the SIMD
+        // (wave % 4) with the least work so far that has a free wave
+        std::vector<int> work(K.ng), order(K.ng);
+        for (int g = 0; g < K.ng; ++g) {
+            work[g] = popcnt(cover(groups[g].second.data()));
+            order[g] = g;
+        }
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+        std::vector<int> load(4, 0), cnt(4, 0), wave_of(K.ng);
+        const int per = (K.ng + 3) / 4;
+        for (int g : order) {
+            int best = -1;
+            for (int q = 0; q < 4; ++q)
+                if (cnt[q] < per && q + 4 * cnt[q] < K.ng && (best < 0 || load[q] < load[best]))
+                    best = q;
+            if (best < 0)
+                for (int q = 0; q < 4; ++q)
+                    if (q + 4 * cnt[q] < K.ng) {
+                        best = q;
+                        break;
+                    }
+            wave_of[g] = best + 4 * cnt[best]++;
+            load[best] += work[g];
+        }
+        for (int g = 0; g < K.ng; ++g) {
+            const int w = wave_of[g];
+            std::copy(groups[g].second.begin(), groups[g].second.end(),
+                      K.grp.begin() + (size_t)w * BW);
+            K.gpart[w] = groups[g].first;
+        }
+        nph_max = std::max(nph_max, (int)K.phases.size());
+    }
+    // tables
+    std::vector<int> grp((size_t)nrb * GW * BW, -1), gpart((size_t)nrb * GW, 0),
+        gslot((size_t)nrb * GW * BW, 0), part((size_t)nrb * nph_max * cap, -1),
+        start((size_t)nrb * GW, 0), phc((size_t)nrb * GW * nph_max, 0), rbng(nrb), rbnph(nrb);
+    std::vector<int> ev;
+    for (int b = 0; b < nrb; ++b) {
+        Block &K = B[b];
+        const int nph = (int)K.phases.size();
+        rbng[b] = K.ng;
+        rbnph[b] = nph;
+        std::vector<int> slot(no, -1);  // slot of each column in its phase (per phase below)
+        for (int h = 0; h < nph; ++h)
+            for (size_t k = 0; k < K.phases[h].size(); ++k)
+                part[((size_t)b * nph_max + h) * cap + k] = K.phases[h][k];
+        for (int wv = 0; wv < K.ng; ++wv) {
+            const size_t G = (size_t)b * GW + wv;
+            int *row = &K.grp[(size_t)wv * BW];
+            // halves: the 4 + 4 split of the rows with the fewest events
+            // (a column live in one half shares its event with such a column
+            // of the other half)
+            auto events_of = [&](unsigned mask) {
+                int tot = 0;
+                for (int h = 0; h < nph; ++h) {
+                    int full = 0, lo = 0, hi = 0;
+                    for (int w : K.phases[h]) {
+                        bool l = false, u = false;
+                        for (int i = 0; i < BW; ++i)
+                            if (row[i] >= 0 && bit(row[i], w)) (mask >> i & 1 ? l : u) = true;
+                        full += l && u;
+                        lo += l && !u;
+                        hi += u && !l;
+                    }
+                    tot += (full + std::max(lo, hi) + 1) / 2 * 2;
+                }
+                return tot;
+            };
+            unsigned best = 0x0F;
+            int best_n = events_of(best);
+            for (unsigned mask = 1; mask < 256; mask += 2)
+                if (__builtin_popcount(mask) == BW / 2) {
+                    const int e = events_of(mask);
+                    if (e < best_n) {
+                        best_n = e;
+                        best = mask;
+                    }
+                }
+            {
+                std::vector<int> lo, hi;
+                for (int i = 0; i < BW; ++i) (best >> i & 1 ? lo : hi).push_back(row[i]);
+                auto key = [](int a) { return a < 0 ? INT_MAX : a; };
+                std::sort(lo.begin(), lo.end(), [&](int x, int y) { return key(x) < key(y); });
+                std::sort(hi.begin(), hi.end(), [&](int x, int y) { return key(x) < key(y); });
+                for (int i = 0; i < HB; ++i) {
+                    row[i] = lo[i];
+                    row[HB + i] = hi[i];
+                }
+            }
+            std::copy(row, row + BW, grp.begin() + G * BW);
+            gpart[G] = K.gpart[wv];
+            const std::vector<int> &op = K.phases[K.gpart[wv]];
+            for (int i = 0; i < BW; ++i)
+                if (row[i] >= 0)
+                    gslot[G * BW + i] =
+                        (int)(std::find(op.begin(), op.end(), row[i]) - op.begin());
+        }
+        // events, phase by phase
+        for (int wv = 0; wv < K.ng; ++wv) {
+            const size_t G = (size_t)b * GW + wv;
+            const int *row = &grp[G * BW];
+            start[G] = (int)(ev.size() / EV);
+            std::vector<unsigned long long> cl(nwd, 0), ch(nwd, 0);
+            for (int i = 0; i < BW; ++i)
+                if (row[i] >= 0)
+                    for (int q = 0; q < nwd; ++q) (i < HB ? cl : ch)[q] |= nb.row(row[i])[q];
+            for (int h = 0; h < nph; ++h) {
+                const std::vector<int> &cols = K.phases[h];
+                for (size_t k = 0; k < cols.size(); ++k) slot[cols[k]] = (int)k;
+                auto off = [&](int i, int w) {
+                    const int v = row[i];
+                    const int p = v >= 0 && w >= 0 ? pidx[(size_t)v * no + w] : -1;
+                    return p >= 0 ? p * TAU_TILE : zero;
+                };
+                auto push = [&](int wa, int wb) {  // wa / wb < 0: that half idle
+                    for (int i = 0; i < BW; ++i) ev.push_back(off(i, i < HB ? wa : wb));
+                    const int sa = wa >= 0 ? slot[wa] : slot[wb];
+                    ev.push_back(sa);
+                    ev.push_back(wb >= 0 ? slot[wb] : sa);
+                };
+                std::vector<int> qlo, qhi;
+                auto visit = [&](int w) {
+                    const bool l = cl[w / 64] >> (w % 64) & 1, u = ch[w / 64] >> (w % 64) & 1;
+                    if (l && u) {
+                        push(w, w);
+                    } else if (l) {
+                        if (!qhi.empty()) {
+                            push(w, qhi.front());
+                            qhi.erase(qhi.begin());
+                        } else {
+                            qlo.push_back(w);
+                        }
+                    } else if (u) {
+                        if (!qlo.empty()) {
+                            push(qlo.front(), w);
+                            qlo.erase(qlo.begin());
+                        } else {
+                            qhi.push_back(w);
+                        }
+                    }
+                };
+                const size_t before = ev.size() / EV;
+                if (h >= K.n_ext) {
+                    // an own part: its groups' rows as columns; in the wave's
+                    // own part a round-robin tournament over that part's
+                    // groups (circle method), its own rows last
+                    std::vector<int> gh;
+                    for (int m = 0; m < K.ng; ++m)
+                        if (gpart[(size_t)b * GW + m] == h) gh.push_back(m);
+                    auto visit_group = [&](int m) {
+                        for (int i = 0; i < BW; ++i) {
+                            const int w = grp[((size_t)b * GW + m) * BW + i];
+                            if (w >= 0) visit(w);
+                        }
+                    };
+                    if (gpart[G] == h) {
+                        const int n = (int)gh.size(), ntg = n + (n & 1);
+                        const int me = (int)(std::find(gh.begin(), gh.end(), wv) - gh.begin());
+                        for (int r = 0; r < ntg - 1; ++r) {
+                            int q;
+                            if (me == ntg - 1) q = r;
+                            else if (me == r) q = ntg - 1;
+                            else q = ((2 * r - me) % (ntg - 1) + (ntg - 1)) % (ntg - 1);
+                            if (q < n && q != me) visit_group(gh[q]);
+                        }
+                        visit_group(wv);
+                    } else {
+                        for (int m : gh) visit_group(m);
+                    }
+                } else {
+                    for (int w : cols) visit(w);
+                }
+                for (int w : qlo) push(w, -1);
+                for (int w : qhi) push(-1, w);
+                int n = (int)(ev.size() / EV - before);
+                while (n % 2) {  // events come in pairs (two tau columns in flight)
+                    for (int i = 0; i < BW; ++i) ev.push_back(zero);
+                    ev.push_back(0);
+                    ev.push_back(0);
+                    ++n;
+                }
+                phc[G * nph_max + h] = n;
+                for (int w : cols) slot[w] = -1;
+            }
+            for (int k = 0; k < 4; ++k) {  // read ahead past the end
+                for (int i = 0; i < BW; ++i) ev.push_back(zero);
+                ev.push_back(0);
+                ev.push_back(0);
+            }
+        }
+    }
+    auto up = [&](auto &dev, const auto &host) {
+        dev.alloc(std::max<size_t>(1, host.size()));
+        BSE_HIP(hipMemcpy(dev.p, host.data(), host.size() * sizeof(host[0]), hipMemcpyHostToDevice));
+    };
+    up(c->res_grp[set], grp);
+    up(c->res_gpart[set], gpart);
+    up(c->res_gslot[set], gslot);
+    up(c->res_part[set], part);
+    up(c->res_ev[set], ev);
+    up(c->res_start[set], start);
+    up(c->res_cnt[set], phc);
+    up(c->res_rbng[set], rbng);
+    up(c->res_rbnph[set], rbnph);
+    PairEvents &e = c->res[set];
+    e.ng = GW;
+    e.nph = nph_max;
+    e.cap = cap;
+    e.nrb = nrb;
+    e.rb_ng = c->res_rbng[set].p;
+    e.rb_nph = c->res_rbnph[set].p;
     e.n_rows = P + 1;
     e.grp = c->res_grp[set].p;
     e.gpart = c->res_gpart[set].p;
@@ -682,7 +1122,6 @@ static void build_event_set(bse_ctx *c, int set, int cap, const Bits &nb,
 static void build_events(bse_ctx *c, const std::vector<int> &pr) {
     const int no = c->n_occ;
     for (auto &e : c->res) e = PairEvents{};
-    if (no > K1D_RES_MAXROWS) return;
     Bits nb;
     nb.nwd = (no + 63) / 64;
     nb.w.assign((size_t)no * nb.nwd, 0);
@@ -693,8 +1132,12 @@ static void build_events(bse_ctx *c, const std::vector<int> &pr) {
         nb.w[(size_t)v * nb.nwd + w / 64] |= 1ull << (w % 64);
         nb.w[(size_t)w * nb.nwd + v / 64] |= 1ull << (v % 64);
     }
-    for (int set = 0; set < K1D_RES_NSETS; ++set)
-        build_event_set(c, set, K1D_RES_CAPS[set], nb, pidx);
+    for (int set = 0; set < K1D_RES_NSETS; ++set) {
+        if (no <= K1D_RES_MAXROWS)
+            build_event_set(c, set, K1D_RES_CAPS[set], nb, pidx);
+        else
+            build_event_blocks(c, set, K1D_RES_CAPS[set], nb, pidx);
+    }
 }
 
 void ctx_build_pairs(bse_ctx *c, int kind, double thr) {
@@ -702,9 +1145,10 @@ void ctx_build_pairs(bse_ctx *c, int kind, double thr) {
     std::vector<double> m((size_t)no * no);
     ctx_measure(c, kind, m.data());
     std::vector<int> pr;
+    const int nu = c->n_up > 0 ? c->n_up : no;
     for (int v = 0; v < no; ++v)
         for (int w = v; w < no; ++w)
-            if (v == w || m[(size_t)v * no + w] > thr) {
+            if (v == w || ((v < nu) == (w < nu) && m[(size_t)v * no + w] > thr)) {
                 pr.push_back(v);
                 pr.push_back(w);
             }
@@ -935,12 +1379,31 @@ static int ensure_ws_chunk(bse_ctx *c, ApplyWs<T> &w, int nvec) {
     }
 }
 
-// P_c on a block in place: Y -= (Y Psi^T) Psi
+// P_c on a block in place: Y -= (Y Psi^T) Psi.  With two spin channels each
+// channel's slots are projected against that channel's orbitals only
+// (P_c^sigma), as two batched GEMM pairs over the trial vectors.
 template <typename T>
 static void project_c(bse_ctx *c, bool bf, int norb, T *Y, T *S, const T *psi, Workspace &ws) {
     const int no = c->n_occ, npw = c->npw;
-    gemm_p<T>(c, bf, true, norb, no, npw, (T)1, Y, npw, 0, psi, npw, 0, (T)0, S, no, 0, 1, ws);
-    gemm_p<T>(c, bf, false, norb, npw, no, (T)-1, S, no, 0, psi, npw, 0, (T)1, Y, npw, 0, 1, ws);
+    if (c->n_up <= 0 || c->n_up >= no) {
+        gemm_p<T>(c, bf, true, norb, no, npw, (T)1, Y, npw, 0, psi, npw, 0, (T)0, S, no, 0, 1, ws);
+        gemm_p<T>(c, bf, false, norb, npw, no, (T)-1, S, no, 0, psi, npw, 0, (T)1, Y, npw, 0, 1,
+                  ws);
+        return;
+    }
+    const int nvec = norb / no;
+    const long long sv = (long long)no * npw;  // one trial vector
+    T *Ss = S;
+    for (int sg = 0; sg < 2; ++sg) {
+        const int off = sg ? c->n_up : 0, ns = sg ? no - c->n_up : c->n_up;
+        T *Yo = Y + (size_t)off * npw;
+        const T *Po = psi + (size_t)off * npw;
+        gemm_p<T>(c, bf, true, ns, ns, npw, (T)1, Yo, npw, sv, Po, npw, 0, (T)0, Ss, ns,
+                  (long long)ns * ns, nvec, ws);
+        gemm_p<T>(c, bf, false, ns, npw, ns, (T)-1, Ss, ns, (long long)ns * ns, Po, npw, 0, (T)1,
+                  Yo, npw, sv, nvec, ws);
+        Ss += (size_t)nvec * ns * ns;
+    }
 }
 
 // ev (optional): 11 events, [0] before the first launch, then one after each
@@ -1047,10 +1510,12 @@ void ctx_profile_apply(bse_ctx *c, int n_vec, const void *in, void *out, int pre
     for (auto &e : ev) (void)hipEventDestroy(e);
 }
 
-// A resident shape needs every orbital of the cell in one workgroup.
+// A resident shape holds every orbital of the cell in one workgroup, or one
+// row block of K1D_RES_MAXROWS of them.
 static bool k1d_shape_fits(const bse_ctx *c, bool dbl, int v) {
     const K1dShape s = k1d_shape(dbl, v);
-    return !s.res || c->n_occ <= s.bi;
+    // more orbitals: row blocks of K1D_RES_MAXROWS need shapes of that many rows
+    return !s.res || c->n_occ <= s.bi || s.bi == K1D_RES_MAXROWS;
 }
 
 // Autotuner: time the K1d stage of every compiled shape on this cell with a

@@ -99,6 +99,7 @@ struct bse_ctx {
     std::vector<double> eps_h;
     double vbar = 0;
     double k1e = 2.0, k1d = 1.0, scissor = 0.0;
+    int n_up = 0;  // spin-up slots when two channels are set (0: one channel)
     // pairs and tau
     std::vector<int> pairs_h;  // [P][2]
     bse::Dev<int2> pairs_d;
@@ -108,10 +109,11 @@ struct bse_ctx {
     bse::Dev<int> csr_order[bse::K1D_NSETS];
     bse::PairCSR csr[bse::K1D_NSETS];
     // events of the resident K1d kernel, one set per LDS capacity in
-    // K1D_RES_CAPS (ng = 0 past K1D_RES_MAXROWS orbitals)
+    // K1D_RES_CAPS (several row blocks past K1D_RES_MAXROWS orbitals)
     bse::Dev<int> res_grp[bse::K1D_RES_NSETS], res_gpart[bse::K1D_RES_NSETS],
         res_gslot[bse::K1D_RES_NSETS], res_part[bse::K1D_RES_NSETS],
-        res_ev[bse::K1D_RES_NSETS], res_start[bse::K1D_RES_NSETS], res_cnt[bse::K1D_RES_NSETS];
+        res_ev[bse::K1D_RES_NSETS], res_start[bse::K1D_RES_NSETS], res_cnt[bse::K1D_RES_NSETS],
+        res_rbng[bse::K1D_RES_NSETS], res_rbnph[bse::K1D_RES_NSETS];
     bse::PairEvents res[bse::K1D_RES_NSETS];
     int k1d_shape[2] = {0, 0};  // chosen K1d shape for FP64 / FP32 (bse_autotune)
     long long n_pairs = 0;
@@ -162,6 +164,7 @@ void ctx_jade(bse_ctx *c, int N, int nm, double *A, double *Q, int start_given, 
               int max_sweeps, int *n_sweeps, double *offsum);
 void ctx_localize(bse_ctx *c, const double *Q);
 void ctx_set_terms(bse_ctx *c, double k1e, double k1d, double scissor);
+void ctx_set_spin(bse_ctx *c, int n_up);
 void ctx_measure(bse_ctx *c, int kind, double *m_host);
 void ctx_build_pairs(bse_ctx *c, int kind, double thr);
 void ctx_screen(bse_ctx *c, const double *phi, const double *lam, int n_pdep, int prec);

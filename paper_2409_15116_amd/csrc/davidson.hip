@@ -358,6 +358,10 @@ void DavRun::advance() {
     // symmetrised, the rest mirrored)
     {
         const std::vector<double> Cn = gram(s, nb, s.V.p, kn, s.W.p + (size_t)nb_old * n);
+        for (const double x : Cn)
+            BSE_REQUIRE(std::isfinite(x), BSE_ERR_ARG,
+                        "Davidson: non-finite entry in the subspace matrix (NaN or Inf in the "
+                        "start block or in the operator's output)");
         for (int i = 0; i < nb_old; ++i)
             for (int j = 0; j < kn; ++j)
                 Tm[(size_t)i * maxb + nb_old + j] = Tm[(size_t)(nb_old + j) * maxb + i] =

@@ -226,16 +226,20 @@ __global__ void __launch_bounds__(64 * NW) k_k1d(const T *__restrict__ A, const 
 // in the same round: the two uses of a kept pair's tau, (v, w) by one wave
 // and (w, v) by the other, are loaded close in time in one CU, and tau comes
 // from HBM about once.  The tau loads of the next phase's first events are
-// issued before its barrier.  The workgroup covers every row, so it
-// finishes the K1e density and writes the Hartree input Hc directly.
+// issued before its barrier.  When the workgroup covers every row it
+// finishes the K1e density and writes the Hartree input Hc directly; with
+// several row blocks (more orbitals than one workgroup holds) each block's
+// workgroup writes its share to Dp[block][s] and the blocks of one grid
+// piece are launched next to each other on one XCD.
 template <typename T, int VPL, int PT, int NW, int NBUF, int CAP>
 __global__ void __launch_bounds__(64 * NW) k_k1d_res(
     const T *__restrict__ A, const T *__restrict__ tau, const T *__restrict__ V,
     const T *__restrict__ u, const int *__restrict__ grp, const int *__restrict__ gpart,
     const int *__restrict__ gslot, const int *__restrict__ part,
     const int *__restrict__ ev, const int *__restrict__ ev_start, const int *__restrict__ ph_cnt,
-    int ng, int nph, int n_occ, int B, long long nr, long long n_rows, int nSc, T k1d,
-    T inv_omega, T *__restrict__ Cr, cplx<T> *__restrict__ Hc) {
+    const int *__restrict__ rb_ng, const int *__restrict__ rb_nph, int nrb, int nph_max,
+    int n_occ, int B, long long nr, long long n_rows, int nSc, T k1d,
+    T inv_omega, T *__restrict__ Cr, cplx<T> *__restrict__ Hc, T *__restrict__ Dp) {
     constexpr int BW = K1D_RES_BW;
     constexpr int EV = BW + 2;  // ints per event: BW tau offsets, two column slots
     constexpr int HB = BW / 2;
@@ -252,11 +256,14 @@ __global__ void __launch_bounds__(64 * NW) k_k1d_res(
     // [slot][word][lane]: a wave's 16-byte reads of one word are contiguous
     __shared__ Vec16 a_s[CAP * NH * K1D_R];
     __shared__ T red[NW * VPL * K1D_R];  // [wave][value][lane]
-    // decode: id = 8 * ((hi8 * NQ + q) * nSc + sc) + lo8; tau tile hi8 * 8 + lo8,
-    // piece q of it: the pieces and vector groups of one tile share an XCD
+    // decode: id = 8 * (((hi8 * NQ + q) * nSc + sc) * nrb + rb) + lo8; tau tile
+    // hi8 * 8 + lo8, piece q of it: the row blocks, pieces and vector groups
+    // of one tile share an XCD
     const int id = blockIdx.x;
     const int lo8 = id & 7;
     int rest = id >> 3;
+    const int rb = rest % nrb;
+    rest /= nrb;
     const int sc = rest % nSc;
     rest /= nSc;
     const int q = rest % NQ;
@@ -266,6 +273,8 @@ __global__ void __launch_bounds__(64 * NW) k_k1d_res(
     const int tid = threadIdx.x, lane = tid & 63;
     const int pt = lane % PT, vg = lane / PT;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int G = rb * NW + wv;  // this wave's group in the tables
+    const int ng = rb_ng[rb], nph = rb_nph[rb];
     const long long rr = r0 + pt < nr ? r0 + pt : nr - 1;
     const bool rok = r0 + pt < nr;
     const int s0 = sc * SW + vg * VPL;  // this lane's first vector
@@ -309,7 +318,7 @@ __global__ void __launch_bounds__(64 * NW) k_k1d_res(
 #pragma unroll
         for (int j = 0; j < VPL; ++j) acc[i][j] = 0;
     const bool act = wv < ng;
-    const int *evg = ev + (size_t)(act ? ev_start[wv] : 0) * EV;
+    const int *evg = ev + (size_t)(act ? ev_start[G] : 0) * EV;
     T t[NBUF][BW];
     if (act) {
         // issued in buffer order, the order the loop waits for them in
@@ -330,7 +339,7 @@ __global__ void __launch_bounds__(64 * NW) k_k1d_res(
 #pragma unroll
             for (int l = 0; l < CAP / NW; ++l) {
                 const int k = wv + NW * l;
-                const int o = part[h * CAP + k];
+                const int o = part[((size_t)rb * nph_max + h) * CAP + k];
                 const T *ao = A + (size_t)(o >= 0 ? o : 0) * nr;
                 VecS x;
 #pragma unroll
@@ -340,7 +349,7 @@ __global__ void __launch_bounds__(64 * NW) k_k1d_res(
         }
         __syncthreads();
         if (act) {
-            const int end = e + ph_cnt[wv * nph + h];
+            const int end = e + ph_cnt[(size_t)G * nph_max + h];
 #pragma unroll 1
             for (; e < end; e += NBUF) {
 #pragma unroll
@@ -369,14 +378,14 @@ __global__ void __launch_bounds__(64 * NW) k_k1d_res(
     if (act) {
         size_t so[VPL];
         vec_offsets(so);
-        const bool last = gpart[wv] == nph - 1;
+        const bool last = gpart[G] == nph - 1;
 #pragma unroll
         for (int i = 0; i < BW; ++i) {
-            const int v = grp[wv * BW + i];
+            const int v = grp[G * BW + i];
             if (v >= 0) {
                 VecS av;
                 if (last) {
-                    av = lds_get(gslot[wv * BW + i]);
+                    av = lds_get(gslot[G * BW + i]);
                 } else {
                     const T *ao = A + (size_t)v * nr;
 #pragma unroll
@@ -396,7 +405,7 @@ __global__ void __launch_bounds__(64 * NW) k_k1d_res(
     for (int j = 0; j < VPL; ++j) red[(wv * VPL + j) * K1D_R + lane] = dn[j];
     __syncthreads();
     // Hc[s / 2] = (D[s], D[s + 1]) / Omega for even s, summed over the waves
-    // in fixed order
+    // in fixed order (or this row block's share into Dp[rb][s])
     if (wv < VPL / 2) {
         const int j = 2 * wv;
         T re = 0, im = 0;
@@ -405,9 +414,16 @@ __global__ void __launch_bounds__(64 * NW) k_k1d_res(
             re += red[(w * VPL + j) * K1D_R + lane];
             im += red[(w * VPL + j + 1) * K1D_R + lane];
         }
-        if (rok && s0 + j < B)
-            Hc[(size_t)((s0 + j) / 2) * nr + rr] =
-                cmake<cplx<T>>(re * inv_omega, s0 + j + 1 < B ? im * inv_omega : (T)0);
+        if (rok && s0 + j < B) {
+            if (nrb == 1) {
+                Hc[(size_t)((s0 + j) / 2) * nr + rr] =
+                    cmake<cplx<T>>(re * inv_omega, s0 + j + 1 < B ? im * inv_omega : (T)0);
+            } else {
+                T *dp = Dp + ((size_t)rb * B + s0 + j) * nr + rr;
+                dp[0] = re * inv_omega;
+                if (s0 + j + 1 < B) dp[nr] = im * inv_omega;
+            }
+        }
     }
 }
 
@@ -449,7 +465,7 @@ static void launch_k1d(const T *A, const T *tau, const T *V, const T *u, const P
 template <typename T, int VPL, int PT, int NW, int NBUF>
 static void launch_k1d_res(const T *A, const T *tau, const T *V, const T *u,
                            const PairEvents *pes, int n_occ, int B, long long nr, T k1d,
-                           T inv_omega, T *Cr, cplx<T> *Hc, hipStream_t st) {
+                           T inv_omega, T *Cr, cplx<T> *Hc, T *Dp, hipStream_t st) {
     constexpr int SW = VPL * (K1D_R / PT);
     // LDS capacity in orbitals: 128 KB of a values, and no more slots than
     // the shape has rows (a shape of 8 waves with 16-byte words keeps 64 KB,
@@ -463,18 +479,27 @@ static void launch_k1d_res(const T *A, const T *tau, const T *V, const T *u,
     const PairEvents &pe = pes[set];
     const int nSc = (B + SW - 1) / SW;
     const long long nrt = (nr + K1D_R - 1) / K1D_R;
-    const long long nblk = (nrt + 7) / 8 * 8 * (K1D_R / PT) * nSc;
-    BSE_REQUIRE(pe.ng >= 1 && pe.ng <= NW && pe.cap == CAP && n_occ <= NW * K1D_RES_BW,
+    const long long nblk = (nrt + 7) / 8 * 8 * (K1D_R / PT) * nSc * pe.nrb;
+    // one row block: every orbital in this shape's waves; several: the tables
+    // give each block K1D_RES_MAXROWS / K1D_RES_BW groups, one per wave
+    BSE_REQUIRE(pe.nrb >= 1 && pe.cap == CAP &&
+                    (pe.nrb == 1 ? pe.ng >= 1 && pe.ng <= NW && n_occ <= NW * K1D_RES_BW
+                                 : NW * K1D_RES_BW == K1D_RES_MAXROWS),
                 BSE_ERR_ARG, "the resident K1d shape holds %d orbitals, the cell has %d",
                 NW * K1D_RES_BW, n_occ);
     BSE_REQUIRE(nblk < (1LL << 31), BSE_ERR_ARG, "grid too large for the K1d kernel");
     BSE_REQUIRE(pe.n_rows * TAU_TILE * (long long)sizeof(T) < (1LL << 31), BSE_ERR_ARG,
                 "too many pairs for the K1d tables");
     k_k1d_res<T, VPL, PT, NW, NBUF, CAP><<<(unsigned)nblk, 64 * NW, 0, st>>>(
-        A, tau, V, u, pe.grp, pe.gpart, pe.gslot, pe.part, pe.ev, pe.ev_start, pe.ph_cnt, pe.ng,
-        pe.nph, n_occ, B, nr,
-        pe.n_rows, nSc, k1d, inv_omega, Cr, Hc);
+        A, tau, V, u, pe.grp, pe.gpart, pe.gslot, pe.part, pe.ev, pe.ev_start, pe.ph_cnt,
+        pe.rb_ng, pe.rb_nph, pe.nrb, pe.nph, n_occ, B, nr, pe.n_rows, nSc, k1d, inv_omega, Cr,
+        Hc, Dp);
     BSE_LAUNCH_CHECK();
+    if (pe.nrb > 1) {
+        dim3 g2(div_up(nr, 256), (B + 1) / 2);
+        k_sum_density<T><<<g2, 256, 0, st>>>(Dp, pe.nrb, B, nr, Hc);
+        BSE_LAUNCH_CHECK();
+    }
 }
 
 // the compiled shapes; variant 0 is the default of each type
@@ -511,7 +536,7 @@ void k1d_apply(const T *A, const T *tau, const T *V, const T *u, const PairCSR *
 #define BSE_K1D_RES_CASE(S_, NW_, NB_, PT_)                                                  \
     if (sh.s == S_ && sh.nw == NW_ && sh.nbuf == NB_ && sh.pt == PT_)                         \
         launch_k1d_res<T, S_ * PT_ / K1D_R, PT_, NW_, NB_>(A, tau, V, u, pes, n_occ, B, nr, k1d,  \
-                                                          inv_omega, Cr, Hc, st);
+                                                          inv_omega, Cr, Hc, Dp, st);
         if constexpr (dbl) {
             BSE_K1D_RES_CASE(2, 16, 2, 64)
             BSE_K1D_RES_CASE(4, 16, 2, 32)

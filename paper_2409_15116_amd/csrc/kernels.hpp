@@ -95,12 +95,22 @@ constexpr int K1D_BI_MIN = 16;
 // column of the other half.  gpart[g] is the
 // part of group g's orbitals and gslot[g * BW + i] the LDS slot of orbital
 // grp[g * BW + i] in it.
+//
+// More orbitals than one workgroup holds (K1D_RES_MAXROWS) are split into nrb
+// row blocks, one workgroup per (grid piece, vector group, row block); block
+// b has rb_ng[b] groups and rb_nph[b] phases, and its tables sit at group
+// index g = b * (K1D_RES_MAXROWS / BW) + wave and part index (b * nph + h)
+// (nph is then the largest phase count); each block writes its share of the
+// K1e density to its own partial grid, summed afterwards in fixed order.
 constexpr int K1D_RES_BW = 8;
 constexpr int K1D_RES_MAXROWS = 128;
 constexpr int K1D_RES_NSETS = 2;
 constexpr int K1D_RES_CAPS[K1D_RES_NSETS] = {128, 64};
 struct PairEvents {
     int ng = 0, nph = 0, cap = 0;
+    int nrb = 0;                   // row blocks (1 when every row fits one workgroup)
+    const int *rb_ng = nullptr;    // [nrb] groups of each row block
+    const int *rb_nph = nullptr;   // [nrb] phases of each row block
     long long n_rows = 0;
     const int *grp = nullptr;
     const int *gpart = nullptr;

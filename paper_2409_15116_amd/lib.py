@@ -61,6 +61,7 @@ def load():
         "bse_create": (i32, [C.POINTER(vp), C.POINTER(_Cell), vp, vp, vp, vp]),
         "bse_destroy": (i32, [vp]),
         "bse_set_terms": (i32, [vp, dbl, dbl, dbl]),
+        "bse_set_spin": (i32, [vp, i32]),
         "bse_pair_measure": (i32, [vp, i32, vp]),
         "bse_build_pairs": (i32, [vp, i32, dbl, C.POINTER(i64)]),
         "bse_spread_matrices": (i32, [vp, vp]),
@@ -115,7 +116,7 @@ def load():
 
 
 def exported_symbols():
-    return ["bse_create", "bse_destroy", "bse_set_terms", "bse_pair_measure", "bse_build_pairs",
+    return ["bse_create", "bse_destroy", "bse_set_terms", "bse_set_spin", "bse_pair_measure", "bse_build_pairs",
             "bse_threshold_for_fraction", "bse_get_pairs", "bse_screen_pairs", "bse_copy_tau",
             "bse_apply_liouville", "bse_apply_chunk", "bse_set_graph", "bse_davidson", "bse_status_str",
             "bse_last_error", "bse_debug_to_grid", "bse_debug_gemm", "bse_profile_apply",
@@ -182,6 +183,10 @@ class BseContext:
 
     def set_terms(self, k1e=2.0, k1d=1.0, scissor=0.0):
         _check(load().bse_set_terms(self.h, k1e, k1d, scissor))
+
+    def set_spin(self, n_up):
+        """Slots [0, n_up) spin up, the rest spin down (n_up = n_occ: one channel)."""
+        _check(load().bse_set_spin(self.h, int(n_up)))
 
     def pair_measure(self, kind=MEASURE_ABS_L1):
         m = np.empty((self.n_occ, self.n_occ))
@@ -339,7 +344,10 @@ class BseContext:
         _check(load().bse_set_k1d_shape(self.h, int(precision), int(shape)))
 
     def davidson(self, X0, n_eig, *, block=None, max_basis=0, restart=0, max_iter=200,
-                 precision=FP64, tol=1e-6, delta=0.05, precond=0, verbose=0):
+                 precision=FP64, tol=1e-6, delta=0.05, precond=0, verbose=0, partial_ok=False):
+        """Lowest n_eig eigenpairs: (omega, X, stats).  partial_ok: return the
+        last Ritz pairs when max_iter is hit (stats["status"] = 4) instead of
+        raising, e.g. to resume from X later."""
         torch = self.torch
         B = block or X0.shape[0]
         o = DavidsonOpts(n_eig, B, max_basis, restart, max_iter, precision, tol, delta, precond,
@@ -353,7 +361,8 @@ class BseContext:
         stats = {"iterations": st.iterations, "n_apply": st.n_apply, "seconds": st.seconds,
                  "learned_used": st.learned_used, "learned_rejected": st.learned_rejected,
                  "resid": np.array(st.resid[:n_eig]), "status": status}
-        _check(status)
+        if not (partial_ok and status == 4):
+            _check(status)
         return om, X, stats
 
 

@@ -13,5 +13,5 @@ imports the other.
 """
 from .cell import (  # noqa: F401
     CellSpec, Cell, diamond_sites, make_cell, spec_by_name, SPECS,
-    trial_block, random_block, dipole_block, near_commuting_matrices,
+    trial_block, random_block, dipole_block, near_commuting_matrices, spin_channels,
 )

@@ -88,6 +88,10 @@ def _spec_table():
     # 216-site cell, 96^3, 25 Ry.
     t["c3"] = CellSpec("c3", 30.0, 96, 25.0, n_occ=216, n_pdep=512, m=3, kfold=True)
     t["c3_lit"] = CellSpec("c3_lit", 30.0, 96, 25.0, n_occ=432, n_pdep=512, m=3, kfold=True)
+    # More orbitals than one K1d workgroup holds, on a small grid (the 64-site
+    # lattice at 10 Ry on 48^3): 2 and 3 row blocks of the resident kernel.
+    t["mb136"] = CellSpec("mb136", 20.0, 48, 10.0, n_occ=136, n_pdep=64, m=2, kfold=True)
+    t["mb300"] = CellSpec("mb300", 20.0, 48, 10.0, n_occ=300, n_pdep=64, m=2, kfold=True)
     # Jittered 64-site snapshots (20 seeds).
     for s in range(20):
         t[f"c5_{s:02d}"] = CellSpec(f"c5_{s:02d}", 20.0, 72, 25.0, n_occ=64,
@@ -662,6 +666,40 @@ def _build_cell(spec: CellSpec) -> Cell:
     return Cell(spec=spec, L=L, n=n, omega=L ** 3, miller=miller, g2=g2, V=V, sites=sites,
                 eps=eps, eps_next=eps_next, psi_canon=psi_c, U=U, psi=psi, eps_mat=eps_mat,
                 phi=phi, lam=lam, jade_history=hist)
+
+
+# --------------------------------------------------------------------------
+# spin-polarised occupations (two channels of one cell's orbitals)
+# --------------------------------------------------------------------------
+def spin_channels(cell: Cell, n_up: int, n_down: int):
+    """Spin-polarised filling of a cell: spin sigma occupies the lowest
+    n_sigma canonical orbitals of the cell (both at most the cell's n_occ),
+    each channel JADE-localised on its own (Sec. 2, Eq. wannier).  Returns
+    (psi [n_up + n_down, n_pw] up then down, eps_mat block-diagonal
+    [n_up + n_down]^2, per-channel (psi, eps_mat) list)."""
+    assert 1 <= n_up <= cell.n_occ and 1 <= n_down <= cell.n_occ
+    b = _RealBasis(cell.L, cell.n, cell.miller)
+    chans = []
+    for n in (n_up, n_down):
+        pc = cell.psi_canon[:n]
+        if n > 1:
+            A = spread_matrices(b.to_grid(pc), cell.L, cell.n)
+            Q, _ = jade(A)
+            U = np.ascontiguousarray(Q.T)
+            psi = U @ pc
+            sg = np.sign(psi[np.arange(n), np.abs(psi).argmax(1)])
+            U *= sg[:, None]
+        else:
+            U = np.eye(1)
+        psi = U @ pc
+        em = (U * cell.eps[None, :n]) @ U.T
+        chans.append((psi, 0.5 * (em + em.T)))
+    psi = np.concatenate([chans[0][0], chans[1][0]])
+    nt = n_up + n_down
+    eps = np.zeros((nt, nt))
+    eps[:n_up, :n_up] = chans[0][1]
+    eps[n_up:, n_up:] = chans[1][1]
+    return psi, eps, chans
 
 
 # --------------------------------------------------------------------------

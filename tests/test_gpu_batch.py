@@ -234,3 +234,45 @@ def test_uneven_cell_apply_matches_oracle(name, rows, prec, tol):
     else:
         assert rel_err(got[:, rows], op.apply(X, rows=rows)[:, rows]) < tol
     ctx.close()
+
+
+def test_uneven_cells_davidson_match_stored_oracle():
+    """Two 48^3 cells of the seeded uneven twelve-cell set (41 and 43
+    orbitals, jittered wells, 40 % of the pairs): the 4 lowest excitations,
+    block 8, from the stored oracle's seeded start, solved alone in FP64 and
+    both together in one FP32 batch, within 1 meV of the FP64 oracle's
+    Davidson (tests/golden/make_goldens.py, tol 1e-7)."""
+    from synth.cell import uneven_batch_specs
+    say("uneven cells vs stored oracle")
+    pkg = _pkg()
+    specs = {s.name: s for s in uneven_batch_specs()}
+    names = ["c4_03", "c4_07"]
+    gold = [golden(n) for n in names]
+    st = torch.cuda.Stream()
+    ctxs, X0 = [], []
+    with torch.cuda.stream(st):
+        for n, g in zip(names, gold):
+            c = make_cell(specs[n])
+            ctx = pkg.context_for(c, stream=st)
+            pkg.setup_pairs_and_screen(ctx, c, fraction=g["fraction"], precision=pkg.FP64)
+            assert ctx.n_pairs == g["n_pairs"], n
+            ctx.autotune(g["block"], pkg.FP32, n_rep=1)
+            ctx.set_graph(True)
+            x0 = _dev(trial_block(c, g["block"], seed=g["start_seed"]))
+            om, _, s = ctx.davidson(x0, g["n_eig"], block=g["block"], tol=DAV_TOL[0],
+                                    max_iter=400, precision=pkg.FP64)
+            err = np.abs(om - np.array(g["omega_ha"])).max()
+            say(" ", n, "FP64 alone: iterations", s["iterations"], "max dev (meV)", err / MEV)
+            assert err < MEV
+            ctxs.append(ctx)
+            X0.append(x0)
+        b = pkg.BseBatch(ctxs, st)
+        oms, _, sts = b.davidson(X0, 4, block=8, tol=DAV_TOL[1], max_iter=400,
+                                 precision=pkg.FP32)
+        b.close()
+        for ctx in ctxs:
+            ctx.close()
+    for n, g, om, s in zip(names, gold, oms, sts):
+        err = np.abs(om - np.array(g["omega_ha"])).max()
+        say(" ", n, "FP32 batch: iterations", s["iterations"], "max dev (meV)", err / MEV)
+        assert err < MEV

@@ -4,14 +4,16 @@ N_pw = 57051, N_pdep = 512, 15 % of the pairs).
 Literal filling (N_occ = 432, tau ~51 GB in FP32, ~102 GB in FP64): a block of
 32 trial vectors applied in one captured graph, in FP32 (the whole block at
 once) and in FP64 (the block no longer fits with its real-space workspaces,
-so it runs in chunks).  The oracle computes sampled output orbitals one by
-one (each needs only the pairs that touch it); P_c is checked on the whole
-output.  Tolerances: 1e-11 (FP64) and 2e-5 (FP32) of the largest sampled
+so it runs in chunks), with the default K1d shape and with every resident
+shape that runs in row blocks of 128 orbitals.  The oracle computes sampled
+output orbitals one by one (each needs only the pairs that touch it); P_c is
+checked on the whole output.  Tolerances: 1e-11 (FP64) and 2e-5 (FP32) of the largest sampled
 output entry.
 
 Gapped filling (N_occ = 216): the 8 lowest excitations with a block of 32 in
-FP32 and BF16x3 agree with the FP64 GPU solve within 1 meV; the FP64 apply
-these solves use is the one pinned above at full size.
+FP32 and BF16x3 agree with the FP64 GPU solve within 1 meV (each precision
+with its autotuned K1d shape); the FP64 apply these solves use is the one
+pinned above at full size.
 
 The cells are periodic supercells of one conventional cell, so their ground
 state is solved class by class of the plane waves the potential couples
@@ -59,8 +61,15 @@ def lit():
 
 
 def _run(c, thr, pairs, X, ref, prec, dt, tol):
+    """The block applied in a captured graph with the default K1d shape and
+    with every resident shape that runs in row blocks (the autotuner's
+    candidates at this size); each output against the oracle's rows."""
     import paper_2409_15116_amd as pkg
     st = torch.cuda.Stream()
+    shapes = [0] + [v for v in range(pkg.k1d_num_shapes(prec))
+                    if pkg.k1d_shape_info(prec, v)["resident"]
+                    and pkg.k1d_shape_info(prec, v)["rows"] == 128]
+    errs = {}
     with torch.cuda.stream(st):
         ctx = pkg.context_for(c, stream=st)
         ctx.build_pairs(pkg.MEASURE_ABS_L1, thr)
@@ -72,31 +81,35 @@ def _run(c, thr, pairs, X, ref, prec, dt, tol):
         Y = torch.empty_like(Xd)
         chunk = ctx.apply_chunk(B, prec)
         say(f"c3: precision {prec}, {ctx.n_pairs} pairs, {chunk} vectors per chunk")
-        ctx.set_graph(True)
-        ctx.apply(Xd, Y, prec)                    # capture
-        Y.fill_(float("nan"))
-        ctx.apply(Xd, Y, prec)                    # replay
-        st.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(st)
-        for _ in range(2):
-            ctx.apply(Xd, Y, prec)
-        e1.record(st)
-        st.synchronize()
-        ms = e0.elapsed_time(e1) / 2
-        say(f"c3: {ms:.1f} ms per block of {B} -> {1e3 * B / ms:.1f} applies/s")
-        ctx.set_graph(False)
-    got = Y.double().cpu().numpy()
-    del Xd, Y
-    ctx.close()
+        for shape in shapes:
+            ctx.set_k1d_shape(prec, shape)
+            ctx.set_graph(True)
+            ctx.apply(Xd, Y, prec)                    # capture
+            Y.fill_(float("nan"))
+            ctx.apply(Xd, Y, prec)                    # replay
+            st.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(2):
+                ctx.apply(Xd, Y, prec)
+            e1.record(st)
+            st.synchronize()
+            ms = e0.elapsed_time(e1) / 2
+            ctx.set_graph(False)
+            got = Y.double().cpu().numpy()
+            assert np.isfinite(got).all(), shape
+            S = got.reshape(-1, c.npw) @ c.psi.T
+            assert np.abs(S).max() < (1e-10 if prec == 0 else 1e-4) * np.abs(got).max(), shape
+            errs[shape] = rel_err(got[VECS][:, ROWS], ref[:, ROWS])
+            say(f"c3: shape {shape}: {ms:.1f} ms per block of {B} -> {1e3 * B / ms:.1f} "
+                f"applies/s, sampled rel err {errs[shape]:.2e}")
+        del Xd, Y
+        ctx.close()
     torch.cuda.empty_cache()
-    assert np.isfinite(got).all()
-    S = got.reshape(-1, c.npw) @ c.psi.T
-    assert np.abs(S).max() < (1e-10 if prec == 0 else 1e-4) * np.abs(got).max()
-    err = rel_err(got[VECS][:, ROWS], ref[:, ROWS])
-    say("c3: sampled rel err", err)
-    assert err < tol
+    for shape, err in errs.items():
+        assert err < tol, (shape, err)
+    assert len(shapes) >= 3
     return chunk
 
 
@@ -124,6 +137,8 @@ def test_c3_gapped_davidson_mixed_vs_fp64():
             ctx = pkg.context_for(c, stream=st)
             pkg.setup_pairs_and_screen(ctx, c, fraction=FRACTION, precision=prec)
             X0 = torch.from_numpy(trial_block(c, B, seed=4321)).to("cuda")
+            shape, _ = ctx.autotune(B, prec, n_rep=1)
+            say(f"c3 gapped: precision {prec}, autotuned K1d shape {shape}")
             ctx.set_graph(True)
             om, X, s = ctx.davidson(X0, 8, block=B, precision=prec, tol=1e-5, max_iter=300)
             ctx.close()
