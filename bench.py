@@ -1,19 +1,24 @@
 """Benchmark: Liouville applies/sec (and Davidson time to solution) on one MI355X.
 
-Default workload: the 64-well diamond cell (L = 20 bohr, 72^3 grid, 25 Ry,
-N_pw = 16879 real dofs) at its literal filling N_occ = 128, N_pdep = 256,
-about 40 % of the orbital pairs kept, a block of 16 trial vectors, FP32
-apply replayed from a hipGraph.  One step = one application of the whole
-operator (sphere->grid FFTs, K1d + V a, K1e Hartree, grid->sphere FFTs,
-eps and P_c GEMMs) to the block.  value = 16 * steps / elapsed seconds.
+Default workload: the 216-well diamond cell (L = 30 bohr, 96^3 grid, 25 Ry,
+N_pw = 57051 real dofs) at its literal filling N_occ = 432, N_pdep = 512,
+15 % of the orbital pairs kept (14 396 pairs), a block of 32 trial vectors,
+applied in FP64 (the paper's arithmetic) from a captured hipGraph; the
+block runs in chunks of the largest length whose workspaces fit in HBM.  One
+step = one application of the whole operator (sphere->grid FFTs, K1d + V a,
+K1e Hartree, grid->sphere FFTs, eps and P_c GEMMs) to the block.
+value = 32 * steps / elapsed seconds.
 
-Also reported: per-stage times of the same apply (HIP events on the
-library's stream), the roofline of the dominant kernel, the FP64 CPU oracle
-on a bounded sample of the same apply (host cores), and the Davidson time to
-the 8 lowest excitation energies of the gapped cell (N_occ = 64) in FP64,
-FP32 and BF16x3 against the stored FP64 oracle result.
+Also reported on the same cell and block: FP32 and split-BF16x3 applies/s
+with each output's deviation from the FP64 output; per-stage times (HIP
+events on the library's stream); the roofline of the dominant kernel; the
+FP64 CPU oracle on a bounded sample of the same apply (host cores); the
+Davidson time to the 8 lowest excitation energies of the gapped 216-well
+cell (N_occ = 216) in FP64, FP32 and BF16x3; and the 64-well cell's numbers
+(literal filling FP32 apply, gapped-cell time to solution against the
+stored FP64 oracle).
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--precision fp32]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--precision fp64]
 """
 from __future__ import annotations
 
@@ -30,7 +35,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Liouville applies/sec and time to 8 lowest VEEs at 1 meV vs FP64 oracle"
 HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFLOPS = 157.3
+FP32_PEAK_TFLOPS = 157.3      # MI355X vector FP32 (256 CUs x 2.4 GHz, packed)
+FP64_PEAK_TFLOPS = 78.6       # MI355X vector FP64
 MEV = 3.674932e-5
 
 
@@ -39,9 +45,10 @@ def log(*a):
 
 
 # HBM traffic of the dominant kernel, measured with rocprofv3 counters and
-# kept as a text summary; it is reported only for the workload it was taken
-# on and while the kernel's sources are the ones that were measured.
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k1d_c2_lit_fp32_b16_hbm.md")
+# kept as text summaries (profiles/*_hbm.md); a summary is used only for the
+# kernel, workload and shape it was taken on, and while the kernel's sources
+# are the ones that were measured.
+PROFILES = os.path.join(ROOT, "profiles")
 K1D_SOURCES = ["paper_2409_15116_amd/csrc/k1d.hip", "paper_2409_15116_amd/csrc/kernels.hpp",
                "paper_2409_15116_amd/csrc/ctx.hip"]
 
@@ -56,28 +63,29 @@ def sources_sha256(paths):
 
 
 def measured_traffic(kernel, workload_key, shape):
-    """Bytes per launch of K1d shape `shape` from the counter summary:
+    """Bytes per launch of K1d shape `shape` from a counter summary:
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch) times the factors that the
-    same counters give for a plain copy of known size; None if the summary
-    does not apply."""
-    if not os.path.exists(TRAFFIC_SUMMARY):
-        return None
-    kv = {}
-    with open(TRAFFIC_SUMMARY) as f:
-        for line in f:
-            if line.startswith("- ") and ": " in line:
-                k, v = line[2:].strip().split(": ", 1)
-                kv[k.strip("`")] = v.strip().strip("`")
-    try:
-        if kv.get("kernel") != kernel or kv.get("workload") != workload_key:
-            return None
-        if kv.get("sources_sha256") != sources_sha256(K1D_SOURCES):
-            return None
-        fetch = float(kv[f"shape_{shape}_fetch_kib"]) * float(kv["fetch_bytes_per_kib"])
-        write = float(kv[f"shape_{shape}_write_kib"]) * float(kv["write_bytes_per_kib"])
-    except (KeyError, ValueError):
-        return None
-    return fetch + write
+    same counters give for a plain copy of known size; None if no summary
+    applies."""
+    import glob
+    for path in sorted(glob.glob(os.path.join(PROFILES, "*_hbm.md"))):
+        kv = {}
+        with open(path) as f:
+            for line in f:
+                if line.startswith("- ") and ": " in line:
+                    k, v = line[2:].strip().split(": ", 1)
+                    kv[k.strip("`")] = v.strip().strip("`")
+        try:
+            if kv.get("kernel") != kernel or kv.get("workload") != workload_key:
+                continue
+            if kv.get("sources_sha256") != sources_sha256(K1D_SOURCES):
+                continue
+            fetch = float(kv[f"shape_{shape}_fetch_kib"]) * float(kv["fetch_bytes_per_kib"])
+            write = float(kv[f"shape_{shape}_write_kib"]) * float(kv["write_bytes_per_kib"])
+        except (KeyError, ValueError):
+            continue
+        return fetch + write
+    return None
 
 
 def sphere_shape(miller, n):
@@ -88,29 +96,61 @@ def sphere_shape(miller, n):
     return ncol, nxp
 
 
-def stage_bytes(cell, B, n_pairs, ncol, nxp, esz):
-    """Algorithmic HBM bytes of each apply stage: every operand read once and
-    every result written once (the unit of each figure is one block apply)."""
-    n, nr, no, npw = cell.n, cell.nr, cell.n_occ, cell.npw
-    norb = B * no
-    nq = (norb + 1) // 2
-    c = 2 * esz
-    t1 = nq * ncol * n * c
-    t2 = nq * nxp * n * n * c
-    grid = norb * nr * esz
-    nbh = (B + 1) // 2
+def algorithmic(cell, B, chunk, n_pairs, esz):
+    """What the method itself must move and compute (the survey's measure):
+    the screened integrals once, the orbitals on the grid once, the trial
+    block in and out in G-space and the orbitals' coefficients; real-space
+    trial orbitals and FFT intermediates are not counted.  The K1d launch of
+    one chunk of trial vectors reads tau, psi(r) and V; its useful products
+    are 2 per trial vector, grid point and pair direction (2P - N_occ)."""
+    nr, no, npw = cell.nr, cell.n_occ, cell.npw
+    tau = n_pairs * nr * esz
+    psi_r = no * nr * esz
     return {
-        "inv_z": norb * npw * esz + t1,
-        "inv_y": t1 + t2,
-        "inv_x": t2 + grid,
-        "k1d": n_pairs * nr * esz + grid + no * nr * esz + nr * esz + grid + nbh * nr * c,
-        "hartree": 2 * 3 * 2 * nbh * nr * c + 2 * nbh * nr * c,
-        "fwd_x": grid + no * nr * esz + nbh * nr * c + t2,
-        "fwd_y": t2 + t1,
-        "fwd_z": t1 + 2 * norb * npw * esz,
-        "eps_gemm": 2 * norb * npw * esz + no * no * esz,
-        "pc_gemm": 3 * norb * npw * esz + 2 * no * npw * esz,
+        "apply_bytes": tau + psi_r + 2 * B * no * npw * esz + no * npw * esz,
+        "block_bytes": B * no * npw * esz,
+        "k1d_bytes_per_launch": tau + psi_r + nr * esz,
+        "k1d_flops_per_launch": 2.0 * chunk * nr * (2 * n_pairs - no),
+        "pc_flops": 4.0 * B * no * no * npw,
+        "eps_flops": 2.0 * B * no * no * npw,
     }
+
+
+def roofline(stages, alg, n_chunks, esz, traffic):
+    """Roofline of the dominant stage (HIP-event times summed over chunks;
+    per launch = sum / chunks)."""
+    dom = max(stages, key=stages.get)
+    peak_tf = FP64_PEAK_TFLOPS if esz == 8 else FP32_PEAK_TFLOPS
+    per_launch_s = stages[dom] * 1e-3 / n_chunks
+    out = {"kernel": dom, "launches_per_apply": n_chunks,
+           "ms_per_launch": per_launch_s * 1e3}
+    if dom == "k1d":
+        b, f = alg["k1d_bytes_per_launch"], alg["k1d_flops_per_launch"]
+        t_hbm, t_alu = b / (HBM_PEAK_GBS * 1e9), f / (peak_tf * 1e12)
+        gbs, tfs = b / per_launch_s / 1e9, f / per_launch_s / 1e12
+        out.update({"algorithmic_bytes": b, "useful_flops": f,
+                    "hbm_frac": gbs / HBM_PEAK_GBS, "alu_frac": tfs / peak_tf})
+        if t_hbm >= t_alu:
+            out.update({"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": gbs / HBM_PEAK_GBS})
+        else:
+            out.update({"bound": "alu", "achieved": tfs, "peak": peak_tf, "unit": "TFLOP/s",
+                        "frac": tfs / peak_tf})
+    elif dom in ("eps_gemm", "pc_gemm"):
+        f = alg["pc_flops" if dom == "pc_gemm" else "eps_flops"] / n_chunks
+        tfs = f / per_launch_s / 1e12
+        out.update({"bound": "mfma", "achieved": tfs, "peak": peak_tf, "unit": "TFLOP/s",
+                    "frac": tfs / peak_tf, "useful_flops": f})
+    else:
+        # an FFT pass: of its traffic only the trial block read by the first
+        # inverse pass and the result written by the last forward pass are
+        # algorithmic (intermediates and real-space orbitals are not)
+        b = alg["block_bytes"] / n_chunks if dom in ("inv_z", "fwd_z") else 0.0
+        gbs = b / per_launch_s / 1e9
+        out.update({"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes": b})
+    out["traffic"] = traffic
+    return out
 
 
 def cpu_baseline(cell, X, threshold):
@@ -154,7 +194,18 @@ def cpu_baseline(cell, X, threshold):
             if threadpoolctl.threadpool_info() else 1
     except Exception:
         threads = os.cpu_count() or 1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": 1.0 / t_vec, "unit": "applies/s", "cores": int(threads), "kind": "oracle",
+            "host": {"nproc": os.cpu_count(), "cpu_model": model, "blas_threads": int(threads),
+                     "fft": "numpy.fft (one thread)"},
             "sample": (f"{n_vec} trial vectors of the same block, one at a time (median); all "
                        f"stages timed except K1d, which is timed on output orbitals {rows} "
                        f"({inc_sub} of {inc_all} pair products) and scaled by pair count; "
@@ -262,15 +313,21 @@ def uneven_batch(args, torch, pkg):
     return out
 
 
-def lanczos_run(args, torch, pkg, ctx, cell, st, prec):
+def lanczos_run(args, torch, pkg):
     """Absorption-spectrum workload (Sec. 4: N_Lanczos x N_pol applications
-    of L): N Lanczos steps for the three dipole perturbations of the bench
-    cell, one block apply of 3 vectors per step, in the bench precision
-    (graph replay).  Reports the chain's wall time, steps and applies per
-    second, and the brightest peak of the x spectrum (eta = 0.02 Ha)."""
-    from synth import dipole_block
+    of L): N Lanczos steps for the three dipole perturbations of the 64-well
+    cell at its literal filling (40 % of the pairs), one block apply of 3
+    vectors per step in FP32 (graph replay).  Reports the chain's wall time,
+    steps and applies per second, and the brightest peak of the x spectrum
+    (eta = 0.02 Ha)."""
+    from synth import dipole_block, make_cell
     n = args.lanczos
+    prec = pkg.FP32
+    cell = make_cell("c2_lit")
+    st = torch.cuda.Stream()
     with torch.cuda.stream(st):
+        ctx = pkg.context_for(cell, stream=st)
+        pkg.setup_pairs_and_screen(ctx, cell, fraction=0.4, precision=prec)
         D = torch.from_numpy(dipole_block(cell, 3)).to("cuda")
         shape, _ = ctx.autotune(3, prec, n_rep=2)   # K1d shape for 3-vector applies (set-up)
         ctx.set_graph(True)
@@ -280,13 +337,14 @@ def lanczos_run(args, torch, pkg, ctx, cell, st, prec):
         alpha, beta = ctx.lanczos(D, n, prec)
         torch.cuda.synchronize()
         sec = time.time() - t
+        ctx.close()
     omega = np.linspace(0.0, 1.0, 2001)
     s = pkg.lanczos_spectrum(alpha[0], beta[0], omega, 0.02)
     peak = float(omega[int(np.argmax(-s.imag))])
     log(f"lanczos: {n} steps x 3 polarisations in {sec:.2f} s, x peak at {peak:.4f} Ha "
         f"(K1d shape {shape})")
-    return {"steps": n, "n_pol": 3, "seconds": sec, "steps_per_s": n / sec,
-            "applies_per_s": 3 * n / sec, "precision": args.precision, "k1d_shape": shape,
+    return {"cell": "c2_lit", "steps": n, "n_pol": 3, "seconds": sec, "steps_per_s": n / sec,
+            "applies_per_s": 3 * n / sec, "precision": "fp32", "k1d_shape": shape,
             "x_peak_ha": peak, "eta_ha": 0.02}
 
 
@@ -300,18 +358,20 @@ def jade_run(args, torch, pkg):
     for name in args.jade.split(","):
         if name.startswith("N") and name[1:].isdigit():
             # synthetic: six near-commuting N x N matrices (the paper's largest
-            # case has 2048 orbitals), from Q = I, on the bench cell's context
+            # case has 2048 orbitals), from Q = I
             N = int(name[1:])
             A0, _ = near_commuting_matrices(N, seed=5)
             st = torch.cuda.Stream()
             with torch.cuda.stream(st):
+                hctx = pkg.context_for(make_cell("c1"), stream=st)   # a handle for the sweeps
                 A = torch.from_numpy(A0).to("cuda")
                 Q0 = torch.eye(N, dtype=torch.float64, device="cuda")   # start: Q = I
                 torch.cuda.synchronize()
                 t1 = time.time()
-                Q, sweeps, off = args._ctx.jade(A, Q0, tol=1e-7, max_sweeps=60)
+                Q, sweeps, off = hctx.jade(A, Q0, tol=1e-7, max_sweeps=60)
                 torch.cuda.synchronize()
                 t2 = time.time()
+                hctx.close()
             rounds = sweeps * (N + (N & 1) - 1)
             log(f"jade {name}: {sweeps} sweeps in {t2 - t1:.3f} s "
                 f"({(t2 - t1) / max(rounds, 1) * 1e6:.1f} us per round), off-diagonal {off:.6g}")
@@ -427,18 +487,126 @@ def learned_c5(args, torch, pkg):
     return out
 
 
+def apply_mode(torch, pkg, cell, thr, Xh, prec, B, steps, warmup, graph=True, tune=True):
+    """One precision on the bench cell: pair list at threshold thr, screened
+    integrals, autotuned K1d shape (set-up, untimed), stage profile, then
+    `steps` graph-replayed applies of the block timed with HIP events on the
+    library's stream and by the host clock (the larger is used).  Returns
+    (result dict, context, output block on the device)."""
+    dt = torch.float64 if prec == pkg.FP64 else torch.float32
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        ctx = pkg.context_for(cell, stream=st)
+        t = time.time()
+        ctx.build_pairs(pkg.MEASURE_ABS_L1, thr)
+        phi = torch.from_numpy(np.ascontiguousarray(cell.phi)).to("cuda")
+        ctx.screen_pairs(phi, cell.lam, prec)
+        del phi
+        torch.cuda.synchronize()
+        t_setup = time.time() - t
+        shape, shape_ms = 0, []
+        if tune:
+            t = time.time()
+            shape, shape_ms = ctx.autotune(B, prec, n_rep=1)
+            log(f"  autotuned K1d shape {shape} ({time.time() - t:.1f} s): "
+                f"{[None if x is None else round(x, 2) for x in shape_ms]} ms")
+        X = torch.from_numpy(Xh).to("cuda", dtype=dt)
+        Y = torch.empty_like(X)
+        chunk = ctx.apply_chunk(B, prec)
+        stages = ctx.profile_apply(X, Y, prec, n_rep=1)
+        log("  stages (ms, summed over chunks):", {k: round(v, 2) for k, v in stages.items()})
+        ctx.set_graph(graph)
+        for _ in range(warmup):
+            ctx.apply(X, Y, prec)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.time()
+        e0.record(st)
+        for _ in range(steps):
+            ctx.apply(X, Y, prec)
+        e1.record(st)
+        torch.cuda.synchronize()
+        wall = time.time() - t0
+        ms_gpu = e0.elapsed_time(e1)
+        del X
+    elapsed = max(wall, ms_gpu / 1e3)
+    res = {"value": B * steps / elapsed, "ms_per_step": 1e3 * elapsed / steps,
+           "k1d_shape": shape, "k1d_ms_by_shape": [None if x is None else round(x, 3)
+                                                    for x in shape_ms],
+           "chunk": chunk, "n_chunks": -(-B // chunk), "stage_ms": stages,
+           "n_pairs": ctx.n_pairs, "setup_seconds": t_setup}
+    return res, ctx, Y
+
+
+def rel_dev(torch, Y, Yref):
+    """max |Y - Yref| / max |Yref| over the block, one trial vector at a time."""
+    num, den = 0.0, 0.0
+    for s in range(Y.shape[0]):
+        r = Yref[s].double()
+        num = max(num, float((Y[s].double() - r).abs().max()))
+        den = max(den, float(r.abs().max()))
+    return num / den
+
+
+def tts_c3(torch, pkg, B=32, fraction=0.15):
+    """Davidson to the 8 lowest VEEs of the gapped 216-well cell (N_occ = 216,
+    96^3, 25 Ry, N_pdep = 512, 15 % of the pairs), block 32, tol 1e-5 Ha, from
+    the same seeded start in FP64, FP32 and BF16x3 (each with its autotuned
+    K1d shape; the FP64 apply is the one pinned against the oracle at full
+    size).  Returns the times, iterations, eigenvalues and each mode's largest
+    deviation from the FP64 eigenvalues."""
+    from synth import make_cell, trial_block
+    t = time.time()
+    cell = make_cell("c3")
+    log(f"c3 gapped cell ready in {time.time() - t:.1f} s")
+    out = {"cell": (f"216-well diamond cell, N_occ = 216 (gapped), 96^3, 25 Ry, N_pdep = 512, "
+                    f"{int(100 * fraction)}% pairs, 8 lowest, block {B}, tol 1e-5 Ha")}
+    X0h = trial_block(cell, B, seed=4321)
+    for name, prec in (("fp64", pkg.FP64), ("fp32", pkg.FP32), ("bf16x3", pkg.BF16X3)):
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            ctx = pkg.context_for(cell, stream=st)
+            pkg.setup_pairs_and_screen(ctx, cell, fraction=fraction, precision=prec)
+            shape, _ = ctx.autotune(B, prec, n_rep=1)         # set-up, not timed
+            X0 = torch.from_numpy(X0h).to("cuda")
+            ctx.set_graph(True)
+            torch.cuda.synchronize()
+            t = time.time()
+            om, X, stt = ctx.davidson(X0, 8, block=B, precision=prec, tol=1e-5, max_iter=400)
+            torch.cuda.synchronize()
+            dt = time.time() - t
+            out["n_pairs"] = ctx.n_pairs
+            ctx.close()
+            del X, X0
+        torch.cuda.empty_cache()
+        out[name] = {"seconds": dt, "iterations": stt["iterations"], "n_apply": stt["n_apply"],
+                     "k1d_shape": shape, "omega_ha": [float(x) for x in om]}
+        log("tts c3", name, out[name])
+    ref = np.array(out["fp64"]["omega_ha"])
+    for name in ("fp32", "bf16x3"):
+        err = float(np.abs(np.array(out[name]["omega_ha"]) - ref).max())
+        out[name]["max_dev_vs_fp64_ha"] = err
+        out[name]["within_1mev_of_fp64"] = bool(err <= MEV)
+        out[name]["speedup_vs_fp64"] = out["fp64"]["seconds"] / out[name]["seconds"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cell", default="c2_lit")
-    ap.add_argument("--block", type=int, default=16)
-    ap.add_argument("--fraction", type=float, default=0.4)
-    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--cell", default="c3_lit")
+    ap.add_argument("--block", type=int, default=32)
+    ap.add_argument("--fraction", type=float, default=0.15)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tts", action="store_true")
+    ap.add_argument("--no-modes", action="store_true",
+                    help="skip the other precisions on the bench cell")
+    ap.add_argument("--no-c2", action="store_true", help="skip the 64-well cell's numbers")
     ap.add_argument("--uneven-batch", type=int, default=0, metavar="N",
                     help="also run the batch of N uneven cells (reported under uneven_batch)")
     ap.add_argument("--learned", type=int, default=0, metavar="N",
@@ -446,7 +614,7 @@ def main():
                          "(4/5 train, 1/5 test; reported under learned)")
     ap.add_argument("--lanczos", type=int, default=0, metavar="N",
                     help="also run N Lanczos steps for the 3 dipole perturbations of the "
-                         "bench cell (reported under lanczos)")
+                         "64-well cell (reported under lanczos)")
     ap.add_argument("--jade", default="", metavar="CELLS",
                     help="also localise the canonical orbitals of these cells (comma list) "
                          "on the GPU (reported under jade)")
@@ -465,8 +633,8 @@ def main():
     from synth import make_cell, trial_block
     pkg.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    prec = {"fp64": pkg.FP64, "fp32": pkg.FP32, "bf16x3": pkg.BF16X3}[args.precision]
-    dt = torch.float64 if prec == pkg.FP64 else torch.float32
+    names = {"fp64": pkg.FP64, "fp32": pkg.FP32, "bf16x3": pkg.BF16X3}
+    prec = names[args.precision]
     esz = 8 if prec == pkg.FP64 else 4
     B = args.block
 
@@ -481,92 +649,91 @@ def main():
     t = time.time()
     cell = make_cell(args.cell)
     log(f"cell ready in {time.time() - t:.1f} s: n_occ={cell.n_occ} npw={cell.npw} n={cell.n}")
-    st = torch.cuda.Stream()
-    with torch.cuda.stream(st):
-        ctx = pkg.context_for(cell, stream=st)
-        t = time.time()
-        thr = pkg.setup_pairs_and_screen(ctx, cell, fraction=args.fraction, precision=prec)
-        torch.cuda.synchronize()
-        t_setup = time.time() - t
-        P = ctx.n_pairs
-        log(f"pairs {P} (threshold {thr:.4g}), setup {t_setup:.2f} s")
-        # the autotuner picks the K1d shape for this cell and block (untimed set-up)
-        t = time.time()
-        shape, shape_ms = ctx.autotune(B, prec, n_rep=2)
-        t_tune = time.time() - t
-        log(f"autotuned K1d shape {shape}: {[None if x is None else round(x, 3) for x in shape_ms]} ms ({t_tune:.1f} s)")
-        Xh = trial_block(cell, B, seed=1234)
-        X = torch.from_numpy(Xh).to("cuda", dtype=dt)
-        Y = torch.empty_like(X)
-        stages = ctx.profile_apply(X, Y, prec, n_rep=3)
-        log("stages (ms):", {k: round(v, 3) for k, v in stages.items()})
-        ctx.set_graph(not args.no_graph)
-        for _ in range(args.warmup):
-            ctx.apply(X, Y, prec)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        t0 = time.time()
-        e0.record(st)
-        for _ in range(args.steps):
-            ctx.apply(X, Y, prec)
-        e1.record(st)
-        torch.cuda.synchronize()
-        wall = time.time() - t0
-        ms_gpu = e0.elapsed_time(e1)
-    elapsed = max(wall, ms_gpu / 1e3)
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = B * args.steps / elapsed
-
-    ncol, nxp = sphere_shape(cell.miller, cell.n)
-    nbytes = stage_bytes(cell, B, P, ncol, nxp, esz)
-    dom = max(stages, key=stages.get)
-    if dom in ("eps_gemm", "pc_gemm"):
-        no, npw = cell.n_occ, cell.npw
-        fl = 2 * B * no * no * npw * (1 if dom == "eps_gemm" else 2)
-        ach = fl / (stages[dom] * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": ach, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / FP32_PEAK_TFLOPS, "traffic": None, "kernel": dom}
-    else:
-        ach = nbytes[dom] / (stages[dom] * 1e-3) / 1e9
-        wkey = f"{args.cell} {args.precision} block {B} fraction {args.fraction}"
-        traffic = measured_traffic(dom, wkey, shape)
-        roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
-                "algorithmic_bytes": nbytes[dom]}
-    roof["stage_ms"] = {k: round(v, 4) for k, v in stages.items()}
-    roof["stage_gbs"] = {k: round(nbytes[k] / (stages[k] * 1e-3) / 1e9, 1) for k in stages}
-    whole_bytes = sum(nbytes[k] for k in nbytes)
+    # pair threshold for the kept fraction (the library's measure and selection)
+    st0 = torch.cuda.Stream()
+    with torch.cuda.stream(st0):
+        c0 = pkg.context_for(cell, stream=st0)
+        thr = pkg.threshold_for_fraction(c0.pair_measure(pkg.MEASURE_ABS_L1), args.fraction)
+        c0.close()
+    Xh = trial_block(cell, B, seed=1234)
+    log(f"headline: {args.precision}, block {B}")
+    head, ctx, Yh = apply_mode(torch, pkg, cell, thr, Xh, prec, B, args.steps, args.warmup,
+                               graph=not args.no_graph)
+    ctx.close()
+    torch.cuda.empty_cache()
+    P = head["n_pairs"]
+    alg = algorithmic(cell, B, head["chunk"], P, esz)
+    wkey = f"{args.cell} {args.precision} block {B} fraction {args.fraction}"
+    traffic = measured_traffic("k1d", wkey, head["k1d_shape"])
+    roof = roofline(head["stage_ms"], alg, head["n_chunks"], esz, traffic)
+    roof["stage_ms"] = {k: round(v, 3) for k, v in head["stage_ms"].items()}
     res = {
-        "metric": METRIC, "value": value, "unit": "applies/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "metric": METRIC, "value": head["value"], "unit": "applies/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "f32+bf16x3"}[args.precision],
         "data": "synthetic",
         "config": {"workload": (f"{args.cell}: {len(cell.sites)}-well diamond cell, L={cell.L} "
                                 f"bohr, {cell.n}^3 grid, {cell.spec.ecut_ry} Ry, N_pw={cell.npw}, "
                                 f"N_occ={cell.n_occ}, N_pdep={cell.n_pdep}, {P} pairs "
-                                f"(fraction {args.fraction}), block {B}, "
+                                f"(fraction {args.fraction}), block {B}, {args.precision}, "
                                 f"{'hipGraph replay' if not args.no_graph else 'eager'}"),
                    "block": B, "n_occ": cell.n_occ, "grid": cell.n, "n_pairs": P,
-                   "precision": args.precision, "k1d_shape": shape,
-                   "k1d_ms_by_shape": [None if x is None else round(x, 3) for x in shape_ms]},
+                   "precision": args.precision, "k1d_shape": head["k1d_shape"],
+                   "chunk": head["chunk"], "k1d_ms_by_shape": head["k1d_ms_by_shape"]},
         "roofline": roof,
-        "whole_apply_gbs": whole_bytes / (ms_per_step * 1e-3) / 1e9,
-        "setup_seconds": t_setup,
+        "whole_apply": {"algorithmic_bytes": alg["apply_bytes"],
+                        "algorithmic_gbs": alg["apply_bytes"] / (head["ms_per_step"] * 1e-3) / 1e9,
+                        "hbm_frac": alg["apply_bytes"] / (head["ms_per_step"] * 1e-3) / 1e9
+                        / HBM_PEAK_GBS},
+        "setup_seconds": head["setup_seconds"],
     }
+    log("headline", {k: res[k] for k in ("value", "ms_per_step")}, roof)
+    if not args.no_modes:
+        modes = {}
+        Yref = Yh
+        for name in ("fp64", "fp32", "bf16x3"):
+            if name == args.precision:
+                continue
+            log(f"mode {name}")
+            r, c2x, Y = apply_mode(torch, pkg, cell, thr, Xh, names[name], B, max(5, args.steps // 2),
+                                   2, graph=not args.no_graph)
+            c2x.close()
+            r["rel_dev_vs_" + args.precision] = rel_dev(torch, Y, Yref)
+            r.pop("stage_ms", None)
+            del Y
+            torch.cuda.empty_cache()
+            modes[name] = r
+            log(f"mode {name}: {r['value']:.1f} applies/s, dev {r['rel_dev_vs_' + args.precision]:.2e}")
+        res["modes"] = modes
+    del Yh
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
         res["cpu_baseline"] = cpu_baseline(cell, Xh, thr)
     if not args.no_tts:
-        log("time to solution")
-        res["time_to_solution"] = time_to_solution(args, torch, pkg)
+        log("time to solution, 216-well gapped cell")
+        res["time_to_solution"] = {"c3": tts_c3(torch, pkg)}
+    if not args.no_c2:
+        log("64-well cell: literal filling FP32 apply, gapped time to solution")
+        c2 = make_cell("c2_lit")
+        st2 = torch.cuda.Stream()
+        with torch.cuda.stream(st2):
+            cx = pkg.context_for(c2, stream=st2)
+            thr2 = pkg.threshold_for_fraction(cx.pair_measure(pkg.MEASURE_ABS_L1), 0.4)
+            cx.close()
+        r2, cx, Y2 = apply_mode(torch, pkg, c2, thr2, trial_block(c2, 16, seed=1234), pkg.FP32,
+                                16, args.steps, args.warmup, graph=not args.no_graph)
+        cx.close()
+        del Y2
+        res["c2_lit_fp32"] = r2
+        if not args.no_tts:
+            res.setdefault("time_to_solution", {})["c2"] = time_to_solution(args, torch, pkg)
     if args.lanczos > 0:
         log("lanczos")
-        res["lanczos"] = lanczos_run(args, torch, pkg, ctx, cell, st, prec)
+        res["lanczos"] = lanczos_run(args, torch, pkg)
     if args.jade:
         log("jade")
-        args._ctx = ctx
         res["jade"] = jade_run(args, torch, pkg)
     if args.uneven_batch > 0:
         log("uneven batch")
@@ -574,7 +741,6 @@ def main():
     if args.learned > 0:
         log("learned preconditioner")
         res["learned"] = learned_c5(args, torch, pkg)
-    ctx.close()
     print(json.dumps(res), flush=True)
 
 

@@ -443,6 +443,19 @@ const char *bse_last_error(void) { return bse::last_error(); }
 
 extern "C" {
 
+bse_status bse_debug_k1d_tables(bse_ctx *c, int set, int64_t *stats) {
+    CHECK_CTX(c);
+    if (!stats) {
+        set_error("bse_debug_k1d_tables: null output");
+        return BSE_ERR_ARG;
+    }
+    BSE_GUARD({
+        long long st[8];
+        bse::ctx_k1d_tables(c, set, st);
+        for (int i = 0; i < 8; ++i) stats[i] = st[i];
+    })
+}
+
 bse_status bse_debug_to_grid(bse_ctx *c, int n_orb, const void *X, void *out, int precision) {
     CHECK_CTX(c);
     if (!X || !out || n_orb < 1) {

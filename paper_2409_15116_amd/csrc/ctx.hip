@@ -684,6 +684,11 @@ static void build_event_set(bse_ctx *c, int set, int cap, const Bits &nb,
     up(c->res_rbng[set], rbng);
     up(c->res_rbnph[set], rbnph);
     PairEvents &e = c->res[set];
+    e.n_ev = (long long)(ev.size() / EV);
+    e.n_kept = 0;
+    for (size_t k = 0; k < ev.size(); k += EV)
+        for (int i = 0; i < BW; ++i) e.n_kept += ev[k + i] != zero;
+    e.n_staged = no;
     e.ng = ng;
     e.nph = nph;
     e.cap = cap;
@@ -1103,6 +1108,13 @@ static void build_event_blocks(bse_ctx *c, int set, int cap, const Bits &nb,
     up(c->res_rbng[set], rbng);
     up(c->res_rbnph[set], rbnph);
     PairEvents &e = c->res[set];
+    e.n_ev = (long long)(ev.size() / EV);
+    e.n_kept = 0;
+    for (size_t k = 0; k < ev.size(); k += EV)
+        for (int i = 0; i < BW; ++i) e.n_kept += ev[k + i] != zero;
+    e.n_staged = 0;
+    for (const Block &K : B)
+        for (const auto &ph : K.phases) e.n_staged += (long long)ph.size();
     e.ng = GW;
     e.nph = nph_max;
     e.cap = cap;
@@ -1587,6 +1599,14 @@ void ctx_set_k1d_shape(bse_ctx *c, int prec, int shape) {
                 k1d_shape(dbl, shape).bi, c->n_occ);
     drop_graph(c);
     c->k1d_shape[dbl ? 0 : 1] = shape;
+}
+
+void ctx_k1d_tables(const bse_ctx *c, int set, long long *st) {
+    BSE_REQUIRE(set >= 0 && set < K1D_RES_NSETS, BSE_ERR_ARG, "unknown table set %d", set);
+    const PairEvents &e = c->res[set];
+    const long long v[8] = {e.nrb, e.nph, e.cap, e.n_ev, e.n_kept, e.n_staged,
+                            c->n_pairs, (long long)c->n_occ};
+    for (int i = 0; i < 8; ++i) st[i] = v[i];
 }
 
 void ctx_project_c64(bse_ctx *c, int n_vec, double *Y) {

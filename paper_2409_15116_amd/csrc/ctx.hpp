@@ -176,6 +176,7 @@ void ctx_apply_entry(bse_ctx *c, int n_vec, const void *in, void *out, int prec)
 void ctx_profile_apply(bse_ctx *c, int n_vec, const void *in, void *out, int prec, int n_rep,
                        double *ms);
 void ctx_project_c64(bse_ctx *c, int n_vec, double *Y);
+void ctx_k1d_tables(const bse_ctx *c, int set, long long *st);
 void ctx_davidson(bse_ctx *c, const bse_davidson_opts *o, const double *X0, double *omega,
                   double *X, bse_davidson_stats *stats, RecordSpec *rec = nullptr);
 void batch_create(bse_batch *b, bse_ctx *const *ctxs, int n, hipStream_t stream);

@@ -112,6 +112,9 @@ struct PairEvents {
     const int *rb_ng = nullptr;    // [nrb] groups of each row block
     const int *rb_nph = nullptr;   // [nrb] phases of each row block
     long long n_rows = 0;
+    // table statistics (host): events incl. padding, event entries on a kept
+    // pair, a values staged per grid piece and vector group (all blocks)
+    long long n_ev = 0, n_kept = 0, n_staged = 0;
     const int *grp = nullptr;
     const int *gpart = nullptr;
     const int *gslot = nullptr;

@@ -79,6 +79,7 @@ def load():
                                C.POINTER(DavidsonStats)]),
         "bse_debug_to_grid": (i32, [vp, i32, vp, vp, i32]),
         "bse_debug_gemm": (i32, [vp, i32, i32, i32, i32, dbl, vp, vp, dbl, vp, i32]),
+        "bse_debug_k1d_tables": (i32, [vp, i32, vp]),
         "bse_mlp_create": (i32, [C.POINTER(vp), i32, i32, i32, vp, vp]),
         "bse_mlp_destroy": (i32, [vp]),
         "bse_mlp_num_params": (C.c_longlong, [vp]),
@@ -119,7 +120,7 @@ def exported_symbols():
     return ["bse_create", "bse_destroy", "bse_set_terms", "bse_set_spin", "bse_pair_measure", "bse_build_pairs",
             "bse_threshold_for_fraction", "bse_get_pairs", "bse_screen_pairs", "bse_copy_tau",
             "bse_apply_liouville", "bse_apply_chunk", "bse_set_graph", "bse_davidson", "bse_status_str",
-            "bse_last_error", "bse_debug_to_grid", "bse_debug_gemm", "bse_profile_apply",
+            "bse_last_error", "bse_debug_to_grid", "bse_debug_gemm", "bse_debug_k1d_tables", "bse_profile_apply",
             "bse_mlp_create", "bse_mlp_destroy", "bse_mlp_num_params", "bse_mlp_get_weights",
             "bse_mlp_set_weights", "bse_mlp_forward", "bse_mlp_forward_noalloc", "bse_mlp_gradients", "bse_mlp_train",
             "bse_set_learned", "bse_learned_centers", "bse_davidson_record",
@@ -183,6 +184,14 @@ class BseContext:
 
     def set_terms(self, k1e=2.0, k1d=1.0, scissor=0.0):
         _check(load().bse_set_terms(self.h, k1e, k1d, scissor))
+
+    def k1d_tables(self, set_=0):
+        """Statistics of the resident K1d tables (bse_debug_k1d_tables)."""
+        st = np.zeros(8, dtype=np.int64)
+        _check(load().bse_debug_k1d_tables(self.h, int(set_), st.ctypes.data))
+        keys = ("row_blocks", "phases", "cap", "events", "kept_entries", "staged", "pairs",
+                "n_occ")
+        return dict(zip(keys, map(int, st)))
 
     def set_spin(self, n_up):
         """Slots [0, n_up) spin up, the rest spin down (n_up = n_occ: one channel)."""
