@@ -173,3 +173,46 @@ def eh_hamiltonian_spin(L, n, miller, V, phi, lam, n_up, n_down, *, k1d=1.0):
                     r0, c0 = off[s] + v * ne, off[s] + w * ne
                     Heh[r0:r0 + ne, c0:c0 + ne] -= k1d * M
     return 0.5 * (Heh + Heh.T), eps, X, dims
+
+
+def eh_coupling(L, n, miller, V, phi, lam, n_occ, *, k1e=2.0, k1d=1.0):
+    """Coupling block of the full (non-TDA) e-h BSE over all empty states,
+    in the (v, c) row-major basis of eh_hamiltonian:
+
+      B^eh_{(v,c),(v',c')} = k1e int int rho_cv v_c rho_c'v'
+                             - k1d int int (psi_v psi_c') W (psi_v' psi_c)
+
+    (the exchange-like part equals the one of the TDA block for real
+    orbitals; the direct part pairs occupied v with empty c' and v' with c).
+    Returns (B, eps, X) with the eigen-decomposition of the discretised H."""
+    H, E = dense_hamiltonian(L, n, miller, V)
+    eps, X = np.linalg.eigh(H)
+    u = X.T @ E
+    nr = E.shape[1]
+    omega = L ** 3
+    uo, ue = u[:n_occ], u[n_occ:]
+    ne = ue.shape[0]
+    dim = n_occ * ne
+    B = np.zeros((dim, dim))
+    if k1e != 0.0:
+        rho_cv = (uo[:, None, :] * ue[None, :, :]).reshape(dim, n, n, n) / omega
+        Fc = np.fft.fftn(rho_cv, axes=(1, 2, 3)).reshape(dim, nr) / nr
+        b = 2.0 * np.pi / L
+        f1 = np.fft.fftfreq(n, d=1.0 / n)
+        G2 = ((b * f1[:, None, None]) ** 2 + (b * f1[None, :, None]) ** 2
+              + (b * f1[None, None, :]) ** 2).reshape(-1)
+        vg = np.zeros_like(G2)
+        vg[G2 > 0] = 4.0 * np.pi / G2[G2 > 0]
+        B += k1e * omega * ((np.conj(Fc) * vg[None, :]) @ Fc.T).real
+    if k1d != 0.0:
+        Wm = dense_w(L, n, miller, phi, lam)
+        for v in range(n_occ):
+            rho = (uo[v][None, :] * ue).reshape(ne, n, n, n) / omega      # psi_v psi_c'
+            Fr = np.fft.fftn(rho, axes=(1, 2, 3)).reshape(ne, nr) / nr
+            g = (np.fft.ifftn((Fr @ Wm.T).reshape(ne, n, n, n), axes=(1, 2, 3)) * nr).real
+            g = g.reshape(ne, nr)                                         # W[psi_v psi_c'](r)
+            # int psi_c psi_v' W[psi_v psi_c'] = (1/N_r) sum_r u_c u_v' g_c'
+            for vp in range(n_occ):
+                Mx = (ue * uo[vp][None, :]) @ g.T / nr                     # [c, c']
+                B[v * ne:(v + 1) * ne, vp * ne:(vp + 1) * ne] -= k1d * Mx
+    return 0.5 * (B + B.T), eps, X
