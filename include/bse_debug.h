@@ -23,7 +23,8 @@ bse_status bse_debug_to_grid(bse_ctx *ctx, int n_orb, const void *X, void *out, 
 
 /* C[M][N] = alpha * A[M][K] * op(B) + beta * C with op(B) = B^T (B is
  * [N][K], nt = 1) or B (B is [K][N], nt = 0), row-major, one batch.
- *   precision BSE_FP64 (double, vector FMA), BSE_FP32 (float, FP32 MFMA),
+ *   precision BSE_FP64 (double; FP64 MFMA when M and N exceed 32, vector
+ *             FMA otherwise), BSE_FP32 (float, FP32 MFMA),
  *             BSE_BF16X3 (float, split-BF16x3 MFMA): the GEMMs of the apply
  *             in each precision.  Synchronises. */
 bse_status bse_debug_gemm(bse_ctx *ctx, int nt, int M, int N, int K, double alpha, const void *A,

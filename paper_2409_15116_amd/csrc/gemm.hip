@@ -1,8 +1,9 @@
 // Dense GEMMs: C = alpha * A * op(B) + beta * C, row-major, strided batches.
 //   NN: B is [K][N];  NT: B is [N][K].
-// The vector-FMA kernel serves FP64 (and FP32 where asked for); the apply's
-// FP32 GEMMs run on the matrix cores (gemm_f32m, or split-BF16x3 gemm_bf16x3,
-// in mfma.hip).
+// FP64 products with both output sides above 32 run on the matrix cores
+// (gemm_f64m in mfma.hip); the vector-FMA kernel below serves the skinny FP64
+// ones and FP32 where asked for; the apply's FP32 GEMMs run on the matrix
+// cores (gemm_f32m, or split-BF16x3 gemm_bf16x3).
 #include "kernels.hpp"
 
 namespace bse {
@@ -210,6 +211,13 @@ void gemm(bool nt, int M, int N, int K, T alpha, const T *A, long long lda, long
           const T *B, long long ldb, long long sB, T beta, T *C, long long ldc, long long sC,
           int batch, Workspace &ws, hipStream_t st) {
     if (M <= 0 || N <= 0 || batch <= 0) return;
+    // FP64 products whose output fills 64 x 64 tiles run on the matrix cores;
+    // skinny ones (the Davidson basis products, 16..32 wide) keep the vector
+    // kernel with tiles sized to the operands
+    if constexpr (sizeof(T) == 8)
+        if (M > 32 && N > 32)
+            return gemm_f64m(nt, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch,
+                             ws, st);
 #define BSE_GEMM_TILE(BM_, BN_)                                                               \
     if (tile_for(M) == BM_ && tile_for(N) == BN_)                                            \
         return gemm_t<T, BM_, BN_>(nt, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, \

@@ -197,6 +197,10 @@ void gemm_bf16x3(bool nt, int M, int N, int K, float alpha, const float *A, long
 void gemm_bf16(bool ta, bool nt, int M, int N, int K, float alpha, const float *A, long long lda,
                const float *B, long long ldb, float beta, float *C, long long ldc, Workspace &ws,
                hipStream_t st);
+// FP64 on the matrix cores (v_mfma_f64_16x16x4f64), same arguments as gemm()
+void gemm_f64m(bool nt, int M, int N, int K, double alpha, const double *A, long long lda,
+               long long sA, const double *B, long long ldb, long long sB, double beta, double *C,
+               long long ldc, long long sC, int batch, Workspace &ws, hipStream_t st);
 // bytes of split-K partials the matrix-core GEMMs above take from their
 // workspace for an M x N x K product (0 when the inner dimension is not split)
 size_t gemm_mfma_ws_bytes(int M, int N, int K, int batch);

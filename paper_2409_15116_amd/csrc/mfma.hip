@@ -264,6 +264,119 @@ static void launch_bf16(dim3 grid, hipStream_t st, int M, int N, int K, float al
     BSE_LAUNCH_CHECK();
 }
 
+// FP64 on the matrix cores: v_mfma_f64_16x16x4f64, FP64 products and
+// accumulation (the plain path's large GEMMs: P_c, eps, the PDEP projection).
+// Lane layout (64 lanes, measured): A element of lane l is A[l % 16][l / 16],
+// B element is B[l / 16][l % 16] as in the FP32 16x16x4 form, but the
+// accumulator rows are interleaved: element i is D[4 i + l / 16][l % 16].
+// Same 64 x 64 tile, 4 waves of 32 x 32, K steps of 16 staged through LDS
+// with the next step prefetched into registers.
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
+template <bool NT>
+__global__ void __launch_bounds__(256) k_gemm_f64m(int M, int N, int K, double alpha,
+                                                   const double *__restrict__ A, long long lda,
+                                                   long long sA, const double *__restrict__ Bm,
+                                                   long long ldb, long long sB, double beta,
+                                                   double *__restrict__ C, long long ldc,
+                                                   long long sC, int kchunk, int nsplit) {
+    __shared__ double As[TB][TK + 1], Bs[TB][TK + 1];
+    const int bz = blockIdx.z;
+    const int batch = bz / nsplit;
+    const int split = bz - batch * nsplit;
+    A += batch * sA;
+    Bm += batch * sB;
+    C += nsplit > 1 ? ((size_t)batch * nsplit + split) * (size_t)M * N : (size_t)(batch * sC);
+    const int m0 = blockIdx.y * TB, n0 = blockIdx.x * TB;
+    const int kbeg = split * kchunk;
+    const int kend = min(K, kbeg + kchunk);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    f64x4_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = (f64x4_t){0.0, 0.0, 0.0, 0.0};
+    double ra[4], rb[4];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            const int idx = tid + l * 256;
+            const int gm = m0 + (idx >> 4), gk = k0 + (idx & 15);
+            ra[l] = (gm < M && gk < kend) ? A[(size_t)gm * lda + gk] : 0.0;
+        }
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            const int idx = tid + l * 256;
+            if (NT) {
+                const int gn = n0 + (idx >> 4), gk = k0 + (idx & 15);
+                rb[l] = (gn < N && gk < kend) ? Bm[(size_t)gn * ldb + gk] : 0.0;
+            } else {
+                const int gn = n0 + (idx & 63), gk = k0 + (idx >> 6);
+                rb[l] = (gn < N && gk < kend) ? Bm[(size_t)gk * ldb + gn] : 0.0;
+            }
+        }
+    };
+    if (kbeg < kend) fetch(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += TK) {
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            const int idx = tid + l * 256;
+            As[idx >> 4][idx & 15] = ra[l];
+            if (NT) Bs[idx >> 4][idx & 15] = rb[l];
+            else Bs[idx & 63][idx >> 6] = rb[l];
+        }
+        __syncthreads();
+        if (k0 + TK < kend) fetch(k0 + TK);
+        const int r16 = lane & 15, kq = lane >> 4;
+#pragma unroll
+        for (int sub = 0; sub < TK / 4; ++sub) {
+            double a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) a[i] = As[wm + i * 16 + r16][4 * sub + kq];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) b[j] = Bs[wn + j * 16 + r16][4 * sub + kq];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    const int c16 = lane & 15, r4 = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int gm = m0 + wm + i * 16 + 4 * e + r4;
+                const int gn = n0 + wn + j * 16 + c16;
+                if (gm < M && gn < N) {
+                    double *c = C + (size_t)gm * ldc + gn;
+                    const double v = acc[i][j][e];
+                    if (nsplit > 1) *c = v;
+                    else *c = beta == 0.0 ? alpha * v : alpha * v + beta * *c;
+                }
+            }
+}
+
+__global__ void k_splitk_reduce_d(const double *__restrict__ part, int nsplit, int M, int N,
+                                  double alpha, double beta, double *__restrict__ C,
+                                  long long ldc, long long sC, int nbatch) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long mn = (long long)M * N;
+    if (i >= mn * nbatch) return;
+    const int b = (int)(i / mn);
+    const long long j = i - b * mn;
+    const int m = (int)(j / N), n = (int)(j - (long long)m * N);
+    double s = 0;
+    for (int k = 0; k < nsplit; ++k) s += part[((size_t)b * nsplit + k) * mn + j];
+    double *c = C + b * sC + (size_t)m * ldc + n;
+    *c = beta == 0.0 ? alpha * s : alpha * s + beta * *c;
+}
+
 // K split of a matrix-core GEMM: skinny products with few output tiles
 // split their inner dimension so that enough workgroups run (partials are
 // summed by a second kernel in fixed order)
@@ -342,6 +455,38 @@ void gemm_bf16(bool ta, bool nt, int M, int N, int K, float alpha, const float *
                const float *B, long long ldb, float beta, float *C, long long ldc, Workspace &ws,
                hipStream_t st) {
     gemm_mfma_any(ta, nt, 0, M, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1, ws, st);
+}
+
+void gemm_f64m(bool nt, int M, int N, int K, double alpha, const double *A, long long lda,
+               long long sA, const double *B, long long ldb, long long sB, double beta, double *C,
+               long long ldc, long long sC, int batch, Workspace &ws, hipStream_t st) {
+    if (M <= 0 || N <= 0 || batch <= 0) return;
+    int kchunk;
+    const int nsplit = mfma_split(M, N, K, batch, &kchunk);
+    dim3 grid(div_up(N, TB), div_up(M, TB), batch * nsplit);
+    double *Cw = C;
+    double a = alpha, b = beta;
+    long long ldw = ldc, sw = sC;
+    if (nsplit > 1) {
+        Cw = (double *)ws.get((size_t)M * N * nsplit * batch * sizeof(double));
+        a = 1.0;
+        b = 0.0;
+        ldw = N;
+        sw = 0;
+    }
+    if (nt)
+        k_gemm_f64m<true><<<grid, 256, 0, st>>>(M, N, K, a, A, lda, sA, B, ldb, sB, b, Cw, ldw, sw,
+                                                kchunk, nsplit);
+    else
+        k_gemm_f64m<false><<<grid, 256, 0, st>>>(M, N, K, a, A, lda, sA, B, ldb, sB, b, Cw, ldw, sw,
+                                                 kchunk, nsplit);
+    BSE_LAUNCH_CHECK();
+    if (nsplit > 1) {
+        const long long tot = (long long)M * N * batch;
+        k_splitk_reduce_d<<<div_up(tot, 256), 256, 0, st>>>(Cw, nsplit, M, N, alpha, beta, C, ldc,
+                                                            sC, batch);
+        BSE_LAUNCH_CHECK();
+    }
 }
 
 void gemm_f32m(bool nt, int M, int N, int K, float alpha, const float *A, long long lda,
