@@ -209,6 +209,22 @@ bse_status bse_apply_liouville(bse_ctx *ctx, int n_vec, const void *A_in, void *
 bse_status bse_profile_apply(bse_ctx *ctx, int n_vec, const void *A_in, void *A_out,
                              int precision, int n_rep, double *ms);
 
+/* Coupling block of the full BSE beyond the Tamm-Dancoff approximation
+ * (Sec. 6 names the full BSE as the extension of the method): the full
+ * problem is [[A, B], [-B, -A]] (a, b) = omega (a, b) with A the operator of
+ * bse_apply_liouville and, for real orbitals,
+ *   (B b)_v = P_c[ k1e psi_v v_c[sum_v' psi_v' b_v']
+ *                  - k1d sum_{v' in N(v)} psi_v' W[psi_v b_v'] ]
+ * (the exchange-like part is K1e; the direct part screens, with the PDEP
+ * form of W of bse_screen_pairs, the product of an occupied orbital with its
+ * pair partner's trial orbital, over the kept pairs of K1d).
+ *   B_in, B_out  dev [n_vec][n_occ][n_pw] as for bse_apply_liouville
+ * B_out is P_c-projected.  Uses the apply's workspaces (chunked like the
+ * apply) plus about 1 GB of batch workspace; synchronises once per batch of
+ * products; not captured in graphs.  BSE_ERR_STATE before bse_screen_pairs. */
+bse_status bse_apply_coupling(bse_ctx *ctx, int n_vec, const void *B_in, void *B_out,
+                              int precision);
+
 /* Number of trial vectors the apply processes at once for a block of n_vec
  * in this precision (sizes the workspaces as bse_apply_liouville does; n_vec
  * when the whole block fits). */
@@ -251,6 +267,25 @@ typedef struct {
  * non-finite entry (NaN or Inf in X0 or in the operator's output). */
 bse_status bse_davidson(bse_ctx *ctx, const bse_davidson_opts *opts, const double *X0,
                         double *omega, double *X, bse_davidson_stats *stats);
+
+/* Lowest n_eig excitation energies of the full BSE (beyond the TDA) by a
+ * Davidson solve of its product form: with an orthonormal basis V of the P_c
+ * space and P = (A + B) V, M = (A - B) V, omega^2 are the eigenvalues of
+ * L^T (V^T P) L, L L^T = V^T M (Stratmann, Scuseria and Frisch 1998; valid
+ * when A - B and A + B are positive definite).  Residuals
+ * (A + B)(X + Y) - omega (X - Y) and (A - B)(X - Y) - omega (X + Y); both
+ * norms <= opts->tol for convergence; new directions are the two residuals
+ * preconditioned with the diagonal of the D term; restart from the Ritz
+ * vectors when the basis (opts->max_basis, default 8 block) is full.  FP64
+ * basis and subspace matrices, applies of A and B in opts->precision.
+ *   X0        dev [block][n_occ][n_pw] FP64 start block (seeded input)
+ *   omega     host [n_eig] out, ascending
+ *   XpY, XmY  dev [n_eig][n_occ][n_pw] FP64 out: X + Y and X - Y of each
+ *             excitation, normalised so that <X + Y, X - Y> = 1
+ * Synchronises.  BSE_ERR_NOCONV when max_iter is hit or A - B is not
+ * positive definite on the subspace; opts->precond must be 0. */
+bse_status bse_davidson_full(bse_ctx *ctx, const bse_davidson_opts *opts, const double *X0,
+                             double *omega, double *XpY, double *XmY, bse_davidson_stats *stats);
 
 /* ---------------------------------------------------------------- learned
  * Learned correction of the diagonal Davidson preconditioner.  Not in the

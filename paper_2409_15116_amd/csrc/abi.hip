@@ -239,6 +239,22 @@ bse_status bse_profile_apply(bse_ctx *c, int n_vec, const void *A_in, void *A_ou
     })
 }
 
+bse_status bse_apply_coupling(bse_ctx *c, int n_vec, const void *B_in, void *B_out,
+                              int precision) {
+    CHECK_CTX(c);
+    BSE_GUARD(bse::ctx_apply_coupling(c, n_vec, B_in, B_out, precision))
+}
+
+bse_status bse_davidson_full(bse_ctx *c, const bse_davidson_opts *opts, const double *X0,
+                             double *omega, double *XpY, double *XmY, bse_davidson_stats *stats) {
+    CHECK_CTX(c);
+    if (!opts || !X0 || !omega || !XpY || !XmY) {
+        set_error("bse_davidson_full: null argument");
+        return BSE_ERR_ARG;
+    }
+    BSE_GUARD(bse::ctx_davidson_full(c, opts, X0, omega, XpY, XmY, stats))
+}
+
 bse_status bse_apply_chunk(bse_ctx *c, int n_vec, int precision, int *chunk) {
     CHECK_CTX(c);
     if (!chunk || n_vec < 1 ||

@@ -176,6 +176,7 @@ void ctx_set_spin(bse_ctx *c, int n_up) {
                 "n_up must be in [1, n_occ = %d], got %d", c->n_occ, n_up);
     c->n_up = n_up >= c->n_occ ? 0 : n_up;
     c->pairs_h.clear();
+    c->cp_items_h.clear();
     c->n_pairs = 0;
     c->have_tau64 = c->have_tau32 = false;
     c->tau64.free();
@@ -1166,6 +1167,7 @@ void ctx_build_pairs(bse_ctx *c, int kind, double thr) {
             }
     c->pairs_h = pr;
     c->n_pairs = (long long)pr.size() / 2;
+    c->cp_items_h.clear();
     c->have_tau64 = c->have_tau32 = false;
     c->tau64.free();
     c->tau32.free();
@@ -1330,6 +1332,19 @@ void ctx_screen(bse_ctx *c, const double *phi, const double *lam, int n_pdep, in
     // tau carries one extra all-zero row (index P) for the K1d block tables;
     // zeroing the whole tiled array also clears the padding of the last tile
     const long long ne = tau_elems((long long)P + 1, (long long)nr);
+    // the PDEP basis stays with the context (the coupling block of the full
+    // BSE screens products of trial orbitals with it)
+    c->n_pdep = n_pdep;
+    c->phi64.alloc((size_t)n_pdep * npw1);
+    c->phif64.alloc((size_t)n_pdep * npw1);
+    c->phi32.alloc((size_t)n_pdep * npw1);
+    c->phif32.alloc((size_t)n_pdep * npw1);
+    BSE_HIP(hipMemcpyAsync(c->phi64.p, phi, (size_t)n_pdep * npw1 * 8, hipMemcpyDeviceToDevice,
+                           c->stream));
+    BSE_HIP(hipMemcpyAsync(c->phif64.p, phif.p, (size_t)n_pdep * npw1 * 8,
+                           hipMemcpyDeviceToDevice, c->stream));
+    convert<double, float>(phi, c->phi32.p, (long long)n_pdep * npw1, c->stream);
+    convert<double, float>(phif.p, c->phif32.p, (long long)n_pdep * npw1, c->stream);
     if (prec == BSE_FP64) {
         c->tau64.alloc(ne);
         c->tau32.alloc(ne);
@@ -1337,16 +1352,12 @@ void ctx_screen(bse_ctx *c, const double *phi, const double *lam, int n_pdep, in
         screen_impl<double>(c, phi, phif.p, n_pdep, false, c->tau64.p, c->tau32.p);
         c->have_tau64 = c->have_tau32 = true;
     } else {
-        Dev<float> p32, pf32;
-        p32.alloc((size_t)n_pdep * npw1);
-        pf32.alloc((size_t)n_pdep * npw1);
-        convert<double, float>(phi, p32.p, (long long)n_pdep * npw1, c->stream);
-        convert<double, float>(phif.p, pf32.p, (long long)n_pdep * npw1, c->stream);
         c->tau64.free();
         c->have_tau64 = false;
         c->tau32.alloc(ne);
         zero<float>(c->tau32.p, ne, c->stream);
-        screen_impl<float>(c, p32.p, pf32.p, n_pdep, prec == BSE_BF16X3, c->tau32.p, nullptr);
+        screen_impl<float>(c, c->phi32.p, c->phif32.p, n_pdep, prec == BSE_BF16X3, c->tau32.p,
+                           nullptr);
         c->have_tau32 = true;
     }
 }
@@ -1448,6 +1459,33 @@ static void apply_impl(bse_ctx *c, int nvec, const T *X, T *Y, bool bf, hipEvent
         }
     }
 }
+
+template <typename T>
+void apply_tda_block(bse_ctx *c, int nvec, const T *X, T *Y, bool bf) {
+    apply_impl<T>(c, nvec, X, Y, bf);
+}
+template void apply_tda_block<double>(bse_ctx *, int, const double *, double *, bool);
+template void apply_tda_block<float>(bse_ctx *, int, const float *, float *, bool);
+
+// apply workspaces of the precision sized for a block of nvec (or the
+// largest chunk that fits); returns the chunk
+template <typename T>
+int apply_ws_chunk(bse_ctx *c, int nvec) {
+    ApplyWs<T> &w = *reinterpret_cast<ApplyWs<T> *>(sizeof(T) == 8 ? (void *)&c->ws64
+                                                                    : (void *)&c->ws32);
+    return ensure_ws_chunk<T>(c, w, nvec);
+}
+template int apply_ws_chunk<double>(bse_ctx *, int);
+template int apply_ws_chunk<float>(bse_ctx *, int);
+
+// P_c on a block of nvec trial vectors in place (the apply's GEMMs)
+template <typename T>
+void project_block(bse_ctx *c, bool bf, int nvec, T *Y, T *S) {
+    const T *psi = sizeof(T) == 8 ? (const T *)c->psi64.p : (const T *)c->psi32.p;
+    project_c<T>(c, bf, nvec * c->n_occ, Y, S, psi, c->aws);
+}
+template void project_block<double>(bse_ctx *, bool, int, double *, double *);
+template void project_block<float>(bse_ctx *, bool, int, float *, float *);
 
 int ctx_chunk(bse_ctx *c, int n_vec, int prec) {
     if (prec == BSE_FP64) return ensure_ws_chunk<double>(c, c->ws64, n_vec);

@@ -135,6 +135,16 @@ struct bse_ctx {
     void *g_out = nullptr;
     // learned preconditioner
     bse::LearnedPre lp;
+    // PDEP basis kept by bse_screen_pairs for the coupling block of the full
+    // BSE (phi and (lambda / (1 - lambda)) phi, packed without G = 0)
+    int n_pdep = 0;
+    bse::Dev<double> phi64, phif64;
+    bse::Dev<float> phi32, phif32;
+    // coupling-block items (pair directions) sorted by target slot, and the
+    // batch workspace of the screened products
+    bse::Dev<int4> cp_items;
+    std::vector<int4> cp_items_h;
+    bse::Workspace cws;
 };
 
 // several contexts applied in one captured launch sequence
@@ -177,6 +187,15 @@ void ctx_profile_apply(bse_ctx *c, int n_vec, const void *in, void *out, int pre
                        double *ms);
 void ctx_project_c64(bse_ctx *c, int n_vec, double *Y);
 void ctx_k1d_tables(const bse_ctx *c, int set, long long *st);
+void ctx_apply_coupling(bse_ctx *c, int n_vec, const void *in, void *out, int prec);
+void ctx_davidson_full(bse_ctx *c, const bse_davidson_opts *o, const double *X0, double *omega,
+                       double *XpY, double *XmY, bse_davidson_stats *stats);
+template <typename T>
+void apply_tda_block(bse_ctx *c, int nvec, const T *X, T *Y, bool bf);
+template <typename T>
+int apply_ws_chunk(bse_ctx *c, int nvec);
+template <typename T>
+void project_block(bse_ctx *c, bool bf, int nvec, T *Y, T *S);
 void ctx_davidson(bse_ctx *c, const bse_davidson_opts *o, const double *X0, double *omega,
                   double *X, bse_davidson_stats *stats, RecordSpec *rec = nullptr);
 void batch_create(bse_batch *b, bse_ctx *const *ctxs, int n, hipStream_t stream);

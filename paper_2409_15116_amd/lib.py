@@ -74,6 +74,9 @@ def load():
         "bse_apply_liouville": (i32, [vp, i32, vp, vp, i32]),
         "bse_set_graph": (i32, [vp, i32]),
         "bse_apply_chunk": (i32, [vp, i32, i32, C.POINTER(i32)]),
+        "bse_apply_coupling": (i32, [vp, i32, vp, vp, i32]),
+        "bse_davidson_full": (i32, [vp, C.POINTER(DavidsonOpts), vp, vp, vp, vp,
+                                    C.POINTER(DavidsonStats)]),
         "bse_profile_apply": (i32, [vp, i32, vp, vp, i32, i32, vp]),
         "bse_davidson": (i32, [vp, C.POINTER(DavidsonOpts), vp, vp, vp,
                                C.POINTER(DavidsonStats)]),
@@ -119,7 +122,7 @@ def load():
 def exported_symbols():
     return ["bse_create", "bse_destroy", "bse_set_terms", "bse_set_spin", "bse_pair_measure", "bse_build_pairs",
             "bse_threshold_for_fraction", "bse_get_pairs", "bse_screen_pairs", "bse_copy_tau",
-            "bse_apply_liouville", "bse_apply_chunk", "bse_set_graph", "bse_davidson", "bse_status_str",
+            "bse_apply_liouville", "bse_apply_coupling", "bse_davidson_full", "bse_apply_chunk", "bse_set_graph", "bse_davidson", "bse_status_str",
             "bse_last_error", "bse_debug_to_grid", "bse_debug_gemm", "bse_debug_k1d_tables", "bse_profile_apply",
             "bse_mlp_create", "bse_mlp_destroy", "bse_mlp_num_params", "bse_mlp_get_weights",
             "bse_mlp_set_weights", "bse_mlp_forward", "bse_mlp_forward_noalloc", "bse_mlp_gradients", "bse_mlp_train",
@@ -289,6 +292,32 @@ class BseContext:
 
     def set_graph(self, enable=True):
         _check(load().bse_set_graph(self.h, 1 if enable else 0))
+
+    def apply_coupling(self, B_in, B_out, precision=FP64):
+        """Coupling block B of the full BSE on a block (bse_apply_coupling)."""
+        dt = self.torch.float64 if precision == FP64 else self.torch.float32
+        nv = B_in.shape[0]
+        shp = (nv, self.n_occ, self.npw)
+        _check(load().bse_apply_coupling(self.h, nv, _dptr(B_in, dt, shp), _dptr(B_out, dt, shp),
+                                         precision))
+        return B_out
+
+    def davidson_full(self, X0, n_eig, *, block=None, max_basis=0, max_iter=300,
+                      precision=FP64, tol=1e-6, delta=0.05, verbose=0):
+        """Lowest n_eig excitations of the full BSE: (omega, X+Y, X-Y, stats)."""
+        torch = self.torch
+        B = block or X0.shape[0]
+        o = DavidsonOpts(n_eig, B, max_basis, 0, max_iter, precision, tol, delta, 0, verbose)
+        om = np.zeros(n_eig)
+        XP = torch.empty((n_eig, self.n_occ, self.npw), dtype=torch.float64, device="cuda")
+        XM = torch.empty_like(XP)
+        st = DavidsonStats()
+        _check(load().bse_davidson_full(self.h, C.byref(o), _dptr(X0, torch.float64,
+                                                                  (B, self.n_occ, self.npw)),
+                                        om.ctypes.data, _dptr(XP, torch.float64),
+                                        _dptr(XM, torch.float64), C.byref(st)))
+        return om, XP, XM, {"iterations": st.iterations, "n_apply": st.n_apply,
+                            "seconds": st.seconds, "resid": np.array(st.resid[:n_eig])}
 
     def apply_chunk(self, n_vec, precision=FP64):
         """Trial vectors the apply processes at once for a block of n_vec."""

@@ -1,7 +1,8 @@
 """Write the stored oracle results used by the GPU parity tests.
 
 Calls only the oracle and the seeded input generator:
-    python tests/golden/make_goldens.py [c1] [c1_f40] [c2] [c4_03] [c4_07]
+    python tests/golden/make_goldens.py [c1] [c1_f40] [c2] [c4_03] [c4_07] [tiny_full]
+        [c1_full_f40]
 Output: tests/golden/<cell>_oracle.json with the lowest excitation energies
 (Ha) of the plain FP64 oracle Davidson, the pair threshold and count, and the
 oracle's iteration count and wall time.
@@ -40,6 +41,50 @@ def _cell(name):
     return make_cell(name)
 
 
+# full BSE beyond the TDA: (cell, kept fraction or None); the lowest
+# excitation energies from explicit A and B matrices of the oracle in the
+# basis of single transitions (slot v holding empty state c of the dense H)
+FULL_CASES = {"tiny_full": ("tiny", None), "c1_full_f40": ("c1", 0.4)}
+
+
+def run_full(case):
+    from oracle.eh import dense_hamiltonian
+    from oracle.full import CouplingOracle, full_bse_omega
+    name, frac = FULL_CASES[case]
+    cell = _cell(name)
+    b = Basis(cell.L, cell.n, cell.miller)
+    u = b.to_grid(cell.psi)
+    m = pair_measure(u, MEASURE_ABS_L1)
+    thr = threshold_for_fraction(m, frac) if frac is not None else -1.0
+    pairs = build_pairs(m, thr)
+    tau = screened_integrals(b, u, pairs, cell.phi, cell.lam)
+    A = LiouvilleOracle(b, cell.psi, cell.eps_mat, cell.V, pairs, tau)
+    Bop = CouplingOracle(A, cell.phi, cell.lam)
+    H, _ = dense_hamiltonian(cell.L, cell.n, cell.miller, cell.V)
+    _, X = np.linalg.eigh(H)
+    n, npw = cell.n_occ, cell.npw
+    Q = np.zeros((n * (npw - n), n, npw))
+    k = 0
+    for v in range(n):
+        for ci in range(n, npw):
+            Q[k, v] = X[:, ci]
+            k += 1
+    t0 = time.time()
+    mats = []
+    for op in (A.apply, Bop.apply):
+        LQ = np.concatenate([op(Q[i:i + 128]) for i in range(0, len(Q), 128)])
+        mats.append(np.einsum("ivg,jvg->ij", Q, LQ))
+    w = full_bse_omega(*mats)
+    wt = np.linalg.eigvalsh(0.5 * (mats[0] + mats[0].T))
+    out = {"cell": name, "fraction": frac, "threshold": thr, "n_pairs": len(pairs),
+           "omega_full_ha": list(map(float, w[:8])), "omega_tda_ha": list(map(float, wt[:8])),
+           "dim": int(len(Q)), "seconds": time.time() - t0, "cpu_count": os.cpu_count()}
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{case}_oracle.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(case, out)
+
+
 def run(case):
     name, frac, n_eig, B, seed = CASES[case]
     cell = _cell(name)
@@ -71,5 +116,5 @@ def run(case):
 
 
 if __name__ == "__main__":
-    for c in (sys.argv[1:] or list(CASES)):
-        run(c)
+    for c in (sys.argv[1:] or list(CASES) + list(FULL_CASES)):
+        (run_full if c in FULL_CASES else run)(c)
