@@ -48,7 +48,7 @@ typedef enum {
     BSE_ERR_ARG = 1,     /* invalid argument (sizes, null pointers, non-finite data) */
     BSE_ERR_HIP = 2,     /* a HIP runtime call or kernel launch failed */
     BSE_ERR_OOM = 3,     /* a workspace allocation failed */
-    BSE_ERR_NOCONV = 4,  /* bse_davidson hit max_iter before tol */
+    BSE_ERR_NOCONV = 4,  /* an iteration limit was hit before its tolerance */
     BSE_ERR_STATE = 5    /* call out of order (e.g. apply before screen_pairs) */
 } bse_status;
 
@@ -141,7 +141,9 @@ bse_status bse_spread_matrices(bse_ctx *ctx, double *A);
  * default start runs the same sweeps on a copy of A^(1) alone (Jacobi's
  * eigenvalue method) instead of the host eigensolver.
  * Synchronises the stream.  Errors: BSE_ERR_ARG (sizes, tol < 0, a
- * non-finite start), BSE_ERR_OOM. */
+ * non-finite start), BSE_ERR_OOM; BSE_ERR_NOCONV when max_sweeps sweeps ran
+ * (0 included) and the last one still rotated: A, Q, n_sweeps and offsum
+ * are then the state after those sweeps, usable as a start for more. */
 bse_status bse_jade(bse_ctx *ctx, int N, int n_mat, double *A, double *Q, int start_given,
                     double tol, int max_sweeps, int *n_sweeps, double *offsum);
 
@@ -261,9 +263,13 @@ typedef struct {
  *   X0     dev  [block][n_occ][n_pw] FP64 start block (seeded random input)
  *   omega  host [n_eig] FP64 out
  *   X      dev  [n_eig][n_occ][n_pw] FP64 out: orthonormal eigenvectors
- * Synchronises once per iteration.  BSE_ERR_NOCONV when max_iter is hit
- * (omega and X then hold the last Ritz pairs: a later call started from X
- * resumes the solve).  BSE_ERR_ARG when the subspace matrix gets a
+ * Synchronises once per iteration (one download: the new Rayleigh-Ritz
+ * columns, the orthonormalisation's kept flags and the previous Ritz block's
+ * residual norms), so convergence is seen one iteration late: the converged
+ * block is returned with its own iteration number, and n_apply includes the
+ * one block applied meanwhile.  BSE_ERR_NOCONV when max_iter is hit (omega
+ * and X then hold the last Ritz pairs: a later call started from X resumes
+ * the solve).  BSE_ERR_ARG when the subspace matrix gets a
  * non-finite entry (NaN or Inf in X0 or in the operator's output). */
 bse_status bse_davidson(bse_ctx *ctx, const bse_davidson_opts *opts, const double *X0,
                         double *omega, double *X, bse_davidson_stats *stats);
@@ -391,15 +397,17 @@ bse_status bse_lanczos_spectrum(const double *alpha, const double *beta, int n_s
  * The K1d kernel (Eq. k1d) is compiled in several shapes: rows per
  * workgroup, trial vectors per workgroup and tau columns in flight.  Shape 0
  * of each precision is the default.  The resident shapes hold every orbital
- * of a grid tile in one workgroup and apply only to cells of at most 64 or
- * 128 orbitals.  Not in the paper: a tuning aid. */
+ * of a grid tile in one workgroup (more orbitals run in row blocks of 128);
+ * the two-point FP64 shapes give each lane two adjacent grid points and need
+ * an even number of grid points.  Not in the paper: a tuning aid. */
 /* Number of compiled K1d shapes for a precision (0 for an unknown one). */
 int bse_k1d_num_shapes(int precision);
 /* Parameters of K1d shape `shape` (BSE_ERR_ARG when out of range): info host
  * [6] gets the rows one workgroup holds (the cell's orbital limit for a
  * resident shape), the trial vectors per workgroup, the tau columns in
- * flight per wave, the waves per workgroup, 1 for a resident shape (0 for a
- * row-block one) and the grid points per workgroup.  Needs no GPU. */
+ * flight per wave, the waves per workgroup, the kernel kind (0 row-block,
+ * 1 resident, 2 resident with two grid points per lane) and the grid points
+ * per workgroup.  Needs no GPU. */
 bse_status bse_k1d_shape_info(int precision, int shape, int *info);
 /* Autotuner: times the K1d stage of every shape on this cell with a block of
  * n_vec vectors (an internal, deterministic input; n_rep timed applies per

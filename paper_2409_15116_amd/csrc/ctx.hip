@@ -1565,6 +1565,8 @@ void ctx_profile_apply(bse_ctx *c, int n_vec, const void *in, void *out, int pre
 static bool k1d_shape_fits(const bse_ctx *c, bool dbl, int v) {
     const K1dShape s = k1d_shape(dbl, v);
     // more orbitals: row blocks of K1D_RES_MAXROWS need shapes of that many rows
+    // the two-point kernel needs an even number of grid points
+    if (s.res == 2 && c->nr % 2) return false;
     return !s.res || c->n_occ <= s.bi || s.bi == K1D_RES_MAXROWS;
 }
 
@@ -1651,7 +1653,6 @@ void ctx_project_c64(bse_ctx *c, int n_vec, double *Y) {
     Dev<double> &S = c->pc64;  // grows only: no device-wide free per call
     S.alloc((size_t)n_vec * c->n_occ * c->n_occ);
     project_c<double>(c, false, n_vec * c->n_occ, Y, S.p, c->psi64.p, c->gws);
-    BSE_HIP(hipStreamSynchronize(c->stream));
 }
 
 void ctx_apply(bse_ctx *c, int n_vec, const void *in, void *out, int prec) {

@@ -2,8 +2,8 @@
 // (Sec. 3: the operator is applied to a block of trial vectors per iteration;
 // Davidson 1975).  The basis, Rayleigh-Ritz matrix, residual norms and the
 // orthogonalisation are FP64 on the device; the apply runs in the requested
-// precision.  The only host work is the small symmetric eigenproblem and the
-// small Cholesky factor, once per iteration.
+// precision.  The only host work is the small symmetric eigenproblem, once
+// per iteration, after the iteration's one wait for the device.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -120,118 +120,150 @@ void sym_eig(int n, std::vector<double> A, std::vector<double> &w, std::vector<d
     Z.swap(Zs);
 }
 
+// page-locked host staging for the iteration's small uploads and its one
+// download: a copy from here is truly asynchronous, so the host only waits
+// once per iteration
+struct Pinned {
+    double *p = nullptr;
+    size_t n = 0, off = 0;
+    Pinned() = default;
+    Pinned(const Pinned &) = delete;
+    Pinned &operator=(const Pinned &) = delete;
+    ~Pinned() {
+        if (p) (void)hipHostFree(p);
+    }
+    void alloc(size_t count) {
+        if (count <= n && p) return;
+        if (p) BSE_HIP(hipHostFree(p));
+        p = nullptr;
+        n = 0;
+        BSE_HIP(hipHostMalloc((void **)&p, count * sizeof(double), hipHostMallocDefault));
+        n = count;
+    }
+};
+
 struct DavState {
     bse_ctx *c;
     long long n;  // n_occ * npw
-    Dev<double> V, W, X, LX, R, Tn, tmp, small, sm, part, norms, theta;
+    Dev<double> V, W, X, R, Tn, tmp, cbuf, gq, minv, keep, coef, sm, part, norms, theta;
     Dev<double> in64, out64;
     Dev<float> in32, out32;
+    Pinned up, down;
     int B = 0;  // rows of the fixed apply buffers
 };
 
-// stream-ordered upload of a small host matrix; returns once the host copy is consumed
-static void upload(bse_ctx *c, Dev<double> &d, const std::vector<double> &h) {
+// stream-ordered upload of a small host matrix through the pinned arena (no
+// wait: the arena is reset after the iteration's synchronisation, and a full
+// arena waits for the stream first)
+static void upload(DavState &s, Dev<double> &d, const std::vector<double> &h) {
     d.alloc(std::max<size_t>(h.size(), 1));
-    BSE_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * 8, hipMemcpyHostToDevice, c->stream));
-    BSE_HIP(hipStreamSynchronize(c->stream));
+    if (s.up.off + h.size() > s.up.n) {
+        BSE_HIP(hipStreamSynchronize(s.c->stream));
+        s.up.off = 0;
+    }
+    BSE_REQUIRE(h.size() <= s.up.n, BSE_ERR_STATE, "upload of %zu values exceeds the arena",
+                h.size());
+    double *dst = s.up.p + s.up.off;
+    std::memcpy(dst, h.data(), h.size() * 8);
+    s.up.off += h.size();
+    BSE_HIP(hipMemcpyAsync(d.p, dst, h.size() * 8, hipMemcpyHostToDevice, s.c->stream));
 }
 
-// rows of Y (k x n) -> C (m x n) = M (m x k) Y, M a small host matrix
-static void small_times(DavState &s, int m, int k, const std::vector<double> &M, const double *Y,
-                        double *C) {
-    upload(s.c, s.small, M);
-    gemm<double>(false, m, (int)s.n, k, 1.0, s.small.p, k, 0, Y, s.n, 0, 0.0, C, s.n, 0, 1,
-                 s.c->gws, s.c->stream);
-}
-
-// G = A B^T (m x k) to host
-static std::vector<double> gram(DavState &s, int m, const double *A, int k, const double *B) {
-    Dev<double> &g = s.small;
-    g.alloc((size_t)std::max(1, m * k));
-    gemm<double>(true, m, k, (int)s.n, 1.0, A, s.n, 0, B, s.n, 0, 0.0, g.p, k, 0, 1, s.c->gws,
+// rows of Y (k x n) -> C (m x n) = M (m x k) Y, M a small device matrix
+static void times_dev(DavState &s, int m, int k, const double *M, const double *Y, double *C) {
+    gemm<double>(false, m, (int)s.n, k, 1.0, M, k, 0, Y, s.n, 0, 0.0, C, s.n, 0, 1, s.c->gws,
                  s.c->stream);
-    std::vector<double> h((size_t)m * k);
-    BSE_HIP(hipMemcpyAsync(h.data(), g.p, h.size() * 8, hipMemcpyDeviceToHost, s.c->stream));
-    BSE_HIP(hipStreamSynchronize(s.c->stream));
-    return h;
 }
 
-// Tn (k rows) -= (Tn V^T) V over the nb basis rows
-static void orth_against(DavState &s, int nb, int k) {
+// Z (k rows) -= (Z V^T) V over the nb basis rows
+static void orth_against(DavState &s, int nb, int k, double *Z) {
     if (nb == 0 || k == 0) return;
-    Dev<double> &sm = s.sm;  // grows only: no device-wide free per iteration
-    sm.alloc((size_t)k * nb);
-    gemm<double>(true, k, nb, (int)s.n, 1.0, s.Tn.p, s.n, 0, s.V.p, s.n, 0, 0.0, sm.p, nb, 0, 1,
+    Dev<double> &sm = s.sm;
+    gemm<double>(true, k, nb, (int)s.n, 1.0, Z, s.n, 0, s.V.p, s.n, 0, 0.0, sm.p, nb, 0, 1,
                  s.c->gws, s.c->stream);
-    gemm<double>(false, k, (int)s.n, nb, -1.0, sm.p, nb, 0, s.V.p, s.n, 0, 1.0, s.Tn.p, s.n, 0, 1,
+    gemm<double>(false, k, (int)s.n, nb, -1.0, sm.p, nb, 0, s.V.p, s.n, 0, 1.0, Z, s.n, 0, 1,
                  s.c->gws, s.c->stream);
-    BSE_HIP(hipStreamSynchronize(s.c->stream));
 }
 
-// Orthonormalise the k rows of Tn: Cholesky-QR of the Gram matrix; when it
-// is numerically singular, an eigen-decomposition drops the collapsed
-// directions.  Returns the number of rows kept (packed to the front).
-static int orthonormalize(DavState &s, int k, double drop2) {
-    if (k == 0) return 0;
-    std::vector<double> G = gram(s, k, s.Tn.p, k, s.Tn.p);
+// Cholesky factor of the k x k Gram matrix G (k <= 64) and the inverse of its
+// kept part, in one workgroup: column j is dropped (its row of Minv and its
+// column of the factor zero, keep[j] = 0) when its pivot is not above
+// drop2 * max_i G_ii, so that the rows Minv Y are orthonormal and the dropped
+// ones zero.  Left-looking: column j of the factor from the finished columns.
+__global__ void __launch_bounds__(64) k_chol_inv(const double *__restrict__ G, int k, double drop2,
+                                                 double *__restrict__ Minv,
+                                                 double *__restrict__ keep) {
+    __shared__ double L[64][65];
+    __shared__ double Mi[64][65];
+    __shared__ double piv[64];
+    __shared__ int kp[64];
+    const int t = threadIdx.x;
+    for (int i = 0; i < k; ++i)
+        if (t < k) L[i][t] = G[(size_t)i * k + t];
+    __syncthreads();
     double gmax = 0;
-    for (int i = 0; i < k; ++i) gmax = std::max(gmax, G[(size_t)i * k + i]);
-    // Cholesky G = L L^T
-    std::vector<double> Lm((size_t)k * k, 0.0);
-    bool ok = gmax > 0;
-    for (int j = 0; j < k && ok; ++j) {
-        double d = G[(size_t)j * k + j];
-        for (int p = 0; p < j; ++p) d -= Lm[(size_t)j * k + p] * Lm[(size_t)j * k + p];
-        if (!(d > drop2 * gmax)) {
-            ok = false;
-            break;
+    for (int i = 0; i < k; ++i) gmax = fmax(gmax, L[i][i]);
+    for (int j = 0; j < k; ++j) {
+        if (t == 0) {
+            double d = L[j][j];
+            for (int p = 0; p < j; ++p) d -= L[j][p] * L[j][p];
+            const bool ok = gmax > 0 && d > drop2 * gmax;
+            kp[j] = ok;
+            piv[j] = ok ? sqrt(d) : 0.0;
         }
-        const double ljj = std::sqrt(d);
-        Lm[(size_t)j * k + j] = ljj;
-        for (int i = j + 1; i < k; ++i) {
-            double v = G[(size_t)i * k + j];
-            for (int p = 0; p < j; ++p) v -= Lm[(size_t)i * k + p] * Lm[(size_t)j * k + p];
-            Lm[(size_t)i * k + j] = v / ljj;
+        __syncthreads();
+        if (t > j && t < k) {
+            double v = L[t][j];
+            for (int p = 0; p < j; ++p) v -= L[t][p] * L[j][p];
+            L[t][j] = kp[j] ? v / piv[j] : 0.0;
         }
+        if (t == 0) L[j][j] = piv[j];
+        __syncthreads();
     }
-    std::vector<double> Minv;
-    int kk = k;
-    if (ok) {
-        // L^{-1} by forward substitution
-        Minv.assign((size_t)k * k, 0.0);
-        for (int col = 0; col < k; ++col) {
-            for (int i = 0; i < k; ++i) {
-                double v = (i == col) ? 1.0 : 0.0;
-                for (int p = 0; p < i; ++p) v -= Lm[(size_t)i * k + p] * Minv[(size_t)p * k + col];
-                Minv[(size_t)i * k + col] = v / Lm[(size_t)i * k + i];
+    // column t of Minv by forward substitution over the kept rows
+    if (t < k) {
+        for (int i = 0; i < k; ++i) {
+            double v = 0;
+            if (kp[i]) {
+                v = i == t ? 1.0 : 0.0;
+                for (int p = 0; p < i; ++p) v -= L[i][p] * Mi[p][t];
+                v /= piv[i];
             }
+            Mi[i][t] = v;
         }
-    } else {
-        std::vector<double> w, Z;
-        sym_eig(k, G, w, Z);
-        std::vector<int> keep;
-        for (int i = k - 1; i >= 0; --i)
-            if (w[i] > drop2 * gmax) keep.push_back(i);
-        kk = (int)keep.size();
-        Minv.assign((size_t)std::max(1, kk) * k, 0.0);
-        for (int r = 0; r < kk; ++r) {
-            const int i = keep[r];
-            const double sc = 1.0 / std::sqrt(w[i]);
-            for (int j = 0; j < k; ++j) Minv[(size_t)r * k + j] = Z[(size_t)j * k + i] * sc;
-        }
-        if (kk == 0) return 0;
     }
-    small_times(s, kk, k, Minv, s.Tn.p, s.tmp.p);
-    BSE_HIP(hipMemcpyAsync(s.Tn.p, s.tmp.p, (size_t)kk * s.n * 8, hipMemcpyDeviceToDevice,
-                           s.c->stream));
-    BSE_HIP(hipStreamSynchronize(s.c->stream));
-    return kk;
+    __syncthreads();
+    for (int i = 0; i < k; ++i)
+        if (t < k) Minv[(size_t)i * k + t] = Mi[i][t];
+    if (t < k) keep[t] = kp[t] ? 1.0 : 0.0;
+}
+
+// Orthonormalise the k rows Z on the device into out (Cholesky-QR: the Gram
+// matrix, its factor, the triangular solve as a small product); rows that
+// collapse become zero and are marked 0 in s.keep.  out must not overlap Z.
+static void chol_qr(DavState &s, int k, double drop2, const double *Z, double *out) {
+    if (k == 0) return;
+    BSE_REQUIRE(k <= 64, BSE_ERR_ARG, "at most 64 rows per orthonormalisation");
+    gemm<double>(true, k, k, (int)s.n, 1.0, Z, s.n, 0, Z, s.n, 0, 0.0, s.gq.p, k, 0, 1,
+                 s.c->gws, s.c->stream);
+    k_chol_inv<<<1, 64, 0, s.c->stream>>>(s.gq.p, k, drop2, s.minv.p, s.keep.p);
+    BSE_LAUNCH_CHECK();
+    times_dev(s, k, k, s.minv.p, Z, out);
 }
 
 // One Davidson solve as a resumable state machine: begin() leaves a block of
 // basis rows waiting to be applied; after the caller has applied it (alone,
 // or together with other cells' blocks in one launch sequence), advance()
 // runs the rest of the iteration and leaves the next block, or sets done.
+//
+// The host waits for the device once per iteration, for one download: the
+// new columns of the Rayleigh-Ritz matrix, which of the new basis rows the
+// orthonormalisation kept, and the residual norms of the previous
+// iteration's Ritz vectors.  Everything else (Ritz vectors, residuals,
+// preconditioner, projections, Gram-Schmidt, Cholesky-QR) is queued behind
+// it without waiting, so the convergence of a Ritz block is seen one
+// iteration after it is formed: the solve then returns that block (still in
+// X) and its iteration number; the block applied meanwhile is discarded.
 struct DavRun {
     bse_ctx *c = nullptr;
     bse_davidson_opts o{};
@@ -241,8 +273,9 @@ struct DavRun {
     double delta = 0.05;
     const double drop2 = 1e-20;
     int n_apply = 0, used = 0, rejected = 0;
-    int nb = 0, it = 0, kr = 0;
-    std::vector<double> theta, Y, rn;
+    int nb = 0, it = 0, kr = 0, it_x = 0;
+    std::vector<double> theta, Y, rn, theta_x;
+    std::vector<char> act;  // basis rows the orthonormalisation kept
     bool learned_on = false, learned_last = false;
     double res_prev = INFINITY;
     bse_status result = BSE_ERR_NOCONV;
@@ -290,13 +323,20 @@ void DavRun::begin(bse_ctx *ctx, const bse_davidson_opts *opts, const double *X0
     s.V.alloc((size_t)maxb * n);
     s.W.alloc((size_t)maxb * n);
     s.X.alloc((size_t)B * n);
-    s.LX.alloc((size_t)B * n);
     s.R.alloc((size_t)B * n);
     s.Tn.alloc((size_t)B * n);
     s.tmp.alloc((size_t)maxb * n);
+    s.cbuf.alloc((size_t)maxb * B);
+    s.gq.alloc((size_t)B * B);
+    s.minv.alloc((size_t)B * B);
+    s.keep.alloc(B);
+    s.coef.alloc((size_t)maxb * maxb);
+    s.sm.alloc((size_t)B * maxb);
     s.part.alloc((size_t)B * 256);
     s.norms.alloc(B);
-    s.theta.alloc(maxb);
+    s.theta.alloc(B);
+    s.up.alloc((size_t)4 * maxb * maxb + 4 * B);
+    s.down.alloc((size_t)maxb * B + 2 * B);
     if (prec == BSE_FP64) {
         s.in64.alloc((size_t)B * n);
         s.out64.alloc((size_t)B * n);
@@ -306,17 +346,21 @@ void DavRun::begin(bse_ctx *ctx, const bse_davidson_opts *opts, const double *X0
     }
     s.B = B;
     rn.assign(B, 0.0);
+    act.assign(maxb, 0);
     Tm.assign((size_t)maxb * maxb, 0.0);
     learned_on = o.precond == 1 && c->lp.net != nullptr;
-    // start block
+    // start block: P_c, then twice Cholesky-QR; one wait to see what is kept
     BSE_HIP(hipMemcpyAsync(s.Tn.p, X0, (size_t)B * n * 8, hipMemcpyDeviceToDevice, c->stream));
     ctx_project_c64(c, B, s.Tn.p);
-    int k = orthonormalize(s, B, drop2);
-    k = orthonormalize(s, k, drop2);
+    chol_qr(s, B, drop2, s.Tn.p, s.tmp.p);
+    chol_qr(s, B, drop2, s.tmp.p, s.V.p);
+    BSE_HIP(hipMemcpyAsync(s.down.p, s.keep.p, B * 8, hipMemcpyDeviceToHost, c->stream));
+    BSE_HIP(hipStreamSynchronize(c->stream));
+    int k = 0;
+    for (int i = 0; i < B; ++i) k += s.down.p[i] > 0.5;
     BSE_REQUIRE(k > 0, BSE_ERR_ARG, "start block has no component in the P_c space");
-    BSE_HIP(hipMemcpyAsync(s.V.p, s.Tn.p, (size_t)k * n * 8, hipMemcpyDeviceToDevice, c->stream));
     nb = 0;
-    pa_k = k;
+    pa_k = B;
 }
 
 // V[nb, nb + pa_k) -> the fixed input buffer (zero rows up to B)
@@ -344,71 +388,95 @@ void DavRun::stage_out() {
 
 void DavRun::advance() {
     const size_t n = s.n;
-    const int nb_old = nb, kn = pa_k;
+    const int nb_old = nb, kn = pa_k, kr_prev = kr;
     n_apply += pa_k;
     nb += pa_k;
     pa_k = 0;
     ++it;
+    // the one wait of the iteration: new columns of T (V_i . W_j for every
+    // basis row i and each new row j), the kept flags of the new rows, and
+    // the squared residual norms of the previous Ritz block
+    gemm<double>(true, nb, kn, (int)n, 1.0, s.V.p, n, 0, s.W.p + (size_t)nb_old * n, n, 0, 0.0,
+                 s.cbuf.p, kn, 0, 1, c->gws, c->stream);
+    double *hC = s.down.p, *hK = hC + (size_t)nb * kn, *hN = hK + kn;
+    BSE_HIP(hipMemcpyAsync(hC, s.cbuf.p, (size_t)nb * kn * 8, hipMemcpyDeviceToHost, c->stream));
+    BSE_HIP(hipMemcpyAsync(hK, s.keep.p, (size_t)kn * 8, hipMemcpyDeviceToHost, c->stream));
+    if (kr_prev > 0)
+        BSE_HIP(hipMemcpyAsync(hN, s.norms.p, (size_t)kr_prev * 8, hipMemcpyDeviceToHost,
+                               c->stream));
+    BSE_HIP(hipStreamSynchronize(c->stream));
+    s.up.off = 0;
+    // the previous Ritz block: converged, or out of iterations
+    if (kr_prev > 0) {
+        for (int i = 0; i < kr_prev; ++i) rn[i] = std::sqrt(std::max(hN[i], 0.0));
+        bool conv = kr_prev >= ne;
+        for (int i = 0; i < ne && conv; ++i) conv = rn[i] <= o.tol;
+        if (o.verbose)
+            fprintf(stderr, "[bse_davidson] it %d nb %d theta0 %.10f res0 %.3e res_max %.3e\n",
+                    it_x, nb_old, theta_x[0], rn[0],
+                    *std::max_element(rn.begin(), rn.begin() + std::min(ne, kr_prev)));
+        if (conv) {
+            result = BSE_OK;
+            done = true;
+            return;
+        }
+        // learned correction: the diagonal preconditioner takes over for good
+        // once a corrected step fails to lower the largest wanted residual
+        const double res_max = *std::max_element(rn.begin(), rn.begin() + std::min(ne, kr_prev));
+        if (learned_last && !(res_max < res_prev)) learned_on = false;
+        res_prev = res_max;
+    }
     if (it > o.max_iter) {
         done = true;
         return;
     }
-    // new columns of T: V_i . W_j for every basis row i and each new row j
-    // (T is symmetric up to the apply's rounding; the new diagonal block is
-    // symmetrised, the rest mirrored)
-    {
-        const std::vector<double> Cn = gram(s, nb, s.V.p, kn, s.W.p + (size_t)nb_old * n);
-        for (const double x : Cn)
-            BSE_REQUIRE(std::isfinite(x), BSE_ERR_ARG,
-                        "Davidson: non-finite entry in the subspace matrix (NaN or Inf in the "
-                        "start block or in the operator's output)");
-        for (int i = 0; i < nb_old; ++i)
-            for (int j = 0; j < kn; ++j)
-                Tm[(size_t)i * maxb + nb_old + j] = Tm[(size_t)(nb_old + j) * maxb + i] =
-                    Cn[(size_t)i * kn + j];
-        for (int a = 0; a < kn; ++a)
-            for (int j = 0; j < kn; ++j)
-                Tm[(size_t)(nb_old + a) * maxb + nb_old + j] =
-                    0.5 * (Cn[(size_t)(nb_old + a) * kn + j] + Cn[(size_t)(nb_old + j) * kn + a]);
-    }
-    std::vector<double> T((size_t)nb * nb);
+    for (size_t i = 0; i < (size_t)nb * kn; ++i)
+        BSE_REQUIRE(std::isfinite(hC[i]), BSE_ERR_ARG,
+                    "Davidson: non-finite entry in the subspace matrix (NaN or Inf in the start "
+                    "block or in the operator's output)");
+    for (int j = 0; j < kn; ++j) act[nb_old + j] = hK[j] > 0.5;
+    // T is symmetric up to the apply's rounding: the new diagonal block is
+    // symmetrised, the rest mirrored
+    for (int i = 0; i < nb_old; ++i)
+        for (int j = 0; j < kn; ++j)
+            Tm[(size_t)i * maxb + nb_old + j] = Tm[(size_t)(nb_old + j) * maxb + i] =
+                hC[(size_t)i * kn + j];
+    for (int a = 0; a < kn; ++a)
+        for (int j = 0; j < kn; ++j)
+            Tm[(size_t)(nb_old + a) * maxb + nb_old + j] =
+                0.5 * (hC[(size_t)(nb_old + a) * kn + j] + hC[(size_t)(nb_old + j) * kn + a]);
+    // Rayleigh-Ritz over the kept rows
+    std::vector<int> idx;
     for (int i = 0; i < nb; ++i)
-        for (int j = 0; j < nb; ++j) T[(size_t)i * nb + j] = Tm[(size_t)i * maxb + j];
-    sym_eig(nb, T, theta, Y);
-    kr = std::min(B, nb);
-    std::vector<double> Yk((size_t)kr * nb);
-    for (int r = 0; r < kr; ++r)
-        for (int j = 0; j < nb; ++j) Yk[(size_t)r * nb + j] = Y[(size_t)j * nb + r];
-    small_times(s, kr, nb, Yk, s.V.p, s.X.p);
-    small_times(s, kr, nb, Yk, s.W.p, s.LX.p);
-    std::vector<double> th(theta.begin(), theta.begin() + kr);
-    upload(c, s.theta, th);
-    residual(s.LX.p, s.X.p, s.theta.p, n, kr, s.R.p, c->stream);
+        if (act[i]) idx.push_back(i);
+    const int na = (int)idx.size();
+    BSE_REQUIRE(na > 0, BSE_ERR_NOCONV, "Davidson: no new directions");
+    std::vector<double> T((size_t)na * na);
+    for (int i = 0; i < na; ++i)
+        for (int j = 0; j < na; ++j) T[(size_t)i * na + j] = Tm[(size_t)idx[i] * maxb + idx[j]];
+    sym_eig(na, T, theta, Y);
+    kr = std::min(B, na);
+    // Ritz coefficients over all nb rows (zero on dropped rows)
+    auto coeffs = [&](int m) {
+        std::vector<double> M((size_t)m * nb, 0.0);
+        for (int r = 0; r < m; ++r)
+            for (int j = 0; j < na; ++j) M[(size_t)r * nb + idx[j]] = Y[(size_t)j * na + r];
+        return M;
+    };
+    upload(s, s.coef, coeffs(kr));
+    times_dev(s, kr, nb, s.coef.p, s.V.p, s.X.p);
+    times_dev(s, kr, nb, s.coef.p, s.W.p, s.R.p);  // L X
+    theta_x.assign(theta.begin(), theta.begin() + kr);
+    it_x = it;
+    upload(s, s.theta, theta_x);
+    // residuals R = L X - theta X (in place) and the preconditioned ones in
+    // one pass, then their norms
+    resid_precond(s.R.p, s.X.p, s.theta.p, c->kin.p, c->epsd.p, c->vbar, delta, c->n_occ,
+                  c->npw, kr, s.Tn.p, c->stream);
     row_norm2(s.R.p, n, kr, s.part.p, s.norms.p, c->stream);
-    BSE_HIP(hipMemcpyAsync(rn.data(), s.norms.p, kr * 8, hipMemcpyDeviceToHost, c->stream));
-    BSE_HIP(hipStreamSynchronize(c->stream));
-    bool conv = true;
-    for (int i = 0; i < kr; ++i) rn[i] = std::sqrt(rn[i]);
-    for (int i = 0; i < ne; ++i) conv = conv && (i < kr) && rn[i] <= o.tol;
-    if (o.verbose)
-        fprintf(stderr, "[bse_davidson] it %d nb %d theta0 %.10f res0 %.3e res_max %.3e\n", it, nb,
-                theta[0], rn[0], *std::max_element(rn.begin(), rn.begin() + ne));
-    if (conv) {
-        result = BSE_OK;
-        done = true;
-        return;
-    }
-    // preconditioned residuals
-    precond_diag(s.R.p, s.theta.p, c->kin.p, c->epsd.p, c->vbar, delta, c->n_occ, c->npw, kr,
-                 s.Tn.p, c->stream);
     if (rec)
         learned_record(c, s.X.p, s.R.p, s.theta.p, s.Tn.p, std::min(ne, kr), kr, rec->Xref,
                        rec->n_ref, c->gws, rec->feat, rec->lab, rec->max_rows, &rec->n_rows);
-    // learned correction; the diagonal preconditioner takes over for good
-    // once a corrected step fails to lower the largest wanted residual
-    const double res_max = *std::max_element(rn.begin(), rn.begin() + ne);
-    if (learned_last && !(res_max < res_prev)) learned_on = false;
-    res_prev = res_max;
     learned_last = false;
     if (learned_on) {
         learned_correction(c, s.R.p, s.theta.p, kr, s.Tn.p, &used, &rejected);
@@ -416,28 +484,28 @@ void DavRun::advance() {
     }
     ctx_project_c64(c, kr, s.Tn.p);
     if (nb + kr > maxb) {
-        const int m = std::min(rst, nb);
-        std::vector<double> Ym((size_t)m * nb);
-        for (int r = 0; r < m; ++r)
-            for (int j = 0; j < nb; ++j) Ym[(size_t)r * nb + j] = Y[(size_t)j * nb + r];
-        small_times(s, m, nb, Ym, s.V.p, s.tmp.p);
+        // restart from the m lowest Ritz vectors; T of the rotated basis is
+        // Ym T Ym^T (the Ritz values up to rounding)
+        const int m = std::min(rst, na);
+        upload(s, s.coef, coeffs(m));
+        times_dev(s, m, nb, s.coef.p, s.V.p, s.tmp.p);
         BSE_HIP(hipMemcpyAsync(s.V.p, s.tmp.p, (size_t)m * n * 8, hipMemcpyDeviceToDevice,
                                c->stream));
-        small_times(s, m, nb, Ym, s.W.p, s.tmp.p);
+        times_dev(s, m, nb, s.coef.p, s.W.p, s.tmp.p);
         BSE_HIP(hipMemcpyAsync(s.W.p, s.tmp.p, (size_t)m * n * 8, hipMemcpyDeviceToDevice,
                                c->stream));
-        // T of the rotated basis: Ym T Ym^T (the Ritz values up to rounding)
-        std::vector<double> TY((size_t)nb * m, 0.0);
-        for (int i = 0; i < nb; ++i)
+        std::vector<double> TY((size_t)na * m, 0.0);
+        for (int i = 0; i < na; ++i)
             for (int q = 0; q < m; ++q) {
                 double acc = 0;
-                for (int l = 0; l < nb; ++l) acc += T[(size_t)i * nb + l] * Ym[(size_t)q * nb + l];
+                for (int l = 0; l < na; ++l) acc += T[(size_t)i * na + l] * Y[(size_t)l * na + q];
                 TY[(size_t)i * m + q] = acc;
             }
+        std::fill(Tm.begin(), Tm.end(), 0.0);
         for (int r = 0; r < m; ++r)
             for (int q = 0; q < m; ++q) {
                 double acc = 0;
-                for (int i = 0; i < nb; ++i) acc += Ym[(size_t)r * nb + i] * TY[(size_t)i * m + q];
+                for (int i = 0; i < na; ++i) acc += Y[(size_t)i * na + r] * TY[(size_t)i * m + q];
                 Tm[(size_t)r * maxb + q] = acc;
             }
         for (int r = 0; r < m; ++r)
@@ -446,25 +514,26 @@ void DavRun::advance() {
                 Tm[(size_t)r * maxb + q] = Tm[(size_t)q * maxb + r] = a;
             }
         nb = m;
+        std::fill(act.begin(), act.end(), 0);
+        std::fill(act.begin(), act.begin() + m, 1);
     }
-    orth_against(s, nb, kr);
-    int kk = orthonormalize(s, kr, drop2);
-    orth_against(s, nb, kk);
-    kk = orthonormalize(s, kk, drop2);
-    BSE_REQUIRE(kk > 0, BSE_ERR_NOCONV, "Davidson: no new directions");
-    BSE_HIP(hipMemcpyAsync(s.V.p + (size_t)nb * n, s.Tn.p, (size_t)kk * n * 8,
-                           hipMemcpyDeviceToDevice, c->stream));
-    pa_k = kk;
+    // Gram-Schmidt against the basis and Cholesky-QR, twice; the second
+    // factor writes the new rows straight into the basis
+    orth_against(s, nb, kr, s.Tn.p);
+    chol_qr(s, kr, drop2, s.Tn.p, s.tmp.p);
+    orth_against(s, nb, kr, s.tmp.p);
+    chol_qr(s, kr, drop2, s.tmp.p, s.V.p + (size_t)nb * n);
+    pa_k = kr;
 }
 
 void DavRun::finish(double *omega, double *Xout, bse_davidson_stats *stats) {
     const size_t n = s.n;
-    const int nout = std::min(ne, kr);
-    for (int i = 0; i < nout; ++i) omega[i] = theta[i];
+    const int nout = std::min(ne, (int)theta_x.size());
+    for (int i = 0; i < nout; ++i) omega[i] = theta_x[i];
     BSE_HIP(hipMemcpyAsync(Xout, s.X.p, (size_t)nout * n * 8, hipMemcpyDeviceToDevice, c->stream));
     BSE_HIP(hipStreamSynchronize(c->stream));
     if (stats) {
-        stats->iterations = std::min(it, o.max_iter);
+        stats->iterations = it_x;
         stats->n_apply = n_apply;
         stats->learned_used = used;
         stats->learned_rejected = rejected;

@@ -180,13 +180,15 @@ void ctx_spread_matrices(bse_ctx *c, double *A) {
     BSE_HIP(hipStreamSynchronize(c->stream));
 }
 
-// Sweeps until one rotates nothing (or max_sweeps); returns the sweeps run.
+// Sweeps until one rotates nothing (or max_sweeps); returns the sweeps run
+// and, in *conv, whether the last one rotated nothing.
 static int run_sweeps(hipStream_t st, double *A, double *Q, int nm, int N, double tol,
-                      int max_sweeps, double2 *cs, int2 *pq, int *flag) {
+                      int max_sweeps, double2 *cs, int2 *pq, int *flag, bool *conv) {
     const int M = N + (N & 1), H = M / 2;
     const long long nthr = (long long)nm * H * H + (long long)N * H;
     const unsigned ablk = (unsigned)((H + 63) / 64), rblk = (unsigned)((nthr + 255) / 256);
     int sweeps = 0;
+    *conv = false;
     while (sweeps < max_sweeps) {
         ++sweeps;
         BSE_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
@@ -199,7 +201,10 @@ static int run_sweeps(hipStream_t st, double *A, double *Q, int nm, int N, doubl
         int any = 0;
         BSE_HIP(hipMemcpyAsync(&any, flag, sizeof(int), hipMemcpyDeviceToHost, st));
         BSE_HIP(hipStreamSynchronize(st));
-        if (!any) break;
+        if (!any) {
+            *conv = true;
+            break;
+        }
     }
     return sweeps;
 }
@@ -243,7 +248,8 @@ void ctx_jade(bse_ctx *c, int N, int nm, double *A, double *Q, int start_given, 
         BSE_LAUNCH_CHECK();
         for (int i = 0; i < N; ++i) q0[(size_t)i * N + i] = 1.0;
         BSE_HIP(hipMemcpyAsync(Q, q0.data(), nn * 8, hipMemcpyHostToDevice, st));
-        run_sweeps(st, a1.p, Q, 1, N, tol, 100, cs.p, pq.p, flag.p);
+        bool conv1 = false;  // the start needs no convergence: the sweeps go on from it
+        run_sweeps(st, a1.p, Q, 1, N, tol, 100, cs.p, pq.p, flag.p, &conv1);
         BSE_HIP(hipMemcpyAsync(q0.data(), Q, nn * 8, hipMemcpyDeviceToHost, st));
         BSE_HIP(hipStreamSynchronize(st));
     }
@@ -262,7 +268,8 @@ void ctx_jade(bse_ctx *c, int N, int nm, double *A, double *Q, int start_given, 
                  (long long)nn, nm, c->gws, st);
     k_symmetrize<<<(unsigned)(((long long)nm * nn + 255) / 256), 256, 0, st>>>(A, nm, N);
     BSE_LAUNCH_CHECK();
-    const int sweeps = run_sweeps(st, A, Q, nm, N, tol, max_sweeps, cs.p, pq.p, flag.p);
+    bool conv = false;
+    const int sweeps = run_sweeps(st, A, Q, nm, N, tol, max_sweeps, cs.p, pq.p, flag.p, &conv);
     if (n_sweeps) *n_sweeps = sweeps;
     if (offsum) {
         std::vector<double> a(nn * nm);
@@ -276,6 +283,9 @@ void ctx_jade(bse_ctx *c, int N, int nm, double *A, double *Q, int start_given, 
         *offsum = s;
     }
     BSE_HIP(hipStreamSynchronize(st));
+    BSE_REQUIRE(conv, BSE_ERR_NOCONV,
+                "bse_jade: not converged in %d sweeps (the last one still rotated); A, Q, "
+                "n_sweeps and offsum hold the state after them", max_sweeps);
 }
 
 void ctx_localize(bse_ctx *c, const double *Q) {

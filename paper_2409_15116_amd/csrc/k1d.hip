@@ -427,6 +427,241 @@ __global__ void __launch_bounds__(64 * NW) k_k1d_res(
     }
 }
 
+// The resident kernel with two grid points per lane (FP64): a workgroup
+// holds every row of a whole 64-point tile for VPL trial vectors; lane l
+// works on the points 2 (l % 32) and 2 (l % 32) + 1 and, in an event, on the
+// rows of its half h = l / 32 of the wave's group: half 0 takes rows 0-3
+// with the event's first column, half 1 rows 4-7 with the second.  A
+// 16-byte tau load brings a lane both of its points of one row (the two
+// halves load different rows in the same instruction), so an event costs
+// four vector-memory instructions instead of eight for the same products;
+// those instructions, not bytes, bound the one-point kernel.  Same tables
+// (groups, parts, event lists) and the same schedule as k_k1d_res.  nr must
+// be even (a lane's two points are both inside the grid or both past its
+// end).
+template <int VPL, int NW, int NBUF, int CAP>
+__global__ void __launch_bounds__(64 * NW) k_k1d_res2(
+    const double *__restrict__ A, const double *__restrict__ tau, const double *__restrict__ V,
+    const double *__restrict__ u, const int *__restrict__ grp, const int *__restrict__ gpart,
+    const int *__restrict__ gslot, const int *__restrict__ part,
+    const int *__restrict__ ev, const int *__restrict__ ev_start, const int *__restrict__ ph_cnt,
+    const int *__restrict__ rb_ng, const int *__restrict__ rb_nph, int nrb, int nph_max,
+    int n_occ, int B, long long nr, long long n_rows, int nSc, double k1d, double inv_omega,
+    double *__restrict__ Cr, cplx<double> *__restrict__ Hc, double *__restrict__ Dp) {
+    constexpr int BW = K1D_RES_BW;
+    constexpr int EV = BW + 2;  // ints per event: BW tau offsets, two column slots
+    constexpr int HB = BW / 2;  // rows per half
+    constexpr int NS = CAP / NW;  // slots a wave stages per phase
+    static_assert(VPL % 2 == 0 && BW == 8, "pairs of vectors, groups of 8 rows");
+    static_assert(NBUF == 2, "events are padded to multiples of 2 per phase");
+    static_assert(CAP % NW == 0, "the waves share the staging");
+    using D2 = double __attribute__((ext_vector_type(2)));
+    using U4 = unsigned __attribute__((ext_vector_type(4)));
+    // a values [slot][vector][point pair]: a half-wave reads 512 contiguous bytes
+    __shared__ D2 a_s[CAP * VPL * 32];
+    static_assert(sizeof(a_s) >= (size_t)NW * 2 * 2 * VPL * 32 * sizeof(double),
+                  "the density reduction reuses the a buffer");
+    // decode: id = 8 * ((hi8 * nSc + sc) * nrb + rb) + lo8; tau tile hi8 * 8 + lo8
+    const int id = blockIdx.x;
+    const int lo8 = id & 7;
+    int rest = id >> 3;
+    const int rb = rest % nrb;
+    rest /= nrb;
+    const int sc = rest % nSc;
+    const long long rt = (long long)(rest / nSc) * 8 + lo8;
+    const long long r0 = rt * K1D_R;
+    if (r0 >= nr) return;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int hf = lane >> 5, pp = lane & 31;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int G = rb * NW + wv;
+    const int ng = rb_ng[rb], nph = rb_nph[rb];
+    const bool rok = r0 + 2 * pp < nr;
+    const long long rp = rok ? r0 + 2 * pp : nr - 2;  // clamp: loads stay in bounds
+    const int s0 = sc * VPL;
+    const size_t sstride = (size_t)n_occ * nr;
+    const __amdgpu_buffer_rsrc_t trs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(tau + rt * n_rows * TAU_TILE), (short)0, (int)(n_rows * TAU_TILE * sizeof(double)),
+        0x00020000);
+    const int voff = pp * 16;
+    // offset of vector j's element rp (vectors past B read vector B - 1)
+    auto vec_off = [&](int j) {
+        int bl = B;
+        asm volatile("" : "+s"(bl));
+        return (size_t)min(s0 + j, bl - 1) * sstride + rp;
+    };
+    auto lds_get = [&](int k, double (&x)[2][VPL]) {
+#pragma unroll
+        for (int j = 0; j < VPL; ++j) {
+            const D2 y = a_s[(k * VPL + j) * 32 + pp];
+            x[0][j] = y.x;
+            x[1][j] = y.y;
+        }
+    };
+    // this half's rows k of an event: 16 bytes of tau at the lane's points
+    // (both halves' table entries are read as scalars, then selected per
+    // lane, so that the table reads stay scalar loads)
+    auto request = [&](U4 (&tb)[HB], const int *cur) {
+#pragma unroll
+        for (int k = 0; k < HB; ++k) {
+            const int oa = __builtin_amdgcn_readfirstlane(cur[k]);
+            const int ob = __builtin_amdgcn_readfirstlane(cur[HB + k]);
+            const int o = hf ? ob : oa;
+            tb[k] = __builtin_amdgcn_raw_buffer_load_b128(trs, o * (int)sizeof(double) + voff, 0, 0);
+        }
+    };
+    auto slot_of = [&](const int *cur) {
+        const int sa = __builtin_amdgcn_readfirstlane(cur[BW]);
+        const int sb = __builtin_amdgcn_readfirstlane(cur[BW + 1]);
+        return hf ? sb : sa;
+    };
+
+    double acc[HB][2][VPL];
+#pragma unroll
+    for (int k = 0; k < HB; ++k)
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int j = 0; j < VPL; ++j) acc[k][p][j] = 0;
+    const bool act = wv < ng;
+    const int *evg = ev + (size_t)(act ? ev_start[G] : 0) * EV;
+    U4 t[NBUF][HB];
+    if (act) {
+        // issued in buffer order, the order the loop waits for them in
+#pragma unroll
+        for (int b = 0; b < NBUF; ++b) {
+            request(t[b], evg + b * EV);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    int e = 0;
+    for (int h = 0; h < nph; ++h) {
+        if (h > 0) __syncthreads();  // every wave is done with the previous part
+        // stage part h, two slots at a time (all their loads issued before
+        // the first LDS write); lane (hf, pp) loads vectors 2c + hf at its
+        // points
+        static_assert(NS % 2 == 0, "slots staged in pairs");
+#pragma unroll
+        for (int l0 = 0; l0 < NS; l0 += 2) {
+            D2 x[2][VPL / 2];
+#pragma unroll
+            for (int l = 0; l < 2; ++l) {
+                const int o = __builtin_amdgcn_readfirstlane(
+                    part[((size_t)rb * nph_max + h) * CAP + wv + NW * (l0 + l)]);
+                const double *ao = A + (size_t)(o >= 0 ? o : 0) * nr;
+#pragma unroll
+                for (int c = 0; c < VPL / 2; ++c)
+                    x[l][c] = *(const D2 *)(ao + vec_off(2 * c + hf));
+            }
+#pragma unroll
+            for (int l = 0; l < 2; ++l)
+#pragma unroll
+                for (int c = 0; c < VPL / 2; ++c)
+                    a_s[((wv + NW * (l0 + l)) * VPL + 2 * c + hf) * 32 + pp] = x[l][c];
+        }
+        __syncthreads();
+        if (act) {
+            const int end = e + ph_cnt[(size_t)G * nph_max + h];
+#pragma unroll 1
+            for (; e < end; e += NBUF) {
+#pragma unroll
+                for (int b = 0; b < NBUF; ++b) {
+                    const int *cur = evg + (e + b) * EV;
+                    double aw[2][VPL];
+                    lds_get(slot_of(cur), aw);
+#pragma unroll
+                    for (int k = 0; k < HB; ++k) {
+                        const double t0 = __builtin_bit_cast(double, (unsigned long long)t[b][k].x |
+                                                             ((unsigned long long)t[b][k].y << 32));
+                        const double t1 = __builtin_bit_cast(double, (unsigned long long)t[b][k].z |
+                                                             ((unsigned long long)t[b][k].w << 32));
+#pragma unroll
+                        for (int j = 0; j < VPL; ++j) {
+                            acc[k][0][j] += t0 * aw[0][j];
+                            acc[k][1][j] += t1 * aw[1][j];
+                        }
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                    request(t[b], cur + NBUF * EV);  // the lists are padded past their end
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+        }
+    }
+    // epilogue: Cr of this half's rows and their share of the density (a
+    // from LDS when the rows' part is the one resident last)
+    const D2 vr = *(const D2 *)(V + rp);
+    double dn[2][VPL];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int j = 0; j < VPL; ++j) dn[p][j] = 0;
+    if (act) {
+        const bool last = gpart[G] == nph - 1;
+#pragma unroll
+        for (int k = 0; k < HB; ++k) {
+            const int gi = G * BW + hf * HB + k;
+            const int v = grp[gi];
+            if (v >= 0) {
+                double av[2][VPL];
+                if (last) {
+                    lds_get(gslot[gi], av);
+                } else {
+                    const double *ao = A + (size_t)v * nr;
+#pragma unroll
+                    for (int j = 0; j < VPL; ++j) {
+                        const D2 y = *(const D2 *)(ao + vec_off(j));
+                        av[0][j] = y.x;
+                        av[1][j] = y.y;
+                    }
+                }
+                const D2 uv = *(const D2 *)(u + (size_t)v * nr + rp);
+#pragma unroll
+                for (int j = 0; j < VPL; ++j) {
+                    if (rok && s0 + j < B) {  // then vec_off(j) is vector s0 + j's own offset
+                        D2 out;
+                        out.x = vr.x * av[0][j] - k1d * acc[k][0][j];
+                        out.y = vr.y * av[1][j] - k1d * acc[k][1][j];
+                        *(D2 *)(Cr + vec_off(j) + (size_t)v * nr) = out;
+                    }
+                    dn[0][j] += uv.x * av[0][j];
+                    dn[1][j] += uv.y * av[1][j];
+                }
+            }
+        }
+    }
+    __syncthreads();  // a_s is free: the density partials of every (wave, half) go there
+    double *red = (double *)a_s;  // [wave * 2 + half][point * VPL + j][pp]
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int j = 0; j < VPL; ++j)
+            red[((size_t)(wv * 2 + hf) * 2 * VPL + p * VPL + j) * 32 + pp] = dn[p][j];
+    __syncthreads();
+    // Hc[s / 2] = (D[s], D[s + 1]) / Omega for even s, summed over the waves
+    // and halves in fixed order (or this row block's share into Dp[rb][s])
+    if (tid < VPL / 2 * 64) {
+        const int jp = tid >> 6, p = (tid >> 5) & 1, q = tid & 31;
+        const int j = 2 * jp;
+        double re = 0, im = 0;
+        for (int w = 0; w < NW * 2; ++w) {
+            re += red[((size_t)w * 2 * VPL + p * VPL + j) * 32 + q];
+            im += red[((size_t)w * 2 * VPL + p * VPL + j + 1) * 32 + q];
+        }
+        const long long r = r0 + 2 * q + p;
+        if (r < nr && s0 + j < B) {
+            if (nrb == 1) {
+                Hc[(size_t)((s0 + j) / 2) * nr + r] =
+                    cmake<cplx<double>>(re * inv_omega, s0 + j + 1 < B ? im * inv_omega : 0.0);
+            } else {
+                double *dp = Dp + ((size_t)rb * B + s0 + j) * nr + r;
+                dp[0] = re * inv_omega;
+                if (s0 + j + 1 < B) dp[nr] = im * inv_omega;
+            }
+        }
+    }
+}
+
 // Hc[s/2](r).{x|y} = sum_ib Dp[ib][s](r)  (fixed order: deterministic)
 template <typename T>
 __global__ void k_sum_density(const T *__restrict__ Dp, int nIb, int B, long long nr,
@@ -502,6 +737,42 @@ static void launch_k1d_res(const T *A, const T *tau, const T *V, const T *u,
     }
 }
 
+template <int VPL, int NW, int NBUF>
+static void launch_k1d_res2(const double *A, const double *tau, const double *V, const double *u,
+                            const PairEvents *pes, int n_occ, int B, long long nr, double k1d,
+                            double inv_omega, double *Cr, cplx<double> *Hc, double *Dp,
+                            hipStream_t st) {
+    // LDS capacity in orbitals: 128 KB of a values (VPL * 512 bytes a slot)
+    constexpr int CAP = std::min(std::min(K1D_RES_MAXROWS, NW * K1D_RES_BW), 256 / VPL);
+    int set = -1;
+    for (int i = 0; i < K1D_RES_NSETS; ++i)
+        if (K1D_RES_CAPS[i] == CAP) set = i;
+    BSE_REQUIRE(set >= 0, BSE_ERR_STATE, "no resident K1d tables for %d orbitals", CAP);
+    const PairEvents &pe = pes[set];
+    BSE_REQUIRE(nr % 2 == 0, BSE_ERR_ARG, "the two-point K1d kernel needs an even grid size");
+    const int nSc = (B + VPL - 1) / VPL;
+    const long long nrt = (nr + K1D_R - 1) / K1D_R;
+    const long long nblk = (nrt + 7) / 8 * 8 * nSc * pe.nrb;
+    BSE_REQUIRE(pe.nrb >= 1 && pe.cap == CAP &&
+                    (pe.nrb == 1 ? pe.ng >= 1 && pe.ng <= NW && n_occ <= NW * K1D_RES_BW
+                                 : NW * K1D_RES_BW == K1D_RES_MAXROWS),
+                BSE_ERR_ARG, "the resident K1d shape holds %d orbitals, the cell has %d",
+                NW * K1D_RES_BW, n_occ);
+    BSE_REQUIRE(nblk < (1LL << 31), BSE_ERR_ARG, "grid too large for the K1d kernel");
+    BSE_REQUIRE(pe.n_rows * TAU_TILE * (long long)sizeof(double) < (1LL << 31), BSE_ERR_ARG,
+                "too many pairs for the K1d tables");
+    k_k1d_res2<VPL, NW, NBUF, CAP><<<(unsigned)nblk, 64 * NW, 0, st>>>(
+        A, tau, V, u, pe.grp, pe.gpart, pe.gslot, pe.part, pe.ev, pe.ev_start, pe.ph_cnt,
+        pe.rb_ng, pe.rb_nph, pe.nrb, pe.nph, n_occ, B, nr, pe.n_rows, nSc, k1d, inv_omega, Cr,
+        Hc, Dp);
+    BSE_LAUNCH_CHECK();
+    if (pe.nrb > 1) {
+        dim3 g2(div_up(nr, 256), (B + 1) / 2);
+        k_sum_density<double><<<g2, 256, 0, st>>>(Dp, pe.nrb, B, nr, Hc);
+        BSE_LAUNCH_CHECK();
+    }
+}
+
 // the compiled shapes; variant 0 is the default of each type
 static constexpr K1dShape K1D_SHAPES32[] = {
     {32, 16, 2, 4},           {32, 16, 1, 4},           {16, 16, 2, 4},
@@ -509,13 +780,15 @@ static constexpr K1dShape K1D_SHAPES32[] = {
     {64, 8, 2, 8},            {32, 8, 2, 8},            {128, 8, 2, 16},
     {128, 4, 2, 16, 1, 64},   {128, 8, 2, 16, 1, 32},   {128, 8, 2, 16, 1, 64},
     {128, 16, 2, 16, 1, 32},  {64, 8, 2, 8, 1, 64},     {64, 16, 2, 8, 1, 32},
-    {64, 4, 2, 8, 1, 64},     {64, 8, 2, 8, 1, 32}};
+    {64, 4, 2, 8, 1, 64},     {64, 8, 2, 8, 1, 32},     {128, 32, 2, 16, 1, 16}};
 static constexpr K1dShape K1D_SHAPES64[] = {
     {32, 8, 1, 4},            {16, 8, 1, 4},            {32, 4, 1, 4},
     {16, 4, 1, 4},            {64, 8, 1, 8},            {64, 4, 1, 8},
     {128, 4, 1, 16},          {128, 2, 2, 16, 1, 64},   {128, 4, 2, 16, 1, 32},
     {128, 4, 2, 16, 1, 64},   {128, 8, 2, 16, 1, 32},   {64, 4, 2, 8, 1, 64},
-    {64, 8, 2, 8, 1, 32},     {64, 2, 2, 8, 1, 64},     {64, 4, 2, 8, 1, 32}};
+    {64, 8, 2, 8, 1, 32},     {64, 2, 2, 8, 1, 64},     {64, 4, 2, 8, 1, 32},
+    {128, 16, 2, 16, 1, 16},  {128, 4, 2, 16, 2, 64},   {128, 2, 2, 16, 2, 64},
+    {64, 2, 2, 8, 2, 64}};
 
 int k1d_num_shapes(bool dbl) {
     return dbl ? (int)(sizeof(K1D_SHAPES64) / sizeof(K1dShape))
@@ -532,6 +805,20 @@ void k1d_apply(const T *A, const T *tau, const T *V, const T *u, const PairCSR *
                T inv_omega, T *Cr, cplx<T> *Hc, T *Dp, hipStream_t st) {
     constexpr bool dbl = sizeof(T) == 8;
     const K1dShape sh = k1d_shape(dbl, shape);
+    if (sh.res == 2) {
+        if constexpr (dbl) {
+#define BSE_K1D_RES2_CASE(S_, NW_, NB_)                                                       \
+    if (sh.s == S_ && sh.nw == NW_ && sh.nbuf == NB_)                                        \
+        launch_k1d_res2<S_, NW_, NB_>(A, tau, V, u, pes, n_occ, B, nr, k1d, inv_omega, Cr, Hc, \
+                                      Dp, st);
+            BSE_K1D_RES2_CASE(4, 16, 2)
+            BSE_K1D_RES2_CASE(2, 16, 2)
+            BSE_K1D_RES2_CASE(2, 8, 2)
+#undef BSE_K1D_RES2_CASE
+            return;
+        }
+        BSE_REQUIRE(false, BSE_ERR_STATE, "two-point K1d shapes are FP64 only");
+    }
     if (sh.res) {
 #define BSE_K1D_RES_CASE(S_, NW_, NB_, PT_)                                                  \
     if (sh.s == S_ && sh.nw == NW_ && sh.nbuf == NB_ && sh.pt == PT_)                         \
@@ -546,6 +833,7 @@ void k1d_apply(const T *A, const T *tau, const T *V, const T *u, const PairCSR *
             BSE_K1D_RES_CASE(8, 8, 2, 32)
             BSE_K1D_RES_CASE(2, 8, 2, 64)
             BSE_K1D_RES_CASE(4, 8, 2, 32)
+            BSE_K1D_RES_CASE(16, 16, 2, 16)
         } else {
             BSE_K1D_RES_CASE(4, 16, 2, 64)
             BSE_K1D_RES_CASE(8, 16, 2, 32)
@@ -555,6 +843,7 @@ void k1d_apply(const T *A, const T *tau, const T *V, const T *u, const PairCSR *
             BSE_K1D_RES_CASE(16, 8, 2, 32)
             BSE_K1D_RES_CASE(4, 8, 2, 64)
             BSE_K1D_RES_CASE(8, 8, 2, 32)
+            BSE_K1D_RES_CASE(32, 16, 2, 16)
         }
 #undef BSE_K1D_RES_CASE
         return;

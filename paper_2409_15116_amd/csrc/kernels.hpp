@@ -174,6 +174,9 @@ void measure_prep(const double *u, long long n, int kind, double *out, hipStream
 void residual(const double *LX, const double *X, const double *theta, long long n, int k,
               double *R, hipStream_t st);
 void row_norm2(const double *X, long long n, int k, double *part, double *out, hipStream_t st);
+void resid_precond(double *R, const double *X, const double *theta, const double *kin,
+                   const double *epsd, double vbar, double delta, int n_occ, int npw, int k,
+                   double *Tn, hipStream_t st);
 void precond_diag(const double *R, const double *theta, const double *kin, const double *epsd,
                   double vbar, double delta, int n_occ, int npw, int k, double *Tn,
                   hipStream_t st);

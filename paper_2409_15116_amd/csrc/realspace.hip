@@ -247,6 +247,36 @@ void row_norm2(const double *X, long long n, int k, double *part, double *out, h
     BSE_LAUNCH_CHECK();
 }
 
+// R[i] = LX[i] - theta_i X[i] in place (R holds LX on entry) and
+// T[i][v][g] = R[i][v][g] / max(kin[g] + vbar - eps_vv[v] - theta_i, delta),
+// one pass for the residual and the diagonal preconditioner
+__global__ void k_resid_precond(double *__restrict__ R, const double *__restrict__ X,
+                                const double *__restrict__ theta, const double *__restrict__ kin,
+                                const double *__restrict__ epsd, double vbar, double delta,
+                                int n_occ, int npw, int k, double *__restrict__ Tn) {
+    const long long n = (long long)n_occ * npw;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * k) return;
+    const int row = (int)(i / n);
+    const long long j = i - (long long)row * n;
+    const int v = (int)(j / npw);
+    const int g = (int)(j - (long long)v * npw);
+    const double th = theta[row];
+    const double r = R[i] - th * X[i];
+    R[i] = r;
+    double d = kin[g] + vbar - epsd[v] - th;
+    d = d > delta ? d : delta;
+    Tn[i] = r / d;
+}
+void resid_precond(double *R, const double *X, const double *theta, const double *kin,
+                   const double *epsd, double vbar, double delta, int n_occ, int npw, int k,
+                   double *Tn, hipStream_t st) {
+    const long long n = (long long)n_occ * npw * k;
+    k_resid_precond<<<div_up(n, 256), 256, 0, st>>>(R, X, theta, kin, epsd, vbar, delta, n_occ,
+                                                     npw, k, Tn);
+    BSE_LAUNCH_CHECK();
+}
+
 // T[i][v][g] = R[i][v][g] / max(kin[g] + vbar - eps_vv[v] + scissor - theta_i, delta)
 __global__ void k_precond_diag(const double *__restrict__ R, const double *__restrict__ theta,
                                const double *__restrict__ kin, const double *__restrict__ epsd,

@@ -19,6 +19,7 @@ FP64, FP32, BF16X3 = 0, 1, 2
 MEASURE_ABS_L1, MEASURE_OVERLAP = 0, 1
 _STATUS = {0: "ok", 1: "invalid argument", 2: "HIP error", 3: "out of device memory",
            4: "not converged", 5: "call out of order"}
+NOCONV = 4  # BSE_ERR_NOCONV: an iteration limit was hit before its tolerance
 
 
 class BseError(RuntimeError):
@@ -212,10 +213,12 @@ class BseContext:
         _check(load().bse_spread_matrices(self.h, A.data_ptr()))
         return A
 
-    def jade(self, A, Q=None, tol=1e-7, max_sweeps=100):
+    def jade(self, A, Q=None, tol=1e-7, max_sweeps=100, partial_ok=False):
         """JADE on device FP64 matrices A [n_mat, N, N] (rotated in place).
         Q: device [N, N] start, or None for the eigenvectors of A[0].  Returns
-        (Q, sweeps, off-diagonal sum)."""
+        (Q, sweeps, off-diagonal sum); raises BseError (BSE_ERR_NOCONV) when
+        max_sweeps ran out while the last sweep still rotated, unless
+        partial_ok, which returns (Q, sweeps, off-diagonal sum, converged)."""
         torch = self.torch
         nm, N = int(A.shape[0]), int(A.shape[1])
         _dptr(A, torch.float64, (nm, N, N))
@@ -224,8 +227,13 @@ class BseContext:
             Q = torch.empty((N, N), dtype=torch.float64, device="cuda")
         _dptr(Q, torch.float64, (N, N))
         sw, off = C.c_int(), C.c_double()
-        _check(load().bse_jade(self.h, N, nm, A.data_ptr(), Q.data_ptr(), int(given), float(tol),
-                               int(max_sweeps), C.byref(sw), C.byref(off)))
+        st = load().bse_jade(self.h, N, nm, A.data_ptr(), Q.data_ptr(), int(given), float(tol),
+                             int(max_sweeps), C.byref(sw), C.byref(off))
+        if partial_ok and st == NOCONV:
+            return Q, int(sw.value), float(off.value), False
+        _check(st)
+        if partial_ok:
+            return Q, int(sw.value), float(off.value), True
         return Q, int(sw.value), float(off.value)
 
     def localize(self, Q):
@@ -399,7 +407,7 @@ class BseContext:
         stats = {"iterations": st.iterations, "n_apply": st.n_apply, "seconds": st.seconds,
                  "learned_used": st.learned_used, "learned_rejected": st.learned_rejected,
                  "resid": np.array(st.resid[:n_eig]), "status": status}
-        if not (partial_ok and status == 4):
+        if not (partial_ok and status == NOCONV):
             _check(status)
         return om, X, stats
 
@@ -426,11 +434,13 @@ def k1d_num_shapes(precision):
 def k1d_shape_info(precision, shape):
     """Parameters of a compiled K1d shape: rows per workgroup (the orbital
     limit of a resident shape), vectors per workgroup, tau columns in flight,
-    waves, resident (bool) and grid points per workgroup."""
+    waves, resident (bool), grid points per workgroup and grid points per
+    lane (2 for the two-point FP64 kernel)."""
     info = np.zeros(6, dtype=np.int32)
     _check(load().bse_k1d_shape_info(int(precision), int(shape), info.ctypes.data))
     return {"rows": int(info[0]), "vectors": int(info[1]), "nbuf": int(info[2]),
-            "waves": int(info[3]), "resident": bool(info[4]), "points": int(info[5])}
+            "waves": int(info[3]), "resident": bool(info[4]), "points": int(info[5]),
+            "points_per_lane": 2 if int(info[4]) == 2 else 1}
 
 
 def _stats_dict(st, n_eig, status):

@@ -98,8 +98,12 @@ def test_jade_edge_cases():
     assert Q.cpu().numpy().tolist() == [[1.0]] and off == 0.0
     # zero sweeps: only the start transform
     A = spread_matrices(b.to_grid(c.psi_canon))
-    Q, sw, off = ctx.jade(_dev(A), _dev(np.eye(8)), max_sweeps=0)
-    assert sw == 0 and np.array_equal(Q.cpu().numpy(), np.eye(8))
+    Q, sw, off, conv = ctx.jade(_dev(A), _dev(np.eye(8)), max_sweeps=0, partial_ok=True)
+    assert sw == 0 and not conv and np.array_equal(Q.cpu().numpy(), np.eye(8))
+    with pytest.raises(_pkg().BseError):        # the sweep limit is reported
+        ctx.jade(_dev(A), _dev(np.eye(8)), max_sweeps=0)
+    Q, sw, off, conv = ctx.jade(_dev(A), _dev(np.eye(8)), tol=1e-7, partial_ok=True)
+    assert conv and sw >= 1
     with pytest.raises(_pkg().BseError):
         ctx.jade(_dev(A), tol=-1.0)
     ctx.close()
@@ -166,7 +170,7 @@ def test_jade_default_start_on_device():
     c, ctx, b = _canonical("c1")
     A, R = near_commuting_matrices(600, seed=4, noise=1e-6)
     Ad = _dev(A)
-    Q, sw, off = ctx.jade(Ad, tol=1e-7, max_sweeps=30)
+    Q, sw, off, _ = ctx.jade(Ad, tol=1e-7, max_sweeps=30, partial_ok=True)
     I = torch.eye(600, dtype=torch.float64, device="cuda")
     assert (Q.T @ Q - I).abs().max().item() < 1e-11
     assert (Q.T @ _dev(A) @ Q - Ad).abs().max().item() < 1e-10

@@ -104,6 +104,8 @@ def test_k1d_shape_info():
                 assert i["rows"] == 8 * i["waves"] <= 128
                 vpl = i["vectors"] * i["points"] // 64
                 assert vpl % 2 == 0 and vpl * esz in (16, 32)
+                if i["points_per_lane"] == 2:       # 16-byte tau loads: FP64 only
+                    assert prec == pkg.FP64 and i["points"] == 64
             else:
                 assert i["points"] == 64
         assert n_res >= 2
