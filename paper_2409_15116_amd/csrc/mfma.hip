@@ -2,19 +2,21 @@
 //
 // Each FP32 operand x is split into hi = bf16(x) and lo = bf16(x - hi), and
 // A B is taken as Ahi Bhi + Ahi Blo + Alo Bhi (the lo*lo term is below the
-// FP32 accumulation error), so three 16x16x16 bf16 MFMAs replace one FP32 FMA
-// chain with a relative error of about 2^-16 instead of 2^-8.
+// FP32 accumulation error), so three bf16 MFMAs replace one FP32 FMA chain
+// with a relative error of about 2^-16 instead of 2^-8.
 //
 // Tile: 64 x 64 per workgroup of 4 waves, each wave a 32 x 32 quadrant made
-// of 2 x 2 MFMA blocks; K steps of 16 staged through LDS as bf16 hi/lo pairs.
-// Lane layout of v_mfma_f32_16x16x16_bf16 (64 lanes): A element i of lane l is
-// A[l % 16][4 (l / 16) + i], B element i is B[4 (l / 16) + i][l % 16], and
-// accumulator element i is D[4 (l / 16) + i][l % 16].
+// of 2 x 2 MFMA blocks; K steps of 32 staged through LDS as bf16 hi/lo pairs.
+// Lane layout of gfx950's v_mfma_f32_16x16x32_bf16 (64 lanes): A element i
+// of lane l is A[l % 16][8 (l / 16) + i], B element i is B[8 (l / 16) + i][l % 16],
+// and accumulator element i is D[4 (l / 16) + i][l % 16].
 #include "kernels.hpp"
 
 namespace bse {
 
 typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 __device__ inline unsigned short bf16_rne(float x) {
@@ -27,7 +29,9 @@ __device__ inline float bf16_to_f32(unsigned short h) { return __uint_as_float((
 constexpr int TB = 64, TK = 16, PADK = 4;
 
 // TA: A is stored [K][M] (C = A^T op(B)); SPLIT: hi/lo split (BF16x3),
-// otherwise one plain bf16 x bf16 product with FP32 accumulate.
+// otherwise one plain bf16 x bf16 product with FP32 accumulate.  K steps of
+// TKB = 32 (one v_mfma_f32_16x16x32_bf16 per block and term).
+constexpr int TKB = 32, PADB = 8;
 template <bool TA, bool NT, bool SPLIT>
 __global__ void __launch_bounds__(256) k_gemm_bf16x3(int M, int N, int K, float alpha,
                                                      const float *__restrict__ A, long long lda,
@@ -35,8 +39,10 @@ __global__ void __launch_bounds__(256) k_gemm_bf16x3(int M, int N, int K, float 
                                                      long long ldb, long long sB, float beta,
                                                      float *__restrict__ C, long long ldc,
                                                      long long sC, int kchunk, int nsplit) {
-    __shared__ unsigned short Ah[TB][TK + PADK], Al[TB][TK + PADK];
-    __shared__ unsigned short Bh[TB][TK + PADK], Bl[TB][TK + PADK];  // [n][k]
+    // rows of 40 bf16 (80 bytes): a lane's 8 consecutive k values are one
+    // aligned 16-byte read
+    __shared__ __attribute__((aligned(16))) unsigned short Ah[TB][TKB + PADB], Al[TB][TKB + PADB];
+    __shared__ __attribute__((aligned(16))) unsigned short Bh[TB][TKB + PADB], Bl[TB][TKB + PADB];
     const int bz = blockIdx.z;
     const int batch = bz / nsplit;
     const int split = bz - batch * nsplit;
@@ -55,20 +61,20 @@ __global__ void __launch_bounds__(256) k_gemm_bf16x3(int M, int N, int K, float 
         for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4_t){0.f, 0.f, 0.f, 0.f};
     // the next k-step's values are loaded into registers while the current
     // one is multiplied from LDS
-    float ra[4], rb[4];
+    float ra[8], rb[8];
     auto fetch = [&](int k0) {
 #pragma unroll
-        for (int l = 0; l < 4; ++l) {
+        for (int l = 0; l < 8; ++l) {
             const int idx = tid + l * 256;
             if (TA) {
                 const int gm = m0 + (idx & 63), gk = k0 + (idx >> 6);
                 ra[l] = (gm < M && gk < kend) ? A[(size_t)gk * lda + gm] : 0.f;
             } else {
-                const int gm = m0 + (idx >> 4), gk = k0 + (idx & 15);
+                const int gm = m0 + (idx >> 5), gk = k0 + (idx & 31);
                 ra[l] = (gm < M && gk < kend) ? A[(size_t)gm * lda + gk] : 0.f;
             }
             if (NT) {
-                const int gn = n0 + (idx >> 4), gk = k0 + (idx & 15);
+                const int gn = n0 + (idx >> 5), gk = k0 + (idx & 31);
                 rb[l] = (gn < N && gk < kend) ? Bm[(size_t)gn * ldb + gk] : 0.f;
             } else {
                 const int gn = n0 + (idx & 63), gk = k0 + (idx >> 6);
@@ -77,50 +83,44 @@ __global__ void __launch_bounds__(256) k_gemm_bf16x3(int M, int N, int K, float 
         }
     };
     if (kbeg < kend) fetch(kbeg);
-    for (int k0 = kbeg; k0 < kend; k0 += TK) {
+    for (int k0 = kbeg; k0 < kend; k0 += TKB) {
 #pragma unroll
-        for (int l = 0; l < 4; ++l) {
+        for (int l = 0; l < 8; ++l) {
             const int idx = tid + l * 256;
-            const int mm = TA ? (idx & 63) : (idx >> 4), ka = TA ? (idx >> 6) : (idx & 15);
+            const int mm = TA ? (idx & 63) : (idx >> 5), ka = TA ? (idx >> 6) : (idx & 31);
             const unsigned short h = bf16_rne(ra[l]);
             Ah[mm][ka] = h;
             if (SPLIT) Al[mm][ka] = bf16_rne(ra[l] - bf16_to_f32(h));
-            const int nn = NT ? (idx >> 4) : (idx & 63), kb = NT ? (idx & 15) : (idx >> 6);
+            const int nn = NT ? (idx >> 5) : (idx & 63), kb = NT ? (idx & 31) : (idx >> 6);
             const unsigned short g = bf16_rne(rb[l]);
             Bh[nn][kb] = g;
             if (SPLIT) Bl[nn][kb] = bf16_rne(rb[l] - bf16_to_f32(g));
         }
         __syncthreads();
-        if (k0 + TK < kend) fetch(k0 + TK);
-        const int r16 = lane & 15, kq = (lane >> 4) * 4;
-        bf16x4_t ah[2], al[2], bh[2], bl[2];
+        if (k0 + TKB < kend) fetch(k0 + TKB);
+        const int r16 = lane & 15, kq = (lane >> 4) * 8;
+        bf16x8_t ah[2], al[2], bh[2], bl[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             const int row = wm + i * 16 + r16;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                ah[i][e] = (short)Ah[row][kq + e];
-                al[i][e] = SPLIT ? (short)Al[row][kq + e] : (short)0;
-            }
+            ah[i] = __builtin_bit_cast(bf16x8_t, *(const u16x8_t *)&Ah[row][kq]);
+            if (SPLIT) al[i] = __builtin_bit_cast(bf16x8_t, *(const u16x8_t *)&Al[row][kq]);
         }
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int col = wn + j * 16 + r16;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                bh[j][e] = (short)Bh[col][kq + e];
-                bl[j][e] = SPLIT ? (short)Bl[col][kq + e] : (short)0;
-            }
+            bh[j] = __builtin_bit_cast(bf16x8_t, *(const u16x8_t *)&Bh[col][kq]);
+            if (SPLIT) bl[j] = __builtin_bit_cast(bf16x8_t, *(const u16x8_t *)&Bl[col][kq]);
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 if (SPLIT) {
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
                 }
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
             }
         __syncthreads();
     }
