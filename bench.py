@@ -426,15 +426,18 @@ def jade_run(args, torch, pkg):
 def learned_c5(args, torch, pkg):
     """Learned preconditioner on jittered 64-well snapshots (N_occ = 64, 72^3,
     25 Ry, 256 PDEP, 40 % of the pairs): plain FP32 solves of the first
-    n_train snapshots record (features, label) rows, the network is trained
-    on the GPU, and the remaining snapshots are solved with the diagonal
-    preconditioner and with the learned correction.  8 lowest, block 16,
-    tol 1e-5 Ha; eigenvalues compared with the plain FP64 GPU solve."""
+    n_train snapshots record (features, label) rows, two networks are
+    trained on the GPU (the one-slot map, and one that also sees the residual
+    windows of the 2 orbitals nearest to each slot), and the remaining
+    snapshots are solved with the diagonal preconditioner and with each
+    learned correction.  8 lowest, block 16, tol 1e-5 Ha; eigenvalues
+    compared with the plain FP64 GPU solve."""
     from synth import make_cell, trial_block
     n_all = args.learned
     n_train = max(1, (4 * n_all) // 5)
     nwg = 127
     kw = 1 + 2 * nwg
+    npart = 2
     n_eig, B, tol = 8, 16, 1e-5
     st = torch.cuda.Stream()
     out = {"snapshots": n_all, "train": n_train, "test": n_all - n_train, "n_eig": n_eig,
@@ -454,7 +457,8 @@ def learned_c5(args, torch, pkg):
             c, ctx, X0 = prepare(i)
             om, X, s = ctx.davidson(X0, n_eig, block=B, precision=pkg.FP32, tol=tol, max_iter=400)
             f, lab, _, s2 = ctx.davidson_record(X0, X.contiguous(), n_eig, nwg, 60000, block=B,
-                                                precision=pkg.FP32, tol=tol, max_iter=400)
+                                                precision=pkg.FP32, tol=tol, max_iter=400,
+                                                n_partners=npart)
             feats.append(f.clone())
             labs.append(lab.clone())
             log(f"learned: snapshot {i} recorded {f.shape[0]} rows ({s['iterations']} iterations)")
@@ -463,16 +467,26 @@ def learned_c5(args, torch, pkg):
         F = torch.cat(feats).contiguous()
         L = torch.cat(labs).contiguous()
         del feats, labs
-        net = pkg.Mlp(kw + 3, 256, kw, pkg.mlp_init_weights(kw + 3, 256, kw, seed=9))
-        torch.cuda.synchronize()
-        t = time.time()
-        losses = net.train(F, L, epochs=30, batch=512, lr=1e-3, seed=2)
-        torch.cuda.synchronize()
-        t_train = time.time() - t
-        out.update({"rows": int(F.shape[0]), "record_seconds": t_rec, "train_seconds": t_train,
-                    "loss_first": float(losses[0]), "loss_last": float(losses[-1])})
-        log(f"learned: trained on {F.shape[0]} rows in {t_train:.1f} s, loss "
-            f"{losses[0]:.4g} -> {losses[-1]:.4g}")
+        # two networks from the same rows: the one-slot map (the first
+        # Kw + 3 feature columns) and the one that also sees the partner
+        # windows of the npart nearest orbitals
+        nets = {}
+        out.update({"rows": int(F.shape[0]), "record_seconds": t_rec, "partners": npart})
+        for name, P in (("learned", 0), ("learned_partners", npart)):
+            fin = kw + 3 + P * kw
+            Fp = F[:, :fin].contiguous()
+            net = pkg.Mlp(fin, 256, kw, pkg.mlp_init_weights(fin, 256, kw, seed=9))
+            torch.cuda.synchronize()
+            t = time.time()
+            losses = net.train(Fp, L, epochs=30, batch=512, lr=1e-3, seed=2)
+            torch.cuda.synchronize()
+            t_train = time.time() - t
+            out[name + "_train"] = {"inputs": fin, "seconds": t_train,
+                                    "loss_first": float(losses[0]), "loss_last": float(losses[-1])}
+            log(f"learned: {name} trained on {F.shape[0]} rows in {t_train:.1f} s, loss "
+                f"{losses[0]:.4g} -> {losses[-1]:.4g}")
+            nets[name] = (net, P)
+            del Fp
         del F, L
         tests = []
         for i in range(n_train, n_all):
@@ -480,8 +494,10 @@ def learned_c5(args, torch, pkg):
             r = {"snapshot": f"c5_{i:02d}"}
             om64, _, s64 = ctx.davidson(X0, n_eig, block=B, precision=pkg.FP64, tol=tol,
                                         max_iter=400)
-            for name, pc in (("diagonal", 0), ("learned", 1)):
-                ctx.set_learned(net if pc else None, nwg)
+            for name in ("diagonal", "learned", "learned_partners"):
+                pc = 0 if name == "diagonal" else 1
+                net, P = nets[name] if pc else (None, 0)
+                ctx.set_learned(net, nwg, n_partners=P)
                 torch.cuda.synchronize()
                 t = time.time()
                 om, _, s = ctx.davidson(X0, n_eig, block=B, precision=pkg.FP32, tol=tol,
@@ -495,10 +511,11 @@ def learned_c5(args, torch, pkg):
             log("learned test", r)
             tests.append(r)
             ctx.close()
-        net.close()
+        for net, _ in nets.values():
+            net.close()
     out["tests"] = tests
-    out["mean_iterations_diagonal"] = float(np.mean([r["diagonal"]["iterations"] for r in tests]))
-    out["mean_iterations_learned"] = float(np.mean([r["learned"]["iterations"] for r in tests]))
+    for name in ("diagonal", "learned", "learned_partners"):
+        out["mean_iterations_" + name] = float(np.mean([r[name]["iterations"] for r in tests]))
     return out
 
 
@@ -550,7 +567,8 @@ def apply_mode(torch, pkg, cell, thr, Xh, prec, B, steps, warmup, graph=True, tu
            "k1d_shape": shape, "k1d_ms_by_shape": [None if x is None else round(x, 3)
                                                     for x in shape_ms],
            "chunk": chunk, "n_chunks": -(-B // chunk), "stage_ms": stages,
-           "n_pairs": ctx.n_pairs, "setup_seconds": t_setup}
+           "n_pairs": ctx.n_pairs, "setup_seconds": t_setup,
+           "k1d_tables": {f"cap{t['cap']}": t for t in (ctx.k1d_tables(0), ctx.k1d_tables(1))}}
     return res, ctx, Y
 
 
@@ -633,6 +651,9 @@ def main():
     ap.add_argument("--jade", default="", metavar="CELLS",
                     help="also localise the canonical orbitals of these cells (comma list) "
                          "on the GPU (reported under jade)")
+    ap.add_argument("--c2-tts-only", action="store_true",
+                    help="only the 64-well gapped cell's Davidson time to solution (FP64, FP32, "
+                         "BF16x3), printed as one JSON line: a short run to profile the solver")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB read + 1 GiB write elementwise kernel first "
                          "(scale reference for HBM byte counters)")
@@ -653,6 +674,10 @@ def main():
     esz = 8 if prec == pkg.FP64 else 4
     B = args.block
 
+    if args.c2_tts_only:
+        print(json.dumps({"time_to_solution": {"c2": time_to_solution(args, torch, pkg)}}),
+              flush=True)
+        return
     if args.calib_copy:
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -697,7 +722,8 @@ def main():
                                 f"{'hipGraph replay' if not args.no_graph else 'eager'}"),
                    "block": B, "n_occ": cell.n_occ, "grid": cell.n, "n_pairs": P,
                    "precision": args.precision, "k1d_shape": head["k1d_shape"],
-                   "chunk": head["chunk"], "k1d_ms_by_shape": head["k1d_ms_by_shape"]},
+                   "chunk": head["chunk"], "k1d_ms_by_shape": head["k1d_ms_by_shape"],
+                   "k1d_tables": head["k1d_tables"]},
         "roofline": roof,
         "whole_apply": {"algorithmic_bytes": alg["apply_bytes"],
                         "algorithmic_gbs": alg["apply_bytes"] / (head["ms_per_step"] * 1e-3) / 1e9,
@@ -718,6 +744,7 @@ def main():
             c2x.close()
             r["rel_dev_vs_" + args.precision] = rel_dev(torch, Y, Yref)
             r.pop("stage_ms", None)
+            r.pop("k1d_tables", None)  # the headline's (same pairs)
             del Y
             torch.cuda.empty_cache()
             modes[name] = r

@@ -346,8 +346,16 @@ bse_status bse_mlp_gradients(bse_mlp *mlp, int n, const float *X, const float *T
 bse_status bse_mlp_train(bse_mlp *mlp, int n, const float *X, const float *T, int epochs,
                          int batch, float lr, uint64_t seed, double *losses);
 /* Attach (mlp, not owned) or detach (NULL) the network used by precond = 1;
- * f_in must be Kw + 3 and k_out Kw for Kw = 1 + 2 n_window_pw. */
+ * f_in must be Kw + 3 + P Kw and k_out Kw for Kw = 1 + 2 n_window_pw and P
+ * the partner windows set by bse_set_learned_partners (default 0). */
 bse_status bse_set_learned(bse_ctx *ctx, bse_mlp *mlp, int n_window_pw);
+/* Partner windows in a slot's features (0 to 4, default 0): after its own
+ * window and the three scalars, the same trial vector's residual windows at
+ * the P orbitals whose Wannier centres are nearest to v (minimum image),
+ * in v's frame and divided by |r_v|.  Applies to bse_davidson_record's rows
+ * and to the network precond = 1 uses; detaches an attached network.
+ * BSE_ERR_ARG outside [0, 4]. */
+bse_status bse_set_learned_partners(bse_ctx *ctx, int n_partners);
 /* Wannier centres (host [n_occ][3], bohr) of the window set-up. */
 bse_status bse_learned_centers(bse_ctx *ctx, double *centers);
 /* bse_davidson that also writes training rows: for every iteration and each
@@ -357,7 +365,8 @@ bse_status bse_learned_centers(bse_ctx *ctx, double *centers);
  * reference eigenvector (Xref dev [n_ref][n_occ][n_pw], sigma aligning its
  * sign) outside the span of the current Ritz vectors x_j, and alpha the
  * least-squares scale of t* onto the diagonal correction M r.
- *   feat  dev [max_rows][Kw + 3] FP32,  label dev [max_rows][Kw] FP32
+ *   feat  dev [max_rows][Kw + 3 + P Kw] FP32 (P: bse_set_learned_partners),
+ *   label dev [max_rows][Kw] FP32
  *   n_rows host out: rows written (recording stops when full). */
 bse_status bse_davidson_record(bse_ctx *ctx, const bse_davidson_opts *opts, const double *X0,
                                const double *Xref, int n_ref, int n_window_pw, float *feat,

@@ -32,10 +32,13 @@ bse_status bse_debug_gemm(bse_ctx *ctx, int nt, int M, int N, int K, double alph
 
 /* Statistics of the resident K1d tables built by bse_build_pairs, table set
  * `set` (0: 128 orbitals of a values in LDS per phase, 1: 64):
- *   stats host [8] out: row blocks, largest phase count, LDS capacity,
+ *   stats host [10] out: row blocks, largest phase count, LDS capacity,
  *   events (incl. padding), event entries on a kept pair (each entry is one
  *   tau load and VPL products per lane), a values staged per grid piece and
- *   vector group summed over the row blocks, kept pairs, orbitals.
+ *   vector group summed over the row blocks, kept pairs, orbitals, and the
+ *   critical path in events summed over the row blocks: with the phase
+ *   barriers (per phase, the busiest wave's events) and without them (the
+ *   busiest wave's total); events / waves is the balanced ideal.
  * BSE_ERR_ARG for an unknown set. */
 bse_status bse_debug_k1d_tables(bse_ctx *ctx, int set, int64_t *stats);
 

@@ -313,6 +313,27 @@ struct Lcg {
 };
 }  // namespace
 
+// critical-path statistics of per-(block, group, phase) event counts
+// cnt[(b * GW + g) * nph + h] (PairEvents::ev_barrier, ev_free)
+static void event_balance(PairEvents &e, const std::vector<int> &cnt, int nrb, int GW, int nph,
+                          const std::vector<int> &ng, const std::vector<int> &nphb) {
+    e.ev_barrier = e.ev_free = 0;
+    for (int b = 0; b < nrb; ++b) {
+        long long fr = 0;
+        for (int g = 0; g < ng[b]; ++g) {
+            long long t = 0;
+            for (int h = 0; h < nphb[b]; ++h) t += cnt[((size_t)b * GW + g) * nph + h];
+            fr = std::max(fr, t);
+        }
+        e.ev_free += fr;
+        for (int h = 0; h < nphb[b]; ++h) {
+            int mx = 0;
+            for (int g = 0; g < ng[b]; ++g) mx = std::max(mx, cnt[((size_t)b * GW + g) * nph + h]);
+            e.ev_barrier += mx;
+        }
+    }
+}
+
 static void build_event_set(bse_ctx *c, int set, int cap, const Bits &nb,
                             const std::vector<int> &pidx) {
     const int no = c->n_occ, BW = K1D_RES_BW, nwd = nb.nwd;
@@ -690,6 +711,7 @@ static void build_event_set(bse_ctx *c, int set, int cap, const Bits &nb,
     for (size_t k = 0; k < ev.size(); k += EV)
         for (int i = 0; i < BW; ++i) e.n_kept += ev[k + i] != zero;
     e.n_staged = no;
+    event_balance(e, phc, 1, ng, nph, std::vector<int>{ng}, std::vector<int>{nph});
     e.ng = ng;
     e.nph = nph;
     e.cap = cap;
@@ -1116,6 +1138,7 @@ static void build_event_blocks(bse_ctx *c, int set, int cap, const Bits &nb,
     e.n_staged = 0;
     for (const Block &K : B)
         for (const auto &ph : K.phases) e.n_staged += (long long)ph.size();
+    event_balance(e, phc, nrb, GW, nph_max, rbng, rbnph);
     e.ng = GW;
     e.nph = nph_max;
     e.cap = cap;
@@ -1644,9 +1667,9 @@ void ctx_set_k1d_shape(bse_ctx *c, int prec, int shape) {
 void ctx_k1d_tables(const bse_ctx *c, int set, long long *st) {
     BSE_REQUIRE(set >= 0 && set < K1D_RES_NSETS, BSE_ERR_ARG, "unknown table set %d", set);
     const PairEvents &e = c->res[set];
-    const long long v[8] = {e.nrb, e.nph, e.cap, e.n_ev, e.n_kept, e.n_staged,
-                            c->n_pairs, (long long)c->n_occ};
-    for (int i = 0; i < 8; ++i) st[i] = v[i];
+    const long long v[10] = {e.nrb,    e.nph,      e.cap,      e.n_ev,       e.n_kept,
+                             e.n_staged, c->n_pairs, c->n_occ, e.ev_barrier, e.ev_free};
+    for (int i = 0; i < 10; ++i) st[i] = v[i];
 }
 
 void ctx_project_c64(bse_ctx *c, int n_vec, double *Y) {

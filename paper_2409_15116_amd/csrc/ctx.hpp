@@ -54,9 +54,13 @@ struct ApplyWs {
     }
 };
 
+constexpr int LEARNED_PMAX = 4;  // partner slots whose windows a slot's features may carry
+
 struct LearnedPre {
     bse_mlp *net = nullptr;    // attached network (not owned)
     int nwg = 0;               // window: G = 0 and the nwg lowest-|G| plane waves
+    int np = 0;                // partner windows per slot in the features (<= LEARNED_PMAX)
+    Dev<int> partner;          // [n_occ][LEARNED_PMAX] nearest other orbitals by centre
     Dev<int> wk;               // half-space index of each window plane wave
     Dev<double> wg;            // its G vector (bohr^-1)
     Dev<double> cen;           // Wannier centres [n_occ][3] (bohr)
@@ -69,7 +73,7 @@ struct LearnedPre {
 struct RecordSpec {
     const double *Xref = nullptr;  // dev [n_ref][n_occ * npw] converged eigenvectors
     int n_ref = 0;
-    float *feat = nullptr;         // dev [max_rows][Kw + 3]
+    float *feat = nullptr;         // dev [max_rows][Kw + 3 + np Kw]
     float *lab = nullptr;          // dev [max_rows][Kw]
     long long max_rows = 0;
     long long n_rows = 0;

@@ -143,13 +143,21 @@ struct Pinned {
 };
 
 struct DavState {
-    bse_ctx *c;
-    long long n;  // n_occ * npw
+    bse_ctx *c = nullptr;
+    long long n = 0;  // n_occ * npw
     Dev<double> V, W, X, R, Tn, tmp, cbuf, gq, minv, keep, coef, sm, part, norms, theta;
     Dev<double> in64, out64;
     Dev<float> in32, out32;
     Pinned up, down;
     int B = 0;  // rows of the fixed apply buffers
+    DavState() = default;
+    DavState(const DavState &) = delete;
+    DavState &operator=(const DavState &) = delete;
+    // queued copies may still read the pinned arena (a solve that ends by
+    // an error): wait for them before the members are freed
+    ~DavState() {
+        if (c) (void)hipStreamSynchronize(c->stream);
+    }
 };
 
 // stream-ordered upload of a small host matrix through the pinned arena (no

@@ -115,6 +115,10 @@ struct PairEvents {
     // table statistics (host): events incl. padding, event entries on a kept
     // pair, a values staged per grid piece and vector group (all blocks)
     long long n_ev = 0, n_kept = 0, n_staged = 0;
+    // critical path in events: sum over row blocks of sum over phases of the
+    // busiest wave's events (the phases end at barriers), and of the busiest
+    // wave's total (what the same lists would cost without barriers)
+    long long ev_barrier = 0, ev_free = 0;
     const int *grp = nullptr;
     const int *gpart = nullptr;
     const int *gslot = nullptr;

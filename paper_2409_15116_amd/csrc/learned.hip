@@ -6,7 +6,9 @@
 // Wannier centre (a phase e^{i G.R_v} per plane wave, so that the map does not
 // depend on where the localised orbital sits) and normalised, plus three
 // scalars (theta - eps_vv, eps_vv - mean V, log |r_v|), to a correction of
-// the diagonally preconditioned residual on the same window.  Trained on
+// the diagonally preconditioned residual on the same window; optionally the
+// features also carry the same trial vector's residual windows at the
+// nearest other orbitals (partner windows).  Trained on
 // (residual, exact-correction) pairs recorded from plain solves; used only
 // behind a safeguard that falls back to the diagonal preconditioner.
 #include <algorithm>
@@ -303,32 +305,44 @@ __global__ void k_centers(const double *__restrict__ u, long long nr, int n, dou
     if (threadIdx.x < 6) out[(size_t)v * 6 + threadIdx.x] = red[threadIdx.x][0] / (double)nr;
 }
 
-// rows = (s, v) of R [k][n_occ][npw]; rn = |r_row|; features [rows][Kw + 3]
+// rows = (s, v) of R [k][n_occ][npw]; rn = |r_row|; features [rows][F],
+// F = Kw + 3 + P Kw: the slot's own window, three scalars, then the windows
+// of its P partner slots (the same trial vector's residual at the orbitals
+// nearest to v, in v's frame and v's scale, so that the map can see the
+// residual the couplings between slots bring in).  P = 0 is the one-slot map.
 __global__ void k_features(const double *__restrict__ R, const double *__restrict__ rn2,
                            const double *__restrict__ theta, const double *__restrict__ epsd,
                            double vbar, const int *__restrict__ wk, const double *__restrict__ wg,
                            const double *__restrict__ cen, int nwg, int n_occ, int npw, int rows,
-                           float *__restrict__ feat) {
+                           int P, const int *__restrict__ partner, float *__restrict__ feat) {
     const int row = blockIdx.x;
     if (row >= rows) return;
     const int s = row / n_occ, v = row - s * n_occ;
-    const int Kw = 1 + 2 * nwg, F = Kw + 3;
+    const int Kw = 1 + 2 * nwg, F = Kw + 3 + P * Kw;
     const double nrm = sqrt(rn2[row]);
     const double inv = nrm > 1e-300 ? 1.0 / nrm : 0.0;
-    const double *r = R + (size_t)row * npw;
     float *f = feat + (size_t)row * F;
-    for (int j = threadIdx.x; j < nwg; j += blockDim.x) {
-        const int k = wk[j];
-        const double ph = wg[3 * j] * cen[3 * v] + wg[3 * j + 1] * cen[3 * v + 1] +
-                          wg[3 * j + 2] * cen[3 * v + 2];
-        double sn, cs;
-        sincos(ph, &sn, &cs);
-        const double re = r[1 + 2 * k], im = r[2 + 2 * k];
-        f[1 + 2 * j] = (float)((re * cs - im * sn) * inv);
-        f[2 + 2 * j] = (float)((re * sn + im * cs) * inv);
+    for (int p = 0; p <= P; ++p) {
+        const int w = p == 0 ? v : partner[(size_t)v * LEARNED_PMAX + p - 1];
+        float *fw = p == 0 ? f : f + Kw + 3 + (p - 1) * Kw;
+        if (w < 0) {  // fewer orbitals than partners
+            for (int j = threadIdx.x; j < Kw; j += blockDim.x) fw[j] = 0.f;
+            continue;
+        }
+        const double *r = R + ((size_t)s * n_occ + w) * npw;
+        for (int j = threadIdx.x; j < nwg; j += blockDim.x) {
+            const int k = wk[j];
+            const double ph = wg[3 * j] * cen[3 * v] + wg[3 * j + 1] * cen[3 * v + 1] +
+                              wg[3 * j + 2] * cen[3 * v + 2];
+            double sn, cs;
+            sincos(ph, &sn, &cs);
+            const double re = r[1 + 2 * k], im = r[2 + 2 * k];
+            fw[1 + 2 * j] = (float)((re * cs - im * sn) * inv);
+            fw[2 + 2 * j] = (float)((re * sn + im * cs) * inv);
+        }
+        if (threadIdx.x == 0) fw[0] = (float)(r[0] * inv);
     }
     if (threadIdx.x == 0) {
-        f[0] = (float)(r[0] * inv);
         f[Kw] = (float)(theta[s] - epsd[v]);
         f[Kw + 1] = (float)(epsd[v] - vbar);
         f[Kw + 2] = (float)log(nrm > 1e-300 ? nrm : 1e-300);
@@ -478,6 +492,28 @@ void learned_setup(bse_ctx *c, int nwg) {
     L.cen.alloc(cen.size());
     BSE_HIP(hipMemcpy(L.cen.p, cen.data(), cen.size() * 8, hipMemcpyHostToDevice));
     L.cen_h = cen;
+    // partners: the LEARNED_PMAX other orbitals with the nearest centres
+    // (minimum image; ties by index), -1 where the cell has fewer
+    const int no = c->n_occ;
+    std::vector<int> part((size_t)no * LEARNED_PMAX, -1);
+    for (int v = 0; v < no; ++v) {
+        std::vector<std::pair<double, int>> d;
+        for (int w = 0; w < no; ++w) {
+            if (w == v) continue;
+            double r2 = 0;
+            for (int a = 0; a < 3; ++a) {
+                double x = cen[(size_t)w * 3 + a] - cen[(size_t)v * 3 + a];
+                x -= c->L * std::round(x / c->L);
+                r2 += x * x;
+            }
+            d.emplace_back(r2, w);
+        }
+        std::sort(d.begin(), d.end());
+        for (int p = 0; p < LEARNED_PMAX && p < (int)d.size(); ++p)
+            part[(size_t)v * LEARNED_PMAX + p] = d[p].second;
+    }
+    L.partner.alloc(part.size());
+    BSE_HIP(hipMemcpy(L.partner.p, part.data(), part.size() * 4, hipMemcpyHostToDevice));
     L.nwg = nwg;
 }
 
@@ -488,20 +524,22 @@ void learned_correction(bse_ctx *c, const double *R, const double *theta, int k,
     bse_mlp *m = L.net;
     if (!m || L.nwg == 0) return;
     const int no = c->n_occ, npw = c->npw, rows = k * no, nwg = L.nwg, Kw = 1 + 2 * nwg;
-    BSE_REQUIRE(m->F == Kw + 3 && m->K == Kw, BSE_ERR_STATE,
-                "network shape (%d -> %d) does not match the window (%d)", m->F, m->K, Kw);
+    const int F = Kw + 3 + L.np * Kw;
+    BSE_REQUIRE(m->F == F && m->K == Kw, BSE_ERR_STATE,
+                "network shape (%d -> %d) does not match the window (%d in, %d out)", m->F, m->K,
+                F, Kw);
     hipStream_t st = c->stream;
     m->stream = st;
     L.rn2.alloc(rows);
     L.part.alloc((size_t)rows * 256);
     row_norm2(R, npw, rows, L.part.p, L.rn2.p, st);
-    L.feat.alloc((size_t)rows * (Kw + 3));
+    L.feat.alloc((size_t)rows * F);
     L.out.alloc((size_t)rows * Kw);
     L.D.alloc((size_t)rows * Kw);
     L.stats.alloc((size_t)rows * 4);
     L.ok.alloc(rows);
     k_features<<<rows, 128, 0, st>>>(R, L.rn2.p, theta, c->epsd.p, c->vbar, L.wk.p, L.wg.p, L.cen.p,
-                                     nwg, no, npw, rows, L.feat.p);
+                                     nwg, no, npw, rows, L.np, L.partner.p, L.feat.p);
     BSE_LAUNCH_CHECK();
     mlp_forward(m, rows, L.feat.p, L.out.p);
     k_correction<<<rows, 256, 0, st>>>(L.out.p, L.rn2.p, R, Tn, L.wk.p, L.wg.p, L.cen.p, nwg, no,
@@ -598,10 +636,10 @@ void learned_record(bse_ctx *c, const double *X, const double *R, const double *
     L.rn2.alloc(rows);
     L.part.alloc((size_t)rows * 256);
     row_norm2(R, npw, rows, L.part.p, L.rn2.p, st);
-    float *f = feat + (size_t)(*n_rows) * (Kw + 3);
+    float *f = feat + (size_t)(*n_rows) * (Kw + 3 + L.np * Kw);
     float *l = lab + (size_t)(*n_rows) * Kw;
     k_features<<<rows, 128, 0, st>>>(R, L.rn2.p, theta, c->epsd.p, c->vbar, L.wk.p, L.wg.p, L.cen.p,
-                                     nwg, no, npw, rows, f);
+                                     nwg, no, npw, rows, L.np, L.partner.p, f);
     BSE_LAUNCH_CHECK();
     k_labels<<<rows, 128, 0, st>>>(Ts.p, Tn, al.p, L.rn2.p, L.wk.p, L.wg.p, L.cen.p, nwg, no, npw,
                                    rows, l);
@@ -778,12 +816,23 @@ bse_status bse_set_learned(bse_ctx *c, bse_mlp *m, int n_window_pw) {
             return BSE_OK;
         }
         bse::learned_setup(c, n_window_pw);
-        const int Kw = 1 + 2 * n_window_pw;
-        BSE_REQUIRE(m->F == Kw + 3 && m->K == Kw, BSE_ERR_ARG,
-                    "network (%d -> %d) does not fit a %d-plane-wave window (%d -> %d)", m->F, m->K,
-                    n_window_pw, Kw + 3, Kw);
+        const int Kw = 1 + 2 * n_window_pw, F = Kw + 3 + c->lp.np * Kw;
+        BSE_REQUIRE(m->F == F && m->K == Kw, BSE_ERR_ARG,
+                    "network (%d -> %d) does not fit a %d-plane-wave window with %d partner "
+                    "windows (%d -> %d)", m->F, m->K, n_window_pw, c->lp.np, F, Kw);
         c->lp.net = m;
     })
+}
+
+bse_status bse_set_learned_partners(bse_ctx *c, int n_partners) {
+    if (!c || n_partners < 0 || n_partners > bse::LEARNED_PMAX) {
+        set_error("bse_set_learned_partners: null context or n_partners outside [0, %d]",
+                  bse::LEARNED_PMAX);
+        return BSE_ERR_ARG;
+    }
+    c->lp.np = n_partners;
+    c->lp.net = nullptr;  // an attached network was shaped for the previous count
+    return BSE_OK;
 }
 
 bse_status bse_learned_centers(bse_ctx *c, double *centers) {

@@ -94,6 +94,7 @@ def load():
         "bse_mlp_gradients": (i32, [vp, i32, vp, vp, vp, vp]),
         "bse_mlp_train": (i32, [vp, i32, vp, vp, i32, i32, C.c_float, C.c_uint64, vp]),
         "bse_set_learned": (i32, [vp, vp, i32]),
+        "bse_set_learned_partners": (i32, [vp, i32]),
         "bse_learned_centers": (i32, [vp, vp]),
         "bse_davidson_record": (i32, [vp, C.POINTER(DavidsonOpts), vp, vp, i32, i32, vp, vp, i64,
                                       C.POINTER(i64), vp, vp, C.POINTER(DavidsonStats)]),
@@ -127,7 +128,8 @@ def exported_symbols():
             "bse_last_error", "bse_debug_to_grid", "bse_debug_gemm", "bse_debug_k1d_tables", "bse_profile_apply",
             "bse_mlp_create", "bse_mlp_destroy", "bse_mlp_num_params", "bse_mlp_get_weights",
             "bse_mlp_set_weights", "bse_mlp_forward", "bse_mlp_forward_noalloc", "bse_mlp_gradients", "bse_mlp_train",
-            "bse_set_learned", "bse_learned_centers", "bse_davidson_record",
+            "bse_set_learned", "bse_set_learned_partners", "bse_learned_centers",
+            "bse_davidson_record",
             "bse_lanczos", "bse_lanczos_spectrum",
             "bse_spread_matrices", "bse_jade", "bse_localize",
             "bse_k1d_num_shapes", "bse_k1d_shape_info", "bse_autotune", "bse_set_k1d_shape",
@@ -191,10 +193,10 @@ class BseContext:
 
     def k1d_tables(self, set_=0):
         """Statistics of the resident K1d tables (bse_debug_k1d_tables)."""
-        st = np.zeros(8, dtype=np.int64)
+        st = np.zeros(10, dtype=np.int64)
         _check(load().bse_debug_k1d_tables(self.h, int(set_), st.ctypes.data))
         keys = ("row_blocks", "phases", "cap", "events", "kept_entries", "staged", "pairs",
-                "n_occ")
+                "n_occ", "critical_events_barriers", "critical_events_free")
         return dict(zip(keys, map(int, st)))
 
     def set_spin(self, n_up):
@@ -333,8 +335,15 @@ class BseContext:
         _check(load().bse_apply_chunk(self.h, int(n_vec), int(precision), C.byref(out)))
         return out.value
 
-    def set_learned(self, mlp, n_window_pw):
+    def set_learned(self, mlp, n_window_pw, n_partners=None):
+        """Attach (or detach with None) the learned preconditioner's network;
+        n_partners (if given) first sets the partner windows per slot."""
+        if n_partners is not None:
+            self.set_learned_partners(n_partners)
         _check(load().bse_set_learned(self.h, mlp.h if mlp is not None else None, n_window_pw))
+
+    def set_learned_partners(self, n_partners):
+        _check(load().bse_set_learned_partners(self.h, int(n_partners)))
 
     def learned_centers(self):
         out = np.empty((self.n_occ, 3))
@@ -343,12 +352,16 @@ class BseContext:
 
     def davidson_record(self, X0, Xref, n_eig, n_window_pw, max_rows, *, block=None,
                         max_basis=0, restart=0, max_iter=200, precision=FP64, tol=1e-6,
-                        delta=0.05):
-        """Plain Davidson that records (features, labels) rows for training."""
+                        delta=0.05, n_partners=0):
+        """Plain Davidson that records (features, labels) rows for training;
+        features carry n_partners partner windows after the own window and
+        the three scalars."""
         torch = self.torch
         B = block or X0.shape[0]
         kw = 1 + 2 * n_window_pw
-        feat = torch.zeros((max_rows, kw + 3), dtype=torch.float32, device="cuda")
+        self.set_learned_partners(n_partners)
+        feat = torch.zeros((max_rows, kw + 3 + n_partners * kw), dtype=torch.float32,
+                           device="cuda")
         lab = torch.zeros((max_rows, kw), dtype=torch.float32, device="cuda")
         o = DavidsonOpts(n_eig, B, max_basis, restart, max_iter, precision, tol, delta, 0, 0)
         om = np.zeros(n_eig)

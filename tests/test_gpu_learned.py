@@ -137,9 +137,63 @@ def _plain_and_record(pkg, name, n_eig=4, block=8):
     return c, ctx, X0, om, feat, lab, st2["iterations"]
 
 
+def test_partner_windows_in_recorded_features():
+    """Rows recorded with 2 partner windows: the first Kw + 3 columns equal
+    the one-slot rows of the same (deterministic) solve, and each partner
+    window is the residual window of the nearest other orbital (by Wannier
+    centre, minimum image) of the same trial vector, in v's frame: per plane
+    wave its modulus times |r_v| equals the modulus of that orbital's own
+    window times |r_w| (a phase shift keeps moduli), its G = 0 entry the
+    same (no phase)."""
+    say("partner windows")
+    pkg = _pkg()
+    c = make_cell("c1j_00")
+    ctx = pkg.context_for(c)
+    pkg.setup_pairs_and_screen(ctx, c, precision=pkg.FP64)
+    X0 = torch.from_numpy(trial_block(c, 8, seed=31)).cuda()
+    om, X, _ = ctx.davidson(X0, 4, block=8, tol=1e-9, max_iter=400)
+    f0, l0, _, _ = ctx.davidson_record(X0, X.contiguous(), 4, NWG, 200000, block=8, tol=1e-7,
+                                       max_iter=400, n_partners=0)
+    f2, l2, _, _ = ctx.davidson_record(X0, X.contiguous(), 4, NWG, 200000, block=8, tol=1e-7,
+                                       max_iter=400, n_partners=2)
+    f0, f2 = f0.cpu().numpy().astype(np.float64), f2.cpu().numpy().astype(np.float64)
+    assert f2.shape == (f0.shape[0], F_IN + 2 * KW)
+    assert np.array_equal(f2[:, :F_IN], f0) and torch.equal(l0, l2)
+    cen = ctx.learned_centers()
+    no, L = c.n_occ, c.L
+    d = cen[None, :, :] - cen[:, None, :]
+    d -= L * np.round(d / L)
+    r2 = (d ** 2).sum(-1)
+    np.fill_diagonal(r2, np.inf)
+    nearest = np.argsort(r2, axis=1, kind="stable")[:, :2]
+    nrm = np.exp(f2[:, KW + 2])                      # |r_row| from the log-norm feature
+    checked = 0
+    for row in range(f2.shape[0]):
+        v = row % no
+        for p in range(2):
+            w = nearest[v, p]                        # ties by index, as the library
+            roww = row - v + w
+            fp = f2[row, F_IN + p * KW: F_IN + (p + 1) * KW] * nrm[row]
+            fw = f2[roww, :KW] * nrm[roww]
+            scale = np.abs(fw).max() + 1e-30
+            assert abs(fp[0] - fw[0]) <= 1e-5 * scale
+            mp = fp[1::2] ** 2 + fp[2::2] ** 2
+            mw = fw[1::2] ** 2 + fw[2::2] ** 2
+            assert np.abs(mp - mw).max() <= 1e-5 * scale ** 2
+            checked += 1
+    assert checked > 0
+    ctx.close()
+
+
 def test_learned_preconditioner_on_jittered_cells():
-    """Train on 6 jittered 8-well snapshots, test on 2 others: the learned
-    correction may only change the iteration count."""
+    """Train on 6 jittered 8-well snapshots, test on 2 others.  The network
+    does not lower the iteration count here (nor on the 64-well snapshots of
+    bench.py --learned): it sees one orbital slot's residual window at a
+    time, while the diagonal preconditioner's main error is the coupling
+    between slots.  What the test pins is what the method guarantees: the
+    converged eigenvalues are unchanged and the progress fallback bounds the
+    cost of a poor correction (at most 5 extra iterations); the measured
+    gains (negative or zero) are printed."""
     say("learned preconditioner")
     pkg = _pkg()
     feats, labs = [], []
