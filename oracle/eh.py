@@ -175,6 +175,37 @@ def eh_hamiltonian_spin(L, n, miller, V, phi, lam, n_up, n_down, *, k1d=1.0):
     return 0.5 * (Heh + Heh.T), eps, X, dims
 
 
+def eh_hamiltonian_spinflip(L, n, miller, V, phi, lam, n_h, n_e, *, k1d=1.0, delta=0.0):
+    """Explicit spin-flip TDA e-h Hamiltonian: holes in the n_h lowest states
+    of one spin, electrons in the states of the other spin above its n_e
+    occupied ones (the same discretised H for both spins, the other spin's
+    levels shifted by delta):
+
+      H^eh = (eps_c + delta - eps_v) delta_vv' delta_cc'
+             - int int rho_{cc'} W rho_{vv'}
+
+    (no exchange-like term: the transition density mixes the spins).
+    Returns (Heh, eps, X) with (v, c) row-major."""
+    H, E = dense_hamiltonian(L, n, miller, V)
+    eps, X = np.linalg.eigh(H)
+    u = X.T @ E
+    nr = E.shape[1]
+    omega = L ** 3
+    uo, ue = u[:n_h], u[n_e:]
+    ne = ue.shape[0]
+    Heh = np.diag((eps[n_e:][None, :] + delta - eps[:n_h][:, None]).reshape(-1))
+    if k1d != 0.0:
+        Wm = dense_w(L, n, miller, phi, lam)
+        for v in range(n_h):
+            for w in range(n_h):
+                rho = (uo[v] * uo[w]).reshape(n, n, n) / omega
+                Fr = np.fft.fftn(rho).reshape(-1) / nr
+                tau = (np.fft.ifftn((Wm @ Fr).reshape(n, n, n)) * nr).real.reshape(-1)
+                M = (ue * tau[None, :]) @ ue.T / nr
+                Heh[v * ne:(v + 1) * ne, w * ne:(w + 1) * ne] -= k1d * M
+    return 0.5 * (Heh + Heh.T), eps, X
+
+
 def eh_coupling(L, n, miller, V, phi, lam, n_occ, *, k1e=2.0, k1d=1.0):
     """Coupling block of the full (non-TDA) e-h BSE over all empty states,
     in the (v, c) row-major basis of eh_hamiltonian:

@@ -1,4 +1,5 @@
-"""Oracle: the spin-polarised, spin-conserving TDA Liouville operator.
+"""Oracle: the spin-polarised TDA Liouville operator, spin-conserving
+(SpinLiouvilleOracle) and spin-flip (SpinFlipOracle, reading below).
 
 Test infrastructure: only the tests, the smoke check and the benchmark's CPU
 baseline use this package.
@@ -93,4 +94,63 @@ class SpinLiouvilleOracle:
         return np.concatenate([op.diag_estimate() for op in self.ch], axis=0)
 
 
-__all__ = ["SpinLiouvilleOracle", "Basis"]
+class SpinFlipOracle:
+    """The spin-flip channel (Sec. 2 lists it beside the spin-conserving one;
+    Sec. 5 obtains the singlet states of the NV and SiV centres with it; the
+    paper prints no separate equation).  The oracle's reading: a
+    spin-flip excitation moves an electron from an occupied orbital of one
+    spin (the holes: psi_v, N_h of them, energies eps, pairs and tau of that
+    spin) into an empty state of the other spin.  Its response a_v lives in
+    the other spin's empty space, so the projector is that of the other
+    spin's occupied orbitals phi_w; the transition density psi_v a_v mixes
+    the spins and has no Hartree response (no K1e), and the direct term
+    screens the hole pair densities psi_v psi_v' of the hole spin:
+
+      (L A)_v = Q_c [ H a_v - sum_v' eps_{vv'} a_v' + Delta a_v
+                      - sum_{v' in N(v)} tau_{vv'} a_v' ],
+      Q_c = 1 - sum_w |phi_w><phi_w|.
+
+    With one H for both spins (the model Hamiltonian has no spin
+    dependence), Delta is a constant shift of the other spin's levels (an
+    exchange splitting; the operator's scissor).  ``holes`` is the closed-
+    shell operator of the hole spin (its k1e is not used)."""
+
+    def __init__(self, holes: LiouvilleOracle, phi: np.ndarray, *, k1d=1.0, delta=0.0):
+        self.h = holes
+        self.b = holes.b
+        self.phi = np.asarray(phi, dtype=np.float64)
+        self.n_occ = holes.n_occ
+        self.k1d = float(k1d)
+        self.delta = float(delta)
+
+    def project_c(self, Y: np.ndarray) -> np.ndarray:
+        """Q_c: the other spin's occupied orbitals projected out of every slot."""
+        S = np.einsum("...vg,wg->...vw", Y, self.phi)
+        return Y - np.einsum("...vw,wg->...vg", S, self.phi)
+
+    def apply(self, X: np.ndarray) -> np.ndarray:
+        """L on a block X [B, N_h, npw] (or one vector)."""
+        single = X.ndim == 2
+        if single:
+            X = X[None]
+        b, h = self.b, self.h
+        out = np.empty_like(X, dtype=np.float64)
+        for s in range(X.shape[0]):
+            a = b.to_grid(X[s])
+            f = h.V[None] * a
+            if self.k1d != 0.0:
+                for p, (v, w) in enumerate(h.pairs):
+                    f[v] -= self.k1d * h.tau[p] * a[w]
+                    if w != v:
+                        f[w] -= self.k1d * h.tau[p] * a[v]
+            Y = b.to_sphere(f) + 0.5 * b.g2_packed[None] * X[s]
+            Y = Y - h.eps @ X[s] + self.delta * X[s]
+            out[s] = self.project_c(Y)
+        return out[0] if single else out
+
+    def diag_estimate(self) -> np.ndarray:
+        vbar = float(self.h.V.mean())
+        return 0.5 * self.b.g2_packed[None, :] + vbar - np.diag(self.h.eps)[:, None] + self.delta
+
+
+__all__ = ["SpinLiouvilleOracle", "SpinFlipOracle", "Basis"]

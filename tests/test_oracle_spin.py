@@ -102,3 +102,58 @@ def test_spin_operator_output_in_each_channels_pc_space(tiny):
     Y = op.apply(rng.standard_normal((2, n_up + n_dn, X.shape[0])))
     assert np.abs(Y[:, :n_up] @ up.psi.T).max() < 1e-12 * np.abs(Y).max()
     assert np.abs(Y[:, n_up:] @ dn.psi.T).max() < 1e-12 * np.abs(Y).max()
+
+
+def _flip_matrix(op, X, n_h, n_e):
+    """Matrix of the spin-flip operator in the basis of single transitions:
+    slot v (a hole of one spin) holding empty state c >= n_e of the other."""
+    npw = X.shape[0]
+    cols = []
+    for v in range(n_h):
+        for cidx in range(n_e, npw):
+            q = np.zeros((n_h, npw))
+            q[v] = X[:, cidx]
+            cols.append(q)
+    Q = np.stack(cols)
+    LQ = np.concatenate([op.apply(Q[i:i + 256]) for i in range(0, len(Q), 256)])
+    return np.einsum("ivg,jvg->ij", Q, LQ)
+
+
+@pytest.mark.parametrize("k1d,delta", [(1.0, 0.0), (1.0, 0.05), (0.0, 0.0)])
+def test_spin_flip_matches_explicit_eh(tiny, k1d, delta):
+    """Spin-flip operator with holes in the 8 lowest up states and electrons
+    above the 7 lowest down states against the explicit spin-flip e-h
+    Hamiltonian (direct term only, other spin shifted by delta): same
+    spectrum to 1e-10 Ha; without K1d it is {eps_c + delta - eps_v}, and a
+    hole in the 8th state flipped into the (empty) 8th down state costs
+    delta there."""
+    from oracle.eh import eh_hamiltonian_spinflip
+    from oracle.spin import SpinFlipOracle
+    c, b = tiny
+    n_h, n_e = 8, 7
+    Heh, eps, X = eh_hamiltonian_spinflip(c.L, c.n, c.miller, c.V, c.phi, c.lam, n_h, n_e,
+                                          k1d=k1d, delta=delta)
+    holes = _channel(c, b, X, n_h, eps)
+    phi = np.ascontiguousarray(X[:, :n_e].T)
+    op = SpinFlipOracle(holes, phi, k1d=k1d, delta=delta)
+    M = _flip_matrix(op, X, n_h, n_e)
+    assert M.shape == Heh.shape
+    assert np.abs(M - M.T).max() <= 1e-12 * np.abs(M).max()
+    e1 = np.linalg.eigvalsh(0.5 * (M + M.T))
+    e2 = np.linalg.eigvalsh(Heh)
+    assert np.abs(e1 - e2).max() < 1e-10
+    if k1d == 0.0:
+        de = np.sort((eps[n_e:][None, :] + delta - eps[:n_h][:, None]).reshape(-1))
+        assert np.abs(e1 - de).max() < 1e-10
+        assert abs(e1.min() - (eps[n_e] + delta - eps[n_h - 1])) < 1e-10
+
+
+def test_spin_flip_output_in_other_spins_pc_space(tiny):
+    from oracle.spin import SpinFlipOracle
+    c, b = tiny
+    from oracle.eh import eh_hamiltonian_spinflip
+    _, eps, X = eh_hamiltonian_spinflip(c.L, c.n, c.miller, c.V, c.phi, c.lam, 8, 7, k1d=0.0)
+    op = SpinFlipOracle(_channel(c, b, X, 8, eps), np.ascontiguousarray(X[:, :7].T))
+    rng = np.random.default_rng(9)
+    Y = op.apply(rng.standard_normal((2, 8, X.shape[0])))
+    assert np.abs(Y @ X[:, :7]).max() < 1e-12 * np.abs(Y).max()
