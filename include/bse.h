@@ -109,6 +109,24 @@ bse_status bse_set_terms(bse_ctx *ctx, double k1e, double k1d, double scissor);
  * 1 <= n_up <= n_occ. */
 bse_status bse_set_spin(bse_ctx *ctx, int n_up);
 
+/* Spin-flip channel (Sec. 2 lists it beside the spin-conserving one; Sec. 5
+ * obtains the NV and SiV singlets with it).  The context's orbitals are the
+ * occupied orbitals of the hole spin (their energies, pairs and tau as
+ * usual); the responses live in the other spin's empty space, so P_c becomes
+ *   P_c = 1 - sum_w |phi_w><phi_w|
+ * over the other spin's occupied orbitals phi, and the transition densities
+ * mix the spins: call bse_set_terms(k1e = 0, k1d = 1, scissor = Delta),
+ * Delta a constant shift of the other spin's levels (an exchange splitting
+ * when one H serves both spins).  The apply is then
+ *   (L A)_v = P_c [ (H - eps + Delta) a_v - sum_{v' in N(v)} tau_{vv'} a_v' ].
+ *   phi  dev [n_proj][n_pw] FP64, caller-owned, copied; orthonormal (checked
+ *        to 1e-8, else BSE_ERR_ARG); n_proj <= n_occ (the hole spin holds
+ *        at least as many electrons); n_proj = 0 (phi may be NULL) returns
+ *        to the context's own orbitals.
+ * Drops a captured graph; keeps pairs and tau.  BSE_ERR_STATE with two spin
+ * channels set (bse_set_spin). */
+bse_status bse_set_projector(bse_ctx *ctx, const double *phi, int n_proj);
+
 /* Wannier localisation (Sec. 2, Eq. wannier, Eq. spread).  The usual order is
  * bse_create with canonical orbitals, bse_spread_matrices, bse_jade,
  * bse_localize, then bse_build_pairs.

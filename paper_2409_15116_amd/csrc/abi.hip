@@ -100,6 +100,11 @@ bse_status bse_set_spin(bse_ctx *c, int n_up) {
     BSE_GUARD(bse::ctx_set_spin(c, n_up))
 }
 
+bse_status bse_set_projector(bse_ctx *c, const double *phi, int n_proj) {
+    CHECK_CTX(c);
+    BSE_GUARD(bse::ctx_set_projector(c, phi, n_proj))
+}
+
 bse_status bse_pair_measure(bse_ctx *c, int measure, double *m) {
     CHECK_CTX(c);
     if (!m) {

@@ -174,6 +174,8 @@ void ctx_set_terms(bse_ctx *c, double k1e, double k1d, double scissor) {
 void ctx_set_spin(bse_ctx *c, int n_up) {
     BSE_REQUIRE(n_up >= 1 && n_up <= c->n_occ, BSE_ERR_ARG,
                 "n_up must be in [1, n_occ = %d], got %d", c->n_occ, n_up);
+    BSE_REQUIRE(c->n_proj == 0 || n_up >= c->n_occ, BSE_ERR_STATE,
+                "two spin channels and a spin-flip projector exclude each other");
     c->n_up = n_up >= c->n_occ ? 0 : n_up;
     c->pairs_h.clear();
     c->cp_items_h.clear();
@@ -182,6 +184,48 @@ void ctx_set_spin(bse_ctx *c, int n_up) {
     c->tau64.free();
     c->tau32.free();
     drop_graph(c);
+}
+
+// The spin-flip channel's projector: the other spin's occupied orbitals phi
+// (device FP64 [n_proj][npw], orthonormal, checked to 1e-8), copied.
+void ctx_set_projector(bse_ctx *c, const double *phi, int n_proj) {
+    BSE_REQUIRE(c->n_up == 0, BSE_ERR_STATE,
+                "two spin channels and a spin-flip projector exclude each other");
+    BSE_REQUIRE(n_proj >= 0 && n_proj <= c->n_occ && (n_proj == 0 || phi), BSE_ERR_ARG,
+                "need 0 <= n_proj <= n_occ = %d (got %d) and orbitals when n_proj > 0", c->n_occ,
+                n_proj);
+    drop_graph(c);
+    if (n_proj == 0) {
+        c->n_proj = 0;
+        c->proj64.free();
+        c->proj32.free();
+        return;
+    }
+    const int npw = c->npw;
+    const size_t len = (size_t)n_proj * npw;
+    c->proj64.alloc(len);
+    c->proj32.alloc(len);
+    BSE_HIP(hipMemcpyAsync(c->proj64.p, phi, len * 8, hipMemcpyDeviceToDevice, c->stream));
+    convert<double, float>(c->proj64.p, c->proj32.p, (long long)len, c->stream);
+    Dev<double> G;
+    G.alloc((size_t)n_proj * n_proj);
+    gemm<double>(true, n_proj, n_proj, npw, 1.0, c->proj64.p, npw, 0, c->proj64.p, npw, 0, 0.0, G.p,
+                 n_proj, 0, 1, c->gws, c->stream);
+    std::vector<double> g((size_t)n_proj * n_proj);
+    BSE_HIP(hipMemcpyAsync(g.data(), G.p, g.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    BSE_HIP(hipStreamSynchronize(c->stream));
+    double dev = 0;
+    for (int i = 0; i < n_proj; ++i)
+        for (int j = 0; j < n_proj; ++j)
+            dev = std::max(dev, std::fabs(g[(size_t)i * n_proj + j] - (i == j ? 1.0 : 0.0)));
+    if (!(dev < 1e-8)) {
+        c->proj64.free();
+        c->proj32.free();
+        c->n_proj = 0;
+        BSE_REQUIRE(false, BSE_ERR_ARG, "projector orbitals are not orthonormal (|G - I| = %.3g)",
+                    dev);
+    }
+    c->n_proj = n_proj;
 }
 
 void ctx_setup(bse_ctx *c, const bse_cell *cell, const double *psi, const double *eps,
@@ -1431,6 +1475,13 @@ static int ensure_ws_chunk(bse_ctx *c, ApplyWs<T> &w, int nvec) {
 template <typename T>
 static void project_c(bse_ctx *c, bool bf, int norb, T *Y, T *S, const T *psi, Workspace &ws) {
     const int no = c->n_occ, npw = c->npw;
+    if (c->n_proj > 0) {  // spin flip: the other spin's occupied orbitals (n_proj <= no)
+        const int np = c->n_proj;
+        const T *P = sizeof(T) == 8 ? (const T *)c->proj64.p : (const T *)c->proj32.p;
+        gemm_p<T>(c, bf, true, norb, np, npw, (T)1, Y, npw, 0, P, npw, 0, (T)0, S, np, 0, 1, ws);
+        gemm_p<T>(c, bf, false, norb, npw, np, (T)-1, S, np, 0, P, npw, 0, (T)1, Y, npw, 0, 1, ws);
+        return;
+    }
     if (c->n_up <= 0 || c->n_up >= no) {
         gemm_p<T>(c, bf, true, norb, no, npw, (T)1, Y, npw, 0, psi, npw, 0, (T)0, S, no, 0, 1, ws);
         gemm_p<T>(c, bf, false, norb, npw, no, (T)-1, S, no, 0, psi, npw, 0, (T)1, Y, npw, 0, 1,

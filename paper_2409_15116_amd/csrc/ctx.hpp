@@ -104,6 +104,11 @@ struct bse_ctx {
     double vbar = 0;
     double k1e = 2.0, k1d = 1.0, scissor = 0.0;
     int n_up = 0;  // spin-up slots when two channels are set (0: one channel)
+    // spin-flip projector: P_c = 1 - sum_w |phi_w><phi_w| over these n_proj
+    // orbitals instead of the context's own (0: the context's orbitals)
+    int n_proj = 0;
+    bse::Dev<double> proj64;
+    bse::Dev<float> proj32;
     // pairs and tau
     std::vector<int> pairs_h;  // [P][2]
     bse::Dev<int2> pairs_d;
@@ -179,6 +184,7 @@ void ctx_jade(bse_ctx *c, int N, int nm, double *A, double *Q, int start_given, 
 void ctx_localize(bse_ctx *c, const double *Q);
 void ctx_set_terms(bse_ctx *c, double k1e, double k1d, double scissor);
 void ctx_set_spin(bse_ctx *c, int n_up);
+void ctx_set_projector(bse_ctx *c, const double *phi, int n_proj);
 void ctx_measure(bse_ctx *c, int kind, double *m_host);
 void ctx_build_pairs(bse_ctx *c, int kind, double thr);
 void ctx_screen(bse_ctx *c, const double *phi, const double *lam, int n_pdep, int prec);

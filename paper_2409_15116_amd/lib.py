@@ -63,6 +63,7 @@ def load():
         "bse_destroy": (i32, [vp]),
         "bse_set_terms": (i32, [vp, dbl, dbl, dbl]),
         "bse_set_spin": (i32, [vp, i32]),
+        "bse_set_projector": (i32, [vp, vp, i32]),
         "bse_pair_measure": (i32, [vp, i32, vp]),
         "bse_build_pairs": (i32, [vp, i32, dbl, C.POINTER(i64)]),
         "bse_spread_matrices": (i32, [vp, vp]),
@@ -122,7 +123,8 @@ def load():
 
 
 def exported_symbols():
-    return ["bse_create", "bse_destroy", "bse_set_terms", "bse_set_spin", "bse_pair_measure", "bse_build_pairs",
+    return ["bse_create", "bse_destroy", "bse_set_terms", "bse_set_spin", "bse_set_projector",
+            "bse_pair_measure", "bse_build_pairs",
             "bse_threshold_for_fraction", "bse_get_pairs", "bse_screen_pairs", "bse_copy_tau",
             "bse_apply_liouville", "bse_apply_coupling", "bse_davidson_full", "bse_apply_chunk", "bse_set_graph", "bse_davidson", "bse_status_str",
             "bse_last_error", "bse_debug_to_grid", "bse_debug_gemm", "bse_debug_k1d_tables", "bse_profile_apply",
@@ -198,6 +200,15 @@ class BseContext:
         keys = ("row_blocks", "phases", "cap", "events", "kept_entries", "staged", "pairs",
                 "n_occ", "critical_events_barriers", "critical_events_free")
         return dict(zip(keys, map(int, st)))
+
+    def set_projector(self, phi):
+        """Spin-flip channel: P_c projects out these orbitals (device FP64
+        [n_proj, npw]) instead of the context's own; None returns to them."""
+        if phi is None:
+            _check(load().bse_set_projector(self.h, None, 0))
+            return
+        _dptr(phi, self.torch.float64, (phi.shape[0], self.npw))
+        _check(load().bse_set_projector(self.h, C.c_void_p(phi.data_ptr()), int(phi.shape[0])))
 
     def set_spin(self, n_up):
         """Slots [0, n_up) spin up, the rest spin down (n_up = n_occ: one channel)."""

@@ -8,7 +8,15 @@ builds one closed-shell operator per channel and couples them through the
 total density.  Apply parity in FP64 / FP32 / BF16x3 (1e-11 / 2e-5 / 1e-4 of
 the largest reference entry) with the default and the autotuned K1d shape,
 output in each channel's P_c space, and the 4 lowest excitations of a
-Davidson solve (FP64 and FP32) within 1 meV of the oracle's Davidson."""
+Davidson solve (FP64 and FP32) within 1 meV of the oracle's Davidson.
+
+The spin-flip channel on the same cell: holes in the 8 up orbitals (their
+energies, 40 % of their pairs), responses in the down spin's empty space
+(bse_set_projector with the 7 down orbitals), no K1e, the down levels
+shifted by 0.1 Ha (scissor).  Apply parity against the oracle's
+SpinFlipOracle (pinned to the explicit spin-flip e-h Hamiltonian) at the
+same bars, output orthogonal to the down orbitals, and the 4 lowest
+excitations of a Davidson solve within 1 meV of the oracle's."""
 import numpy as np
 import pytest
 
@@ -107,3 +115,111 @@ def test_spin_davidson_matches_oracle(spin_case):
         Xh = X.cpu().numpy()
         assert np.abs(Xh[:, :N_UP] @ psi[:N_UP].T).max() < 1e-8
         assert np.abs(Xh[:, N_UP:] @ psi[N_UP:].T).max() < 1e-8
+
+
+DELTA = 0.1
+
+
+@pytest.fixture(scope="module")
+def flip_case():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle.liouville import Basis, LiouvilleOracle
+    from oracle.pairs import MEASURE_ABS_L1, build_pairs, pair_measure, threshold_for_fraction
+    from oracle.screening import screened_integrals
+    from oracle.spin import SpinFlipOracle
+    from synth import spin_channels
+    c = cell("c1")
+    _, _, ch = spin_channels(c, N_UP, N_DN)
+    (pu, eu), (pd, _) = ch
+    b = Basis(c.L, c.n, c.miller)
+    u = b.to_grid(pu)
+    m = pair_measure(u, MEASURE_ABS_L1)
+    thr = threshold_for_fraction(m, 0.4)
+    pr = build_pairs(m, thr)
+    holes = LiouvilleOracle(b, pu, eu, c.V, pr, screened_integrals(b, u, pr, c.phi, c.lam))
+    op = SpinFlipOracle(holes, pd, k1d=1.0, delta=DELTA)
+    return c, pu, eu, pd, thr, pr, op
+
+
+def _flip_ctx(pkg, c, pu, eu, pd, thr, prec, stream=None):
+    psi_d = torch.from_numpy(np.ascontiguousarray(pu)).to("cuda")
+    V_d = torch.from_numpy(np.ascontiguousarray(c.V.reshape(-1))).to("cuda")
+    ctx = pkg.BseContext(c.L, c.n, c.miller, psi_d, eu, V_d, stream=stream)
+    ctx.set_terms(k1e=0.0, k1d=1.0, scissor=DELTA)
+    ctx.set_projector(torch.from_numpy(np.ascontiguousarray(pd)).to("cuda"))
+    ctx.build_pairs(pkg.MEASURE_ABS_L1, thr)
+    phi = torch.from_numpy(np.ascontiguousarray(c.phi)).to("cuda")
+    ctx.screen_pairs(phi, c.lam, prec)
+    return ctx
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 2e-5), (2, 1e-4)])
+def test_spin_flip_apply_matches_oracle(flip_case, prec, tol):
+    import paper_2409_15116_amd as pkg
+    from synth import random_block
+    c, pu, eu, pd, thr, pr, op = flip_case
+    say("spin flip apply", prec)
+    ctx = _flip_ctx(pkg, c, pu, eu, pd, thr, prec)
+    assert [tuple(p) for p in ctx.get_pairs()] == pr
+    X = random_block((3, N_UP, c.npw), seed=37) / (1.0 + 0.5 * c.g2)[None, None, :]
+    ref = op.apply(X)
+    dt = torch.float64 if prec == 0 else torch.float32
+    for tune in (False, True):
+        if tune:
+            shape, _ = ctx.autotune(3, prec, n_rep=1)
+            say("  autotuned K1d shape", shape)
+        Y = torch.empty((3, N_UP, c.npw), dtype=dt, device="cuda")
+        ctx.apply(torch.from_numpy(X).to("cuda", dtype=dt), Y, prec)
+        got = Y.double().cpu().numpy()
+        assert rel_err(got, ref) < tol, tune
+        # the responses live in the down spin's empty space
+        assert np.abs(got @ pd.T).max() < (1e-12 if prec == 0 else 1e-5) * np.abs(got).max()
+    ctx.close()
+
+
+def test_spin_flip_davidson_matches_oracle(flip_case):
+    import paper_2409_15116_amd as pkg
+    from oracle.davidson import davidson
+    from synth import random_block
+    c, pu, eu, pd, thr, pr, op = flip_case
+    X0 = random_block((4, N_UP, c.npw), seed=4321)
+    om_o, _, it, _ = davidson(op.apply, op.project_c, op.diag_estimate(), X0, 4, tol=1e-7)
+    say("spin flip davidson: oracle", om_o, it, "iterations")
+    for prec in (0, 1):
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            ctx = _flip_ctx(pkg, c, pu, eu, pd, thr, prec, stream=st)
+            ctx.set_graph(True)
+            om, X, s = ctx.davidson(torch.from_numpy(X0).to("cuda"), 4, block=4, precision=prec,
+                                    tol=1e-6 if prec == 0 else 1e-5, max_iter=400)
+            ctx.close()
+        err = np.abs(om - om_o).max()
+        say("  precision", prec, "iterations", s["iterations"], "max |omega - oracle| (meV)",
+            err / MEV)
+        assert err < MEV
+        assert np.abs(X.cpu().numpy() @ pd.T).max() < 1e-8
+
+
+def test_projector_errors():
+    """Non-orthonormal projector orbitals, too many of them, and a projector
+    together with two spin channels are refused."""
+    import paper_2409_15116_amd as pkg
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = cell("c1")
+    ctx = pkg.context_for(c)
+    bad = torch.from_numpy(np.ascontiguousarray(2.0 * c.psi[:3])).to("cuda")
+    with pytest.raises(pkg.BseError):
+        ctx.set_projector(bad)
+    many = torch.zeros((c.n_occ + 1, c.npw), dtype=torch.float64, device="cuda")
+    with pytest.raises(pkg.BseError):
+        ctx.set_projector(many)
+    ctx.set_projector(torch.from_numpy(np.ascontiguousarray(c.psi[:3])).to("cuda"))
+    with pytest.raises(pkg.BseError):
+        ctx.set_spin(4)
+    ctx.set_projector(None)
+    ctx.set_spin(4)
+    with pytest.raises(pkg.BseError):
+        ctx.set_projector(torch.from_numpy(np.ascontiguousarray(c.psi[:3])).to("cuda"))
+    ctx.close()
