@@ -519,6 +519,39 @@ def learned_c5(args, torch, pkg):
     return out
 
 
+def counters_run(args, torch, pkg):
+    """The bench cell and block, pairs at the bench fraction, screening, then
+    one eager apply of the block in FP64 and one in FP32 with the given K1d
+    shapes: every kernel of an apply dispatched a few times, nothing else."""
+    from synth import make_cell, trial_block
+    cell = make_cell(args.cell)
+    out = {"cell": args.cell, "block": args.block, "fraction": args.fraction, "applies": []}
+    for prec, shape in ((pkg.FP64, args.counters_run[0]), (pkg.FP32, args.counters_run[1])):
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            ctx = pkg.context_for(cell, stream=st)
+            thr = pkg.threshold_for_fraction(ctx.pair_measure(pkg.MEASURE_ABS_L1), args.fraction)
+            ctx.build_pairs(pkg.MEASURE_ABS_L1, thr)
+            phi = torch.from_numpy(np.ascontiguousarray(cell.phi)).to("cuda")
+            ctx.screen_pairs(phi, cell.lam, prec)
+            del phi
+            ctx.set_k1d_shape(prec, shape)
+            dt = torch.float64 if prec == pkg.FP64 else torch.float32
+            X = torch.from_numpy(trial_block(cell, args.block, seed=1234)).to("cuda", dtype=dt)
+            Y = torch.empty_like(X)
+            torch.cuda.synchronize()
+            t = time.time()
+            ctx.apply(X, Y, prec)
+            torch.cuda.synchronize()
+            out["applies"].append({"precision": int(prec), "k1d_shape": shape,
+                                   "chunk": ctx.apply_chunk(args.block, prec),
+                                   "seconds": time.time() - t, "n_pairs": ctx.n_pairs})
+            ctx.close()
+            del X, Y
+        torch.cuda.empty_cache()
+    return out
+
+
 def apply_mode(torch, pkg, cell, thr, Xh, prec, B, steps, warmup, graph=True, tune=True):
     """One precision on the bench cell: pair list at threshold thr, screened
     integrals, autotuned K1d shape (set-up, untimed), stage profile, then
@@ -651,6 +684,10 @@ def main():
     ap.add_argument("--jade", default="", metavar="CELLS",
                     help="also localise the canonical orbitals of these cells (comma list) "
                          "on the GPU (reported under jade)")
+    ap.add_argument("--counters-run", nargs=2, type=int, default=None, metavar=("FP64", "FP32"),
+                    help="only the bench cell's set-up and one eager block apply in FP64 and one "
+                         "in FP32 with these K1d shapes (no autotuning, no timing): a short run "
+                         "for per-kernel counters")
     ap.add_argument("--c2-tts-only", action="store_true",
                     help="only the 64-well gapped cell's Davidson time to solution (FP64, FP32, "
                          "BF16x3), printed as one JSON line: a short run to profile the solver")
@@ -674,6 +711,9 @@ def main():
     esz = 8 if prec == pkg.FP64 else 4
     B = args.block
 
+    if args.counters_run:
+        print(json.dumps(counters_run(args, torch, pkg)), flush=True)
+        return
     if args.c2_tts_only:
         print(json.dumps({"time_to_solution": {"c2": time_to_solution(args, torch, pkg)}}),
               flush=True)
