@@ -471,9 +471,9 @@ bse_status bse_debug_k1d_tables(bse_ctx *c, int set, int64_t *stats) {
         return BSE_ERR_ARG;
     }
     BSE_GUARD({
-        long long st[8];
+        long long st[10];
         bse::ctx_k1d_tables(c, set, st);
-        for (int i = 0; i < 8; ++i) stats[i] = st[i];
+        for (int i = 0; i < 10; ++i) stats[i] = st[i];
     })
 }
 

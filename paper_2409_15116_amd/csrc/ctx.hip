@@ -1715,6 +1715,7 @@ void ctx_set_k1d_shape(bse_ctx *c, int prec, int shape) {
     c->k1d_shape[dbl ? 0 : 1] = shape;
 }
 
+// st: host [10] (the layout bse_debug_k1d_tables documents)
 void ctx_k1d_tables(const bse_ctx *c, int set, long long *st) {
     BSE_REQUIRE(set >= 0 && set < K1D_RES_NSETS, BSE_ERR_ARG, "unknown table set %d", set);
     const PairEvents &e = c->res[set];

@@ -79,3 +79,30 @@ def test_rowblock_resident_shapes_match_oracle(case, prec, tol):
             n_res += 1
         ctx.close()
     assert n_res >= 2
+
+
+@pytest.mark.parametrize("name", ["c1", "mb136", "mb300"])
+def test_k1d_table_statistics(name):
+    """bse_debug_k1d_tables on one-block and row-block tables: every field is
+    filled and consistent (kept entries = twice the off-diagonal pairs plus
+    the diagonal ones; the critical path with the phase barriers is at least
+    the one without, which is at least the balanced share of the events)."""
+    import paper_2409_15116_amd as pkg
+    say("k1d tables", name)
+    c = cell(name)
+    ctx = pkg.context_for(c)
+    thr = pkg.threshold_for_fraction(ctx.pair_measure(pkg.MEASURE_ABS_L1), 0.4)
+    ctx.build_pairs(pkg.MEASURE_ABS_L1, thr)
+    P = ctx.n_pairs
+    for set_, cap in ((0, 128), (1, 64)):
+        t = ctx.k1d_tables(set_)
+        assert t["cap"] == cap and t["pairs"] == P and t["n_occ"] == c.n_occ
+        assert t["row_blocks"] == -(-c.n_occ // 128)
+        assert t["kept_entries"] == 2 * P - c.n_occ
+        assert t["critical_events_barriers"] >= t["critical_events_free"] > 0
+        # at most 16 waves per row block share its events (each list ends
+        # with 4 read-ahead zero events)
+        nrb = t["row_blocks"]
+        assert t["critical_events_free"] * 16 >= t["events"] - 4 * 16 * nrb
+        assert t["staged"] >= c.n_occ
+    ctx.close()
