@@ -49,7 +49,8 @@ def log(*a):
 # kernel, workload and shape it was taken on, and while the kernel's sources
 # are the ones that were measured.
 PROFILES = os.path.join(ROOT, "profiles")
-K1D_SOURCES = ["paper_2409_15116_amd/csrc/k1d.hip", "paper_2409_15116_amd/csrc/kernels.hpp",
+K1D_SOURCES = ["paper_2409_15116_amd/csrc/k1d.hip", "paper_2409_15116_amd/csrc/k1d_plan.hip",
+               "paper_2409_15116_amd/csrc/kernels.hpp",
                "paper_2409_15116_amd/csrc/ctx.hip"]
 
 

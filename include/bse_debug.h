@@ -42,6 +42,24 @@ bse_status bse_debug_gemm(bse_ctx *ctx, int nt, int M, int N, int K, double alph
  * BSE_ERR_ARG for an unknown set. */
 bse_status bse_debug_k1d_tables(bse_ctx *ctx, int set, int64_t *stats);
 
+/* Host-only (no device is touched): plan the resident K1d tables for a kept
+ * pair list as bse_build_pairs would, check them against what the kernels
+ * assume (every row in one wave, each kept entry (v, w) and (w, v) exactly
+ * once in its row's events with the column staged in that phase, even phase
+ * counts, read-ahead padding), and report their statistics.
+ *   pairs        host [n_pairs][2] int32, v <= w, every (v, v) present,
+ *                no duplicates (the list bse_get_pairs returns)
+ *   set          table set as in bse_debug_k1d_tables
+ *   stats        host [10] out, the layout of bse_debug_k1d_tables
+ *   wave_events  host [n_wave] out (may be NULL when n_wave = 0): events of
+ *                each wave, row block by row block (row blocks x waves per
+ *                block entries, the waves per block being 16 when there are
+ *                several row blocks, else the group count)
+ * BSE_ERR_ARG for a malformed pair list or too small an output;
+ * BSE_ERR_STATE if the plan fails its check. */
+bse_status bse_debug_k1d_plan(int n_occ, const int32_t *pairs, int64_t n_pairs, int set,
+                              int64_t *stats, int32_t *wave_events, int64_t n_wave);
+
 #ifdef __cplusplus
 }
 #endif

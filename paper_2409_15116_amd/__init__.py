@@ -6,7 +6,8 @@ GPU; calling it does, and raises when the library or the GPU is missing.
 """
 from .lib import (  # noqa: F401
     BF16X3, FP32, FP64, MEASURE_ABS_L1, MEASURE_OVERLAP, BseBatch, BseContext, BseError, Mlp,
-    exported_symbols, k1d_num_shapes, k1d_shape_info, lanczos_spectrum, load, mlp_init_weights,
+    exported_symbols, k1d_num_shapes, k1d_plan, k1d_shape_info, lanczos_spectrum, load,
+    mlp_init_weights,
     pack_params, threshold_for_fraction, unpack_params,
 )
 

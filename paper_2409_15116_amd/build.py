@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbse.so")
-SOURCES = ["fft.hip", "realspace.hip", "k1d.hip", "gemm.hip", "mfma.hip", "ctx.hip", "davidson.hip", "batch.hip", "lanczos.hip", "jade.hip",
+SOURCES = ["fft.hip", "realspace.hip", "k1d.hip", "k1d_plan.hip", "gemm.hip", "mfma.hip", "ctx.hip", "davidson.hip", "batch.hip", "lanczos.hip", "jade.hip",
            "learned.hip", "full.hip", "abi.hip"]
 ARCH = os.environ.get("BSE_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",

@@ -477,6 +477,31 @@ bse_status bse_debug_k1d_tables(bse_ctx *c, int set, int64_t *stats) {
     })
 }
 
+bse_status bse_debug_k1d_plan(int n_occ, const int32_t *pairs, int64_t n_pairs, int set,
+                              int64_t *stats, int32_t *wave_events, int64_t n_wave) {
+    if (!pairs || !stats || set < 0 || set >= bse::K1D_RES_NSETS || n_wave < 0 ||
+        (n_wave > 0 && !wave_events)) {
+        set_error("bse_debug_k1d_plan: bad argument");
+        return BSE_ERR_ARG;
+    }
+    BSE_GUARD({
+        const bse::K1dPlan pl = bse::k1d_plan(n_occ, pairs, n_pairs, bse::K1D_RES_CAPS[set]);
+        bse::k1d_plan_check(pl, n_occ, pairs, n_pairs);
+        const long long v[10] = {pl.nrb,   pl.nph,  pl.cap,        pl.n_ev,       pl.n_kept,
+                                 pl.n_staged, n_pairs, n_occ, pl.ev_barrier, pl.ev_free};
+        for (int i = 0; i < 10; ++i) stats[i] = v[i];
+        const long long nw = (long long)pl.nrb * pl.ng;
+        BSE_REQUIRE(n_wave == 0 || n_wave >= nw, BSE_ERR_ARG,
+                    "bse_debug_k1d_plan: wave_events holds %lld entries, the plan has %lld waves",
+                    (long long)n_wave, nw);
+        for (long long g = 0; n_wave > 0 && g < nw; ++g) {
+            long long s = 0;
+            for (int h = 0; h < pl.nph; ++h) s += pl.phc[(size_t)g * pl.nph + h];
+            wave_events[g] = (int32_t)s;
+        }
+    })
+}
+
 bse_status bse_debug_to_grid(bse_ctx *c, int n_orb, const void *X, void *out, int precision) {
     CHECK_CTX(c);
     if (!X || !out || n_orb < 1) {

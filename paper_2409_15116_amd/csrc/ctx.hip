@@ -327,896 +327,36 @@ void ctx_measure(bse_ctx *c, int kind, double *m_host) {
         }
 }
 
-// Tables of the resident K1d kernel, one set per LDS capacity (orbitals
-// whose a values fit in LDS at once).  When the cell has more orbitals than
-// that, the columns are split into phases (parts of at most cap orbitals)
-// with few kept pairs between parts: a pair inside a part has both of its
-// uses in the same phase, close in time.  Inside each part the orbitals are
-// split into row groups of K1D_RES_BW so that the groups touch few columns:
-// a wave visits every column that pairs with any orbital of its group, so
-// the sum over groups of the number of such columns is the work.  Both steps
-// start greedy and improve by swaps that do not make them worse (a fixed
-// pseudo-random sequence: the tables are deterministic).
-namespace {
-struct Bits {
-    int nwd;
-    std::vector<unsigned long long> w;  // [n][nwd]
-    const unsigned long long *row(int v) const { return &w[(size_t)v * nwd]; }
-};
-int pop_and(const unsigned long long *a, const unsigned long long *b, int n) {
-    int s = 0;
-    for (int k = 0; k < n; ++k) s += __builtin_popcountll(a[k] & b[k]);
-    return s;
-}
-struct Lcg {
-    unsigned long long st = 0x2545F4914F6CDD1Dull;
-    int operator()(int n) {
-        st = st * 6364136223846793005ull + 1442695040888963407ull;
-        return (int)((st >> 33) % (unsigned long long)n);
-    }
-};
-}  // namespace
-
-// critical-path statistics of per-(block, group, phase) event counts
-// cnt[(b * GW + g) * nph + h] (PairEvents::ev_barrier, ev_free)
-static void event_balance(PairEvents &e, const std::vector<int> &cnt, int nrb, int GW, int nph,
-                          const std::vector<int> &ng, const std::vector<int> &nphb) {
-    e.ev_barrier = e.ev_free = 0;
-    for (int b = 0; b < nrb; ++b) {
-        long long fr = 0;
-        for (int g = 0; g < ng[b]; ++g) {
-            long long t = 0;
-            for (int h = 0; h < nphb[b]; ++h) t += cnt[((size_t)b * GW + g) * nph + h];
-            fr = std::max(fr, t);
-        }
-        e.ev_free += fr;
-        for (int h = 0; h < nphb[b]; ++h) {
-            int mx = 0;
-            for (int g = 0; g < ng[b]; ++g) mx = std::max(mx, cnt[((size_t)b * GW + g) * nph + h]);
-            e.ev_barrier += mx;
-        }
-    }
-}
-
-static void build_event_set(bse_ctx *c, int set, int cap, const Bits &nb,
-                            const std::vector<int> &pidx) {
-    const int no = c->n_occ, BW = K1D_RES_BW, nwd = nb.nwd;
-    const long long P = c->n_pairs;
-    const int nph = (no + cap - 1) / cap;
-    Lcg rnd;
-    // parts: part_of[v]
-    std::vector<int> part_of(no, 0);
-    if (nph == 2) {
-        const int s0 = (no + 1) / 2;
-        std::vector<unsigned long long> m0(nwd, 0);
-        std::vector<char> in0(no, 0);
-        in0[0] = 1;
-        m0[0] |= 1ull;
-        for (int k = 1; k < s0; ++k) {
-            int best = -1, best_s = -1;
-            for (int v = 0; v < no; ++v) {
-                if (in0[v]) continue;
-                const int s = pop_and(nb.row(v), m0.data(), nwd);
-                if (s > best_s) {
-                    best = v;
-                    best_s = s;
-                }
-            }
-            in0[best] = 1;
-            m0[best / 64] |= 1ull << (best % 64);
-        }
-        for (int v = 0; v < no; ++v) part_of[v] = in0[v] ? 0 : 1;
-        auto cut = [&]() {
-            std::vector<unsigned long long> m1(nwd, 0);
-            for (int v = 0; v < no; ++v)
-                if (part_of[v]) m1[v / 64] |= 1ull << (v % 64);
-            int s = 0;
-            for (int v = 0; v < no; ++v)
-                if (!part_of[v]) s += pop_and(nb.row(v), m1.data(), nwd);
-            return s;
-        };
-        int cc = cut();
-        std::vector<int> p0, p1;
-        for (int v = 0; v < no; ++v) (part_of[v] ? p1 : p0).push_back(v);
-        for (int it = 0; it < 4000 && !p1.empty(); ++it) {
-            const int i = rnd((int)p0.size()), j = rnd((int)p1.size());
-            std::swap(part_of[p0[i]], part_of[p1[j]]);
-            const int nc = cut();
-            if (nc <= cc) {
-                cc = nc;
-                std::swap(p0[i], p1[j]);
-            } else {
-                std::swap(part_of[p0[i]], part_of[p1[j]]);
-            }
-        }
-    }
-    std::vector<std::vector<int>> parts(nph);
-    for (int v = 0; v < no; ++v) parts[part_of[v]].push_back(v);
-    std::vector<int> slot(no);
-    std::vector<int> part_tbl((size_t)nph * cap, -1);
-    for (int h = 0; h < nph; ++h)
-        for (size_t k = 0; k < parts[h].size(); ++k) {
-            slot[parts[h][k]] = (int)k;
-            part_tbl[(size_t)h * cap + k] = parts[h][k];
-        }
-    // row groups inside each part
-    std::vector<int> gpart;  // part of each group
-    std::vector<int> grp;    // [ng][BW]
-    for (int h = 0; h < nph; ++h) {
-        const std::vector<int> &mem = parts[h];
-        const int g0 = (int)gpart.size();
-        const int ngh = ((int)mem.size() + BW - 1) / BW;
-        std::vector<char> used(mem.size(), 0);
-        for (int g = 0; g < ngh; ++g) {
-            gpart.push_back(h);
-            const int size = std::min(BW, (int)mem.size() - g * BW);
-            std::vector<unsigned long long> cv(nwd, 0);
-            for (int i = 0; i < BW; ++i) {
-                if (i >= size) {
-                    grp.push_back(-1);
-                    continue;
-                }
-                int best = -1, best_s = 0;
-                for (size_t k = 0; k < mem.size(); ++k) {
-                    if (used[k]) continue;
-                    const unsigned long long *m = nb.row(mem[k]);
-                    int s = 0;
-                    for (int q = 0; q < nwd; ++q)
-                        s += __builtin_popcountll(m[q] & cv[q]) - __builtin_popcountll(m[q] & ~cv[q]);
-                    if (best < 0 || (i > 0 && s > best_s)) {
-                        best = (int)k;
-                        best_s = s;
-                    }
-                    if (i == 0) break;  // the seed: first free orbital of the part
-                }
-                used[best] = 1;
-                grp.push_back(mem[best]);
-                const unsigned long long *m = nb.row(mem[best]);
-                for (int q = 0; q < nwd; ++q) cv[q] |= m[q];
-            }
-        }
-        // swaps between groups of this part
-        if (ngh > 1) {
-            auto cost = [&](int g) {
-                std::vector<unsigned long long> cv(nwd, 0);
-                for (int i = 0; i < BW; ++i) {
-                    const int v = grp[(size_t)g * BW + i];
-                    if (v >= 0)
-                        for (int q = 0; q < nwd; ++q) cv[q] |= nb.row(v)[q];
-                }
-                int n = 0;
-                for (int q = 0; q < nwd; ++q) n += __builtin_popcountll(cv[q]);
-                return n;
-            };
-            std::vector<int> gc(ngh);
-            for (int g = 0; g < ngh; ++g) gc[g] = cost(g0 + g);
-            for (int it = 0; it < 10000; ++it) {
-                const int a = rnd(ngh);
-                int b = rnd(ngh - 1);
-                if (b >= a) ++b;
-                const int i = rnd(BW), j = rnd(BW);
-                int &x = grp[(size_t)(g0 + a) * BW + i], &y = grp[(size_t)(g0 + b) * BW + j];
-                if (x < 0 && y < 0) continue;
-                std::swap(x, y);
-                const int ca = cost(g0 + a), cb = cost(g0 + b);
-                if (ca + cb <= gc[a] + gc[b]) {
-                    gc[a] = ca;
-                    gc[b] = cb;
-                } else {
-                    std::swap(x, y);
-                }
-            }
-        }
-    }
-    const int ng = (int)gpart.size();
-    BSE_REQUIRE(ng <= K1D_RES_MAXROWS / BW, BSE_ERR_STATE, "too many row groups (%d)", ng);
-    for (int g = 0; g < ng; ++g)
-        std::sort(grp.begin() + (size_t)g * BW, grp.begin() + (size_t)(g + 1) * BW,
-                  [](int a, int b) { return (a < 0 ? INT_MAX : a) < (b < 0 ? INT_MAX : b); });
-    // wave order: a workgroup's waves are spread over the CU's four SIMDs
-    // in turn (wave w on SIMD w % 4), and every phase ends at a barrier, so
-    // the groups are ordered to even out each SIMD's events in each phase
-    // (greedy by total, then swaps that do not raise the sum over phases of
-    // the busiest SIMD's events)
-    if (ng > 4) {
-        std::vector<std::vector<int>> E(ng, std::vector<int>(nph, 0));
-        for (int g = 0; g < ng; ++g) {
-            std::vector<unsigned long long> cv(nwd, 0);
-            for (int i = 0; i < BW; ++i) {
-                const int v = grp[(size_t)g * BW + i];
-                if (v >= 0)
-                    for (int q = 0; q < nwd; ++q) cv[q] |= nb.row(v)[q];
-            }
-            for (int w = 0; w < no; ++w)
-                if (cv[w / 64] >> (w % 64) & 1) ++E[g][part_of[w]];
-            for (int h = 0; h < nph; ++h) E[g][h] = (E[g][h] + 3) / 4 * 4;
-        }
-        std::vector<int> perm(ng);  // wave -> group
-        for (int g = 0; g < ng; ++g) perm[g] = g;
-        auto tot = [&](int g) {
-            int s = 0;
-            for (int h = 0; h < nph; ++h) s += E[g][h];
-            return s;
-        };
-        std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return tot(a) > tot(b); });
-        {  // greedy: largest first onto the least loaded SIMD with a free wave
-            std::vector<int> load(4, 0);
-            const int per = (ng + 3) / 4;
-            std::vector<int> order = perm;
-            std::vector<std::vector<int>> bins(4);
-            for (int g : order) {
-                int best = -1;
-                for (int s = 0; s < 4; ++s)
-                    if ((int)bins[s].size() < per && (best < 0 || load[s] < load[best])) best = s;
-                bins[best].push_back(g);
-                load[best] += tot(g);
-            }
-            std::vector<int> used(4, 0);
-            for (int w = 0; w < ng; ++w) {
-                auto &b = bins[w % 4];
-                perm[w] = used[w % 4] < (int)b.size() ? b[used[w % 4]++] : -1;
-            }
-            // a SIMD short of groups leaves -1 slots: fill them with the rest
-            std::vector<int> rest;
-            for (int s = 0; s < 4; ++s)
-                for (int k = used[s]; k < (int)bins[s].size(); ++k) rest.push_back(bins[s][k]);
-            for (int w = 0, k = 0; w < ng; ++w)
-                if (perm[w] < 0) perm[w] = rest[k++];
-        }
-        auto span = [&]() {
-            int s = 0;
-            for (int h = 0; h < nph; ++h) {
-                int mx = 0;
-                for (int q = 0; q < 4; ++q) {
-                    int l = 0;
-                    for (int w = q; w < ng; w += 4) l += E[perm[w]][h];
-                    mx = std::max(mx, l);
-                }
-                s += mx;
-            }
-            return s;
-        };
-        int cur = span();
-        for (int it = 0; it < 4000; ++it) {
-            const int a = rnd(ng), b = rnd(ng);
-            if (a % 4 == b % 4) continue;
-            std::swap(perm[a], perm[b]);
-            const int s = span();
-            if (s <= cur) cur = s;
-            else std::swap(perm[a], perm[b]);
-        }
-        std::vector<int> grp2(grp.size()), gpart2(ng);
-        for (int w = 0; w < ng; ++w) {
-            std::copy(grp.begin() + (size_t)perm[w] * BW, grp.begin() + (size_t)(perm[w] + 1) * BW,
-                      grp2.begin() + (size_t)w * BW);
-            gpart2[w] = gpart[perm[w]];
-        }
-        grp.swap(grp2);
-        gpart.swap(gpart2);
-    }
-    // halves: each group's rows are ordered so that rows 0-3 and rows 4-7
-    // share few columns (the split of the 8 rows into two sets of 4 that
-    // gives the fewest events when a column live in only one half is paired
-    // with another such column of the other half)
-    for (int g = 0; g < ng; ++g) {
-        int *row = &grp[(size_t)g * BW];
-        auto events_of = [&](unsigned mask) {
-            int tot = 0;
-            for (int h = 0; h < nph; ++h) {
-                int full = 0, lo = 0, hi = 0;
-                for (int w : parts[h]) {
-                    bool l = false, u = false;
-                    for (int i = 0; i < BW; ++i)
-                        if (row[i] >= 0 && pidx[(size_t)row[i] * no + w] >= 0)
-                            (mask >> i & 1 ? l : u) = true;
-                    full += l && u;
-                    lo += l && !u;
-                    hi += u && !l;
-                }
-                tot += (full + std::max(lo, hi) + 1) / 2 * 2;
-            }
-            return tot;
-        };
-        unsigned best = 0x0F;
-        int best_n = events_of(best);
-        for (unsigned mask = 1; mask < 256; mask += 2)  // row 0 in the first half
-            if (__builtin_popcount(mask) == BW / 2) {
-                const int e = events_of(mask);
-                if (e < best_n) {
-                    best_n = e;
-                    best = mask;
-                }
-            }
-        std::vector<int> lo, hi;
-        for (int i = 0; i < BW; ++i) (best >> i & 1 ? lo : hi).push_back(row[i]);
-        auto key = [](int a) { return a < 0 ? INT_MAX : a; };
-        std::sort(lo.begin(), lo.end(), [&](int a, int b) { return key(a) < key(b); });
-        std::sort(hi.begin(), hi.end(), [&](int a, int b) { return key(a) < key(b); });
-        for (int i = 0; i < BW / 2; ++i) {
-            row[i] = lo[i];
-            row[BW / 2 + i] = hi[i];
-        }
-    }
-    // events: phase by phase; in the phase of its own part a group follows a
-    // round-robin tournament over that part's groups (circle method, an odd
-    // count gets a bye; in round r it visits its partner's columns and its
-    // own come last), in another phase it visits that part's groups in order
-    // An event is 8 tau offsets and two column slots: rows 0-3 take column
-    // A, rows 4-7 column B.  A column live in both halves is one event (A =
-    // B); columns live in one half only are paired with the next such column
-    // of the other half, in visiting order; one left over takes an event of
-    // its own with the other half on the zero row.
-    const int EV = BW + 2;
-    const int HB = BW / 2;
-    const int zero = (int)(P * TAU_TILE);
-    std::vector<int> ev, start(ng), phc((size_t)ng * nph);
-    auto off = [&](int g, int i, int w) {
-        const int v = grp[(size_t)g * BW + i];
-        const int p = v >= 0 && w >= 0 ? pidx[(size_t)v * no + w] : -1;
-        return p >= 0 ? p * TAU_TILE : zero;
-    };
-    auto push = [&](int g, int wa, int wb) {  // wa / wb < 0: that half idle
-        for (int i = 0; i < BW; ++i) ev.push_back(off(g, i, i < HB ? wa : wb));
-        const int sa = wa >= 0 ? slot[wa] : slot[wb];
-        const int sb = wb >= 0 ? slot[wb] : sa;
-        ev.push_back(sa);
-        ev.push_back(sb);
-    };
-    auto push_zero = [&]() {
-        for (int i = 0; i < BW; ++i) ev.push_back(zero);
-        ev.push_back(0);
-        ev.push_back(0);
-    };
-    for (int g = 0; g < ng; ++g) {
-        start[g] = (int)(ev.size() / EV);
-        std::vector<unsigned long long> cl(nwd, 0), ch(nwd, 0);
-        for (int i = 0; i < BW; ++i) {
-            const int v = grp[(size_t)g * BW + i];
-            if (v >= 0)
-                for (int q = 0; q < nwd; ++q) (i < HB ? cl : ch)[q] |= nb.row(v)[q];
-        }
-        std::vector<int> qlo, qhi;  // columns waiting for a partner, in order
-        auto visit = [&](int m) {
-            for (int i = 0; i < BW; ++i) {
-                const int w = grp[(size_t)m * BW + i];
-                if (w < 0) continue;
-                const bool l = cl[w / 64] >> (w % 64) & 1, u = ch[w / 64] >> (w % 64) & 1;
-                if (l && u) {
-                    push(g, w, w);
-                } else if (l) {
-                    if (!qhi.empty()) {
-                        push(g, w, qhi.front());
-                        qhi.erase(qhi.begin());
-                    } else {
-                        qlo.push_back(w);
-                    }
-                } else if (u) {
-                    if (!qlo.empty()) {
-                        push(g, qlo.front(), w);
-                        qlo.erase(qlo.begin());
-                    } else {
-                        qhi.push_back(w);
-                    }
-                }
-            }
-        };
-        for (int h = 0; h < nph; ++h) {
-            const size_t before = ev.size() / EV;
-            std::vector<int> gh;
-            for (int m = 0; m < ng; ++m)
-                if (gpart[m] == h) gh.push_back(m);
-            if (gpart[g] == h) {
-                const int n = (int)gh.size(), nt = n + (n & 1);
-                const int me = (int)(std::find(gh.begin(), gh.end(), g) - gh.begin());
-                for (int r = 0; r < nt - 1; ++r) {
-                    int q;
-                    if (me == nt - 1) q = r;
-                    else if (me == r) q = nt - 1;
-                    else q = ((2 * r - me) % (nt - 1) + (nt - 1)) % (nt - 1);
-                    if (q < n && q != me) visit(gh[q]);
-                }
-                visit(g);
-            } else {
-                for (int m : gh) visit(m);
-            }
-            for (int w : qlo) push(g, w, -1);
-            for (int w : qhi) push(g, -1, w);
-            qlo.clear();
-            qhi.clear();
-            int n = (int)(ev.size() / EV - before);
-            while (n % 2) {
-                push_zero();
-                ++n;
-            }
-            phc[(size_t)g * nph + h] = n;
-        }
-        for (int k = 0; k < 4; ++k) push_zero();  // read ahead past the end
-    }
-    auto up = [&](auto &dev, const auto &host) {
-        dev.alloc(std::max<size_t>(1, host.size()));
-        BSE_HIP(hipMemcpy(dev.p, host.data(), host.size() * sizeof(host[0]), hipMemcpyHostToDevice));
-    };
-    std::vector<int> gslot(grp.size(), 0);
-    for (size_t k = 0; k < grp.size(); ++k)
-        if (grp[k] >= 0) gslot[k] = slot[grp[k]];
-    up(c->res_grp[set], grp);
-    up(c->res_gpart[set], gpart);
-    up(c->res_gslot[set], gslot);
-    up(c->res_part[set], part_tbl);
-    up(c->res_ev[set], ev);
-    up(c->res_start[set], start);
-    up(c->res_cnt[set], phc);
-    const std::vector<int> rbng{ng}, rbnph{nph};
-    up(c->res_rbng[set], rbng);
-    up(c->res_rbnph[set], rbnph);
-    PairEvents &e = c->res[set];
-    e.n_ev = (long long)(ev.size() / EV);
-    e.n_kept = 0;
-    for (size_t k = 0; k < ev.size(); k += EV)
-        for (int i = 0; i < BW; ++i) e.n_kept += ev[k + i] != zero;
-    e.n_staged = no;
-    event_balance(e, phc, 1, ng, nph, std::vector<int>{ng}, std::vector<int>{nph});
-    e.ng = ng;
-    e.nph = nph;
-    e.cap = cap;
-    e.nrb = 1;
-    e.rb_ng = c->res_rbng[set].p;
-    e.rb_nph = c->res_rbnph[set].p;
-    e.n_rows = P + 1;
-    e.grp = c->res_grp[set].p;
-    e.gpart = c->res_gpart[set].p;
-    e.gslot = c->res_gslot[set].p;
-    e.part = c->res_part[set].p;
-    e.ev = c->res_ev[set].p;
-    e.ev_start = c->res_start[set].p;
-    e.ph_cnt = c->res_cnt[set].p;
-}
-
-// Resident K1d tables for more orbitals than one workgroup holds: the rows
-// are split into nrb row blocks of at most K1D_RES_MAXROWS orbitals, each laid
-// out like one workgroup's tables (groups of K1D_RES_BW rows, one per wave;
-// phases of at most cap resident columns).  A block's columns are the
-// orbitals that pair with one of its rows.  The other blocks' orbitals come
-// first, in parts ordered by a round-robin tournament over the blocks (in
-// round r blocks I and J take each other's columns, so the two uses of a
-// pair between them fall close in time in workgroups launched next to each
-// other on one XCD); the block's own rows come last, split into parts with
-// few pairs between them (a pair inside one part has both uses in the same
-// phase, in one CU), and the last part's a values stay in LDS for the
-// epilogue.  Row blocks and own parts grow greedily by kept pairs and are
-// improved by swaps that do not add pairs between them; groups grow greedily
-// by shared columns and are improved by swaps that do not add columns (a
-// fixed pseudo-random sequence: the tables are deterministic).
-static void build_event_blocks(bse_ctx *c, int set, int cap, const Bits &nb,
-                               const std::vector<int> &pidx) {
-    const int no = c->n_occ, BW = K1D_RES_BW, nwd = nb.nwd;
-    const int GW = K1D_RES_MAXROWS / BW;  // groups (waves) of one row block
-    const long long P = c->n_pairs;
-    const int nrb = (no + K1D_RES_MAXROWS - 1) / K1D_RES_MAXROWS;
-    Lcg rnd;
-    auto bit = [&](int v, int w) { return (int)((nb.row(v)[w / 64] >> (w % 64)) & 1); };
-    // pool split into parts of the given sizes with few pairs between parts
-    auto partition = [&](const std::vector<int> &pool, const std::vector<int> &sizes) {
-        const int k = (int)sizes.size();
-        std::vector<int> of(no, -1);
-        std::vector<std::vector<int>> parts(k);
-        std::vector<std::vector<unsigned long long>> pm(k, std::vector<unsigned long long>(nwd, 0));
-        for (int b = 0; b < k; ++b)
-            for (int t = 0; t < sizes[b]; ++t) {
-                int best = -1, best_s = -1;
-                for (int v : pool) {
-                    if (of[v] >= 0) continue;
-                    if (t == 0) {  // seed: the first free member
-                        best = v;
-                        break;
-                    }
-                    const int s = pop_and(nb.row(v), pm[b].data(), nwd);
-                    if (s > best_s) {
-                        best = v;
-                        best_s = s;
-                    }
-                }
-                of[best] = b;
-                parts[b].push_back(best);
-                pm[b][best / 64] |= 1ull << (best % 64);
-            }
-        auto links = [&](int v, int b) { return pop_and(nb.row(v), pm[b].data(), nwd); };
-        for (int it = 0; it < 20000 && k > 1; ++it) {
-            const int a = rnd(k);
-            int b = rnd(k - 1);
-            if (b >= a) ++b;
-            if (parts[a].empty() || parts[b].empty()) continue;
-            const int i = rnd((int)parts[a].size()), j = rnd((int)parts[b].size());
-            const int v = parts[a][i], w = parts[b][j];
-            const int vw = bit(v, w);
-            // change of the pairs between parts when v and w trade places
-            // (links count v's own diagonal pair inside its part)
-            const int d = (links(v, a) - bit(v, v)) - (links(v, b) - vw) +
-                          (links(w, b) - bit(w, w)) - (links(w, a) - vw);
-            if (d > 0) continue;
-            parts[a][i] = w;
-            parts[b][j] = v;
-            of[v] = b;
-            of[w] = a;
-            pm[a][v / 64] &= ~(1ull << (v % 64));
-            pm[b][w / 64] &= ~(1ull << (w % 64));
-            pm[a][w / 64] |= 1ull << (w % 64);
-            pm[b][v / 64] |= 1ull << (v % 64);
-        }
-        for (auto &q : parts) std::sort(q.begin(), q.end());
-        return parts;
-    };
-    auto balanced = [](int n, int k) {
-        std::vector<int> sz(k, n / k);
-        for (int i = 0; i < n % k; ++i) ++sz[i];
-        return sz;
-    };
-    std::vector<int> all(no);
-    for (int v = 0; v < no; ++v) all[v] = v;
-    const std::vector<std::vector<int>> blocks = partition(all, balanced(no, nrb));
-    std::vector<int> blk_of(no);
-    for (int b = 0; b < nrb; ++b)
-        for (int v : blocks[b]) blk_of[v] = b;
-    // columns a group touches (union of its rows' pair masks)
-    auto cover = [&](const int *row) {
-        std::vector<unsigned long long> cv(nwd, 0);
-        for (int i = 0; i < BW; ++i)
-            if (row[i] >= 0)
-                for (int q = 0; q < nwd; ++q) cv[q] |= nb.row(row[i])[q];
-        return cv;
-    };
-    auto popcnt = [&](const std::vector<unsigned long long> &m) {
-        int n = 0;
-        for (unsigned long long x : m) n += __builtin_popcountll(x);
-        return n;
-    };
-    // groups of BW rows inside one part: greedy growth by shared columns,
-    // then swaps between groups that do not add columns
-    auto make_groups = [&](const std::vector<int> &mem) {
-        const int ngh = ((int)mem.size() + BW - 1) / BW;
-        std::vector<int> grp((size_t)ngh * BW, -1);
-        std::vector<char> used(mem.size(), 0);
-        for (int g = 0; g < ngh; ++g) {
-            std::vector<unsigned long long> cv(nwd, 0);
-            const int size = std::min(BW, (int)mem.size() - g * BW);
-            for (int i = 0; i < size; ++i) {
-                int best = -1, best_s = INT_MIN;
-                for (size_t k = 0; k < mem.size(); ++k) {
-                    if (used[k]) continue;
-                    if (i == 0) {
-                        best = (int)k;
-                        break;
-                    }
-                    const unsigned long long *m = nb.row(mem[k]);
-                    int sc = 0;
-                    for (int q = 0; q < nwd; ++q)
-                        sc += __builtin_popcountll(m[q] & cv[q]) - __builtin_popcountll(m[q] & ~cv[q]);
-                    if (sc > best_s) {
-                        best = (int)k;
-                        best_s = sc;
-                    }
-                }
-                used[best] = 1;
-                grp[(size_t)g * BW + i] = mem[best];
-                for (int q = 0; q < nwd; ++q) cv[q] |= nb.row(mem[best])[q];
-            }
-        }
-        if (ngh > 1) {
-            std::vector<int> gc(ngh);
-            for (int g = 0; g < ngh; ++g) gc[g] = popcnt(cover(&grp[(size_t)g * BW]));
-            for (int it = 0; it < 10000; ++it) {
-                const int a = rnd(ngh);
-                int b = rnd(ngh - 1);
-                if (b >= a) ++b;
-                int &x = grp[(size_t)a * BW + rnd(BW)], &y = grp[(size_t)b * BW + rnd(BW)];
-                if (x < 0 && y < 0) continue;
-                std::swap(x, y);
-                const int ca = popcnt(cover(&grp[(size_t)a * BW])),
-                          cb = popcnt(cover(&grp[(size_t)b * BW]));
-                if (ca + cb <= gc[a] + gc[b]) {
-                    gc[a] = ca;
-                    gc[b] = cb;
-                } else {
-                    std::swap(x, y);
-                }
-            }
-        }
-        return grp;
-    };
-    const int EV = BW + 2, HB = BW / 2;
-    const int zero = (int)(P * TAU_TILE);
-    const int nt = nrb + (nrb & 1);
-    auto partner = [&](int I, int r) {
-        if (I == nt - 1) return r;
-        if (I == r) return nt - 1;
-        return ((2 * r - I) % (nt - 1) + (nt - 1)) % (nt - 1);
-    };
-    struct Block {
-        std::vector<std::vector<int>> phases;  // resident columns of each phase
-        int n_ext = 0;                         // phases of other blocks' columns
-        std::vector<int> grp, gpart;           // [GW][BW], [GW] (own phase)
-        int ng = 0;
-    };
-    std::vector<Block> B(nrb);
-    int nph_max = 0;
-    for (int b = 0; b < nrb; ++b) {
-        Block &K = B[b];
-        const std::vector<int> &own = blocks[b];
-        std::vector<char> touch(no, 0);
-        for (int v : own)
-            for (int w = 0; w < no; ++w)
-                if (bit(v, w)) touch[w] = 1;
-        std::vector<int> ext;
-        for (int r = 0; r < nt - 1; ++r) {
-            const int J = partner(b, r);
-            if (J >= nrb) continue;
-            for (int w : blocks[J])
-                if (touch[w]) ext.push_back(w);
-        }
-        for (size_t i = 0; i < ext.size(); i += cap)
-            K.phases.emplace_back(ext.begin() + i,
-                                  ext.begin() + std::min(ext.size(), i + (size_t)cap));
-        K.n_ext = (int)K.phases.size();
-        const int nown = ((int)own.size() + cap - 1) / cap;
-        const auto oparts = partition(own, balanced((int)own.size(), nown));
-        K.grp.assign((size_t)GW * BW, -1);
-        K.gpart.assign(GW, 0);
-        std::vector<std::pair<int, std::vector<int>>> groups;  // (own phase, rows)
-        for (int h = 0; h < nown; ++h) {
-            K.phases.push_back(oparts[h]);
-            const std::vector<int> g = make_groups(oparts[h]);
-            for (size_t q = 0; q < g.size(); q += BW)
-                groups.emplace_back(K.n_ext + h, std::vector<int>(g.begin() + q, g.begin() + q + BW));
-        }
-        K.ng = (int)groups.size();
-        BSE_REQUIRE(K.ng <= GW, BSE_ERR_STATE, "row block %d needs %d groups", b, K.ng);
-        // waves: groups with the most columns first, each onto the SIMD
-        // (wave % 4) with the least work so far that has a free wave
-        std::vector<int> work(K.ng), order(K.ng);
-        for (int g = 0; g < K.ng; ++g) {
-            work[g] = popcnt(cover(groups[g].second.data()));
-            order[g] = g;
-        }
-        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
-        std::vector<int> load(4, 0), cnt(4, 0), wave_of(K.ng);
-        const int per = (K.ng + 3) / 4;
-        for (int g : order) {
-            int best = -1;
-            for (int q = 0; q < 4; ++q)
-                if (cnt[q] < per && q + 4 * cnt[q] < K.ng && (best < 0 || load[q] < load[best]))
-                    best = q;
-            if (best < 0)
-                for (int q = 0; q < 4; ++q)
-                    if (q + 4 * cnt[q] < K.ng) {
-                        best = q;
-                        break;
-                    }
-            wave_of[g] = best + 4 * cnt[best]++;
-            load[best] += work[g];
-        }
-        for (int g = 0; g < K.ng; ++g) {
-            const int w = wave_of[g];
-            std::copy(groups[g].second.begin(), groups[g].second.end(),
-                      K.grp.begin() + (size_t)w * BW);
-            K.gpart[w] = groups[g].first;
-        }
-        nph_max = std::max(nph_max, (int)K.phases.size());
-    }
-    // tables
-    std::vector<int> grp((size_t)nrb * GW * BW, -1), gpart((size_t)nrb * GW, 0),
-        gslot((size_t)nrb * GW * BW, 0), part((size_t)nrb * nph_max * cap, -1),
-        start((size_t)nrb * GW, 0), phc((size_t)nrb * GW * nph_max, 0), rbng(nrb), rbnph(nrb);
-    std::vector<int> ev;
-    for (int b = 0; b < nrb; ++b) {
-        Block &K = B[b];
-        const int nph = (int)K.phases.size();
-        rbng[b] = K.ng;
-        rbnph[b] = nph;
-        std::vector<int> slot(no, -1);  // slot of each column in its phase (per phase below)
-        for (int h = 0; h < nph; ++h)
-            for (size_t k = 0; k < K.phases[h].size(); ++k)
-                part[((size_t)b * nph_max + h) * cap + k] = K.phases[h][k];
-        for (int wv = 0; wv < K.ng; ++wv) {
-            const size_t G = (size_t)b * GW + wv;
-            int *row = &K.grp[(size_t)wv * BW];
-            // halves: the 4 + 4 split of the rows with the fewest events
-            // (a column live in one half shares its event with such a column
-            // of the other half)
-            auto events_of = [&](unsigned mask) {
-                int tot = 0;
-                for (int h = 0; h < nph; ++h) {
-                    int full = 0, lo = 0, hi = 0;
-                    for (int w : K.phases[h]) {
-                        bool l = false, u = false;
-                        for (int i = 0; i < BW; ++i)
-                            if (row[i] >= 0 && bit(row[i], w)) (mask >> i & 1 ? l : u) = true;
-                        full += l && u;
-                        lo += l && !u;
-                        hi += u && !l;
-                    }
-                    tot += (full + std::max(lo, hi) + 1) / 2 * 2;
-                }
-                return tot;
-            };
-            unsigned best = 0x0F;
-            int best_n = events_of(best);
-            for (unsigned mask = 1; mask < 256; mask += 2)
-                if (__builtin_popcount(mask) == BW / 2) {
-                    const int e = events_of(mask);
-                    if (e < best_n) {
-                        best_n = e;
-                        best = mask;
-                    }
-                }
-            {
-                std::vector<int> lo, hi;
-                for (int i = 0; i < BW; ++i) (best >> i & 1 ? lo : hi).push_back(row[i]);
-                auto key = [](int a) { return a < 0 ? INT_MAX : a; };
-                std::sort(lo.begin(), lo.end(), [&](int x, int y) { return key(x) < key(y); });
-                std::sort(hi.begin(), hi.end(), [&](int x, int y) { return key(x) < key(y); });
-                for (int i = 0; i < HB; ++i) {
-                    row[i] = lo[i];
-                    row[HB + i] = hi[i];
-                }
-            }
-            std::copy(row, row + BW, grp.begin() + G * BW);
-            gpart[G] = K.gpart[wv];
-            const std::vector<int> &op = K.phases[K.gpart[wv]];
-            for (int i = 0; i < BW; ++i)
-                if (row[i] >= 0)
-                    gslot[G * BW + i] =
-                        (int)(std::find(op.begin(), op.end(), row[i]) - op.begin());
-        }
-        // events, phase by phase
-        for (int wv = 0; wv < K.ng; ++wv) {
-            const size_t G = (size_t)b * GW + wv;
-            const int *row = &grp[G * BW];
-            start[G] = (int)(ev.size() / EV);
-            std::vector<unsigned long long> cl(nwd, 0), ch(nwd, 0);
-            for (int i = 0; i < BW; ++i)
-                if (row[i] >= 0)
-                    for (int q = 0; q < nwd; ++q) (i < HB ? cl : ch)[q] |= nb.row(row[i])[q];
-            for (int h = 0; h < nph; ++h) {
-                const std::vector<int> &cols = K.phases[h];
-                for (size_t k = 0; k < cols.size(); ++k) slot[cols[k]] = (int)k;
-                auto off = [&](int i, int w) {
-                    const int v = row[i];
-                    const int p = v >= 0 && w >= 0 ? pidx[(size_t)v * no + w] : -1;
-                    return p >= 0 ? p * TAU_TILE : zero;
-                };
-                auto push = [&](int wa, int wb) {  // wa / wb < 0: that half idle
-                    for (int i = 0; i < BW; ++i) ev.push_back(off(i, i < HB ? wa : wb));
-                    const int sa = wa >= 0 ? slot[wa] : slot[wb];
-                    ev.push_back(sa);
-                    ev.push_back(wb >= 0 ? slot[wb] : sa);
-                };
-                std::vector<int> qlo, qhi;
-                auto visit = [&](int w) {
-                    const bool l = cl[w / 64] >> (w % 64) & 1, u = ch[w / 64] >> (w % 64) & 1;
-                    if (l && u) {
-                        push(w, w);
-                    } else if (l) {
-                        if (!qhi.empty()) {
-                            push(w, qhi.front());
-                            qhi.erase(qhi.begin());
-                        } else {
-                            qlo.push_back(w);
-                        }
-                    } else if (u) {
-                        if (!qlo.empty()) {
-                            push(qlo.front(), w);
-                            qlo.erase(qlo.begin());
-                        } else {
-                            qhi.push_back(w);
-                        }
-                    }
-                };
-                const size_t before = ev.size() / EV;
-                if (h >= K.n_ext) {
-                    // an own part: its groups' rows as columns; in the wave's
-                    // own part a round-robin tournament over that part's
-                    // groups (circle method), its own rows last
-                    std::vector<int> gh;
-                    for (int m = 0; m < K.ng; ++m)
-                        if (gpart[(size_t)b * GW + m] == h) gh.push_back(m);
-                    auto visit_group = [&](int m) {
-                        for (int i = 0; i < BW; ++i) {
-                            const int w = grp[((size_t)b * GW + m) * BW + i];
-                            if (w >= 0) visit(w);
-                        }
-                    };
-                    if (gpart[G] == h) {
-                        const int n = (int)gh.size(), ntg = n + (n & 1);
-                        const int me = (int)(std::find(gh.begin(), gh.end(), wv) - gh.begin());
-                        for (int r = 0; r < ntg - 1; ++r) {
-                            int q;
-                            if (me == ntg - 1) q = r;
-                            else if (me == r) q = ntg - 1;
-                            else q = ((2 * r - me) % (ntg - 1) + (ntg - 1)) % (ntg - 1);
-                            if (q < n && q != me) visit_group(gh[q]);
-                        }
-                        visit_group(wv);
-                    } else {
-                        for (int m : gh) visit_group(m);
-                    }
-                } else {
-                    for (int w : cols) visit(w);
-                }
-                for (int w : qlo) push(w, -1);
-                for (int w : qhi) push(-1, w);
-                int n = (int)(ev.size() / EV - before);
-                while (n % 2) {  // events come in pairs (two tau columns in flight)
-                    for (int i = 0; i < BW; ++i) ev.push_back(zero);
-                    ev.push_back(0);
-                    ev.push_back(0);
-                    ++n;
-                }
-                phc[G * nph_max + h] = n;
-                for (int w : cols) slot[w] = -1;
-            }
-            for (int k = 0; k < 4; ++k) {  // read ahead past the end
-                for (int i = 0; i < BW; ++i) ev.push_back(zero);
-                ev.push_back(0);
-                ev.push_back(0);
-            }
-        }
-    }
-    auto up = [&](auto &dev, const auto &host) {
-        dev.alloc(std::max<size_t>(1, host.size()));
-        BSE_HIP(hipMemcpy(dev.p, host.data(), host.size() * sizeof(host[0]), hipMemcpyHostToDevice));
-    };
-    up(c->res_grp[set], grp);
-    up(c->res_gpart[set], gpart);
-    up(c->res_gslot[set], gslot);
-    up(c->res_part[set], part);
-    up(c->res_ev[set], ev);
-    up(c->res_start[set], start);
-    up(c->res_cnt[set], phc);
-    up(c->res_rbng[set], rbng);
-    up(c->res_rbnph[set], rbnph);
-    PairEvents &e = c->res[set];
-    e.n_ev = (long long)(ev.size() / EV);
-    e.n_kept = 0;
-    for (size_t k = 0; k < ev.size(); k += EV)
-        for (int i = 0; i < BW; ++i) e.n_kept += ev[k + i] != zero;
-    e.n_staged = 0;
-    for (const Block &K : B)
-        for (const auto &ph : K.phases) e.n_staged += (long long)ph.size();
-    event_balance(e, phc, nrb, GW, nph_max, rbng, rbnph);
-    e.ng = GW;
-    e.nph = nph_max;
-    e.cap = cap;
-    e.nrb = nrb;
-    e.rb_ng = c->res_rbng[set].p;
-    e.rb_nph = c->res_rbnph[set].p;
-    e.n_rows = P + 1;
-    e.grp = c->res_grp[set].p;
-    e.gpart = c->res_gpart[set].p;
-    e.gslot = c->res_gslot[set].p;
-    e.part = c->res_part[set].p;
-    e.ev = c->res_ev[set].p;
-    e.ev_start = c->res_start[set].p;
-    e.ph_cnt = c->res_cnt[set].p;
-}
-
 static void build_events(bse_ctx *c, const std::vector<int> &pr) {
-    const int no = c->n_occ;
     for (auto &e : c->res) e = PairEvents{};
-    Bits nb;
-    nb.nwd = (no + 63) / 64;
-    nb.w.assign((size_t)no * nb.nwd, 0);
-    std::vector<int> pidx((size_t)no * no, -1);
-    for (long long p = 0; p < c->n_pairs; ++p) {
-        const int v = pr[2 * p], w = pr[2 * p + 1];
-        pidx[(size_t)v * no + w] = pidx[(size_t)w * no + v] = (int)p;
-        nb.w[(size_t)v * nb.nwd + w / 64] |= 1ull << (w % 64);
-        nb.w[(size_t)w * nb.nwd + v / 64] |= 1ull << (v % 64);
-    }
     for (int set = 0; set < K1D_RES_NSETS; ++set) {
-        if (no <= K1D_RES_MAXROWS)
-            build_event_set(c, set, K1D_RES_CAPS[set], nb, pidx);
-        else
-            build_event_blocks(c, set, K1D_RES_CAPS[set], nb, pidx);
+        const K1dPlan pl = k1d_plan(c->n_occ, pr.data(), c->n_pairs, K1D_RES_CAPS[set]);
+        auto up = [&](auto &dev, const std::vector<int> &host) {
+            dev.alloc(std::max<size_t>(1, host.size()));
+            BSE_HIP(hipMemcpy(dev.p, host.data(), host.size() * sizeof(int),
+                              hipMemcpyHostToDevice));
+            return dev.p;
+        };
+        PairEvents &e = c->res[set];
+        e.grp = up(c->res_grp[set], pl.grp);
+        e.gpart = up(c->res_gpart[set], pl.gpart);
+        e.gslot = up(c->res_gslot[set], pl.gslot);
+        e.part = up(c->res_part[set], pl.part);
+        e.ev = up(c->res_ev[set], pl.ev);
+        e.ev_start = up(c->res_start[set], pl.start);
+        e.ph_cnt = up(c->res_cnt[set], pl.phc);
+        e.rb_ng = up(c->res_rbng[set], pl.rbng);
+        e.rb_nph = up(c->res_rbnph[set], pl.rbnph);
+        e.ng = pl.ng;
+        e.nph = pl.nph;
+        e.cap = pl.cap;
+        e.nrb = pl.nrb;
+        e.n_rows = c->n_pairs + 1;
+        e.n_ev = pl.n_ev;
+        e.n_kept = pl.n_kept;
+        e.n_staged = pl.n_staged;
+        e.ev_barrier = pl.ev_barrier;
+        e.ev_free = pl.ev_free;
     }
 }
 

@@ -379,6 +379,19 @@ __global__ void __launch_bounds__(64 * NW) k_k1d_res(
         size_t so[VPL];
         vec_offsets(so);
         const bool last = gpart[G] == nph - 1;
+        // a helper slot (-2 - k, rows 4-7) holds a share of the columns of
+        // the row in slot k: its sums go to that row's
+#pragma unroll
+        for (int i = HB; i < BW; ++i) {
+            const int hv = grp[G * BW + i];
+            if (hv < -1) {
+#pragma unroll
+                for (int k = 0; k < HB; ++k)
+                    if (k == -2 - hv)
+#pragma unroll
+                        for (int j = 0; j < VPL; ++j) acc[k][j] += acc[i][j];
+            }
+        }
 #pragma unroll
         for (int i = 0; i < BW; ++i) {
             const int v = grp[G * BW + i];
@@ -598,6 +611,26 @@ __global__ void __launch_bounds__(64 * NW) k_k1d_res2(
         for (int j = 0; j < VPL; ++j) dn[p][j] = 0;
     if (act) {
         const bool last = gpart[G] == nph - 1;
+        // a helper slot (-2 - k0, half 1) holds a share of the columns of the
+        // row in slot k0 of half 0: its sums cross to the lanes of half 0
+        // that hold the same points
+#pragma unroll
+        for (int k1 = 0; k1 < HB; ++k1) {
+            const int hv = grp[G * BW + HB + k1];
+            if (hv < -1) {
+#pragma unroll
+                for (int p = 0; p < 2; ++p)
+#pragma unroll
+                    for (int j = 0; j < VPL; ++j) {
+                        const double o = __shfl_xor(acc[k1][p][j], 32);
+                        if (hf == 0) {
+#pragma unroll
+                            for (int k = 0; k < HB; ++k)
+                                if (k == -2 - hv) acc[k][p][j] += o;
+                        }
+                    }
+            }
+        }
 #pragma unroll
         for (int k = 0; k < HB; ++k) {
             const int gi = G * BW + hf * HB + k;

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <algorithm>
+#include <vector>
 
 #include "common.hpp"
 
@@ -127,6 +128,19 @@ struct PairEvents {
     const int *ev_start = nullptr;
     const int *ph_cnt = nullptr;
 };
+
+// Host tables of one resident event set (what PairEvents points at on the
+// device) and their statistics, planned from the kept pair list alone.
+struct K1dPlan {
+    std::vector<int> grp, gpart, gslot, part, ev, start, phc, rbng, rbnph;
+    int ng = 0, nph = 0, cap = 0, nrb = 0;
+    long long n_ev = 0, n_kept = 0, n_staged = 0, ev_barrier = 0, ev_free = 0;
+};
+// pairs: [P][2] with v <= w, every diagonal (v, v) present; cap: resident
+// columns per phase (one of K1D_RES_CAPS).  Throws on a bad pair list.
+K1dPlan k1d_plan(int n_occ, const int *pairs, long long P, int cap);
+// Throws (BSE_ERR_STATE) when the plan breaks what the kernels assume.
+void k1d_plan_check(const K1dPlan &pl, int n_occ, const int *pairs, long long P);
 
 // Compiled shapes of the K1d kernel (the autotuner's choices): BI rows per
 // workgroup, S trial vectors per workgroup, NBUF columns of tau in flight,

@@ -85,6 +85,7 @@ def load():
         "bse_debug_to_grid": (i32, [vp, i32, vp, vp, i32]),
         "bse_debug_gemm": (i32, [vp, i32, i32, i32, i32, dbl, vp, vp, dbl, vp, i32]),
         "bse_debug_k1d_tables": (i32, [vp, i32, vp]),
+        "bse_debug_k1d_plan": (i32, [i32, vp, i64, i32, vp, vp, i64]),
         "bse_mlp_create": (i32, [C.POINTER(vp), i32, i32, i32, vp, vp]),
         "bse_mlp_destroy": (i32, [vp]),
         "bse_mlp_num_params": (C.c_longlong, [vp]),
@@ -127,7 +128,7 @@ def exported_symbols():
             "bse_pair_measure", "bse_build_pairs",
             "bse_threshold_for_fraction", "bse_get_pairs", "bse_screen_pairs", "bse_copy_tau",
             "bse_apply_liouville", "bse_apply_coupling", "bse_davidson_full", "bse_apply_chunk", "bse_set_graph", "bse_davidson", "bse_status_str",
-            "bse_last_error", "bse_debug_to_grid", "bse_debug_gemm", "bse_debug_k1d_tables", "bse_profile_apply",
+            "bse_last_error", "bse_debug_to_grid", "bse_debug_gemm", "bse_debug_k1d_tables", "bse_debug_k1d_plan", "bse_profile_apply",
             "bse_mlp_create", "bse_mlp_destroy", "bse_mlp_num_params", "bse_mlp_get_weights",
             "bse_mlp_set_weights", "bse_mlp_forward", "bse_mlp_forward_noalloc", "bse_mlp_gradients", "bse_mlp_train",
             "bse_set_learned", "bse_set_learned_partners", "bse_learned_centers",
@@ -151,6 +152,26 @@ def _dptr(t, dtype, shape=None):
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
     return C.c_void_p(t.data_ptr())
+
+
+_TABLE_KEYS = ("row_blocks", "phases", "cap", "events", "kept_entries", "staged", "pairs",
+               "n_occ", "critical_events_barriers", "critical_events_free")
+
+
+def k1d_plan(n_occ, pairs, set_=0):
+    """Plan and check the resident K1d tables for a pair list on the host
+    (bse_debug_k1d_plan): the statistics of bse_debug_k1d_tables plus
+    'wave_events' [row blocks, 16], the events of each wave (zero for a wave
+    without a row group)."""
+    pr = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    st = np.zeros(10, dtype=np.int64)
+    nrb = max(1, -(-int(n_occ) // 128))
+    we = np.zeros(nrb * 16, dtype=np.int32)
+    _check(load().bse_debug_k1d_plan(int(n_occ), pr.ctypes.data, len(pr), int(set_),
+                                     st.ctypes.data, we.ctypes.data, len(we)))
+    out = dict(zip(_TABLE_KEYS, map(int, st)))
+    out["wave_events"] = we.reshape(nrb, 16)
+    return out
 
 
 def threshold_for_fraction(m: np.ndarray, fraction: float) -> float:
@@ -197,9 +218,7 @@ class BseContext:
         """Statistics of the resident K1d tables (bse_debug_k1d_tables)."""
         st = np.zeros(10, dtype=np.int64)
         _check(load().bse_debug_k1d_tables(self.h, int(set_), st.ctypes.data))
-        keys = ("row_blocks", "phases", "cap", "events", "kept_entries", "staged", "pairs",
-                "n_occ", "critical_events_barriers", "critical_events_free")
-        return dict(zip(keys, map(int, st)))
+        return dict(zip(_TABLE_KEYS, map(int, st)))
 
     def set_projector(self, phi):
         """Spin-flip channel: P_c projects out these orbitals (device FP64
