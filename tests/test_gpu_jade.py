@@ -194,3 +194,30 @@ def test_full_size_c2():
     Q, sw, off = ctx.jade(A, tol=1e-7)
     assert off == pytest.approx(hist[-1], rel=1e-6)
     ctx.close()
+
+
+def test_full_size_c2_lit_capped():
+    """The 128-orbital literal cell (the gapless filling, 72^3): the spread
+    matrices match the oracle's; from the library's own start every further
+    sweep keeps or lowers the off-diagonal sum; with the sweeps capped while
+    pairs still rotate the state is reported as not converged, and it is a
+    valid one (Q orthogonal, the returned matrices equal Q^T A Q)."""
+    say("jade_full_size", "c2_lit")
+    c = make_cell("c2_lit")
+    ctx = _pkg().context_for(c, localized=False)
+    b = Basis(c.L, c.n, c.miller)
+    ref = spread_matrices(b.to_grid(c.psi_canon))
+    A0 = ctx.spread_matrices()
+    assert np.abs(A0.cpu().numpy() - ref).max() < 1e-12
+    offs = []
+    for ms in (1, 2, 4, 8):
+        A = A0.clone()
+        Q, sw, off, conv = ctx.jade(A, tol=1e-7, max_sweeps=ms, partial_ok=True)
+        assert sw == ms and not conv
+        offs.append(off)
+    assert all(o2 <= o1 * (1 + 1e-12) for o1, o2 in zip(offs, offs[1:])), offs
+    Qh, Ah = Q.cpu().numpy(), A.cpu().numpy()
+    assert np.abs(Qh.T @ Qh - np.eye(c.n_occ)).max() < 1e-10
+    rot = np.einsum("ji,mjk,kl->mil", Qh, ref, Qh)
+    assert np.abs(Ah - rot).max() < 1e-9 * np.abs(ref).max()
+    ctx.close()
