@@ -331,6 +331,7 @@ static void build_events(bse_ctx *c, const std::vector<int> &pr) {
     for (auto &e : c->res) e = PairEvents{};
     for (int set = 0; set < K1D_RES_NSETS; ++set) {
         const K1dPlan pl = k1d_plan(c->n_occ, pr.data(), c->n_pairs, K1D_RES_CAPS[set]);
+        k1d_plan_check(pl, c->n_occ, pr.data(), c->n_pairs);  // linear in the events
         auto up = [&](auto &dev, const std::vector<int> &host) {
             dev.alloc(std::max<size_t>(1, host.size()));
             BSE_HIP(hipMemcpy(dev.p, host.data(), host.size() * sizeof(int),

@@ -690,10 +690,12 @@ static void refine_block(GroupCoster &gc, std::vector<std::pair<int, Layout>> &g
 // out like one workgroup's tables (groups of K1D_RES_BW rows, one per wave;
 // phases of at most cap resident columns).  A block's columns are the
 // orbitals that pair with one of its rows.  The other blocks' orbitals come
-// first, in parts ordered by a round-robin tournament over the blocks (in
-// round r blocks I and J take each other's columns, so the two uses of a
-// pair between them fall close in time in workgroups launched next to each
-// other on one XCD); the block's own rows come last, split into parts with
+// first, in one order common to all blocks (by block, then index), so that
+// the workgroups of one grid piece, launched next to each other on one XCD,
+// stage the same columns at about the same time and most of their a values
+// come from L2 (measured faster than ordering the blocks' visits so that the
+// two uses of a pair between two blocks fall together); the block's own rows
+// come last, split into parts with
 // few pairs between them (a pair inside one part has both uses in the same
 // phase, in one CU), and the last part's a values stay in LDS for the
 // epilogue.  Row blocks and own parts grow greedily by kept pairs and are
@@ -781,12 +783,6 @@ static void plan_blocks(K1dPlan &pl, int no, long long P, int cap, const Bits &n
     };
     const int EV = BW + 2, HB = BW / 2;
     const int zero = (int)(P * TAU_TILE);
-    const int nt = nrb + (nrb & 1);
-    auto partner = [&](int I, int r) {
-        if (I == nt - 1) return r;
-        if (I == r) return nt - 1;
-        return ((2 * r - I) % (nt - 1) + (nt - 1)) % (nt - 1);
-    };
     struct Block {
         std::vector<std::vector<int>> phases;  // resident columns of each phase
         int n_ext = 0;                         // phases of other blocks' columns
@@ -804,12 +800,10 @@ static void plan_blocks(K1dPlan &pl, int no, long long P, int cap, const Bits &n
             for (int w = 0; w < no; ++w)
                 if (bit(v, w)) touch[w] = 1;
         std::vector<int> ext;
-        for (int r = 0; r < nt - 1; ++r) {
-            const int J = partner(b, r);
-            if (J >= nrb) continue;
-            for (int w : blocks[J])
-                if (touch[w]) ext.push_back(w);
-        }
+        for (int J = 0; J < nrb; ++J)
+            if (J != b)
+                for (int w : blocks[J])
+                    if (touch[w]) ext.push_back(w);
         for (size_t i = 0; i < ext.size(); i += cap)
             K.phases.emplace_back(ext.begin() + i,
                                   ext.begin() + std::min(ext.size(), i + (size_t)cap));
