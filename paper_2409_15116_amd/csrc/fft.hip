@@ -45,9 +45,11 @@ struct FftTile {
 // Lines per workgroup of the z passes (even: a sphere column and its mirror
 // share a tile): their global side is whole lines, so
 // the tile width does not shape their memory access; narrower tiles leave
-// room for more workgroups per CU to hide the latency of the sphere gathers.
-constexpr int FFT_ZC = 16;
-static_assert(FFT_ZC % 2 == 0, "z tiles hold column pairs");
+// room for more workgroups per CU to hide the latency of the sphere gathers
+// (measured: 16 lines best in FP32, 8 in FP64, whose lines take twice the LDS).
+template <typename T>
+constexpr int FFT_ZC = sizeof(T) == 8 ? 8 : 16;
+static_assert(FFT_ZC<float> % 2 == 0 && FFT_ZC<double> % 2 == 0, "z tiles hold column pairs");
 // Upper bounds on the lines per workgroup of the y and x passes, whose tile
 // width is the length of the contiguous runs they read and write.
 constexpr int FFT_YC = 64;
@@ -231,11 +233,11 @@ __global__ void __launch_bounds__(256) k_sph_inv_z(const T *__restrict__ X, int 
     extern __shared__ unsigned char smem_raw[];
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
     constexpr int n = N;
-    constexpr int C = FftTile<T, N, FFT_ZC>::C;
-    constexpr int lc = FftTile<T, N, FFT_ZC>::lc;
-    C2 *sb = sa + FftTile<T, N, FFT_ZC>::buf;
-    C2 *stw = sb + FftTile<T, N, FFT_ZC>::buf;
-    constexpr int CP = FftTile<T, N, FFT_ZC>::CP;
+    constexpr int C = FftTile<T, N, FFT_ZC<T>>::C;
+    constexpr int lc = FftTile<T, N, FFT_ZC<T>>::lc;
+    C2 *sb = sa + FftTile<T, N, FFT_ZC<T>>::buf;
+    C2 *stw = sb + FftTile<T, N, FFT_ZC<T>>::buf;
+    constexpr int CP = FftTile<T, N, FFT_ZC<T>>::CP;
     const int L0 = blockIdx.x * C;
     FFT_FOR(i, n * CP) sa[i] = cmake<C2>(0, 0);
     load_twiddles<T>(stw, tw, n);
@@ -309,7 +311,7 @@ __global__ void __launch_bounds__(256) k_sph_inv_z(const T *__restrict__ X, int 
             put(wave + j * NWAVE, ent[beg[j] + e], x1, x2, has2);
     }
     __syncthreads();
-    C2 *res = lds_fft<T, N, true, FFT_ZC>(sa, sb, stw, (T)1);
+    C2 *res = lds_fft<T, N, true, FFT_ZC<T>>(sa, sb, stw, (T)1);
     FFT_FOR(i, n * C) {
         const int c = i / n, z = i - c * n;
         const int L = L0 + c;
@@ -519,12 +521,12 @@ __global__ void __launch_bounds__(256) k_sph_fwd_z(const cplx<T> *__restrict__ T
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
     constexpr int n = N;
-    constexpr int C = FftTile<T, N, FFT_ZC>::C;
-    constexpr int lc = FftTile<T, N, FFT_ZC>::lc;
+    constexpr int C = FftTile<T, N, FFT_ZC<T>>::C;
+    constexpr int lc = FftTile<T, N, FFT_ZC<T>>::lc;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
-    C2 *sb = sa + FftTile<T, N, FFT_ZC>::buf;
-    C2 *stw = sb + FftTile<T, N, FFT_ZC>::buf;
-    constexpr int CP = FftTile<T, N, FFT_ZC>::CP;
+    C2 *sb = sa + FftTile<T, N, FFT_ZC<T>>::buf;
+    C2 *stw = sb + FftTile<T, N, FFT_ZC<T>>::buf;
+    constexpr int CP = FftTile<T, N, FFT_ZC<T>>::CP;
     const int L0 = blockIdx.x * C;
     FFT_FOR(i, n * C) {
         const int c = i / n, z = i - c * n;
@@ -534,7 +536,7 @@ __global__ void __launch_bounds__(256) k_sph_fwd_z(const cplx<T> *__restrict__ T
     }
     load_twiddles<T>(stw, tw, n);  // after the data loads: they overlap
     __syncthreads();
-    C2 *res = lds_fft<T, N, true, FFT_ZC>(sa, sb, stw, (T)-1);
+    C2 *res = lds_fft<T, N, true, FFT_ZC<T>>(sa, sb, stw, (T)-1);
     const T inv_nr = (T)1 / ((T)n * (T)n * (T)n);
     const T sq2 = (T)1.41421356237309504880;
     constexpr int NWAVE = FFT_NT >> 6;
@@ -618,12 +620,12 @@ __global__ void __launch_bounds__(256) k_grid_z(cplx<T> *__restrict__ A, int n_l
     using C2 = cplx<T>;
     extern __shared__ unsigned char smem_raw[];
     constexpr int n = N;
-    constexpr int C = FftTile<T, N, FFT_ZC>::C;
-    constexpr int lc = FftTile<T, N, FFT_ZC>::lc;
+    constexpr int C = FftTile<T, N, FFT_ZC<T>>::C;
+    constexpr int lc = FftTile<T, N, FFT_ZC<T>>::lc;
     C2 *sa = reinterpret_cast<C2 *>(smem_raw);
-    C2 *sb = sa + FftTile<T, N, FFT_ZC>::buf;
-    C2 *stw = sb + FftTile<T, N, FFT_ZC>::buf;
-    constexpr int CP = FftTile<T, N, FFT_ZC>::CP;
+    C2 *sb = sa + FftTile<T, N, FFT_ZC<T>>::buf;
+    C2 *stw = sb + FftTile<T, N, FFT_ZC<T>>::buf;
+    constexpr int CP = FftTile<T, N, FFT_ZC<T>>::CP;
     const int L0 = blockIdx.x * C;
     FFT_FOR(i, n * C) {
         const int c = i / n, z = i - c * n;
@@ -633,7 +635,7 @@ __global__ void __launch_bounds__(256) k_grid_z(cplx<T> *__restrict__ A, int n_l
     }
     load_twiddles<T>(stw, tw, n);  // after the data loads: they overlap
     __syncthreads();
-    C2 *res = lds_fft<T, N, true, FFT_ZC>(sa, sb, stw, sign);
+    C2 *res = lds_fft<T, N, true, FFT_ZC<T>>(sa, sb, stw, sign);
     FFT_FOR(i, n * C) {
         const int c = i / n, z = i - c * n;
         const int L = L0 + c;
@@ -743,8 +745,8 @@ static void sph_inverse_n(const SphereMaps &m, const T *X, int n_orb, T *out, cp
     const int nq = n_lines_for(n_orb, ps);
     {
         const int n_lines = nq * m.ncol;
-        k_sph_inv_z<T, N><<<div_up(n_lines, FftTile<T, N, FFT_ZC>::C), 256,
-                            FftTile<T, N, FFT_ZC>::lds, st>>>(
+        k_sph_inv_z<T, N><<<div_up(n_lines, FftTile<T, N, FFT_ZC<T>>::C), 256,
+                            FftTile<T, N, FFT_ZC<T>>::lds, st>>>(
             X, n_orb, m.npw, m.ent, m.col_ptr, m.ncol, n_lines, T1, tw, ps);
         BSE_LAUNCH_CHECK();
         if (ev) BSE_HIP(hipEventRecord(ev[0], st));
@@ -792,8 +794,8 @@ static void sph_forward_n(const SphereMaps &m, const T *Cr, const T *u, const cp
     }
     {
         const int n_lines = nq * m.ncol;
-        k_sph_fwd_z<T, N><<<div_up(n_lines, FftTile<T, N, FFT_ZC>::C), 256,
-                            FftTile<T, N, FFT_ZC>::lds, st>>>(
+        k_sph_fwd_z<T, N><<<div_up(n_lines, FftTile<T, N, FFT_ZC<T>>::C), 256,
+                            FftTile<T, N, FFT_ZC<T>>::lds, st>>>(
             T1, m.ent, m.col_ptr, m.ncol, n_lines, n_orb, m.npw, X, m.kin, kin_scale, Y, tw,
             n_occ);
         BSE_LAUNCH_CHECK();
@@ -806,7 +808,7 @@ static void grid_fft_n(cplx<T> *A, int nb, T sign, const cplx<T> *tw, hipStream_
     using C2 = cplx<T>;
     constexpr int n = N;
     const int n_lines = nb * n * n;
-    k_grid_z<T, N><<<div_up(n_lines, FftTile<T, N, FFT_ZC>::C), 256, FftTile<T, N, FFT_ZC>::lds,
+    k_grid_z<T, N><<<div_up(n_lines, FftTile<T, N, FFT_ZC<T>>::C), 256, FftTile<T, N, FFT_ZC<T>>::lds,
                      st>>>(A, n_lines, tw, sign);
     BSE_LAUNCH_CHECK();
     using FY = FftTile<T, N, FFT_YC, FFT_YKB>;
