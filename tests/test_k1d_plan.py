@@ -84,3 +84,30 @@ def test_plan_rejects_malformed_pair_lists():
         with pytest.raises(pkg.BseError) as e:
             pkg.k1d_plan(3, pr, 0)
         assert e.value.status == 1  # BSE_ERR_ARG
+
+
+EDGE_SIZES = [1, 8, 9, 64, 127, 128, 129, 255, 256, 257]
+
+
+@pytest.mark.parametrize("n,kind", [(n, k) for k in ("diagonal", "chain") for n in EDGE_SIZES]
+                         + [(n, "dense") for n in EDGE_SIZES if n <= 129])
+def test_plan_edge_cases(n, kind):
+    """Degenerate pair lists at block-size edges: only the diagonal (no
+    partners), every pair kept, and a chain (each orbital with its two
+    neighbours); the planner's own check passes and every kept entry is
+    counted once."""
+    if kind == "diagonal":
+        pr = np.stack([np.arange(n), np.arange(n)], 1)
+    elif kind == "dense":
+        v, w = np.triu_indices(n)
+        pr = np.stack([v, w], 1)
+    else:
+        v = np.arange(n)
+        pr = np.concatenate([np.stack([v, v], 1), np.stack([v[:-1], v[1:]], 1)])
+        pr = pr[np.lexsort((pr[:, 1], pr[:, 0]))]
+    pr = pr.astype(np.int32)
+    for set_ in (0, 1):
+        t = pkg.k1d_plan(n, pr, set_)
+        assert t["kept_entries"] == 2 * len(pr) - n
+        assert t["row_blocks"] == max(1, -(-n // 128))
+        assert t["staged"] >= n
